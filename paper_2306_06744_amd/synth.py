@@ -1,0 +1,158 @@
+"""Seeded synthetic inputs for the adaptation cycle.
+
+This module only draws numbers and states workload shapes; it holds none of
+the method's arithmetic (no keys, no criterion, no transfer).  Both the GPU
+library's callers and the CPU oracle's tests take their inputs from here.
+
+Inputs, each with the passage it stands in for:
+  * solution-point positions on one axis (Gauss-Legendre points mapped to
+    [0, 1]; the FR solution points of Section 2.1, family read as
+    Gauss-Legendre), given as data so both sides use identical bits;
+  * isentropic-vortex centres and strengths (Section 5.2) per workload;
+  * the vortex path of the paper's adaptive runs: free stream (u, v) = (1, 1),
+    time step 0.001 and adaptation every 10 steps (Section 5.2), so the
+    centre moves by 0.01 per axis per cycle;
+  * random solution arrays (the transfer is linear in u, so any values test
+    it) and random refine/keep/coarsen flags.
+RNG: numpy PCG64, seed 1000*k + i for parity case i of workload k and
+1000*k for timing.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+def gl_nodes01(p: int) -> np.ndarray:
+    """Gauss-Legendre points of degree-p FR on [0, 1] (closed forms, p <= 3)."""
+    if p == 0:
+        x = [0.0]
+    elif p == 1:
+        r = 1.0 / math.sqrt(3.0)
+        x = [-r, r]
+    elif p == 2:
+        r = math.sqrt(3.0 / 5.0)
+        x = [-r, 0.0, r]
+    elif p == 3:
+        a = math.sqrt(3.0 / 7.0 - 2.0 / 7.0 * math.sqrt(6.0 / 5.0))
+        b = math.sqrt(3.0 / 7.0 + 2.0 / 7.0 * math.sqrt(6.0 / 5.0))
+        x = [-b, -a, a, b]
+    else:
+        raise ValueError("closed forms only for p <= 3")
+    return np.array([(1.0 + v) / 2.0 for v in x], dtype=np.float64)
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+@dataclass
+class Workload:
+    """One synthetic adaptation workload (cubic domain [lo, lo+length)^dim)."""
+    name: str
+    dim: int
+    d_min: int
+    d_max: int
+    p: int
+    nvar: int
+    lo: tuple
+    length: float
+    r_in: float
+    r_out: float
+    dist_axes: int
+    periodic_dist: bool
+    centres: list = field(default_factory=list)    # per vortex, 3 coords
+    strengths: list = field(default_factory=list)
+    cycles: int = 1
+    advect: tuple = (0.0, 0.0, 0.0)               # centre shift per cycle
+    start_depth: int | None = None                 # uniform start (default d_min)
+
+    def centres_at(self, cycle: int) -> list:
+        return [tuple(c[a] + cycle * self.advect[a] for a in range(3)) for c in self.centres]
+
+
+def workload_2d_small(seed: int = 1000) -> Workload:
+    """2D, [-5,5]^2, uniform level 3, max level 6, p=2, 4 variables, one
+    vortex of strength 5 centred uniformly in [-2,2]^2; radii 5 / 6."""
+    g = rng(seed)
+    c = g.uniform(-2.0, 2.0, size=2)
+    return Workload("2d_small_p2_l3-6", 2, 3, 6, 2, 4, (-5.0, -5.0), 10.0, 5.0, 6.0, 2, False,
+                    centres=[(float(c[0]), float(c[1]), 0.0)], strengths=[5.0], cycles=1)
+
+
+def workload_3d_extruded(seed: int = 2000) -> Workload:
+    """3D, [-5,5]^3, uniform level 4, max level 7, p=3, 5 variables, one
+    z-extruded vortex (strength U[3,7], centre U[-2,2]^2, xy distance),
+    10 cycles advected by +0.1 in x per cycle."""
+    g = rng(seed)
+    c = g.uniform(-2.0, 2.0, size=2)
+    s = g.uniform(3.0, 7.0)
+    return Workload("3d_extruded_p3_l4-7", 3, 4, 7, 3, 5, (-5.0, -5.0, -5.0), 10.0, 5.0, 6.0, 2,
+                    False, centres=[(float(c[0]), float(c[1]), 0.0)], strengths=[float(s)],
+                    cycles=10, advect=(0.1, 0.0, 0.0))
+
+
+def random_flags(seed: int, n: int, p_refine: float = 0.3, p_coarsen: float = 0.4) -> np.ndarray:
+    g = rng(seed)
+    r = g.random(n)
+    f = np.zeros(n, dtype=np.int8)
+    f[r < p_refine] = 1
+    f[(r >= p_refine) & (r < p_refine + p_coarsen)] = -1
+    return f
+
+
+def random_solution(seed: int, nvar: int, npts: int, n: int) -> np.ndarray:
+    """(nvar, npts, n) float64 standard-normal values."""
+    return rng(seed).standard_normal((nvar, npts, n))
+
+
+# --------------------------------------------------------------- paper runs
+@dataclass
+class PaperRun:
+    """One adaptive run of Section 5.2 replayed without the solver.
+
+    The criterion depends only on the vortex axis, which moves with the free
+    stream (1, 1): the centre at cycle k (time 0.01 k) is (0.01 k, 0.01 k).
+    ``cycles`` adaptations run at k = 0 .. cycles-1, after ``warmup`` extra
+    adaptations at the k = 0 centre from a uniform mesh at ``start_depth``.
+    Distances use the minimum image (the vortex crosses the periodic boundary).
+    ``z_layers`` > 1 marks the 3D slab, run as a cube of that many identical
+    level-d_min layers (count = leaves / z_layers)."""
+    name: str
+    dim: int
+    d_min: int
+    d_max: int
+    p: int
+    half_width: float
+    cycles: int
+    start_depth: int
+    warmup: int = 12
+    z_layers: int = 1
+
+    @property
+    def lo(self):
+        return tuple([-self.half_width] * self.dim)
+
+    @property
+    def length(self):
+        return 2.0 * self.half_width
+
+    def centre(self, k: int):
+        t = k * 0.01
+        return (t, t, 0.0)
+
+
+def paper_runs() -> list:
+    runs = []
+    for dmax in (6, 7, 8):
+        for p in (1, 2, 3):
+            runs.append(PaperRun(f"2d_w25_d{dmax}_p{p}", 2, 3, dmax, p, 12.5, 2500, 3))
+    for dmax in (8, 9, 10):
+        for p in (1, 2, 3):
+            runs.append(PaperRun(f"2d_w100_d{dmax}_p{p}", 2, 3, dmax, p, 50.0, 10000, dmax))
+    for dmax in (6, 7, 8):
+        for p in (1, 2, 3):
+            runs.append(PaperRun(f"3d_slab_d{dmax}_p{p}", 3, 4, dmax, p, 12.5, 2500, 4, z_layers=16))
+    return runs
