@@ -1,0 +1,187 @@
+"""Throughput of the adaptation cycle on one MI355X.
+
+A step is one complete cycle over the whole mesh, through the C ABI:
+flag -> adapt -> 2:1 balance -> face connectivity -> old/new mapping ->
+FP64 solution transfer.  Workload: 3D [-5,5]^3, uniform level 4 (4096
+leaves), levels 4..7, p = 3 (64 Gauss-Legendre points), 5 FP64 variables, one
+z-extruded isentropic-vortex indicator (xy distance, radii 5 / 6) whose
+centre moves +0.1 in x per cycle.  The first --warmup cycles (default 3:
+4096 -> ~28k -> ~213k -> ~1.64M leaves) are untimed; the --steps timed cycles
+(default 7: cycles 3..9) are the steady state of that 10-cycle workload.
+
+value = new leaves summed over the timed cycles / timed wall time.
+roofline: the transfer kernel (the dominant one), algorithmic bytes = every
+old element read once + every new element written once (E = 8 * 64 * 5 B)
++ the mapping it reads (4 + 1 B per new element), over its HIP-event time.
+cpu_baseline: the CPU oracle (single thread) on cycles 0..1 of the workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cycle_bytes(dim, E, n_old, n_new, n_hang):
+    """Compulsory HBM bytes of one cycle: keys read/written, nbr, hang rows,
+    each old element read once and each new one written once."""
+    return (8 * n_old + 8 * n_new + 4 * 2 * dim * n_new + 4 * (2 + (1 << (dim - 1))) * n_hang
+            + E * (n_old + n_new))
+
+
+def cpu_baseline(w, nodes, cycles=2):
+    import numpy as np
+    import oracle
+    from paper_2306_06744_amd import synth
+    o = oracle.Tree(w.dim, w.d_min, w.d_max)
+    u = synth.random_solution(7, w.nvar, (w.p + 1) ** w.dim, o.size())
+    total_new, t_all = 0, 0.0
+    for cyc in range(cycles):
+        t0 = time.perf_counter()
+        f = o.flag(w.centres_at(cyc), w.r_in, w.r_out, nodes, w.lo, w.length,
+                   dist_axes=w.dist_axes, periodic_dist=w.periodic_dist)
+        o.adapt(f)
+        o.balance()
+        o.connect()
+        o.map()
+        u = o.transfer(w.p, u)
+        t_all += time.perf_counter() - t0
+        total_new += o.size()
+    del np
+    return {"value": total_new / t_all, "unit": "octants/s", "cores": 1, "kind": "oracle",
+            "sample": f"cycles 0..{cycles - 1} of the same workload ({total_new} new leaves, "
+                      f"{t_all:.1f} s, pointer-tree oracle, one thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=7)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=2000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs the adaptation cycle on a single "
+              "MI355X and has no multi-GPU path (--gpus must be 1).", file=sys.stderr)
+        sys.exit(2)
+    if args.warmup < 3:
+        log("note: fewer than 3 warm-up cycles times the growth phase, not the steady state")
+
+    import torch
+    import paper_2306_06744_amd as lt
+    from paper_2306_06744_amd import synth
+
+    w = synth.workload_3d_extruded(args.seed)
+    nodes = synth.gl_nodes01(w.p)
+    npts = (w.p + 1) ** w.dim
+    E = 8 * npts * w.nvar
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    t = lt.Tree.uniform(w.dim, w.d_min, w.d_max)
+    cap = 4_000_000  # leaves per solution buffer (steady state ~1.7M)
+    u = [torch.empty((w.nvar, npts, cap), dtype=torch.float64, device="cuda") for _ in range(2)]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(args.seed)
+    u[0][:, :, : t.size()].normal_(generator=g)
+    cur = 0
+
+    def step(cyc, ev=None):
+        nonlocal cur
+        n_old = t.size()
+        f = t.flag(w.centres_at(cyc), w.r_in, w.r_out, nodes, w.lo, w.length,
+                   dist_axes=w.dist_axes, periodic_dist=w.periodic_dist)
+        t.adapt(f)
+        t.balance()
+        t.connect()
+        t.map()
+        n_new, _, n_hang = t.sizes()
+        if n_new > cap:
+            raise RuntimeError("solution buffer too small")
+        if ev is not None:
+            ev[0].record(stream)
+        t.transfer(w.p, u[cur], u_new=u[1 - cur])
+        if ev is not None:
+            ev[1].record(stream)
+        cur = 1 - cur
+        return n_old, n_new, n_hang
+
+    for c in range(args.warmup):
+        n_old, n_new, _ = step(c)
+        log(f"warmup cycle {c}: {n_old} -> {n_new}")
+    torch.cuda.synchronize()
+
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    sizes = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        sizes.append(step(args.warmup + k, events[k]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    total_new = sum(s[1] for s in sizes)
+    tr_ms = [a.elapsed_time(b) for a, b in events]
+    tr_bytes = [E * n_old + (E + 5) * n_new for n_old, n_new, _ in sizes]
+    achieved = sum(tr_bytes) / (sum(tr_ms) * 1e-3) / 1e9
+    cyc_bytes = sum(cycle_bytes(w.dim, E, *s) for s in sizes)
+    for k, (s, ms) in enumerate(zip(sizes, tr_ms)):
+        log(f"cycle {args.warmup + k}: {s[0]} -> {s[1]} leaves, {s[2]} hanging faces, "
+            f"transfer {ms:.3f} ms")
+
+    result = {
+        "metric": "adapted octants/s (flag->adapt->balance->connect->map->transfer), plain FP64 cycle",
+        "value": total_new / elapsed,
+        "unit": "octants/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "3D linear octree [-5,5]^3, uniform level 4 -> levels 4..7, p=3 "
+                        "(64 GL points), 5 FP64 variables, z-extruded vortex indicator "
+                        "(radii 5/6) advected +0.1 x per cycle",
+            "cycles_timed": [args.warmup, args.warmup + args.steps - 1],
+            "leaves_new_mean": total_new / args.steps,
+            "cycle_hbm_frac": cyc_bytes / elapsed / (HBM_PEAK_GBS * 1e9),
+            "transfer_ms_mean": sum(tr_ms) / len(tr_ms),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_transfer<3,4> (FP64 transfer)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        try:
+            result["cpu_baseline"] = cpu_baseline(w, nodes)
+        except Exception as e:  # the oracle is optional on a box without g++
+            log(f"cpu_baseline skipped: {e}")
+            result["cpu_baseline"] = None
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,184 @@
+/*
+ * lt.h -- C ABI of the MI355X (gfx950) adaptation cycle on linear trees.
+ *
+ * One tree (a 2D linear quadtree or 3D linear octree) lives in device memory
+ * as an ascending array of 64-bit Morton IDs.  The cycle of the h-adaptive
+ * flux-reconstruction method is
+ *
+ *     lt_flag -> lt_adapt -> lt_balance -> lt_connect -> lt_map -> lt_transfer
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers documented as "device" are HIP device pointers; "host" ones are
+ *     ordinary host memory read during the call only.
+ *   - `stream` is a hipStream_t (may be NULL for the null stream).  Kernels are
+ *     enqueued on it in call order.  Calls that must learn a size on the host
+ *     (lt_build, lt_adapt, lt_balance, lt_connect, lt_map) synchronise the
+ *     stream before returning; lt_flag and lt_transfer do not.
+ *   - Every call returns an lt_status; no exception crosses the ABI.  The text
+ *     of the last error of the calling thread is lt_last_error().
+ *   - Caller-owned buffers (flags, solution arrays, export targets) stay owned
+ *     by the caller.  Everything else (keys, the pre-adapt snapshot, nbr, hang,
+ *     map arrays, scratch) is owned by the tree and freed by lt_destroy.
+ *   - A tree is not thread-safe; use one tree per host thread or serialise.
+ *
+ * Morton ID layout (Section 2.2, Algorithm "Morton Encoding"): the anchor
+ * (lowest corner) of an octant in integer units of the finest resolution
+ * 2^-d_max is bit-interleaved with x least significant (bit k of axis a at
+ * position dim*k + a), then shifted left by m_b = bitlength(d_max) bits that
+ * hold the depth.  Ascending IDs list leaves depth-first, a parent before its
+ * children, and a first child's ID is its parent's plus one.
+ */
+#ifndef LT_H
+#define LT_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lt_tree_s* lt_tree;
+
+typedef enum {
+  LT_OK = 0,
+  LT_ERR_ARG = 1,          /* bad argument: null pointer, size or value out of range   */
+  LT_ERR_OOM = 2,          /* a device or pinned-host allocation failed                */
+  LT_ERR_HIP = 3,          /* a HIP runtime call or kernel launch failed               */
+  LT_ERR_DEPTH = 4,        /* dim*d_max + m_b > 64, or a depth outside [0, d_max]      */
+  LT_ERR_INVALID_TREE = 5, /* keys not strictly ascending / not a complete linear tree */
+  LT_ERR_UNBALANCED = 6,   /* a step that needs a 2:1-balanced tree found it is not    */
+  LT_ERR_STATE = 7,        /* call order violated (e.g. lt_map before any lt_adapt)    */
+  LT_ERR_INTERNAL = 8      /* a device-side consistency check failed                   */
+} lt_status;
+
+/* Export / view selectors. */
+typedef enum {
+  LT_KEYS = 0,      /* uint64  [n_cur]                                      */
+  LT_OLD_KEYS = 1,  /* uint64  [n_old]       keys before the last lt_adapt  */
+  LT_NBR = 2,       /* int32   [n_cur * 2*dim]                              */
+  LT_HANG = 3,      /* int32   [n_hang * (2 + 2^(dim-1))]                   */
+  LT_MAP_SRC = 4,   /* int32   [n_cur]                                      */
+  LT_MAP_KIND = 5   /* int8    [n_cur]                                      */
+} lt_field;
+
+#define LT_MAX_VORTICES 8
+#define LT_MAX_DEGREE 7
+
+/* Tree geometry.  The domain is the cube [0, 2^d_max)^dim in finest units. */
+typedef struct {
+  int dim;                /* 2 or 3                                                   */
+  int d_min;              /* coarsening floor: no leaf coarsens below this depth      */
+  int d_max;              /* refinement ceiling; dim*d_max + bitlength(d_max) <= 64   */
+  unsigned periodic_mask; /* bit a set: axis a is periodic (neighbour keys wrap)      */
+  int balance;            /* 2:1 balance across 0 faces, 1 faces+edges, 2 + corners   */
+} lt_geom;
+
+/* Geometric refinement criterion (Section 5.2): an element is flagged +1 when
+ * more of its (p+1)^dim solution points lie strictly within r_in of the
+ * nearest vortex axis than strictly beyond r_out, -1 when fewer, 0 otherwise;
+ * +1 becomes 0 at depth d_max and -1 becomes 0 at depth <= d_min.
+ * Point k of an element of depth D with anchor x (finest units) on axis a is
+ *   lo[a] + dx * (x_a + s * nodes01[k]),  s = 2^(d_max - D), dx = len / 2^d_max,
+ * evaluated in FP64 in exactly that order without fused multiply-adds;
+ * r^2 = sum over axes a < dist_axes of (X_a - centre_a)^2 in axis order,
+ * with the minimum image d - len*floor(d/len + 0.5) when periodic_dist. */
+typedef struct {
+  int nvort;              /* 1 .. LT_MAX_VORTICES                                     */
+  const double* centre;   /* host, centre[3*v + a]                                    */
+  double r_in, r_out;
+  int dist_axes;          /* 2: distance in the xy plane (z-extruded field), 3: xyz   */
+  int periodic_dist;      /* 1: minimum-image distance with period len               */
+  int p;                  /* polynomial degree, 0 .. LT_MAX_DEGREE                   */
+  const double* nodes01;  /* host, p+1 solution-point positions in [0,1] on one axis */
+  double lo[3];           /* physical position of the domain's lowest corner         */
+  double len;             /* physical edge length of the cubic domain                */
+} lt_flag_params;
+
+/* Uniform tree of all 2^(dim*depth) octants at `depth` (d_min <= depth <= d_max
+ * is not required: depth may be below d_min or above it up to d_max).
+ * Ownership of *out passes to the caller (release with lt_destroy). */
+lt_status lt_build_uniform(const lt_geom* geom, int depth, void* stream, lt_tree* out);
+
+/* Tree from `n` device keys (copied).  The keys must be strictly ascending and
+ * form a complete linear tree (the leaves tile the domain exactly); otherwise
+ * LT_ERR_INVALID_TREE.  Balance is not checked here. */
+lt_status lt_build(const lt_geom* geom, const uint64_t* keys, int64_t n, void* stream,
+                   lt_tree* out);
+
+/* Flags of the current leaves (Section 5.2 criterion, see lt_flag_params).
+ * flags: device int8 [n_cur], written in key order.  Asynchronous. */
+lt_status lt_flag(lt_tree t, const lt_flag_params* fp, int8_t* flags, void* stream);
+
+/* Adaptation procedure (Section 4.1): every leaf flagged +1 (depth < d_max) is
+ * replaced by its 2^dim children; a family of 2^dim sibling leaves all flagged
+ * -1 (depth > d_min) is replaced by its parent; every other -1 acts as 0.  No
+ * octant changes more than once.  flags: device int8 [n_cur], values -1, 0, 1
+ * (others: LT_ERR_ARG detected on the device, tree unchanged).  The keys
+ * before the call are kept as the old tree for lt_map / lt_transfer. */
+lt_status lt_adapt(lt_tree t, const int8_t* flags, void* stream);
+
+/* Strong 2:1 balance (Section 3.2): replace the tree by its coarsest
+ * refinement in which any two leaves touching across a face (or edge /
+ * corner, per geom.balance; periodic axes wrap) differ by at most one level.
+ * On error the tree is a valid, possibly partially balanced refinement. */
+lt_status lt_balance(lt_tree t, void* stream);
+
+/* Face connectivity (Section 3.3).  Face f = 2*axis + side (side 0 = low
+ * coordinate); a conforming face f meets face f^1 of its neighbour.
+ *   nbr[2*dim*e + f] = index of the one leaf of depth <= depth(e) across face f
+ *                      (same depth: conforming; one coarser: e is a fine side),
+ *                    = -1 when 2^(dim-1) leaves one level finer lie across
+ *                      (e is the coarse side; see hang),
+ *                    = -2 across a non-periodic domain boundary.
+ *   hang row r = [e, f, k_0 .. k_{2^(dim-1)-1}], rows sorted by (e, f); k_s is
+ *   the fine leaf whose tangential child bits (lower axis first) equal s.
+ * Needs a 2:1-balanced tree (LT_ERR_UNBALANCED otherwise). */
+lt_status lt_connect(lt_tree t, void* stream);
+
+/* Old->new mapping (Section 4.2, mapping algorithm): for each current leaf j,
+ *   map_kind[j] = 0      map_src[j] = old index of the same octant (copy),
+ *   map_kind[j] = 1 + c  map_src[j] = old index of its parent (refined, child c),
+ *   map_kind[j] = -1     map_src[j] = old index of its first child (fused; the
+ *                        2^dim children are old[src .. src + 2^dim - 1]).
+ * LT_ERR_STATE without a prior lt_adapt; LT_ERR_UNBALANCED when a leaf fits
+ * none of the three cases (the old tree was not balanced). */
+lt_status lt_map(lt_tree t, void* stream);
+
+/* Solution transfer (Section 4.2) from the old tree to the current one:
+ * copy; interpolation of the parent polynomial at the child's points
+ * (eq. parent_soln); L2 projection of the 2^dim children onto the parent.
+ * Solution layout: u[(v * n_p + i) * ld + e], n_p = (p+1)^dim, point index
+ * i = i_x + (p+1) (i_y + (p+1) i_z) over Gauss-Legendre points, variable v
+ * slowest, element e fastest.  u_old: device FP64, ld_old >= n_old; u_new:
+ * device FP64, ld_new >= n_cur, written for every current leaf.  Computes the
+ * mapping first if lt_map has not run since the last change.  precision 0 is
+ * FP64 throughout; other values return LT_ERR_ARG.  p in 1..3 for dim 3,
+ * 1..LT_MAX_DEGREE for dim 2.  Asynchronous (unless the mapping was stale). */
+lt_status lt_transfer(lt_tree t, int p, int nvar, const double* u_old, int64_t ld_old,
+                      double* u_new, int64_t ld_new, int precision, void* stream);
+
+/* Host-side sizes (no device work): current leaves, leaves before the last
+ * lt_adapt (-1 if none), rows of the hanging-face table (-1 before lt_connect).
+ * Any pointer may be NULL. */
+lt_status lt_size(lt_tree t, int64_t* n_cur, int64_t* n_old, int64_t* n_hang);
+
+/* Borrowed device pointer to one of the tree's arrays (NULL if not computed);
+ * valid until the next call that changes the tree. */
+lt_status lt_view(lt_tree t, lt_field what, const void** ptr, int64_t* count);
+
+/* Stream-ordered device-to-device copy of one of the tree's arrays into the
+ * caller's device buffer `dst` holding `capacity` elements of that field's
+ * type; LT_ERR_ARG if it is too small.  dst may be NULL when the field is
+ * empty; LT_ERR_STATE if the field has not been computed. */
+lt_status lt_export(lt_tree t, lt_field what, void* dst, int64_t capacity, void* stream);
+
+/* Text of the calling thread's last error ("" if none). */
+const char* lt_last_error(void);
+
+/* Frees the tree and everything it owns (NULL is ignored).  Synchronises the
+ * device before freeing. */
+void lt_destroy(lt_tree t);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,227 @@
+"""Python binding of ``liblt.so`` (include/lt.h): the adaptation cycle of
+the h-adaptive flux-reconstruction method on linear trees, on one MI355X.
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+PyTorch supplies device memory and the current stream.  Importing works
+without a GPU; using a tree needs the built library and a HIP device, and
+raises ``LtError`` if either is missing (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(HERE, "liblt.so")
+
+LT_KEYS, LT_OLD_KEYS, LT_NBR, LT_HANG, LT_MAP_SRC, LT_MAP_KIND = range(6)
+LT_MAX_VORTICES = 8
+LT_MAX_DEGREE = 7
+
+STATUS = {0: "LT_OK", 1: "LT_ERR_ARG", 2: "LT_ERR_OOM", 3: "LT_ERR_HIP", 4: "LT_ERR_DEPTH",
+          5: "LT_ERR_INVALID_TREE", 6: "LT_ERR_UNBALANCED", 7: "LT_ERR_STATE",
+          8: "LT_ERR_INTERNAL"}
+
+# Every symbol include/lt.h declares.
+EXPORTS = ["lt_build_uniform", "lt_build", "lt_flag", "lt_adapt", "lt_balance", "lt_connect",
+           "lt_map", "lt_transfer", "lt_size", "lt_view", "lt_export", "lt_last_error",
+           "lt_destroy"]
+
+
+class LtError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Geom(C.Structure):
+    _fields_ = [("dim", C.c_int), ("d_min", C.c_int), ("d_max", C.c_int),
+                ("periodic_mask", C.c_uint), ("balance", C.c_int)]
+
+
+class FlagParams(C.Structure):
+    _fields_ = [("nvort", C.c_int), ("centre", C.POINTER(C.c_double)),
+                ("r_in", C.c_double), ("r_out", C.c_double), ("dist_axes", C.c_int),
+                ("periodic_dist", C.c_int), ("p", C.c_int),
+                ("nodes01", C.POINTER(C.c_double)), ("lo", C.c_double * 3),
+                ("len", C.c_double)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load liblt.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO_PATH):
+            raise LtError(3, f"{SO_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(SO_PATH)
+        P, i64, i32 = C.c_void_p, C.c_int64, C.c_int
+        L.lt_build_uniform.argtypes = [C.POINTER(Geom), i32, P, C.POINTER(P)]
+        L.lt_build.argtypes = [C.POINTER(Geom), P, i64, P, C.POINTER(P)]
+        L.lt_flag.argtypes = [P, C.POINTER(FlagParams), P, P]
+        L.lt_adapt.argtypes = [P, P, P]
+        L.lt_balance.argtypes = [P, P]
+        L.lt_connect.argtypes = [P, P]
+        L.lt_map.argtypes = [P, P]
+        L.lt_transfer.argtypes = [P, i32, i32, P, i64, P, i64, i32, P]
+        L.lt_size.argtypes = [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+        L.lt_view.argtypes = [P, i32, C.POINTER(P), C.POINTER(i64)]
+        L.lt_export.argtypes = [P, i32, P, i64, P]
+        L.lt_last_error.restype = C.c_char_p
+        L.lt_destroy.argtypes = [P]
+        L.lt_destroy.restype = None
+        for name in EXPORTS:
+            if name not in ("lt_last_error", "lt_destroy"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise LtError(rc, lib().lt_last_error().decode())
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise LtError(3, "no HIP device is available")
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t) -> C.c_void_p:
+    assert t.is_cuda and t.is_contiguous()
+    return C.c_void_p(t.data_ptr())
+
+
+class Tree:
+    """One linear quadtree / octree in device memory (owns an lt_tree)."""
+
+    def __init__(self, handle: C.c_void_p, geom: Geom):
+        self._h = handle
+        self.geom = geom
+        self.dim = geom.dim
+
+    # ---- construction
+    @classmethod
+    def uniform(cls, dim, d_min, d_max, depth=None, periodic_mask=None, balance=2) -> "Tree":
+        g = Geom(dim, d_min, d_max, (1 << dim) - 1 if periodic_mask is None else periodic_mask,
+                 balance)
+        h = C.c_void_p()
+        _stream()
+        _check(lib().lt_build_uniform(C.byref(g), d_min if depth is None else depth, _stream(),
+                                      C.byref(h)))
+        return cls(h, g)
+
+    @classmethod
+    def from_keys(cls, keys, dim, d_min, d_max, periodic_mask=None, balance=2) -> "Tree":
+        """keys: device int64 tensor holding the uint64 Morton IDs."""
+        torch = _torch()
+        k = keys.to(device="cuda", dtype=torch.int64).contiguous()
+        g = Geom(dim, d_min, d_max, (1 << dim) - 1 if periodic_mask is None else periodic_mask,
+                 balance)
+        h = C.c_void_p()
+        _check(lib().lt_build(C.byref(g), _dptr(k), k.numel(), _stream(), C.byref(h)))
+        return cls(h, g)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.lt_destroy(h)
+            self._h = None
+
+    # ---- sizes
+    def sizes(self):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().lt_size(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def size(self) -> int:
+        return self.sizes()[0]
+
+    # ---- cycle
+    def flag(self, centres, r_in, r_out, nodes01, lo, length, dist_axes=None,
+             periodic_dist=False, out=None):
+        torch = _torch()
+        n = self.size()
+        if out is None:
+            out = torch.empty(n, dtype=torch.int8, device="cuda")
+        cen = (C.c_double * (3 * len(centres)))()
+        for v, c in enumerate(centres):
+            for a in range(len(c)):
+                cen[3 * v + a] = float(c[a])
+        nodes = (C.c_double * len(nodes01))(*[float(x) for x in nodes01])
+        lo3 = (C.c_double * 3)(*([float(x) for x in lo] + [0.0] * (3 - len(lo))))
+        fp = FlagParams(len(centres), C.cast(cen, C.POINTER(C.c_double)), float(r_in),
+                        float(r_out), int(dist_axes or self.dim), int(bool(periodic_dist)),
+                        len(nodes01) - 1, C.cast(nodes, C.POINTER(C.c_double)), lo3,
+                        float(length))
+        _check(lib().lt_flag(self._h, C.byref(fp), _dptr(out), _stream()))
+        return out
+
+    def adapt(self, flags):
+        torch = _torch()
+        f = flags.to(device="cuda", dtype=torch.int8).contiguous()
+        if f.numel() != self.size():
+            raise LtError(1, "flags must have one entry per leaf")
+        _check(lib().lt_adapt(self._h, _dptr(f), _stream()))
+
+    def balance(self):
+        _check(lib().lt_balance(self._h, _stream()))
+
+    def connect(self):
+        _check(lib().lt_connect(self._h, _stream()))
+
+    def map(self):
+        _check(lib().lt_map(self._h, _stream()))
+
+    def transfer(self, p, u_old, u_new=None, precision=0):
+        """u_old: (nvar, n_p, ld_old) float64 device tensor -> (nvar, n_p, n_cur)."""
+        torch = _torch()
+        assert u_old.dtype == torch.float64 and u_old.is_cuda and u_old.is_contiguous()
+        nvar, npts, ld_old = u_old.shape
+        if npts != (p + 1) ** self.dim:
+            raise LtError(1, "u_old has the wrong number of points per element")
+        n = self.size()
+        if u_new is None:
+            u_new = torch.empty((nvar, npts, n), dtype=torch.float64, device="cuda")
+        _check(lib().lt_transfer(self._h, p, nvar, _dptr(u_old), ld_old, _dptr(u_new),
+                                 u_new.shape[2], precision, _stream()))
+        return u_new
+
+    # ---- results
+    def export(self, what: int):
+        torch = _torch()
+        n, n_old, n_hang = self.sizes()
+        nf = 2 * self.dim
+        w = 2 + (1 << (self.dim - 1))
+        shapes = {LT_KEYS: ((n,), torch.int64), LT_OLD_KEYS: ((max(n_old, 0),), torch.int64),
+                  LT_NBR: ((n, nf), torch.int32), LT_HANG: ((max(n_hang, 0), w), torch.int32),
+                  LT_MAP_SRC: ((n,), torch.int32), LT_MAP_KIND: ((n,), torch.int8)}
+        shape, dt = shapes[what]
+        out = torch.empty(shape, dtype=dt, device="cuda")
+        ptr = _dptr(out) if out.numel() else C.c_void_p()
+        _check(lib().lt_export(self._h, what, ptr, out.numel(), _stream()))
+        return out
+
+    def keys(self):
+        return self.export(LT_KEYS)
+
+    def old_keys(self):
+        return self.export(LT_OLD_KEYS)
+
+    def nbr(self):
+        return self.export(LT_NBR)
+
+    def hang(self):
+        return self.export(LT_HANG)
+
+    def mapping(self):
+        return self.export(LT_MAP_SRC), self.export(LT_MAP_KIND)

@@ -1,0 +1,130 @@
+// lt_flag.hip -- geometric refinement criterion (Section 5.2).
+//
+// Built with -ffp-contract=off: the physical point coordinates and squared
+// distances are evaluated as separately rounded FP64 operations in a fixed
+// order, so the integer decision r^2 < R_in^2 / r^2 > R_out^2 is reproducible
+// bit for bit on any IEEE FP64 implementation that follows the same order.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+
+#include "tree.hpp"
+
+#pragma clang fp contract(off)
+
+namespace lt {
+namespace {
+
+struct FlagArgs {
+  KeyGeom g;
+  int p, nvort, dist_axes, periodic_dist;
+  double lo[3], len, dx, rin2, rout2;
+  double nodes[LT_MAX_DEGREE + 1];
+  double c[LT_MAX_VORTICES][3];
+};
+
+// One thread per element.  The coordinate of point index k on axis a depends
+// only on (a, k), so the (p+1) values per axis are computed once.
+template <int N1>
+__global__ __launch_bounds__(256) void k_flag(FlagArgs A, const uint64_t* __restrict__ keys, int64_t n,
+                                              int8_t* __restrict__ flags) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const KeyGeom& g = A.g;
+  const uint64_t key = keys[e];
+  const int d = key_depth(g, key);
+  uint64_t x[3];
+  demorton(g, key_m(g, key), x);
+  const double s = double(uint64_t(1) << (g.dmax - d));
+  double X[3][N1];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      const double t = s * A.nodes[k];
+      const double u = double(x[a]) + t;
+      const double w = A.dx * u;
+      X[a][k] = A.lo[a] + w;
+    }
+  const int nz = g.dim == 3 ? N1 : 1;
+  int n_in = 0, n_out = 0;
+  for (int iz = 0; iz < nz; ++iz)
+#pragma unroll
+    for (int iy = 0; iy < N1; ++iy)
+#pragma unroll
+      for (int ix = 0; ix < N1; ++ix) {
+        const double P[3] = {X[0][ix], X[1][iy], X[2][iz]};
+        double best = 0.0;
+        for (int v = 0; v < A.nvort; ++v) {
+          double r2 = 0.0;
+          for (int a = 0; a < A.dist_axes; ++a) {
+            double dd = P[a] - A.c[v][a];
+            if (A.periodic_dist) {
+              const double q = dd / A.len;
+              const double f = floor(q + 0.5);
+              const double sh = A.len * f;
+              dd = dd - sh;
+            }
+            const double sq = dd * dd;
+            r2 = r2 + sq;
+          }
+          if (v == 0 || r2 < best) best = r2;
+        }
+        n_in += best < A.rin2 ? 1 : 0;
+        n_out += best > A.rout2 ? 1 : 0;
+      }
+  int f = n_in > n_out ? 1 : (n_in < n_out ? -1 : 0);
+  if (f == 1 && d >= g.dmax) f = 0;
+  if (f == -1 && d <= g.dmin) f = 0;
+  flags[e] = int8_t(f);
+}
+
+template <int N1>
+hipError_t launch(const FlagArgs& A, const uint64_t* keys, int64_t n, int8_t* flags, hipStream_t s) {
+  const unsigned blocks = unsigned((n + 255) / 256);
+  k_flag<N1><<<blocks, 256, 0, s>>>(A, keys, n, flags);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+lt_status launch_flag(const KeyGeom& g, const lt_flag_params* fp, const uint64_t* keys, int64_t n,
+                      int8_t* flags, hipStream_t stream) {
+  if (fp->nvort < 1 || fp->nvort > LT_MAX_VORTICES || !fp->centre)
+    return fail(LT_ERR_ARG, "nvort must be in 1..LT_MAX_VORTICES with centres given");
+  if (fp->p < 0 || fp->p > LT_MAX_DEGREE || !fp->nodes01)
+    return fail(LT_ERR_ARG, "p must be in 0..LT_MAX_DEGREE with nodes01 given");
+  if (fp->dist_axes < 1 || fp->dist_axes > g.dim) return fail(LT_ERR_ARG, "dist_axes out of range");
+  if (!(fp->len > 0.0)) return fail(LT_ERR_ARG, "len must be positive");
+  FlagArgs A{};
+  A.g = g;
+  A.p = fp->p;
+  A.nvort = fp->nvort;
+  A.dist_axes = fp->dist_axes;
+  A.periodic_dist = fp->periodic_dist ? 1 : 0;
+  for (int a = 0; a < 3; ++a) A.lo[a] = a < g.dim ? fp->lo[a] : 0.0;
+  A.len = fp->len;
+  A.dx = fp->len / double(uint64_t(1) << g.dmax);
+  A.rin2 = fp->r_in * fp->r_in;
+  A.rout2 = fp->r_out * fp->r_out;
+  for (int k = 0; k <= fp->p; ++k) A.nodes[k] = fp->nodes01[k];
+  for (int v = 0; v < fp->nvort; ++v)
+    for (int a = 0; a < 3; ++a) A.c[v][a] = fp->centre[3 * v + a];
+  if (n == 0) return LT_OK;
+  hipError_t e;
+  switch (fp->p + 1) {
+    case 1: e = launch<1>(A, keys, n, flags, stream); break;
+    case 2: e = launch<2>(A, keys, n, flags, stream); break;
+    case 3: e = launch<3>(A, keys, n, flags, stream); break;
+    case 4: e = launch<4>(A, keys, n, flags, stream); break;
+    case 5: e = launch<5>(A, keys, n, flags, stream); break;
+    case 6: e = launch<6>(A, keys, n, flags, stream); break;
+    case 7: e = launch<7>(A, keys, n, flags, stream); break;
+    default: e = launch<8>(A, keys, n, flags, stream); break;
+  }
+  if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("flag launch: ") + hipGetErrorString(e));
+  return LT_OK;
+}
+
+}  // namespace lt

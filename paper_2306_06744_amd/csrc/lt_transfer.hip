@@ -1,0 +1,244 @@
+// lt_transfer.hip -- FP64 solution transfer between the old and new tree
+// (Section 4.2).
+//
+// With Gauss-Legendre solution points the operators factor per axis.  On one
+// axis with nodes z_i and weights w_i:
+//   refinement (interpolation of the parent polynomial, eq. parent_soln):
+//       A_b[i][k] = l_k((z_i + 2b - 1) / 2),            child half b in {0, 1}
+//   coarsening (L2 projection M u^P = sum_b S_b u^b): the Gauss-Legendre rule
+//   integrates the degree-2p products exactly, so M = diag(w) and
+//       P_b[i][k] = (1/2) (w_k / w_i) A_b[k][i].
+// In d dimensions the child-c operators are tensor products over the axes of
+// the factor for that axis's child bit, so each is applied as d passes of a
+// (p+1) x (p+1) product along one axis (sum factorisation) instead of one
+// dense (p+1)^d x (p+1)^d product: the same result up to rounding order, with
+// (p+1)^(d-1) times fewer flops, which keeps the transfer bound by HBM bytes
+// rather than by FP64 throughput.
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "tree.hpp"
+
+namespace lt {
+namespace {
+
+// Gauss-Legendre nodes (Newton on P_n from Chebyshev starting points),
+// weights, then the factors A_0, A_1, P_0, P_1 (row-major, n x n each).
+__global__ void k_build_ops(int n, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double z[LT_MAX_DEGREE + 1], w[LT_MAX_DEGREE + 1];
+  for (int i = 0; i < n; ++i) {
+    double x = -cos(M_PI * (2.0 * i + 1.0) / (2.0 * n));
+    double dp = 1.0;
+    for (int it = 0; it < 60; ++it) {
+      // P_n(x) and P_n'(x) by the Bonnet recurrence
+      double pm = 1.0, pc = x;
+      if (n == 1) {
+        pc = x;
+        pm = 1.0;
+      }
+      for (int k = 2; k <= n; ++k) {
+        const double pn = ((2 * k - 1) * x * pc - (k - 1) * pm) / k;
+        pm = pc;
+        pc = pn;
+      }
+      dp = n * (pm - x * pc) / (1.0 - x * x);
+      const double dx = pc / dp;
+      x -= dx;
+      if (fabs(dx) <= 1e-16 * fmax(1.0, fabs(x))) break;
+    }
+    double pm = 1.0, pc = x;
+    for (int k = 2; k <= n; ++k) {
+      const double pn = ((2 * k - 1) * x * pc - (k - 1) * pm) / k;
+      pm = pc;
+      pc = pn;
+    }
+    dp = n * (pm - x * pc) / (1.0 - x * x);
+    z[i] = x;
+    w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+  double* A0 = out;
+  double* A1 = out + n * n;
+  double* P0 = out + 2 * n * n;
+  double* P1 = out + 3 * n * n;
+  for (int b = 0; b < 2; ++b) {
+    double* A = b ? A1 : A0;
+    for (int i = 0; i < n; ++i) {
+      const double xi = (z[i] + 2.0 * b - 1.0) * 0.5;
+      for (int k = 0; k < n; ++k) {
+        double l = 1.0;
+        for (int m = 0; m < n; ++m)
+          if (m != k) l *= (xi - z[m]) / (z[k] - z[m]);
+        A[i * n + k] = l;
+      }
+    }
+  }
+  for (int b = 0; b < 2; ++b) {
+    const double* A = b ? A1 : A0;
+    double* P = b ? P1 : P0;
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < n; ++k) P[i * n + k] = 0.5 * (w[k] / w[i]) * A[k * n + i];
+  }
+}
+
+// out = (Mz (x) My (x) Mx) in, for a tensor array with x fastest.
+template <int DIM, int N>
+__device__ inline void tensor_apply(const double* __restrict__ Mx, const double* __restrict__ My,
+                                    const double* __restrict__ Mz, const double* in, double* out) {
+  constexpr int NZ = DIM == 3 ? N : 1;
+  constexpr int NP = N * N * NZ;
+  double t[NP];
+#pragma unroll
+  for (int r = 0; r < N * NZ; ++r)
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) acc += Mx[i * N + k] * in[r * N + k];
+      t[r * N + i] = acc;
+    }
+  if constexpr (DIM == 2) {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int x = 0; x < N; ++x) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) acc += My[i * N + k] * t[k * N + x];
+        out[i * N + x] = acc;
+      }
+  } else {
+    double t2[NP];
+#pragma unroll
+    for (int z = 0; z < N; ++z)
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int x = 0; x < N; ++x) {
+          double acc = 0.0;
+#pragma unroll
+          for (int k = 0; k < N; ++k) acc += My[i * N + k] * t[(z * N + k) * N + x];
+          t2[(z * N + i) * N + x] = acc;
+        }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int y = 0; y < N; ++y)
+#pragma unroll
+        for (int x = 0; x < N; ++x) {
+          double acc = 0.0;
+#pragma unroll
+          for (int k = 0; k < N; ++k) acc += Mz[i * N + k] * t2[(k * N + y) * N + x];
+          out[(i * N + y) * N + x] = acc;
+        }
+  }
+}
+
+// One thread per (new element, variable).  Consecutive threads handle
+// consecutive new elements, so every load and store of one point index is a
+// contiguous run across the wave in the element-fastest layout.
+template <int DIM, int N>
+__global__ __launch_bounds__(256) void k_transfer(const double* __restrict__ ops,
+                                                  const int32_t* __restrict__ src,
+                                                  const int8_t* __restrict__ kind, int64_t n,
+                                                  const double* __restrict__ uo, int64_t ldo,
+                                                  double* __restrict__ un, int64_t ldn) {
+  constexpr int NP = DIM == 3 ? N * N * N : N * N;
+  constexpr int NC = 1 << DIM;
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int v = blockIdx.y;
+  const double* U = uo + int64_t(v) * NP * ldo;
+  double* O = un + int64_t(v) * NP * ldn;
+  const int kd = kind[j];
+  const int64_t s = src[j];
+  if (kd == 0) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) O[i * ldn + j] = U[i * ldo + s];
+    return;
+  }
+  const double* A = ops;
+  const double* P = ops + 2 * N * N;
+  double in[NP], out[NP];
+  if (kd > 0) {
+    const int c = kd - 1;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) in[i] = U[i * ldo + s];
+    tensor_apply<DIM, N>(A + (c & 1) * N * N, A + ((c >> 1) & 1) * N * N, A + ((c >> 2) & 1) * N * N,
+                         in, out);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) O[i * ldn + j] = out[i];
+    return;
+  }
+  double acc[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) acc[i] = 0.0;
+  for (int c = 0; c < NC; ++c) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) in[i] = U[i * ldo + s + c];
+    tensor_apply<DIM, N>(P + (c & 1) * N * N, P + ((c >> 1) & 1) * N * N, P + ((c >> 2) & 1) * N * N,
+                         in, out);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) acc[i] += out[i];
+  }
+#pragma unroll
+  for (int i = 0; i < NP; ++i) O[i * ldn + j] = acc[i];
+}
+
+template <int DIM, int N>
+hipError_t launch(const double* ops, const int32_t* src, const int8_t* kind, int64_t n, int nvar,
+                  const double* uo, int64_t ldo, double* un, int64_t ldn, hipStream_t s) {
+  dim3 grid(unsigned((n + 255) / 256), unsigned(nvar));
+  k_transfer<DIM, N><<<grid, 256, 0, s>>>(ops, src, kind, n, uo, ldo, un, ldn);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+lt_status build_transfer_ops(int p, double** ops, hipStream_t stream) {
+  if (*ops) return LT_OK;
+  const int n = p + 1;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, sizeof(double) * 4 * n * n);
+  if (e != hipSuccess) return fail(LT_ERR_OOM, "transfer operator allocation failed");
+  k_build_ops<<<1, 64, 0, stream>>>(n, static_cast<double*>(q));
+  e = hipGetLastError();
+  if (e != hipSuccess) {
+    (void)hipFree(q);
+    return fail(LT_ERR_HIP, std::string("operator build: ") + hipGetErrorString(e));
+  }
+  *ops = static_cast<double*>(q);
+  return LT_OK;
+}
+
+lt_status launch_transfer(int dim, int p, const double* ops, const int32_t* src, const int8_t* kind,
+                          int64_t n, int nvar, const double* u_old, int64_t ld_old, double* u_new,
+                          int64_t ld_new, hipStream_t s) {
+  if (n == 0) return LT_OK;
+  if (nvar > 65535) return fail(LT_ERR_ARG, "nvar too large");
+  hipError_t e = hipErrorInvalidValue;
+  if (dim == 3) {
+    switch (p) {
+      case 1: e = launch<3, 2>(ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s); break;
+      case 2: e = launch<3, 3>(ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s); break;
+      case 3: e = launch<3, 4>(ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s); break;
+      default: return fail(LT_ERR_ARG, "3D transfer supports p = 1..3");
+    }
+  } else {
+    switch (p) {
+      case 1: e = launch<2, 2>(ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s); break;
+      case 2: e = launch<2, 3>(ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s); break;
+      case 3: e = launch<2, 4>(ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s); break;
+      case 4: e = launch<2, 5>(ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s); break;
+      case 5: e = launch<2, 6>(ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s); break;
+      case 6: e = launch<2, 7>(ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s); break;
+      case 7: e = launch<2, 8>(ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s); break;
+      default: return fail(LT_ERR_ARG, "2D transfer supports p = 1..7");
+    }
+  }
+  if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("transfer launch: ") + hipGetErrorString(e));
+  return LT_OK;
+}
+
+}  // namespace lt

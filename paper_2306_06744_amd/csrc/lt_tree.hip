@@ -1,0 +1,784 @@
+// lt_tree.hip -- tree kernels and the C ABI of the adaptation cycle.
+//
+// Keys stay sorted throughout: every kernel that changes the leaf set counts
+// its outputs per input leaf, takes an exclusive scan of the counts with
+// decoupled look-back, and writes its outputs in input order, which is
+// Morton order.  No sort, no linearisation pass and no atomics decide any
+// output position, so results are deterministic.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "tree.hpp"
+
+using lt::KeyGeom;
+
+namespace lt {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+lt_status fail(lt_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+}  // namespace lt
+
+#define LT_HIP(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return lt::fail(LT_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define LT_TRY(expr)                \
+  do {                              \
+    lt_status s_ = (expr);          \
+    if (s_ != LT_OK) return s_;     \
+  } while (0)
+
+namespace lt {
+namespace {
+
+constexpr int kItems = 4;  // items per thread in scan-emit kernels
+constexpr int64_t kTile = int64_t(kBlock) * kItems;
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------------ kernels
+__global__ void k_clear_scan(uint64_t* status, int64_t ntiles, DevCtr* ctr, int clear_err) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < ntiles) status[i] = 0;
+  if (i == 0) {
+    ctr->ticket = 0;
+    ctr->total = 0;
+    ctr->nmarked = 0;
+    if (clear_err) ctr->err = 0;
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Uniform tree: leaf i of depth D has Morton index i * span(D).
+__global__ void k_uniform(KeyGeom g, int depth, int64_t n, uint64_t* keys) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) keys[i] = make_key(g, uint64_t(i) << (g.dim * (g.dmax - depth)), depth);
+}
+
+// Complete linear tree check: each key valid, and the Morton range of leaf i
+// ends exactly where leaf i+1 starts (so keys ascend, tile, and do not overlap).
+__global__ void k_validate(KeyGeom g, const uint64_t* __restrict__ keys, int64_t n, unsigned* err) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t k = keys[i];
+  const int d = key_depth(g, k);
+  const uint64_t m = key_m(g, k);
+  bool ok = d <= g.dmax;
+  if (ok) {
+    if ((m & (span(g, d) - 1)) != 0) ok = false;                      // padding bits
+    if (g.dim * g.dmax < 64 && (m >> (g.dim * g.dmax)) != 0) ok = false;  // outside the domain
+  }
+  if (ok) {
+    const uint64_t end = m + span(g, d);
+    if (i + 1 < n) {
+      const uint64_t kn = keys[i + 1];
+      if (key_depth(g, kn) > g.dmax || key_m(g, kn) != end) ok = false;
+    } else {
+      const uint64_t full = g.dim * g.dmax >= 64 ? 0 : (uint64_t(1) << (g.dim * g.dmax));
+      if (end != full) ok = false;
+    }
+    if (i == 0 && m != 0) ok = false;
+  }
+  if (!ok) atomicOr(err, ERR_INVALID_TREE);
+}
+
+// Adaptation (Section 4.1).  Per leaf: +1 -> 2^dim children, first leaf of a
+// complete all -1 family -> parent, other members of such a family -> nothing,
+// everything else -> itself.
+__global__ __launch_bounds__(kBlock) void k_adapt(KeyGeom g, const uint64_t* __restrict__ in,
+                                                  const int8_t* __restrict__ flags, int64_t n,
+                                                  uint64_t* __restrict__ out, int64_t cap,
+                                                  ScanState st) {
+  const int64_t tile = take_ticket(st);
+  const int64_t base = tile * kTile + int64_t(threadIdx.x) * kItems;
+  const int nc = g.nchild();
+  uint64_t key[kItems];
+  int act[kItems];  // 0 keep, 1 refine, 2 emit parent, 3 drop
+  int64_t local = 0;
+  unsigned err = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t i = base + k;
+    act[k] = 3;
+    key[k] = 0;
+    if (i >= n) continue;
+    const uint64_t kk = in[i];
+    key[k] = kk;
+    int f = flags[i];
+    if (f < -1 || f > 1) {
+      err |= ERR_BAD_FLAG;
+      f = 0;
+    }
+    const int d = key_depth(g, kk);
+    if (f == 1 && d >= g.dmax) f = 0;
+    if (f == -1 && d <= g.dmin) f = 0;
+    int a = 0;
+    if (f == 1) {
+      a = 1;
+    } else if (f == -1) {
+      // The family is complete iff the 2^dim keys around i are exactly the
+      // siblings (consecutive, same depth, raw IDs incrementing by one).
+      const uint64_t m = key_m(g, kk);
+      const int c = child_index(g, m, d);
+      const int64_t h = i - c;
+      const uint64_t step = uint64_t(1) << (g.dim * (g.dmax - d) + g.mb);
+      const uint64_t k0 = kk - uint64_t(c) * step;
+      bool all = h >= 0 && h + nc <= n;
+      for (int j = 0; all && j < nc; ++j)
+        if (in[h + j] != k0 + uint64_t(j) * step || flags[h + j] != -1) all = false;
+      if (all) a = c == 0 ? 2 : 3;
+    }
+    act[k] = a;
+    local += a == 1 ? nc : (a == 3 ? 0 : 1);
+  }
+  int64_t blk;
+  const int64_t thr = block_exclusive(local, &blk);
+  int64_t o = tile_prefix(st, tile, blk) + thr;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int a = act[k];
+    if (a == 3) continue;
+    const int cnt = a == 1 ? nc : 1;
+    if (o + cnt > cap) {
+      err |= ERR_CAPACITY;
+      o += cnt;
+      continue;
+    }
+    const uint64_t kk = key[k];
+    const int d = key_depth(g, kk);
+    if (a == 0) {
+      out[o] = kk;
+    } else if (a == 2) {
+      out[o] = make_key(g, key_m(g, kk), d - 1);
+    } else {
+      const uint64_t m = key_m(g, kk);
+      for (int c = 0; c < nc; ++c) out[o + c] = child_key(g, m, d, c);
+    }
+    o += cnt;
+  }
+  if (err) atomicOr(st.err, err);
+}
+
+// 2:1 balance, marking pass.  For a leaf L of depth D with parent P, the
+// leaves that touch L and are two or more levels coarser are exactly the
+// leaves strictly containing one of the 2^dim - 1 depth-(D-1) neighbours of P
+// around the vertex L shares with P (the searching keys of Section 3.2),
+// restricted to face / face+edge neighbours for the weaker balance kinds.
+// Such a leaf gets bit 0 (split); L gets bit 1 (check again next pass).
+// Only leaves with bit 2 (new or re-checked) are examined unless check_all.
+__global__ __launch_bounds__(kBlock) void k_balance_mark(KeyGeom g, const uint64_t* __restrict__ keys,
+                                                         int64_t n, uint32_t* mark, int check_all,
+                                                         DevCtr* ctr) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (!check_all && !(mark[i] & 4u)) return;
+  const uint64_t key = keys[i];
+  const int d = key_depth(g, key);
+  if (d < 2) return;
+  const int limit = g.balance == 0 ? 1 : (g.balance == 1 ? 2 : 3);
+  uint64_t x[3];
+  demorton(g, key_m(g, key), x);
+  const uint64_t S = uint64_t(1) << (g.dmax - d + 1);  // parent size
+  uint64_t pa[3];
+  int b[3];
+  for (int a = 0; a < 3; ++a) {
+    pa[a] = x[a] & ~(S - 1);
+    b[a] = int((x[a] >> (g.dmax - d)) & 1);
+  }
+  unsigned long long fresh_marks = 0;
+  bool self = false;
+  const int nc = g.nchild();
+  for (int sub = 1; sub < nc; ++sub) {
+    if (__popc(unsigned(sub)) > limit) continue;
+    uint64_t q[3] = {pa[0], pa[1], pa[2]};
+    bool ok = true;
+    for (int a = 0; a < g.dim; ++a)
+      if ((sub >> a) & 1) ok = ok && shift_coord(g, a, pa[a], b[a] ? int64_t(S) : -int64_t(S), &q[a]);
+    if (!ok) continue;
+    const int64_t j = last_le(keys, n, point_key(g, morton(g, q)));
+    if (j >= 0 && key_depth(g, keys[j]) < d - 1) {
+      const uint32_t was = atomicOr(&mark[j], 1u);
+      if (!(was & 1u)) fresh_marks++;
+      self = true;
+    }
+  }
+  if (self) atomicOr(&mark[i], 2u);
+  if (fresh_marks) atomicAdd(&ctr->nmarked, fresh_marks);
+}
+
+// 2:1 balance, refinement pass: split bit-0 leaves one level, in order.  The
+// new mark array holds bit 2 for leaves to examine next pass: the children of
+// split leaves and the leaves that found a violation.
+__global__ __launch_bounds__(kBlock) void k_balance_refine(KeyGeom g, const uint64_t* __restrict__ in,
+                                                           const uint32_t* __restrict__ mark, int64_t n,
+                                                           uint64_t* __restrict__ out,
+                                                           uint32_t* __restrict__ mark_out, int64_t cap,
+                                                           ScanState st) {
+  const int64_t tile = take_ticket(st);
+  const int64_t base = tile * kTile + int64_t(threadIdx.x) * kItems;
+  const int nc = g.nchild();
+  uint32_t w[kItems];
+  int64_t local = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t i = base + k;
+    w[k] = 0;
+    if (i >= n) continue;
+    w[k] = mark[i] | 8u;  // bit 3: valid item
+    local += (w[k] & 1u) ? nc : 1;
+  }
+  int64_t blk;
+  const int64_t thr = block_exclusive(local, &blk);
+  int64_t o = tile_prefix(st, tile, blk) + thr;
+  unsigned err = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    if (!(w[k] & 8u)) continue;
+    const int64_t i = base + k;
+    const uint64_t kk = in[i];
+    const int cnt = (w[k] & 1u) ? nc : 1;
+    if (o + cnt > cap) {
+      err |= ERR_CAPACITY;
+      o += cnt;
+      continue;
+    }
+    if (w[k] & 1u) {
+      const uint64_t m = key_m(g, kk);
+      const int d = key_depth(g, kk);
+      for (int c = 0; c < nc; ++c) {
+        out[o + c] = child_key(g, m, d, c);
+        mark_out[o + c] = 4u;
+      }
+    } else {
+      out[o] = kk;
+      mark_out[o] = (w[k] & 2u) ? 4u : 0u;
+    }
+    o += cnt;
+  }
+  if (err) atomicOr(st.err, err);
+}
+
+// Face connectivity (Section 3.3).  For face f = 2a + side the same-size box
+// across the face is located by the leaf that holds its anchor: depth <= D
+// means that leaf holds the whole box; deeper means the box is subdivided and
+// e is the coarse side of a hanging face, whose 2^(dim-1) fine leaves are the
+// box's children on the side facing e.
+__global__ __launch_bounds__(kBlock) void k_connect(KeyGeom g, const uint64_t* __restrict__ keys,
+                                                    int64_t n, int32_t* __restrict__ nbr,
+                                                    int32_t* __restrict__ hang, int64_t cap_rows,
+                                                    ScanState st) {
+  const int64_t tile = take_ticket(st);
+  const int64_t base = tile * kTile + int64_t(threadIdx.x) * kItems;
+  const int nf = 2 * g.dim;
+  const int nh = 1 << (g.dim - 1);
+  const int width = 2 + nh;
+  unsigned hm[kItems];
+  int64_t local = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t e = base + k;
+    hm[k] = 0;
+    if (e >= n) continue;
+    const uint64_t key = keys[e];
+    const int d = key_depth(g, key);
+    uint64_t x[3];
+    demorton(g, key_m(g, key), x);
+    const int64_t s = int64_t(1) << (g.dmax - d);
+    for (int f = 0; f < nf; ++f) {
+      const int a = f >> 1;
+      uint64_t q[3] = {x[0], x[1], x[2]};
+      int32_t v;
+      if (!shift_coord(g, a, x[a], (f & 1) ? s : -s, &q[a])) {
+        v = -2;
+      } else {
+        const int64_t j = last_le(keys, n, point_key(g, morton(g, q)));
+        if (j < 0) {
+          v = -2;  // unreachable for a complete tree (keys[0] has anchor 0)
+        } else if (key_depth(g, keys[j]) <= d) {
+          v = int32_t(j);
+        } else {
+          v = -1;
+          hm[k] |= 1u << f;
+        }
+      }
+      nbr[e * nf + f] = v;
+    }
+    local += __popc(hm[k]);
+  }
+  int64_t blk;
+  const int64_t thr = block_exclusive(local, &blk);
+  int64_t o = tile_prefix(st, tile, blk) + thr;
+  unsigned err = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    if (!hm[k]) continue;
+    const int64_t e = base + k;
+    const uint64_t key = keys[e];
+    const int d = key_depth(g, key);
+    uint64_t x[3];
+    demorton(g, key_m(g, key), x);
+    const int64_t s = int64_t(1) << (g.dmax - d);
+    for (int f = 0; f < nf; ++f) {
+      if (!((hm[k] >> f) & 1u)) continue;
+      if (o >= cap_rows) {  // table too small: the host grows it and runs again
+        o++;
+        continue;
+      }
+      const int a = f >> 1, side = f & 1;
+      uint64_t q[3] = {x[0], x[1], x[2]};
+      shift_coord(g, a, x[a], side ? s : -s, &q[a]);
+      const uint64_t mq = morton(g, q);
+      int32_t* row = hang + o * width;
+      row[0] = int32_t(e);
+      row[1] = f;
+      for (int slot = 0; slot < nh; ++slot) {
+        int c = (1 - side) << a, j = 0;
+        for (int t = 0; t < g.dim; ++t) {
+          if (t == a) continue;
+          c |= ((slot >> j) & 1) << t;
+          ++j;
+        }
+        const uint64_t ck = child_key(g, mq, d, c);
+        const int64_t idx = lower_bound(keys, n, ck);
+        if (idx >= n || keys[idx] != ck) {
+          err |= ERR_UNBALANCED;
+          row[2 + slot] = -1;
+        } else {
+          row[2 + slot] = int32_t(idx);
+        }
+      }
+      o++;
+    }
+  }
+  if (err) atomicOr(st.err, err);
+}
+
+// Old -> new mapping (Section 4.2): lower bound of each new key in the old tree.
+__global__ __launch_bounds__(kBlock) void k_map(KeyGeom g, const uint64_t* __restrict__ old_keys,
+                                                int64_t n_old, const uint64_t* __restrict__ keys,
+                                                int64_t n, int32_t* __restrict__ src,
+                                                int8_t* __restrict__ kind, unsigned* err) {
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const uint64_t key = keys[j];
+  const int64_t B = lower_bound(old_keys, n_old, key);
+  const int d = key_depth(g, key);
+  if (B < n_old && old_keys[B] == key) {
+    src[j] = int32_t(B);
+    kind[j] = 0;
+    return;
+  }
+  if (B > 0 && d > 0) {
+    const uint64_t pk = old_keys[B - 1];
+    const uint64_t m = key_m(g, key);
+    const uint64_t pm = key_m(g, pk);
+    if (key_depth(g, pk) == d - 1 && (m & ~(span(g, d - 1) - 1)) == pm) {
+      src[j] = int32_t(B - 1);
+      kind[j] = int8_t(1 + child_index(g, m, d));
+      return;
+    }
+  }
+  const int nc = g.nchild();
+  if (B + nc <= n_old && old_keys[B] == key + 1 && d < g.dmax) {
+    const uint64_t last = child_key(g, key_m(g, key), d, nc - 1);
+    if (old_keys[B + nc - 1] == last) {
+      src[j] = int32_t(B);
+      kind[j] = -1;
+      return;
+    }
+  }
+  src[j] = -1;
+  kind[j] = 0;
+  atomicOr(err, ERR_MAP);
+}
+
+// ------------------------------------------------------------------ host helpers
+template <class T>
+lt_status grow(T** p, int64_t* cap, int64_t need) {
+  if (need <= *cap && *p) return LT_OK;
+  int64_t ncap = std::max<int64_t>(need + need / 4, 1024);
+  if (*p) {
+    hipError_t e = hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("hipFree: ") + hipGetErrorString(e));
+  }
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, size_t(ncap) * sizeof(T));
+  if (e != hipSuccess || !q)
+    return fail(LT_ERR_OOM, "device allocation of " + std::to_string(size_t(ncap) * sizeof(T)) +
+                                " bytes failed");
+  *p = static_cast<T*>(q);
+  *cap = ncap;
+  return LT_OK;
+}
+
+lt_status prep_scan(lt_tree t, int64_t n_items, hipStream_t stream, int clear_err, ScanState* st) {
+  const int64_t ntiles = std::max<int64_t>(1, ceil_div(n_items, kTile));
+  LT_TRY(grow(&t->status, &t->status_cap, ntiles));
+  k_clear_scan<<<unsigned(ceil_div(ntiles, 256)), 256, 0, stream>>>(t->status, ntiles, t->dctr,
+                                                                      clear_err);
+  LT_HIP(hipGetLastError());
+  st->status = t->status;
+  st->ticket = &t->dctr->ticket;
+  st->err = &t->dctr->err;
+  st->total = &t->dctr->total;
+  st->ntiles = ntiles;
+  return LT_OK;
+}
+
+lt_status read_ctr(lt_tree t, hipStream_t stream) {
+  LT_HIP(hipMemcpyAsync(t->hctr, t->dctr, sizeof(DevCtr), hipMemcpyDeviceToHost, stream));
+  LT_HIP(hipStreamSynchronize(stream));
+  return LT_OK;
+}
+
+lt_status clear_err(lt_tree t, hipStream_t stream) {
+  k_clear_scan<<<1, 64, 0, stream>>>(t->status, 0, t->dctr, 1);
+  LT_HIP(hipGetLastError());
+  return LT_OK;
+}
+
+lt_status check_geom(const lt_geom* g) {
+  if (!g) return fail(LT_ERR_ARG, "geom is NULL");
+  if (g->dim != 2 && g->dim != 3) return fail(LT_ERR_ARG, "dim must be 2 or 3");
+  if (g->d_max < 1 || g->d_min < 0 || g->d_min > g->d_max)
+    return fail(LT_ERR_DEPTH, "need 0 <= d_min <= d_max and d_max >= 1");
+  int mb = 0;
+  while ((g->d_max >> mb) != 0) ++mb;
+  if (g->dim * g->d_max + mb > 64) return fail(LT_ERR_DEPTH, "dim*d_max + bitlength(d_max) > 64");
+  if (g->dim == 3 && g->d_max > 21) return fail(LT_ERR_DEPTH, "3D d_max above 21");
+  if (g->balance < 0 || g->balance > 2) return fail(LT_ERR_ARG, "balance must be 0, 1 or 2");
+  return LT_OK;
+}
+
+lt_status new_tree(const lt_geom* geom, lt_tree* out) {
+  LT_TRY(check_geom(geom));
+  if (!out) return fail(LT_ERR_ARG, "out is NULL");
+  lt_tree t = new lt_tree_s;
+  int mb = 0;
+  while ((geom->d_max >> mb) != 0) ++mb;
+  t->g.dim = geom->dim;
+  t->g.dmax = geom->d_max;
+  t->g.dmin = geom->d_min;
+  t->g.mb = mb;
+  t->g.periodic = geom->periodic_mask & ((1u << geom->dim) - 1);
+  t->g.balance = geom->balance;
+  hipError_t e = hipGetDevice(&t->device);
+  if (e == hipSuccess) e = hipMalloc(&t->dctr, sizeof(DevCtr));
+  if (e == hipSuccess) e = hipHostMalloc(&t->hctr, sizeof(DevCtr), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    lt_destroy(t);
+    return fail(LT_ERR_HIP, std::string("tree setup: ") + hipGetErrorString(e));
+  }
+  std::memset(t->hctr, 0, sizeof(DevCtr));
+  e = hipMemset(t->dctr, 0, sizeof(DevCtr));
+  if (e != hipSuccess) {
+    lt_destroy(t);
+    return fail(LT_ERR_HIP, std::string("tree setup: ") + hipGetErrorString(e));
+  }
+  *out = t;
+  return LT_OK;
+}
+
+void invalidate(lt_tree t) {
+  t->conn_valid = false;
+  t->n_hang = -1;
+  t->map_valid = false;
+}
+
+lt_status do_map(lt_tree t, hipStream_t stream) {
+  if (!t->has_old) return fail(LT_ERR_STATE, "lt_map needs a prior lt_adapt");
+  LT_TRY(grow(&t->map_src, &t->map_cap, t->n_cur));
+  LT_TRY(grow(&t->map_kind, &t->kind_cap, t->n_cur));
+  LT_TRY(clear_err(t, stream));
+  if (t->n_cur > 0)
+    k_map<<<unsigned(ceil_div(t->n_cur, kBlock)), kBlock, 0, stream>>>(
+        t->g, t->kbuf[t->old], t->n_old, t->kbuf[t->cur], t->n_cur, t->map_src, t->map_kind,
+        &t->dctr->err);
+  LT_HIP(hipGetLastError());
+  LT_TRY(read_ctr(t, stream));
+  if (t->hctr->err & ERR_MAP)
+    return fail(LT_ERR_UNBALANCED,
+                "a new leaf is neither an old leaf, a child of one, nor a parent of 2^dim old leaves");
+  if (t->hctr->err) return fail(LT_ERR_INTERNAL, "device check failed in lt_map");
+  t->map_valid = true;
+  return LT_OK;
+}
+
+}  // namespace
+}  // namespace lt
+
+using namespace lt;
+
+// =================================================================== C ABI
+extern "C" {
+
+const char* lt_last_error(void) { return lt::g_err.c_str(); }
+
+lt_status lt_build_uniform(const lt_geom* geom, int depth, void* stream, lt_tree* out) {
+  lt_tree t = nullptr;
+  LT_TRY(new_tree(geom, &t));
+  if (depth < 0 || depth > geom->d_max) {
+    lt_destroy(t);
+    return fail(LT_ERR_DEPTH, "uniform depth outside [0, d_max]");
+  }
+  if (geom->dim * depth > 40) {
+    lt_destroy(t);
+    return fail(LT_ERR_ARG, "uniform tree too large");
+  }
+  const int64_t n = int64_t(1) << (geom->dim * depth);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  lt_status st = grow(&t->kbuf[t->cur], &t->kcap[t->cur], n);
+  if (st != LT_OK) {
+    lt_destroy(t);
+    return st;
+  }
+  k_uniform<<<unsigned(ceil_div(n, kBlock)), kBlock, 0, s>>>(t->g, depth, n, t->kbuf[t->cur]);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    lt_destroy(t);
+    return fail(LT_ERR_HIP, std::string("uniform build: ") + hipGetErrorString(e));
+  }
+  t->n_cur = n;
+  *out = t;
+  return LT_OK;
+}
+
+lt_status lt_build(const lt_geom* geom, const uint64_t* keys, int64_t n, void* stream, lt_tree* out) {
+  if (!keys || n < 1) return fail(LT_ERR_ARG, "keys must be a non-empty device array");
+  lt_tree t = nullptr;
+  LT_TRY(new_tree(geom, &t));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  lt_status st = grow(&t->kbuf[t->cur], &t->kcap[t->cur], n);
+  if (st != LT_OK) {
+    lt_destroy(t);
+    return st;
+  }
+  hipError_t e = hipMemcpyAsync(t->kbuf[t->cur], keys, size_t(n) * 8, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) {
+    k_validate<<<unsigned(ceil_div(n, kBlock)), kBlock, 0, s>>>(t->g, t->kbuf[t->cur], n,
+                                                                 &t->dctr->err);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(t->hctr, t->dctr, sizeof(DevCtr), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    lt_destroy(t);
+    return fail(LT_ERR_HIP, std::string("build: ") + hipGetErrorString(e));
+  }
+  if (t->hctr->err) {
+    lt_destroy(t);
+    return fail(LT_ERR_INVALID_TREE, "keys are not the ascending IDs of a complete linear tree");
+  }
+  t->n_cur = n;
+  *out = t;
+  return LT_OK;
+}
+
+lt_status lt_flag(lt_tree t, const lt_flag_params* fp, int8_t* flags, void* stream) {
+  if (!t || !fp || !flags) return fail(LT_ERR_ARG, "NULL argument");
+  return launch_flag(t->g, fp, t->kbuf[t->cur], t->n_cur, flags, static_cast<hipStream_t>(stream));
+}
+
+lt_status lt_adapt(lt_tree t, const int8_t* flags, void* stream) {
+  if (!t || !flags) return fail(LT_ERR_ARG, "NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n = t->n_cur;
+  LT_TRY(grow(&t->kbuf[t->tmp], &t->kcap[t->tmp], n * t->g.nchild()));
+  ScanState st;
+  LT_TRY(prep_scan(t, n, s, 1, &st));
+  k_adapt<<<unsigned(st.ntiles), kBlock, 0, s>>>(t->g, t->kbuf[t->cur], flags, n, t->kbuf[t->tmp],
+                                                   t->kcap[t->tmp], st);
+  LT_HIP(hipGetLastError());
+  LT_TRY(read_ctr(t, s));
+  if (t->hctr->err & ERR_BAD_FLAG) return fail(LT_ERR_ARG, "flags must be -1, 0 or 1");
+  if (t->hctr->err) return fail(LT_ERR_INTERNAL, "device check failed in lt_adapt");
+  // old <- cur, cur <- tmp, tmp <- previous old buffer
+  const int prev_old = t->old;
+  t->old = t->cur;
+  t->cur = t->tmp;
+  t->tmp = prev_old;
+  t->n_old = n;
+  t->n_cur = t->hctr->total;
+  t->has_old = true;
+  invalidate(t);
+  return LT_OK;
+}
+
+lt_status lt_balance(lt_tree t, void* stream) {
+  if (!t) return fail(LT_ERR_ARG, "NULL tree");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int mi = 0;
+  LT_TRY(grow(&t->mbuf[mi], &t->mcap[mi], t->n_cur));
+  k_fill_u32<<<unsigned(ceil_div(t->n_cur, 256)), 256, 0, s>>>(t->mbuf[mi], t->n_cur, 0u);
+  LT_HIP(hipGetLastError());
+  const int max_pass = 4 * t->g.dmax + 16;
+  for (int pass = 0;; ++pass) {
+    if (pass > max_pass) return fail(LT_ERR_INTERNAL, "balance did not converge");
+    LT_TRY(clear_err(t, s));
+    k_balance_mark<<<unsigned(ceil_div(t->n_cur, kBlock)), kBlock, 0, s>>>(
+        t->g, t->kbuf[t->cur], t->n_cur, t->mbuf[mi], pass == 0 ? 1 : 0, t->dctr);
+    LT_HIP(hipGetLastError());
+    LT_TRY(read_ctr(t, s));
+    const int64_t marked = int64_t(t->hctr->nmarked);
+    if (marked == 0) break;
+    const int64_t n_new = t->n_cur + marked * (t->g.nchild() - 1);
+    LT_TRY(grow(&t->kbuf[t->tmp], &t->kcap[t->tmp], n_new));
+    LT_TRY(grow(&t->mbuf[1 - mi], &t->mcap[1 - mi], n_new));
+    ScanState st;
+    LT_TRY(prep_scan(t, t->n_cur, s, 1, &st));
+    const int64_t cap = std::min(t->kcap[t->tmp], t->mcap[1 - mi]);
+    k_balance_refine<<<unsigned(st.ntiles), kBlock, 0, s>>>(t->g, t->kbuf[t->cur], t->mbuf[mi],
+                                                             t->n_cur, t->kbuf[t->tmp],
+                                                             t->mbuf[1 - mi], cap, st);
+    LT_HIP(hipGetLastError());
+    LT_TRY(read_ctr(t, s));
+    if (t->hctr->err) return fail(LT_ERR_INTERNAL, "device check failed in lt_balance");
+    if (t->hctr->total != n_new) return fail(LT_ERR_INTERNAL, "balance refinement size mismatch");
+    std::swap(t->cur, t->tmp);
+    t->n_cur = n_new;
+    mi = 1 - mi;
+    invalidate(t);
+  }
+  return LT_OK;
+}
+
+lt_status lt_connect(lt_tree t, void* stream) {
+  if (!t) return fail(LT_ERR_ARG, "NULL tree");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n = t->n_cur;
+  const int nf = 2 * t->g.dim;
+  const int width = 2 + (1 << (t->g.dim - 1));
+  LT_TRY(grow(&t->nbr, &t->nbr_cap, n * nf));
+  if (t->hang_cap < 1024) LT_TRY(grow(&t->hang, &t->hang_cap, int64_t(1024) * width));
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    const int64_t cap_rows = t->hang_cap / width;
+    ScanState st;
+    LT_TRY(prep_scan(t, n, s, 1, &st));
+    k_connect<<<unsigned(st.ntiles), kBlock, 0, s>>>(t->g, t->kbuf[t->cur], n, t->nbr, t->hang,
+                                                      cap_rows, st);
+    LT_HIP(hipGetLastError());
+    LT_TRY(read_ctr(t, s));
+    if (t->hctr->err & ERR_UNBALANCED)
+      return fail(LT_ERR_UNBALANCED, "tree is not 2:1 balanced across a face");
+    if (t->hctr->err) return fail(LT_ERR_INTERNAL, "device check failed in lt_connect");
+    const int64_t rows = t->hctr->total;
+    if (rows <= cap_rows) {
+      t->n_hang = rows;
+      t->conn_valid = true;
+      return LT_OK;
+    }
+    // The hanging-face table overflowed: grow it to the exact size and rerun.
+    LT_TRY(grow(&t->hang, &t->hang_cap, rows * width));
+  }
+  return fail(LT_ERR_INTERNAL, "hanging-face table overflowed twice");
+}
+
+lt_status lt_map(lt_tree t, void* stream) {
+  if (!t) return fail(LT_ERR_ARG, "NULL tree");
+  return do_map(t, static_cast<hipStream_t>(stream));
+}
+
+lt_status lt_transfer(lt_tree t, int p, int nvar, const double* u_old, int64_t ld_old, double* u_new,
+                      int64_t ld_new, int precision, void* stream) {
+  if (!t || !u_old || !u_new) return fail(LT_ERR_ARG, "NULL argument");
+  if (precision != 0) return fail(LT_ERR_ARG, "only precision 0 (FP64) is available");
+  if (nvar < 1) return fail(LT_ERR_ARG, "nvar must be positive");
+  if (p < 1 || p > (t->g.dim == 3 ? 3 : LT_MAX_DEGREE))
+    return fail(LT_ERR_ARG, "unsupported polynomial degree for this dimension");
+  if (!t->has_old) return fail(LT_ERR_STATE, "lt_transfer needs a prior lt_adapt");
+  if (ld_old < t->n_old || ld_new < t->n_cur) return fail(LT_ERR_ARG, "leading dimension too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!t->map_valid) LT_TRY(lt_map(t, stream));
+  LT_TRY(build_transfer_ops(p, &t->ops[p], s));
+  return launch_transfer(t->g.dim, p, t->ops[p], t->map_src, t->map_kind, t->n_cur, nvar, u_old,
+                         ld_old, u_new, ld_new, s);
+}
+
+lt_status lt_size(lt_tree t, int64_t* n_cur, int64_t* n_old, int64_t* n_hang) {
+  if (!t) return fail(LT_ERR_ARG, "NULL tree");
+  if (n_cur) *n_cur = t->n_cur;
+  if (n_old) *n_old = t->has_old ? t->n_old : -1;
+  if (n_hang) *n_hang = t->conn_valid ? t->n_hang : -1;
+  return LT_OK;
+}
+
+static lt_status field_info(lt_tree t, lt_field what, const void** ptr, int64_t* count, size_t* elem) {
+  const int nf = 2 * t->g.dim, width = 2 + (1 << (t->g.dim - 1));
+  switch (what) {
+    case LT_KEYS: *ptr = t->kbuf[t->cur]; *count = t->n_cur; *elem = 8; break;
+    case LT_OLD_KEYS:
+      *ptr = t->has_old ? t->kbuf[t->old] : nullptr; *count = t->has_old ? t->n_old : 0; *elem = 8; break;
+    case LT_NBR:
+      *ptr = t->conn_valid ? t->nbr : nullptr; *count = t->conn_valid ? t->n_cur * nf : 0; *elem = 4; break;
+    case LT_HANG:
+      *ptr = t->conn_valid ? t->hang : nullptr; *count = t->conn_valid ? t->n_hang * width : 0; *elem = 4; break;
+    case LT_MAP_SRC:
+      *ptr = t->map_valid ? t->map_src : nullptr; *count = t->map_valid ? t->n_cur : 0; *elem = 4; break;
+    case LT_MAP_KIND:
+      *ptr = t->map_valid ? t->map_kind : nullptr; *count = t->map_valid ? t->n_cur : 0; *elem = 1; break;
+    default: return fail(LT_ERR_ARG, "unknown field");
+  }
+  return LT_OK;
+}
+
+lt_status lt_view(lt_tree t, lt_field what, const void** ptr, int64_t* count) {
+  if (!t || !ptr || !count) return fail(LT_ERR_ARG, "NULL argument");
+  size_t elem;
+  return field_info(t, what, ptr, count, &elem);
+}
+
+lt_status lt_export(lt_tree t, lt_field what, void* dst, int64_t capacity, void* stream) {
+  if (!t) return fail(LT_ERR_ARG, "NULL tree");
+  const void* p;
+  int64_t count;
+  size_t elem;
+  LT_TRY(field_info(t, what, &p, &count, &elem));
+  if (!p && count > 0) return fail(LT_ERR_STATE, "field not computed");
+  if (capacity < count) return fail(LT_ERR_ARG, "destination too small");
+  if (count > 0 && !dst) return fail(LT_ERR_ARG, "NULL destination");
+  if (count > 0)
+    LT_HIP(hipMemcpyAsync(dst, p, size_t(count) * elem, hipMemcpyDeviceToDevice,
+                          static_cast<hipStream_t>(stream)));
+  return LT_OK;
+}
+
+void lt_destroy(lt_tree t) {
+  if (!t) return;
+  (void)hipDeviceSynchronize();
+  for (auto& b : t->kbuf) if (b) (void)hipFree(b);
+  for (auto& b : t->mbuf) if (b) (void)hipFree(b);
+  if (t->nbr) (void)hipFree(t->nbr);
+  if (t->hang) (void)hipFree(t->hang);
+  if (t->map_src) (void)hipFree(t->map_src);
+  if (t->map_kind) (void)hipFree(t->map_kind);
+  if (t->status) (void)hipFree(t->status);
+  if (t->dctr) (void)hipFree(t->dctr);
+  if (t->hctr) (void)hipHostFree(t->hctr);
+  for (auto& o : t->ops) if (o) (void)hipFree(o);
+  delete t;
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// scan.hpp -- single-pass exclusive scan with decoupled look-back, for
+// kernels that count outputs per input and then write them in input order.
+//
+// Each workgroup takes a tile ticket from a device counter (so every earlier
+// tile is already resident), reduces its counts, publishes the aggregate,
+// walks back over earlier tiles' published words until it meets an inclusive
+// prefix, then publishes its own inclusive prefix.  A tile status word packs
+// a 2-bit state (0 not ready, 1 aggregate, 2 inclusive prefix) over a 62-bit
+// value.  The status words and the ticket counter must be zero at launch.
+// The wait on a predecessor is bounded; on overrun the kernel records
+// ERR_LOOKBACK and carries on with a wrong offset so that every wave exits.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lt {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+
+enum : unsigned {
+  ERR_LOOKBACK = 1u << 0,
+  ERR_BAD_FLAG = 1u << 1,
+  ERR_UNBALANCED = 1u << 2,
+  ERR_INVALID_TREE = 1u << 3,
+  ERR_MAP = 1u << 4,
+  ERR_CAPACITY = 1u << 5,
+};
+
+struct ScanState {
+  uint64_t* status;       // one word per tile
+  unsigned long long* ticket;
+  unsigned* err;
+  int64_t* total;         // written by the last tile: sum of all counts
+  int64_t ntiles;
+};
+
+constexpr uint64_t kStAgg = uint64_t(1) << 62;
+constexpr uint64_t kStInc = uint64_t(2) << 62;
+constexpr uint64_t kStVal = (uint64_t(1) << 62) - 1;
+constexpr long kSpinLimit = 1L << 22;
+
+__device__ inline uint64_t ld_acquire(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_release(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Inclusive scan of v across the 64 lanes of a wave.
+__device__ inline int64_t wave_inclusive(int64_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(v, o, 64);
+    if (lane >= o) v += y;
+  }
+  return v;
+}
+
+// Exclusive scan of v over the workgroup; *total receives the sum.
+__device__ inline int64_t block_exclusive(int64_t v, int64_t* total) {
+  __shared__ int64_t wsum[kWaves];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t inc = wave_inclusive(v);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  int64_t before = 0, all = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) {
+    if (i < w) before += wsum[i];
+    all += wsum[i];
+  }
+  __syncthreads();
+  *total = all;
+  return before + inc - v;
+}
+
+// Called by every thread of the tile; returns the tile's exclusive prefix.
+__device__ inline int64_t tile_prefix(const ScanState& st, int64_t tile, int64_t aggregate) {
+  __shared__ int64_t s_prefix;
+  if (threadIdx.x == 0) {
+    int64_t excl = 0;
+    if (tile == 0) {
+      st_release(&st.status[0], kStInc | uint64_t(aggregate));
+    } else {
+      st_release(&st.status[tile], kStAgg | uint64_t(aggregate));
+      int64_t t = tile - 1;
+      long spins = 0;
+      while (t >= 0) {
+        const uint64_t s = ld_acquire(&st.status[t]);
+        const uint64_t state = s & ~kStVal;
+        if (state == 0) {
+          if (++spins > kSpinLimit) {
+            atomicOr(st.err, ERR_LOOKBACK);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += int64_t(s & kStVal);
+        if (state == kStInc) break;
+        --t;
+      }
+      st_release(&st.status[tile], kStInc | uint64_t(excl + aggregate));
+    }
+    if (tile == st.ntiles - 1) *st.total = excl + aggregate;
+    s_prefix = excl;
+  }
+  __syncthreads();
+  return s_prefix;
+}
+
+__device__ inline int64_t take_ticket(const ScanState& st) {
+  __shared__ int64_t s_tile;
+  if (threadIdx.x == 0) s_tile = int64_t(atomicAdd(st.ticket, 1ull));
+  __syncthreads();
+  return s_tile;
+}
+
+}  // namespace lt

@@ -1,0 +1,70 @@
+// tree.hpp -- internal state of one linear tree and the host helpers shared
+// by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/lt.h"
+#include "keys.hpp"
+#include "scan.hpp"
+
+namespace lt {
+
+// Small device-side counters, read back in one copy.
+struct DevCtr {
+  unsigned err;
+  unsigned pad;
+  int64_t total;
+  unsigned long long nmarked;
+  unsigned long long ticket;
+};
+
+void set_error(const std::string& msg);
+lt_status fail(lt_status s, const std::string& msg);
+
+// Flag kernel launcher (its own translation unit: no FP contraction there).
+lt_status launch_flag(const KeyGeom& g, const lt_flag_params* fp, const uint64_t* keys, int64_t n,
+                      int8_t* flags, hipStream_t stream);
+
+// Builds (once per degree) the FP64 1D transfer operators into ops.
+lt_status build_transfer_ops(int p, double** ops, hipStream_t stream);
+
+lt_status launch_transfer(int dim, int p, const double* ops, const int32_t* src,
+                          const int8_t* kind, int64_t n, int nvar, const double* u_old,
+                          int64_t ld_old, double* u_new, int64_t ld_new, hipStream_t stream);
+
+}  // namespace lt
+
+struct lt_tree_s {
+  lt::KeyGeom g{};
+  int device = 0;
+  uint64_t* kbuf[3] = {nullptr, nullptr, nullptr};
+  int64_t kcap[3] = {0, 0, 0};
+  int cur = 0, tmp = 1, old = 2;  // roles of the three key buffers
+  int64_t n_cur = 0, n_old = -1, n_hang = -1;
+  bool has_old = false;
+
+  uint32_t* mbuf[2] = {nullptr, nullptr};  // balance marks, ping-pong
+  int64_t mcap[2] = {0, 0};
+
+  int32_t* nbr = nullptr;
+  int64_t nbr_cap = 0;
+  int32_t* hang = nullptr;
+  int64_t hang_cap = 0;  // rows
+  bool conn_valid = false;
+
+  int32_t* map_src = nullptr;
+  int8_t* map_kind = nullptr;
+  int64_t map_cap = 0;
+  int64_t kind_cap = 0;
+  bool map_valid = false;
+
+  uint64_t* status = nullptr;  // look-back tile words
+  int64_t status_cap = 0;
+  lt::DevCtr* dctr = nullptr;
+  lt::DevCtr* hctr = nullptr;  // pinned mirror
+
+  double* ops[LT_MAX_DEGREE + 1] = {};
+};

@@ -1,0 +1,112 @@
+"""GPU parity at full workload sizes.
+
+The two synthetic workloads (2D [-5,5]^2 levels 3-6 p2 4 variables, one
+cycle; 3D [-5,5]^3 levels 4-7 p3 5 variables, ten cycles advected +0.1 in x,
+up to ~1.7M leaves) run through the C ABI in the launch configuration the
+benchmark times.  Flags, keys, connectivity and the mapping are checked bit
+for bit against SHA-256 hashes of the oracle's arrays (tests/golden, written
+by make_workload_golden.py from the oracle only).  The transfer is checked on
+a seeded sample of new elements against the oracle's dense operators applied
+to the same synthetic input; the small 2D workload is checked in full."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_06744_amd import synth
+
+from gpu_util import rel_l2
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def golden(name):
+    with open(os.path.join(HERE, "golden", f"workload_{name}.json")) as fh:
+        return json.load(fh)["cycles"]
+
+
+def sampled_transfer_check(dim, p, u_old, u_new, src, kind, rng, nsample=3000):
+    I, P = oracle.operators(dim, p)
+    n = u_new.shape[2]
+    js = rng.choice(n, size=min(nsample, n), replace=False)
+    # always include some of each kind
+    for k in (0, -1):
+        idx = np.flatnonzero(kind == k)
+        if len(idx):
+            js = np.concatenate([js, rng.choice(idx, size=min(200, len(idx)), replace=False)])
+    idx = np.flatnonzero(kind > 0)
+    if len(idx):
+        js = np.concatenate([js, rng.choice(idx, size=min(200, len(idx)), replace=False)])
+    exp = np.zeros((u_old.shape[0], u_old.shape[1], len(js)))
+    for t, j in enumerate(js):
+        s, k = int(src[j]), int(kind[j])
+        if k == 0:
+            exp[:, :, t] = u_old[:, :, s]
+        elif k > 0:
+            exp[:, :, t] = u_old[:, :, s] @ I[k - 1].T
+        else:
+            exp[:, :, t] = sum(u_old[:, :, s + c] @ P[c].T for c in range(1 << dim))
+    return rel_l2(u_new[:, :, js], exp)
+
+
+@pytest.mark.parametrize("name,maker,seed", [("2d_small", synth.workload_2d_small, 1000),
+                                             ("3d_extruded", synth.workload_3d_extruded, 2000)])
+def test_workload_cycles_bit_exact(name, maker, seed):
+    import torch
+    import paper_2306_06744_amd as lt
+    w = maker(seed)
+    gold = golden(name)
+    assert len(gold) == w.cycles
+    t = lt.Tree.uniform(w.dim, w.d_min, w.d_max)
+    nodes = synth.gl_nodes01(w.p)
+    npts = (w.p + 1) ** w.dim
+    rng = np.random.default_rng(seed)
+    for cyc, rec in enumerate(gold):
+        print(f"{name} cycle {cyc}: {rec['n_old']} -> {rec['n_new']}", flush=True)
+        assert t.size() == rec["n_old"]
+        f = t.flag(w.centres_at(cyc), w.r_in, w.r_out, nodes, w.lo, w.length,
+                   dist_axes=w.dist_axes, periodic_dist=w.periodic_dist)
+        assert sha(f.cpu().numpy()) == rec["flags"], "flags"
+        t.adapt(f)
+        assert t.size() == rec["n_adapt"]
+        t.balance()
+        assert t.size() == rec["n_new"]
+        assert sha(t.keys().cpu().numpy().view(np.uint64)) == rec["keys"], "keys"
+        t.connect()
+        assert t.sizes()[2] == rec["n_hang"]
+        assert sha(t.nbr().cpu().numpy()) == rec["nbr"], "nbr"
+        assert sha(t.hang().cpu().numpy()) == rec["hang"], "hang"
+        t.map()
+        src, kind = (a.cpu().numpy() for a in t.mapping())
+        assert sha(src) == rec["map_src"] and sha(kind) == rec["map_kind"], "mapping"
+        u_old = torch.from_numpy(synth.random_solution(seed + cyc, w.nvar, npts, rec["n_old"])).cuda()
+        u_new = t.transfer(w.p, u_old).cpu().numpy()
+        err = sampled_transfer_check(w.dim, w.p, u_old.cpu().numpy(), u_new, src, kind, rng)
+        assert err <= 1e-13, f"transfer sample rel L2 {err:.3e}"
+        del u_old, u_new
+        torch.cuda.empty_cache()
+
+
+def test_small_workload_transfer_full():
+    """Whole-array transfer parity on the 2D workload (every element)."""
+    import torch
+    import paper_2306_06744_amd as lt
+    w = synth.workload_2d_small(1000)
+    t = lt.Tree.uniform(w.dim, w.d_min, w.d_max)
+    o = oracle.Tree(w.dim, w.d_min, w.d_max)
+    nodes = synth.gl_nodes01(w.p)
+    args = (w.centres_at(0), w.r_in, w.r_out, nodes, w.lo, w.length, w.dist_axes, w.periodic_dist)
+    t.adapt(t.flag(*args))
+    o.adapt(o.flag(*args))
+    t.balance()
+    o.balance()
+    u = synth.random_solution(1000, w.nvar, (w.p + 1) ** w.dim, o.old_size())
+    assert rel_l2(t.transfer(w.p, torch.from_numpy(u).cuda()).cpu().numpy(), o.transfer(w.p, u)) <= 1e-13
