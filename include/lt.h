@@ -150,9 +150,16 @@ lt_status lt_map(lt_tree t, void* stream);
  * i = i_x + (p+1) (i_y + (p+1) i_z) over Gauss-Legendre points, variable v
  * slowest, element e fastest.  u_old: device FP64, ld_old >= n_old; u_new:
  * device FP64, ld_new >= n_cur, written for every current leaf.  Computes the
- * mapping first if lt_map has not run since the last change.  precision 0 is
- * FP64 throughout; other values return LT_ERR_ARG.  p in 1..3 for dim 3,
- * 1..LT_MAX_DEGREE for dim 2.  Asynchronous (unless the mapping was stale). */
+ * mapping first if lt_map has not run since the last change.
+ *   precision 0: FP64 throughout (sum-factorised); p in 1..3 for dim 3,
+ *                1..LT_MAX_DEGREE for dim 2.
+ *   precision 1: dense operator products on BF16 matrix cores with every
+ *                operand split in three BF16 terms and FP32 accumulation,
+ *                then an FP64 shift that makes each new element's cell mean
+ *                (Gauss-Legendre quadrature mean) equal the FP64 one; copies
+ *                are exact.  Needs 64 points per element (dim 3 with p = 3,
+ *                or dim 2 with p = 7).  Relative L2 error ~1e-7 against FP64.
+ * Other values return LT_ERR_ARG.  Asynchronous (unless the mapping was stale). */
 lt_status lt_transfer(lt_tree t, int p, int nvar, const double* u_old, int64_t ld_old,
                       double* u_new, int64_t ld_new, int precision, void* stream);
 

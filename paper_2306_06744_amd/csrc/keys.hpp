@@ -141,6 +141,50 @@ __device__ inline int64_t last_le(const uint64_t* __restrict__ keys, int64_t n, 
   return lo - 1;
 }
 
+// Index of the last key <= probe (or -1), searching outward from a hint index
+// h in [0, n): gallop away from h in doubling steps until the probe is
+// bracketed, then bisect.  Neighbour keys usually lie close to the querying
+// leaf in Morton order, so the probes stay in a few cache lines.
+__device__ inline int64_t last_le_near(const uint64_t* __restrict__ keys, int64_t n, uint64_t probe,
+                                       int64_t h) {
+  int64_t lo, hi;  // invariant: keys[lo] <= probe (lo == -1: none), keys[hi] > probe (hi == n: none)
+  if (keys[h] <= probe) {
+    lo = h;
+    int64_t step = 1;
+    for (;;) {
+      hi = lo + step;
+      if (hi >= n) {
+        hi = n;
+        break;
+      }
+      if (keys[hi] > probe) break;
+      lo = hi;
+      step <<= 1;
+    }
+  } else {
+    hi = h;
+    int64_t step = 1;
+    for (;;) {
+      lo = hi - step;
+      if (lo < 0) {
+        lo = -1;
+        break;
+      }
+      if (keys[lo] <= probe) break;
+      hi = lo;
+      step <<= 1;
+    }
+  }
+  while (hi - lo > 1) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (keys[mid] <= probe)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
 // First index with keys[i] >= probe (n if none).
 __device__ inline int64_t lower_bound(const uint64_t* __restrict__ keys, int64_t n, uint64_t probe) {
   int64_t lo = 0, hi = n;

@@ -49,31 +49,64 @@ __global__ __launch_bounds__(256) void k_flag(FlagArgs A, const uint64_t* __rest
     }
   const int nz = g.dim == 3 ? N1 : 1;
   int n_in = 0, n_out = 0;
-  for (int iz = 0; iz < nz; ++iz)
+  if (A.nvort == 1) {
+    // Squared distance per axis and point index; r^2 = (dx^2 + dy^2) + dz^2,
+    // the same sums in the same order as point by point (a missing axis adds
+    // an exact 0).
+    double D2[3][N1];
 #pragma unroll
-    for (int iy = 0; iy < N1; ++iy)
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int ix = 0; ix < N1; ++ix) {
-        const double P[3] = {X[0][ix], X[1][iy], X[2][iz]};
-        double best = 0.0;
-        for (int v = 0; v < A.nvort; ++v) {
-          double r2 = 0.0;
-          for (int a = 0; a < A.dist_axes; ++a) {
-            double dd = P[a] - A.c[v][a];
-            if (A.periodic_dist) {
-              const double q = dd / A.len;
-              const double f = floor(q + 0.5);
-              const double sh = A.len * f;
-              dd = dd - sh;
-            }
-            const double sq = dd * dd;
-            r2 = r2 + sq;
-          }
-          if (v == 0 || r2 < best) best = r2;
+      for (int k = 0; k < N1; ++k) {
+        double dd = X[a][k] - A.c[0][a];
+        if (A.periodic_dist) {
+          const double q = dd / A.len;
+          const double f = floor(q + 0.5);
+          const double sh = A.len * f;
+          dd = dd - sh;
         }
-        n_in += best < A.rin2 ? 1 : 0;
-        n_out += best > A.rout2 ? 1 : 0;
+        D2[a][k] = a < A.dist_axes ? dd * dd : 0.0;
       }
+    for (int iz = 0; iz < nz; ++iz)
+#pragma unroll
+      for (int iy = 0; iy < N1; ++iy)
+#pragma unroll
+        for (int ix = 0; ix < N1; ++ix) {
+          const double xy = D2[0][ix] + D2[1][iy];
+          const double r2 = xy + D2[2][iz];
+          n_in += r2 < A.rin2 ? 1 : 0;
+          n_out += r2 > A.rout2 ? 1 : 0;
+        }
+  } else {
+    for (int iz = 0; iz < nz; ++iz)
+#pragma unroll
+      for (int iy = 0; iy < N1; ++iy)
+#pragma unroll
+        for (int ix = 0; ix < N1; ++ix) {
+          const double P[3] = {X[0][ix], X[1][iy], X[2][iz]};
+          double best = 0.0;
+          for (int v = 0; v < A.nvort; ++v) {
+            double r2 = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              if (a < A.dist_axes) {
+                double dd = P[a] - A.c[v][a];
+                if (A.periodic_dist) {
+                  const double q = dd / A.len;
+                  const double f = floor(q + 0.5);
+                  const double sh = A.len * f;
+                  dd = dd - sh;
+                }
+                const double sq = dd * dd;
+                r2 = r2 + sq;
+              }
+            }
+            if (v == 0 || r2 < best) best = r2;
+          }
+          n_in += best < A.rin2 ? 1 : 0;
+          n_out += best > A.rout2 ? 1 : 0;
+        }
+  }
   int f = n_in > n_out ? 1 : (n_in < n_out ? -1 : 0);
   if (f == 1 && d >= g.dmax) f = 0;
   if (f == -1 && d <= g.dmin) f = 0;

@@ -24,7 +24,8 @@ namespace lt {
 namespace {
 
 // Gauss-Legendre nodes (Newton on P_n from Chebyshev starting points),
-// weights, then the factors A_0, A_1, P_0, P_1 (row-major, n x n each).
+// weights, then the factors A_0, A_1, P_0, P_1 (row-major, n x n each),
+// followed by the n weights.
 __global__ void k_build_ops(int n, double* out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double z[LT_MAX_DEGREE + 1], w[LT_MAX_DEGREE + 1];
@@ -80,6 +81,7 @@ __global__ void k_build_ops(int n, double* out) {
     for (int i = 0; i < n; ++i)
       for (int k = 0; k < n; ++k) P[i * n + k] = 0.5 * (w[k] / w[i]) * A[k * n + i];
   }
+  for (int i = 0; i < n; ++i) out[4 * n * n + i] = w[i];
 }
 
 // out = (Mz (x) My (x) Mx) in, for a tensor array with x fastest.
@@ -135,9 +137,9 @@ __device__ inline void tensor_apply(const double* __restrict__ Mx, const double*
   }
 }
 
-// One thread per (new element, variable).  Consecutive threads handle
-// consecutive new elements, so every load and store of one point index is a
-// contiguous run across the wave in the element-fastest layout.
+// One thread per (new element, variable) -- used for 2D.  Consecutive
+// threads handle consecutive new elements, so every load and store of one
+// point index is a contiguous run across the wave in the element-fastest layout.
 template <int DIM, int N>
 __global__ __launch_bounds__(256) void k_transfer(const double* __restrict__ ops,
                                                   const int32_t* __restrict__ src,
@@ -186,12 +188,158 @@ __global__ __launch_bounds__(256) void k_transfer(const double* __restrict__ ops
   for (int i = 0; i < NP; ++i) O[i * ldn + j] = acc[i];
 }
 
+// 3D, copy pass.  A block of 4 waves covers 64 consecutive new elements of one
+// variable; lane = element, and the waves stride over the point rows, so each
+// lane keeps NP/4 independent loads in flight.  Only copy elements do work.
+template <int NP>
+__global__ __launch_bounds__(256) void k_copy3(const int32_t* __restrict__ src,
+                                               const int8_t* __restrict__ kind, int64_t n,
+                                               const double* __restrict__ uo, int64_t ldo,
+                                               double* __restrict__ un, int64_t ldn) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t j = int64_t(blockIdx.x) * 64 + lane;
+  if (j >= n || kind[j] != 0) return;
+  const int v = blockIdx.y;
+  const double* U = uo + int64_t(v) * NP * ldo + src[j];
+  double* O = un + int64_t(v) * NP * ldn + j;
+  constexpr int R = (NP + 3) / 4;
+  double t[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = w + 4 * r;
+    if (i < NP) t[r] = U[int64_t(i) * ldo];
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = w + 4 * r;
+    if (i < NP) O[int64_t(i) * ldn] = t[r];
+  }
+}
+
+// x then y pass inside one z-slab (N x N values, x fastest).
+template <int N>
+__device__ inline void xy_pass(const double* Mx, const double* My, const double* in, double* out) {
+  double t[N * N];
+#pragma unroll
+  for (int y = 0; y < N; ++y)
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double a = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) a += Mx[i * N + k] * in[y * N + k];
+      t[y * N + i] = a;
+    }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int x = 0; x < N; ++x) {
+      double a = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) a += My[i * N + k] * t[k * N + x];
+      out[i * N + x] = a;
+    }
+}
+
+// 3D, interpolation / projection pass.  A block of N waves covers 64
+// consecutive new elements of one variable; lane = element and wave w owns
+// z-slab w (N*N points) of the input and of the output.  The x and y passes
+// act within a slab and stay in registers; the z pass mixes slabs through
+// LDS.  A fused element needs two z rounds (children with z bit 0, then 1),
+// a refined one a single round.  Blocks of copies only leave at once (the
+// same 64 elements are seen by every wave, so the exit is block-uniform).
+template <int N>
+__global__ __launch_bounds__(64 * N) void k_interp3(const double* __restrict__ ops,
+                                                    const int32_t* __restrict__ src,
+                                                    const int8_t* __restrict__ kind, int64_t n,
+                                                    const double* __restrict__ uo, int64_t ldo,
+                                                    double* __restrict__ un, int64_t ldn) {
+  constexpr int NN = N * N;
+  constexpr int NP = NN * N;
+  __shared__ double T[N][NN][64];
+  __shared__ double M[4][NN];  // A_0, A_1, P_0, P_1
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t j = int64_t(blockIdx.x) * 64 + lane;
+  const int kd = j < n ? int(kind[j]) : 0;
+  if (__ballot(kd != 0) == 0) return;
+  const int rounds = __ballot(kd < 0) != 0 ? 2 : 1;
+  for (int i = threadIdx.x; i < 4 * NN; i += blockDim.x) M[i / NN][i % NN] = ops[i];
+  const int v = blockIdx.y;
+  const double* U = uo + int64_t(v) * NP * ldo + int64_t(w) * NN * ldo;
+  const int64_t s = kd != 0 ? int64_t(src[j]) : 0;
+  const int c = kd > 0 ? kd - 1 : 0;
+  double acc[NN];
+#pragma unroll
+  for (int r = 0; r < NN; ++r) acc[r] = 0.0;
+  __syncthreads();
+  for (int rz = 0; rz < rounds; ++rz) {
+    double sl[NN];
+#pragma unroll
+    for (int r = 0; r < NN; ++r) sl[r] = 0.0;
+    if (kd > 0) {
+      if (rz == 0) {
+        double in[NN];
+#pragma unroll
+        for (int r = 0; r < NN; ++r) in[r] = U[int64_t(r) * ldo + s];
+        xy_pass<N>(M[c & 1], M[(c >> 1) & 1], in, sl);
+      }
+    } else if (kd < 0) {
+#pragma unroll 1
+      for (int cc = 0; cc < 4; ++cc) {
+        const int child = cc + 4 * rz;
+        double in[NN], t[NN];
+#pragma unroll
+        for (int r = 0; r < NN; ++r) in[r] = U[int64_t(r) * ldo + s + child];
+        xy_pass<N>(M[2 + (cc & 1)], M[2 + (cc >> 1)], in, t);
+#pragma unroll
+        for (int r = 0; r < NN; ++r) sl[r] += t[r];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NN; ++r) T[w][r][lane] = sl[r];
+    __syncthreads();
+    if (kd > 0 && rz == 0) {
+      const double* Mz = M[(c >> 2) & 1] + w * N;
+#pragma unroll
+      for (int r = 0; r < NN; ++r) {
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) a += Mz[k] * T[k][r][lane];
+        acc[r] = a;
+      }
+    } else if (kd < 0) {
+      const double* Mz = M[2 + rz] + w * N;
+#pragma unroll
+      for (int r = 0; r < NN; ++r) {
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) a += Mz[k] * T[k][r][lane];
+        acc[r] += a;
+      }
+    }
+    __syncthreads();
+  }
+  if (kd != 0) {
+    double* O = un + int64_t(v) * NP * ldn + int64_t(w) * NN * ldn + j;
+#pragma unroll
+    for (int r = 0; r < NN; ++r) O[int64_t(r) * ldn] = acc[r];
+  }
+}
+
 template <int DIM, int N>
 hipError_t launch(const double* ops, const int32_t* src, const int8_t* kind, int64_t n, int nvar,
                   const double* uo, int64_t ldo, double* un, int64_t ldn, hipStream_t s) {
-  dim3 grid(unsigned((n + 255) / 256), unsigned(nvar));
-  k_transfer<DIM, N><<<grid, 256, 0, s>>>(ops, src, kind, n, uo, ldo, un, ldn);
-  return hipGetLastError();
+  if constexpr (DIM == 3) {
+    dim3 grid(unsigned((n + 63) / 64), unsigned(nvar));
+    k_copy3<N * N * N><<<grid, 256, 0, s>>>(src, kind, n, uo, ldo, un, ldn);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_interp3<N><<<grid, 64 * N, 0, s>>>(ops, src, kind, n, uo, ldo, un, ldn);
+    return hipGetLastError();
+  } else {
+    dim3 grid(unsigned((n + 255) / 256), unsigned(nvar));
+    k_transfer<DIM, N><<<grid, 256, 0, s>>>(ops, src, kind, n, uo, ldo, un, ldn);
+    return hipGetLastError();
+  }
 }
 
 }  // namespace
@@ -200,7 +348,7 @@ lt_status build_transfer_ops(int p, double** ops, hipStream_t stream) {
   if (*ops) return LT_OK;
   const int n = p + 1;
   void* q = nullptr;
-  hipError_t e = hipMalloc(&q, sizeof(double) * 4 * n * n);
+  hipError_t e = hipMalloc(&q, sizeof(double) * (4 * n * n + n));
   if (e != hipSuccess) return fail(LT_ERR_OOM, "transfer operator allocation failed");
   k_build_ops<<<1, 64, 0, stream>>>(n, static_cast<double*>(q));
   e = hipGetLastError();

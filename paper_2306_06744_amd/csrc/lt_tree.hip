@@ -47,8 +47,6 @@ lt_status fail(lt_status s, const std::string& msg) {
 namespace lt {
 namespace {
 
-constexpr int kItems = 4;  // items per thread in scan-emit kernels
-constexpr int64_t kTile = int64_t(kBlock) * kItems;
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -215,7 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_balance_mark(KeyGeom g, const uint64
     for (int a = 0; a < g.dim; ++a)
       if ((sub >> a) & 1) ok = ok && shift_coord(g, a, pa[a], b[a] ? int64_t(S) : -int64_t(S), &q[a]);
     if (!ok) continue;
-    const int64_t j = last_le(keys, n, point_key(g, morton(g, q)));
+    const int64_t j = last_le_near(keys, n, point_key(g, morton(g, q)), i);
     if (j >= 0 && key_depth(g, keys[j]) < d - 1) {
       const uint32_t was = atomicOr(&mark[j], 1u);
       if (!(was & 1u)) fresh_marks++;
@@ -311,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void k_connect(KeyGeom g, const uint64_t* _
       if (!shift_coord(g, a, x[a], (f & 1) ? s : -s, &q[a])) {
         v = -2;
       } else {
-        const int64_t j = last_le(keys, n, point_key(g, morton(g, q)));
+        const int64_t j = last_le_near(keys, n, point_key(g, morton(g, q)), e);
         if (j < 0) {
           v = -2;  // unreachable for a complete tree (keys[0] has anchor 0)
         } else if (key_depth(g, keys[j]) <= d) {
@@ -359,8 +357,8 @@ __global__ __launch_bounds__(kBlock) void k_connect(KeyGeom g, const uint64_t* _
           ++j;
         }
         const uint64_t ck = child_key(g, mq, d, c);
-        const int64_t idx = lower_bound(keys, n, ck);
-        if (idx >= n || keys[idx] != ck) {
+        const int64_t idx = last_le_near(keys, n, ck, e);
+        if (idx < 0 || keys[idx] != ck) {
           err |= ERR_UNBALANCED;
           row[2 + slot] = -1;
         } else {
@@ -413,25 +411,7 @@ __global__ __launch_bounds__(kBlock) void k_map(KeyGeom g, const uint64_t* __res
 }
 
 // ------------------------------------------------------------------ host helpers
-template <class T>
-lt_status grow(T** p, int64_t* cap, int64_t need) {
-  if (need <= *cap && *p) return LT_OK;
-  int64_t ncap = std::max<int64_t>(need + need / 4, 1024);
-  if (*p) {
-    hipError_t e = hipFree(*p);
-    *p = nullptr;
-    *cap = 0;
-    if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("hipFree: ") + hipGetErrorString(e));
-  }
-  void* q = nullptr;
-  hipError_t e = hipMalloc(&q, size_t(ncap) * sizeof(T));
-  if (e != hipSuccess || !q)
-    return fail(LT_ERR_OOM, "device allocation of " + std::to_string(size_t(ncap) * sizeof(T)) +
-                                " bytes failed");
-  *p = static_cast<T*>(q);
-  *cap = ncap;
-  return LT_OK;
-}
+}  // namespace
 
 lt_status prep_scan(lt_tree t, int64_t n_items, hipStream_t stream, int clear_err, ScanState* st) {
   const int64_t ntiles = std::max<int64_t>(1, ceil_div(n_items, kTile));
@@ -458,6 +438,8 @@ lt_status clear_err(lt_tree t, hipStream_t stream) {
   LT_HIP(hipGetLastError());
   return LT_OK;
 }
+
+namespace {
 
 lt_status check_geom(const lt_geom* g) {
   if (!g) return fail(LT_ERR_ARG, "geom is NULL");
@@ -630,33 +612,38 @@ lt_status lt_adapt(lt_tree t, const int8_t* flags, void* stream) {
 lt_status lt_balance(lt_tree t, void* stream) {
   if (!t) return fail(LT_ERR_ARG, "NULL tree");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  // One host readback per pass (the number of leaves to split).  The refine
+  // pass's own consistency checks land in the error word and are read with
+  // the next pass's count.
   int mi = 0;
   LT_TRY(grow(&t->mbuf[mi], &t->mcap[mi], t->n_cur));
   k_fill_u32<<<unsigned(ceil_div(t->n_cur, 256)), 256, 0, s>>>(t->mbuf[mi], t->n_cur, 0u);
   LT_HIP(hipGetLastError());
+  LT_TRY(clear_err(t, s));
   const int max_pass = 4 * t->g.dmax + 16;
+  int64_t expect_total = -1;
   for (int pass = 0;; ++pass) {
     if (pass > max_pass) return fail(LT_ERR_INTERNAL, "balance did not converge");
-    LT_TRY(clear_err(t, s));
     k_balance_mark<<<unsigned(ceil_div(t->n_cur, kBlock)), kBlock, 0, s>>>(
         t->g, t->kbuf[t->cur], t->n_cur, t->mbuf[mi], pass == 0 ? 1 : 0, t->dctr);
     LT_HIP(hipGetLastError());
     LT_TRY(read_ctr(t, s));
+    if (t->hctr->err) return fail(LT_ERR_INTERNAL, "device check failed in lt_balance");
+    if (expect_total >= 0 && t->hctr->total != expect_total)
+      return fail(LT_ERR_INTERNAL, "balance refinement size mismatch");
     const int64_t marked = int64_t(t->hctr->nmarked);
     if (marked == 0) break;
     const int64_t n_new = t->n_cur + marked * (t->g.nchild() - 1);
     LT_TRY(grow(&t->kbuf[t->tmp], &t->kcap[t->tmp], n_new));
     LT_TRY(grow(&t->mbuf[1 - mi], &t->mcap[1 - mi], n_new));
     ScanState st;
-    LT_TRY(prep_scan(t, t->n_cur, s, 1, &st));
+    LT_TRY(prep_scan(t, t->n_cur, s, 0, &st));  // also zeroes the mark count for the next pass
     const int64_t cap = std::min(t->kcap[t->tmp], t->mcap[1 - mi]);
     k_balance_refine<<<unsigned(st.ntiles), kBlock, 0, s>>>(t->g, t->kbuf[t->cur], t->mbuf[mi],
                                                              t->n_cur, t->kbuf[t->tmp],
                                                              t->mbuf[1 - mi], cap, st);
     LT_HIP(hipGetLastError());
-    LT_TRY(read_ctr(t, s));
-    if (t->hctr->err) return fail(LT_ERR_INTERNAL, "device check failed in lt_balance");
-    if (t->hctr->total != n_new) return fail(LT_ERR_INTERNAL, "balance refinement size mismatch");
+    expect_total = n_new;
     std::swap(t->cur, t->tmp);
     t->n_cur = n_new;
     mi = 1 - mi;
@@ -704,7 +691,7 @@ lt_status lt_map(lt_tree t, void* stream) {
 lt_status lt_transfer(lt_tree t, int p, int nvar, const double* u_old, int64_t ld_old, double* u_new,
                       int64_t ld_new, int precision, void* stream) {
   if (!t || !u_old || !u_new) return fail(LT_ERR_ARG, "NULL argument");
-  if (precision != 0) return fail(LT_ERR_ARG, "only precision 0 (FP64) is available");
+  if (precision != 0 && precision != 1) return fail(LT_ERR_ARG, "precision must be 0 or 1");
   if (nvar < 1) return fail(LT_ERR_ARG, "nvar must be positive");
   if (p < 1 || p > (t->g.dim == 3 ? 3 : LT_MAX_DEGREE))
     return fail(LT_ERR_ARG, "unsupported polynomial degree for this dimension");
@@ -712,6 +699,7 @@ lt_status lt_transfer(lt_tree t, int p, int nvar, const double* u_old, int64_t l
   if (ld_old < t->n_old || ld_new < t->n_cur) return fail(LT_ERR_ARG, "leading dimension too small");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (!t->map_valid) LT_TRY(lt_map(t, stream));
+  if (precision == 1) return launch_split_transfer(t, p, nvar, u_old, ld_old, u_new, ld_new, s);
   LT_TRY(build_transfer_ops(p, &t->ops[p], s));
   return launch_transfer(t->g.dim, p, t->ops[p], t->map_src, t->map_kind, t->n_cur, nvar, u_old,
                          ld_old, u_new, ld_new, s);
@@ -778,6 +766,10 @@ void lt_destroy(lt_tree t) {
   if (t->dctr) (void)hipFree(t->dctr);
   if (t->hctr) (void)hipHostFree(t->hctr);
   for (auto& o : t->ops) if (o) (void)hipFree(o);
+  if (t->split_frags) (void)hipFree(t->split_frags);
+  if (t->split_vec) (void)hipFree(t->split_vec);
+  if (t->split_R) (void)hipFree(t->split_R);
+  if (t->split_F) (void)hipFree(t->split_F);
   delete t;
 }
 

@@ -17,6 +17,8 @@ namespace lt {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
+constexpr int kItems = 8;                              // items per thread in scan-emit kernels
+constexpr int64_t kTile = int64_t(kBlock) * kItems;    // items per look-back tile
 
 enum : unsigned {
   ERR_LOOKBACK = 1u << 0,
@@ -38,7 +40,7 @@ struct ScanState {
 constexpr uint64_t kStAgg = uint64_t(1) << 62;
 constexpr uint64_t kStInc = uint64_t(2) << 62;
 constexpr uint64_t kStVal = (uint64_t(1) << 62) - 1;
-constexpr long kSpinLimit = 1L << 22;
+constexpr long kSpinLimit = 1L << 20;
 
 __device__ inline uint64_t ld_acquire(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -76,36 +78,59 @@ __device__ inline int64_t block_exclusive(int64_t v, int64_t* total) {
   return before + inc - v;
 }
 
+// Sum of v over the 64 lanes of a wave (result in every lane).
+__device__ inline int64_t wave_sum(int64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 // Called by every thread of the tile; returns the tile's exclusive prefix.
+// The first wave does the look-back: lane k reads the status word of tile
+// (base - k), so one round trip covers 64 predecessors.  The window is
+// resolved once every lane up to the nearest inclusive prefix is ready;
+// if all 64 hold aggregates, their sum is taken and the window moves on.
 __device__ inline int64_t tile_prefix(const ScanState& st, int64_t tile, int64_t aggregate) {
   __shared__ int64_t s_prefix;
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
     int64_t excl = 0;
     if (tile == 0) {
-      st_release(&st.status[0], kStInc | uint64_t(aggregate));
+      if (lane == 0) st_release(&st.status[0], kStInc | uint64_t(aggregate));
     } else {
-      st_release(&st.status[tile], kStAgg | uint64_t(aggregate));
-      int64_t t = tile - 1;
+      if (lane == 0) st_release(&st.status[tile], kStAgg | uint64_t(aggregate));
+      int64_t base = tile - 1;
       long spins = 0;
-      while (t >= 0) {
-        const uint64_t s = ld_acquire(&st.status[t]);
-        const uint64_t state = s & ~kStVal;
-        if (state == 0) {
-          if (++spins > kSpinLimit) {
-            atomicOr(st.err, ERR_LOOKBACK);
+      for (;;) {
+        const int64_t idx = base - lane;
+        const uint64_t w = idx >= 0 ? ld_acquire(&st.status[idx]) : (kStInc | 0);
+        const uint64_t state = w & ~kStVal;
+        const unsigned long long ready = __ballot(state != 0);
+        const unsigned long long inc = __ballot(state == kStInc);
+        if (inc) {
+          const int L = __ffsll(inc) - 1;  // nearest inclusive prefix
+          const unsigned long long need = L == 63 ? ~0ull : ((1ull << (L + 1)) - 1);
+          if ((ready & need) == need) {
+            excl += wave_sum(lane <= L ? int64_t(w & kStVal) : 0);
             break;
           }
-          __builtin_amdgcn_s_sleep(1);
+        } else if (ready == ~0ull) {
+          excl += wave_sum(int64_t(w & kStVal));
+          base -= 64;
           continue;
         }
-        excl += int64_t(s & kStVal);
-        if (state == kStInc) break;
-        --t;
+        if (++spins > kSpinLimit) {
+          if (lane == 0) atomicOr(st.err, ERR_LOOKBACK);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
       }
-      st_release(&st.status[tile], kStInc | uint64_t(excl + aggregate));
+      if (lane == 0) st_release(&st.status[tile], kStInc | uint64_t(excl + aggregate));
     }
-    if (tile == st.ntiles - 1) *st.total = excl + aggregate;
-    s_prefix = excl;
+    if (lane == 0) {
+      if (tile == st.ntiles - 1) *st.total = excl + aggregate;
+      s_prefix = excl;
+    }
   }
   __syncthreads();
   return s_prefix;

@@ -24,12 +24,58 @@ struct DevCtr {
 void set_error(const std::string& msg);
 lt_status fail(lt_status s, const std::string& msg);
 
+#define LT_TRY_STATUS(expr)         \
+  do {                              \
+    lt_status s_ = (expr);          \
+    if (s_ != LT_OK) return s_;     \
+  } while (0)
+
 // Flag kernel launcher (its own translation unit: no FP contraction there).
 lt_status launch_flag(const KeyGeom& g, const lt_flag_params* fp, const uint64_t* keys, int64_t n,
                       int8_t* flags, hipStream_t stream);
 
 // Builds (once per degree) the FP64 1D transfer operators into ops.
 lt_status build_transfer_ops(int p, double** ops, hipStream_t stream);
+
+// Grow a device buffer to hold `need` elements (contents are not kept).
+template <class T>
+inline lt_status grow(T** p, int64_t* cap, int64_t need) {
+  if (need <= *cap && *p) return LT_OK;
+  int64_t ncap = std::max<int64_t>(need + need / 4, 1024);
+  if (*p) {
+    hipError_t e = hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("hipFree: ") + hipGetErrorString(e));
+  }
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, size_t(ncap) * sizeof(T));
+  if (e != hipSuccess || !q)
+    return fail(LT_ERR_OOM, "device allocation of " + std::to_string(size_t(ncap) * sizeof(T)) +
+                                " bytes failed");
+  *p = static_cast<T*>(q);
+  *cap = ncap;
+  return LT_OK;
+}
+
+
+}  // namespace lt
+
+struct lt_tree_s;
+
+namespace lt {
+
+// Zero the look-back words for n_items of scan work and the counters (and
+// the error word if clear_err); fills st for a scan kernel on `stream`.
+lt_status prep_scan(lt_tree_s* t, int64_t n_items, hipStream_t stream, int clear_err, ScanState* st);
+// Copy the device counters to the pinned mirror and wait for the stream.
+lt_status read_ctr(lt_tree_s* t, hipStream_t stream);
+// Zero the counters and the error word.
+lt_status clear_err(lt_tree_s* t, hipStream_t stream);
+
+// Split-precision (BF16 x 3 on MFMA, FP64 cell means) transfer; asynchronous.
+lt_status launch_split_transfer(lt_tree_s* t, int p, int nvar, const double* u_old, int64_t ld_old,
+                                double* u_new, int64_t ld_new, hipStream_t s);
 
 lt_status launch_transfer(int dim, int p, const double* ops, const int32_t* src,
                           const int8_t* kind, int64_t n, int nvar, const double* u_old,
@@ -66,5 +112,12 @@ struct lt_tree_s {
   lt::DevCtr* dctr = nullptr;
   lt::DevCtr* hctr = nullptr;  // pinned mirror
 
-  double* ops[LT_MAX_DEGREE + 1] = {};
+  double* ops[LT_MAX_DEGREE + 1] = {};  // 1D factors A_0, A_1, P_0, P_1 and weights
+
+  void* split_frags = nullptr;  // BF16 x 3 operator fragments (64-point elements)
+  double* split_vec = nullptr;  // FP64 mean weights
+  int32_t* split_R = nullptr;   // first child of each refined family
+  int64_t split_R_cap = 0;
+  int32_t* split_F = nullptr;   // fused parents
+  int64_t split_F_cap = 0;
 };
