@@ -104,8 +104,33 @@ lt_status lt_build_uniform(const lt_geom* geom, int depth, void* stream, lt_tree
 lt_status lt_build(const lt_geom* geom, const uint64_t* keys, int64_t n, void* stream,
                    lt_tree* out);
 
+/* Ensemble of `nmesh` independent trees in one key array, each starting
+ * uniform at depth[m] (form 2 of the cycle: every later call -- adapt,
+ * balance, connect, map, transfer -- then runs each step for all meshes in one
+ * launch).  geom->d_max is the shared finest level (the key resolution) and
+ * geom->d_min is ignored; mesh m refines no deeper than d_max[m] and coarsens
+ * no coarser than d_min[m] (0 <= d_min[m] <= d_max[m] <= geom->d_max).  The
+ * mesh index is stored above the Morton bits, so keys sort mesh by mesh and
+ * leaves of different meshes never touch; indices in nbr, hang and the
+ * mapping are ensemble-global.  LT_ERR_DEPTH if the index does not fit in 64
+ * bits.  Host arrays of nmesh entries.  Ownership of *out passes to the caller. */
+lt_status lt_build_batch(const lt_geom* geom, int nmesh, const int* d_min, const int* d_max,
+                         const int* depth, void* stream, lt_tree* out);
+
+/* Flags of an ensemble: per_mesh[m] (host, nmesh entries, all with the same p)
+ * gives the criterion of mesh m.  Point coordinates are computed at the shared
+ * finest level, which is exact: the scalings by powers of two commute with
+ * the rounding.  flags: device int8 [n_cur]. */
+lt_status lt_flag_batch(lt_tree t, const lt_flag_params* per_mesh, int nmesh, int8_t* flags,
+                        void* stream);
+
+/* offsets[m] = index of the first leaf of mesh m, offsets[nmesh] = n_cur
+ * (host array of nmesh + 1; a single tree has nmesh = 1).  Synchronises. */
+lt_status lt_mesh_offsets(lt_tree t, int64_t* offsets, void* stream);
+
 /* Flags of the current leaves (Section 5.2 criterion, see lt_flag_params).
- * flags: device int8 [n_cur], written in key order.  Asynchronous. */
+ * flags: device int8 [n_cur], written in key order.  Asynchronous.  An
+ * ensemble takes lt_flag_batch instead (LT_ERR_ARG here). */
 lt_status lt_flag(lt_tree t, const lt_flag_params* fp, int8_t* flags, void* stream);
 
 /* Adaptation procedure (Section 4.1): every leaf flagged +1 (depth < d_max) is

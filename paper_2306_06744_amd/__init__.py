@@ -23,9 +23,9 @@ STATUS = {0: "LT_OK", 1: "LT_ERR_ARG", 2: "LT_ERR_OOM", 3: "LT_ERR_HIP", 4: "LT_
           8: "LT_ERR_INTERNAL"}
 
 # Every symbol include/lt.h declares.
-EXPORTS = ["lt_build_uniform", "lt_build", "lt_flag", "lt_adapt", "lt_balance", "lt_connect",
-           "lt_map", "lt_transfer", "lt_size", "lt_view", "lt_export", "lt_last_error",
-           "lt_destroy"]
+EXPORTS = ["lt_build_uniform", "lt_build", "lt_build_batch", "lt_flag_batch", "lt_mesh_offsets",
+           "lt_flag", "lt_adapt", "lt_balance", "lt_connect", "lt_map", "lt_transfer", "lt_size",
+           "lt_view", "lt_export", "lt_last_error", "lt_destroy"]
 
 
 class LtError(RuntimeError):
@@ -60,6 +60,9 @@ def lib() -> C.CDLL:
         P, i64, i32 = C.c_void_p, C.c_int64, C.c_int
         L.lt_build_uniform.argtypes = [C.POINTER(Geom), i32, P, C.POINTER(P)]
         L.lt_build.argtypes = [C.POINTER(Geom), P, i64, P, C.POINTER(P)]
+        L.lt_build_batch.argtypes = [C.POINTER(Geom), i32, P, P, P, P, C.POINTER(P)]
+        L.lt_flag_batch.argtypes = [P, P, i32, P, P]
+        L.lt_mesh_offsets.argtypes = [P, P, P]
         L.lt_flag.argtypes = [P, C.POINTER(FlagParams), P, P]
         L.lt_adapt.argtypes = [P, P, P]
         L.lt_balance.argtypes = [P, P]
@@ -101,6 +104,21 @@ def _dptr(t) -> C.c_void_p:
     return C.c_void_p(t.data_ptr())
 
 
+def _flag_params(dim, centres, r_in, r_out, nodes01, lo, length, dist_axes=None,
+                 periodic_dist=False):
+    """lt_flag_params and the ctypes arrays it points to (keep them alive)."""
+    cen = (C.c_double * (3 * len(centres)))()
+    for v, c in enumerate(centres):
+        for a in range(len(c)):
+            cen[3 * v + a] = float(c[a])
+    nodes = (C.c_double * len(nodes01))(*[float(x) for x in nodes01])
+    lo3 = (C.c_double * 3)(*([float(x) for x in lo] + [0.0] * (3 - len(lo))))
+    fp = FlagParams(len(centres), C.cast(cen, C.POINTER(C.c_double)), float(r_in), float(r_out),
+                    int(dist_axes or dim), int(bool(periodic_dist)), len(nodes01) - 1,
+                    C.cast(nodes, C.POINTER(C.c_double)), lo3, float(length))
+    return fp, (cen, nodes)
+
+
 class Tree:
     """One linear quadtree / octree in device memory (owns an lt_tree)."""
 
@@ -131,6 +149,20 @@ class Tree:
         _check(lib().lt_build(C.byref(g), _dptr(k), k.numel(), _stream(), C.byref(h)))
         return cls(h, g)
 
+    @classmethod
+    def batch(cls, dim, d_finest, d_min, d_max, depth, periodic_mask=None, balance=2) -> "Tree":
+        """Ensemble of len(d_min) trees in one key array (per-mesh lists)."""
+        nm = len(d_min)
+        g = Geom(dim, 0, d_finest, (1 << dim) - 1 if periodic_mask is None else periodic_mask,
+                 balance)
+        arr = lambda v: (C.c_int * nm)(*[int(x) for x in v])
+        h = C.c_void_p()
+        _check(lib().lt_build_batch(C.byref(g), nm, arr(d_min), arr(d_max), arr(depth), _stream(),
+                                    C.byref(h)))
+        t = cls(h, g)
+        t.nmesh = nm
+        return t
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value and _lib is not None:
@@ -153,18 +185,32 @@ class Tree:
         n = self.size()
         if out is None:
             out = torch.empty(n, dtype=torch.int8, device="cuda")
-        cen = (C.c_double * (3 * len(centres)))()
-        for v, c in enumerate(centres):
-            for a in range(len(c)):
-                cen[3 * v + a] = float(c[a])
-        nodes = (C.c_double * len(nodes01))(*[float(x) for x in nodes01])
-        lo3 = (C.c_double * 3)(*([float(x) for x in lo] + [0.0] * (3 - len(lo))))
-        fp = FlagParams(len(centres), C.cast(cen, C.POINTER(C.c_double)), float(r_in),
-                        float(r_out), int(dist_axes or self.dim), int(bool(periodic_dist)),
-                        len(nodes01) - 1, C.cast(nodes, C.POINTER(C.c_double)), lo3,
-                        float(length))
+        fp, _keep = _flag_params(self.dim, centres, r_in, r_out, nodes01, lo, length, dist_axes,
+                                 periodic_dist)
         _check(lib().lt_flag(self._h, C.byref(fp), _dptr(out), _stream()))
         return out
+
+    def flag_batch(self, per_mesh, out=None):
+        """per_mesh: list of dicts with keys centres, r_in, r_out, nodes01, lo, length,
+        dist_axes, periodic_dist (one per mesh)."""
+        torch = _torch()
+        n = self.size()
+        if out is None:
+            out = torch.empty(n, dtype=torch.int8, device="cuda")
+        keep = []
+        fps = (FlagParams * len(per_mesh))()
+        for m, a in enumerate(per_mesh):
+            fps[m], k = _flag_params(self.dim, **a)
+            keep.append(k)
+        _check(lib().lt_flag_batch(self._h, C.cast(fps, C.c_void_p), len(per_mesh), _dptr(out),
+                                   _stream()))
+        return out
+
+    def mesh_offsets(self):
+        nm = getattr(self, "nmesh", 1)
+        offs = (C.c_int64 * (nm + 1))()
+        _check(lib().lt_mesh_offsets(self._h, C.cast(offs, C.c_void_p), _stream()))
+        return [int(x) for x in offs]
 
     def adapt(self, flags):
         torch = _torch()

@@ -13,13 +13,22 @@
 
 namespace lt {
 
+// Geometry of one tree, or of an ensemble of independent trees held in one
+// key array.  For an ensemble the mesh index sits above the Morton bits
+// (bit mesh_shift = mb + dim*dmax and up), so the concatenated keys stay
+// globally sorted mesh by mesh, and every search and scan of a single tree
+// works on the whole ensemble unchanged; dmax is then the shared finest
+// level and each mesh has its own refinement ceiling and coarsening floor.
 struct KeyGeom {
   int dim;            // 2 or 3
-  int dmax;           // finest depth
+  int dmax;           // finest depth (key resolution)
   int mb;             // bits that hold the depth
-  int dmin;           // coarsening floor
+  int dmin;           // coarsening floor (single tree)
   unsigned periodic;  // bit a: axis a wraps
   int balance;        // 0 face, 1 edge, 2 corner
+  int mesh_shift;     // first bit of the mesh index
+  int nmesh;          // 1 for a single tree
+  const int8_t* lim;  // ensemble: per mesh {floor, ceiling} (device), else null
 
   __host__ __device__ uint64_t width() const { return uint64_t(1) << dmax; }
   __host__ __device__ uint64_t depth_mask() const { return (uint64_t(1) << mb) - 1; }
@@ -86,6 +95,29 @@ __host__ __device__ inline void demorton(const KeyGeom& g, uint64_t m, uint64_t*
 
 __host__ __device__ inline int key_depth(const KeyGeom& g, uint64_t key) {
   return int(key & g.depth_mask());
+}
+// The mesh bits of a key, in place (0 for a single tree).
+__host__ __device__ inline uint64_t key_mesh_bits(const KeyGeom& g, uint64_t key) {
+  return g.nmesh > 1 ? (key >> g.mesh_shift) << g.mesh_shift : 0;
+}
+__host__ __device__ inline int key_mesh(const KeyGeom& g, uint64_t key) {
+  return g.nmesh > 1 ? int(key >> g.mesh_shift) : 0;
+}
+// Morton index of the anchor without the mesh bits.
+__host__ __device__ inline uint64_t key_morton(const KeyGeom& g, uint64_t key) {
+  const uint64_t m = key >> g.mb;
+  return g.nmesh > 1 ? (m & ((uint64_t(1) << (g.dim * g.dmax)) - 1)) : m;
+}
+// Coarsening floor and refinement ceiling of the tree a key belongs to.
+__device__ inline void depth_limits(const KeyGeom& g, uint64_t key, int* lo, int* hi) {
+  if (g.lim) {
+    const int m = key_mesh(g, key);
+    *lo = g.lim[2 * m];
+    *hi = g.lim[2 * m + 1];
+  } else {
+    *lo = g.dmin;
+    *hi = g.dmax;
+  }
 }
 __host__ __device__ inline uint64_t key_m(const KeyGeom& g, uint64_t key) { return key >> g.mb; }
 __host__ __device__ inline uint64_t make_key(const KeyGeom& g, uint64_t m, int depth) {

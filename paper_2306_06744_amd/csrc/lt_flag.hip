@@ -8,6 +8,7 @@
 
 #include <cmath>
 #include <string>
+#include <vector>
 
 #include "tree.hpp"
 
@@ -26,16 +27,19 @@ struct FlagArgs {
 
 // One thread per element.  The coordinate of point index k on axis a depends
 // only on (a, k), so the (p+1) values per axis are computed once.
+// For an ensemble (tab != null) each element takes the parameters of its mesh.
 template <int N1>
-__global__ __launch_bounds__(256) void k_flag(FlagArgs A, const uint64_t* __restrict__ keys, int64_t n,
+__global__ __launch_bounds__(256) void k_flag(FlagArgs A0, const FlagArgs* __restrict__ tab,
+                                              const uint64_t* __restrict__ keys, int64_t n,
                                               int8_t* __restrict__ flags) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= n) return;
-  const KeyGeom& g = A.g;
+  const KeyGeom& g = A0.g;
   const uint64_t key = keys[e];
+  const FlagArgs& A = tab ? tab[key_mesh(g, key)] : A0;
   const int d = key_depth(g, key);
   uint64_t x[3];
-  demorton(g, key_m(g, key), x);
+  demorton(g, key_morton(g, key), x);
   const double s = double(uint64_t(1) << (g.dmax - d));
   double X[3][N1];
 #pragma unroll
@@ -108,22 +112,22 @@ __global__ __launch_bounds__(256) void k_flag(FlagArgs A, const uint64_t* __rest
         }
   }
   int f = n_in > n_out ? 1 : (n_in < n_out ? -1 : 0);
-  if (f == 1 && d >= g.dmax) f = 0;
-  if (f == -1 && d <= g.dmin) f = 0;
+  int lo, hi;
+  depth_limits(g, key, &lo, &hi);
+  if (f == 1 && d >= hi) f = 0;
+  if (f == -1 && d <= lo) f = 0;
   flags[e] = int8_t(f);
 }
 
 template <int N1>
-hipError_t launch(const FlagArgs& A, const uint64_t* keys, int64_t n, int8_t* flags, hipStream_t s) {
+hipError_t launch(const FlagArgs& A, const FlagArgs* tab, const uint64_t* keys, int64_t n, int8_t* flags,
+                  hipStream_t s) {
   const unsigned blocks = unsigned((n + 255) / 256);
-  k_flag<N1><<<blocks, 256, 0, s>>>(A, keys, n, flags);
+  k_flag<N1><<<blocks, 256, 0, s>>>(A, tab, keys, n, flags);
   return hipGetLastError();
 }
 
-}  // namespace
-
-lt_status launch_flag(const KeyGeom& g, const lt_flag_params* fp, const uint64_t* keys, int64_t n,
-                      int8_t* flags, hipStream_t stream) {
+lt_status fill_args(const KeyGeom& g, const lt_flag_params* fp, FlagArgs* out) {
   if (fp->nvort < 1 || fp->nvort > LT_MAX_VORTICES || !fp->centre)
     return fail(LT_ERR_ARG, "nvort must be in 1..LT_MAX_VORTICES with centres given");
   if (fp->p < 0 || fp->p > LT_MAX_DEGREE || !fp->nodes01)
@@ -144,18 +148,51 @@ lt_status launch_flag(const KeyGeom& g, const lt_flag_params* fp, const uint64_t
   for (int k = 0; k <= fp->p; ++k) A.nodes[k] = fp->nodes01[k];
   for (int v = 0; v < fp->nvort; ++v)
     for (int a = 0; a < 3; ++a) A.c[v][a] = fp->centre[3 * v + a];
-  if (n == 0) return LT_OK;
-  hipError_t e;
-  switch (fp->p + 1) {
-    case 1: e = launch<1>(A, keys, n, flags, stream); break;
-    case 2: e = launch<2>(A, keys, n, flags, stream); break;
-    case 3: e = launch<3>(A, keys, n, flags, stream); break;
-    case 4: e = launch<4>(A, keys, n, flags, stream); break;
-    case 5: e = launch<5>(A, keys, n, flags, stream); break;
-    case 6: e = launch<6>(A, keys, n, flags, stream); break;
-    case 7: e = launch<7>(A, keys, n, flags, stream); break;
-    default: e = launch<8>(A, keys, n, flags, stream); break;
+  *out = A;
+  return LT_OK;
+}
+
+hipError_t dispatch(int n1, const FlagArgs& A, const FlagArgs* tab, const uint64_t* keys, int64_t n,
+                    int8_t* flags, hipStream_t stream) {
+  switch (n1) {
+    case 1: return launch<1>(A, tab, keys, n, flags, stream);
+    case 2: return launch<2>(A, tab, keys, n, flags, stream);
+    case 3: return launch<3>(A, tab, keys, n, flags, stream);
+    case 4: return launch<4>(A, tab, keys, n, flags, stream);
+    case 5: return launch<5>(A, tab, keys, n, flags, stream);
+    case 6: return launch<6>(A, tab, keys, n, flags, stream);
+    case 7: return launch<7>(A, tab, keys, n, flags, stream);
+    default: return launch<8>(A, tab, keys, n, flags, stream);
   }
+}
+
+}  // namespace
+
+lt_status launch_flag(const KeyGeom& g, const lt_flag_params* fp, const uint64_t* keys, int64_t n,
+                      int8_t* flags, hipStream_t stream) {
+  FlagArgs A;
+  LT_TRY_STATUS(fill_args(g, fp, &A));
+  if (n == 0) return LT_OK;
+  const hipError_t e = dispatch(fp->p + 1, A, nullptr, keys, n, flags, stream);
+  if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("flag launch: ") + hipGetErrorString(e));
+  return LT_OK;
+}
+
+size_t flag_args_size() { return sizeof(FlagArgs); }
+
+// Copies the per-mesh table from pageable host memory (staged by the runtime
+// before the call returns, so the host copy may go out of scope at once).
+lt_status launch_flag_batch(const KeyGeom& g, const lt_flag_params* fps, int nmesh, void* dev_table,
+                            const uint64_t* keys, int64_t n, int8_t* flags, hipStream_t stream) {
+  std::vector<FlagArgs> H(static_cast<size_t>(nmesh));
+  for (int m = 0; m < nmesh; ++m) {
+    LT_TRY_STATUS(fill_args(g, &fps[m], &H[m]));
+    if (fps[m].p != fps[0].p) return fail(LT_ERR_ARG, "every mesh of an ensemble flag call needs the same p");
+  }
+  hipError_t e = hipMemcpyAsync(dev_table, H.data(), sizeof(FlagArgs) * nmesh, hipMemcpyHostToDevice,
+                                stream);
+  if (e == hipSuccess && n > 0)
+    e = dispatch(fps[0].p + 1, H[0], static_cast<const FlagArgs*>(dev_table), keys, n, flags, stream);
   if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("flag launch: ") + hipGetErrorString(e));
   return LT_OK;
 }

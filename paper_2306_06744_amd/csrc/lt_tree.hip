@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "tree.hpp"
 
@@ -73,6 +74,33 @@ __global__ void k_uniform(KeyGeom g, int depth, int64_t n, uint64_t* keys) {
   if (i < n) keys[i] = make_key(g, uint64_t(i) << (g.dim * (g.dmax - depth)), depth);
 }
 
+// Ensemble of uniform trees: mesh m holds 2^(dim*depth_m) leaves starting at offs[m].
+__global__ void k_uniform_batch(KeyGeom g, const int64_t* __restrict__ offs,
+                                const int8_t* __restrict__ depth, int nmesh, int64_t n,
+                                uint64_t* __restrict__ keys) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int lo = 0, hi = nmesh - 1;
+  while (lo < hi) {  // last mesh whose first leaf is <= i
+    const int mid = (lo + hi + 1) >> 1;
+    if (offs[mid] <= i)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int d = depth[lo];
+  keys[i] = (uint64_t(lo) << g.mesh_shift) |
+            make_key(g, uint64_t(i - offs[lo]) << (g.dim * (g.dmax - d)), d);
+}
+
+// First leaf of every mesh (offs[nmesh] = n).
+__global__ void k_mesh_offsets(KeyGeom g, const uint64_t* __restrict__ keys, int64_t n, int nmesh,
+                               int64_t* __restrict__ offs) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m > nmesh) return;
+  offs[m] = m == nmesh ? n : lower_bound(keys, n, uint64_t(m) << g.mesh_shift);
+}
+
 // Complete linear tree check: each key valid, and the Morton range of leaf i
 // ends exactly where leaf i+1 starts (so keys ascend, tile, and do not overlap).
 __global__ void k_validate(KeyGeom g, const uint64_t* __restrict__ keys, int64_t n, unsigned* err) {
@@ -128,8 +156,10 @@ __global__ __launch_bounds__(kBlock) void k_adapt(KeyGeom g, const uint64_t* __r
       f = 0;
     }
     const int d = key_depth(g, kk);
-    if (f == 1 && d >= g.dmax) f = 0;
-    if (f == -1 && d <= g.dmin) f = 0;
+    int lo, hi;
+    depth_limits(g, kk, &lo, &hi);
+    if (f == 1 && d >= hi) f = 0;
+    if (f == -1 && d <= lo) f = 0;
     int a = 0;
     if (f == 1) {
       a = 1;
@@ -195,7 +225,8 @@ __global__ __launch_bounds__(kBlock) void k_balance_mark(KeyGeom g, const uint64
   if (d < 2) return;
   const int limit = g.balance == 0 ? 1 : (g.balance == 1 ? 2 : 3);
   uint64_t x[3];
-  demorton(g, key_m(g, key), x);
+  demorton(g, key_morton(g, key), x);
+  const uint64_t mhi = key_mesh_bits(g, key) >> g.mb;
   const uint64_t S = uint64_t(1) << (g.dmax - d + 1);  // parent size
   uint64_t pa[3];
   int b[3];
@@ -213,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_balance_mark(KeyGeom g, const uint64
     for (int a = 0; a < g.dim; ++a)
       if ((sub >> a) & 1) ok = ok && shift_coord(g, a, pa[a], b[a] ? int64_t(S) : -int64_t(S), &q[a]);
     if (!ok) continue;
-    const int64_t j = last_le_near(keys, n, point_key(g, morton(g, q)), i);
+    const int64_t j = last_le_near(keys, n, point_key(g, morton(g, q) | mhi), i);
     if (j >= 0 && key_depth(g, keys[j]) < d - 1) {
       const uint32_t was = atomicOr(&mark[j], 1u);
       if (!(was & 1u)) fresh_marks++;
@@ -300,7 +331,8 @@ __global__ __launch_bounds__(kBlock) void k_connect(KeyGeom g, const uint64_t* _
     const uint64_t key = keys[e];
     const int d = key_depth(g, key);
     uint64_t x[3];
-    demorton(g, key_m(g, key), x);
+    demorton(g, key_morton(g, key), x);
+    const uint64_t mhi = key_mesh_bits(g, key) >> g.mb;
     const int64_t s = int64_t(1) << (g.dmax - d);
     for (int f = 0; f < nf; ++f) {
       const int a = f >> 1;
@@ -309,7 +341,7 @@ __global__ __launch_bounds__(kBlock) void k_connect(KeyGeom g, const uint64_t* _
       if (!shift_coord(g, a, x[a], (f & 1) ? s : -s, &q[a])) {
         v = -2;
       } else {
-        const int64_t j = last_le_near(keys, n, point_key(g, morton(g, q)), e);
+        const int64_t j = last_le_near(keys, n, point_key(g, morton(g, q) | mhi), e);
         if (j < 0) {
           v = -2;  // unreachable for a complete tree (keys[0] has anchor 0)
         } else if (key_depth(g, keys[j]) <= d) {
@@ -334,7 +366,8 @@ __global__ __launch_bounds__(kBlock) void k_connect(KeyGeom g, const uint64_t* _
     const uint64_t key = keys[e];
     const int d = key_depth(g, key);
     uint64_t x[3];
-    demorton(g, key_m(g, key), x);
+    demorton(g, key_morton(g, key), x);
+    const uint64_t mhi = key_mesh_bits(g, key) >> g.mb;
     const int64_t s = int64_t(1) << (g.dmax - d);
     for (int f = 0; f < nf; ++f) {
       if (!((hm[k] >> f) & 1u)) continue;
@@ -345,7 +378,7 @@ __global__ __launch_bounds__(kBlock) void k_connect(KeyGeom g, const uint64_t* _
       const int a = f >> 1, side = f & 1;
       uint64_t q[3] = {x[0], x[1], x[2]};
       shift_coord(g, a, x[a], side ? s : -s, &q[a]);
-      const uint64_t mq = morton(g, q);
+      const uint64_t mq = morton(g, q) | mhi;
       int32_t* row = hang + o * width;
       row[0] = int32_t(e);
       row[1] = f;
@@ -466,6 +499,9 @@ lt_status new_tree(const lt_geom* geom, lt_tree* out) {
   t->g.mb = mb;
   t->g.periodic = geom->periodic_mask & ((1u << geom->dim) - 1);
   t->g.balance = geom->balance;
+  t->g.mesh_shift = mb + geom->dim * geom->d_max;
+  t->g.nmesh = 1;
+  t->g.lim = nullptr;
   hipError_t e = hipGetDevice(&t->device);
   if (e == hipSuccess) e = hipMalloc(&t->dctr, sizeof(DevCtr));
   if (e == hipSuccess) e = hipHostMalloc(&t->hctr, sizeof(DevCtr), hipHostMallocDefault);
@@ -579,8 +615,93 @@ lt_status lt_build(const lt_geom* geom, const uint64_t* keys, int64_t n, void* s
   return LT_OK;
 }
 
+lt_status lt_build_batch(const lt_geom* geom, int nmesh, const int* d_min, const int* d_max,
+                         const int* depth, void* stream, lt_tree* out) {
+  if (!geom || !d_min || !d_max || !depth || !out || nmesh < 1)
+    return fail(LT_ERR_ARG, "NULL argument or no mesh");
+  lt_geom g0 = *geom;
+  g0.d_min = 0;
+  LT_TRY(check_geom(&g0));
+  int mb = 0;
+  while ((geom->d_max >> mb) != 0) ++mb;
+  int mesh_bits = 0;
+  while (((nmesh - 1) >> mesh_bits) != 0) ++mesh_bits;
+  if (mb + geom->dim * geom->d_max + mesh_bits > 64)
+    return fail(LT_ERR_DEPTH, "mesh index does not fit above the Morton bits");
+  std::vector<int8_t> lim(2 * size_t(nmesh)), dep(nmesh);
+  std::vector<int64_t> offs(size_t(nmesh) + 1, 0);
+  for (int m = 0; m < nmesh; ++m) {
+    if (d_min[m] < 0 || d_min[m] > d_max[m] || d_max[m] > geom->d_max || depth[m] < 0 ||
+        depth[m] > geom->d_max)
+      return fail(LT_ERR_DEPTH, "mesh " + std::to_string(m) + ": need 0 <= d_min <= d_max <= finest");
+    if (geom->dim * depth[m] > 36) return fail(LT_ERR_ARG, "uniform mesh too large");
+    lim[2 * m] = int8_t(d_min[m]);
+    lim[2 * m + 1] = int8_t(d_max[m]);
+    dep[m] = int8_t(depth[m]);
+    offs[m + 1] = offs[m] + (int64_t(1) << (geom->dim * depth[m]));
+  }
+  const int64_t n = offs[nmesh];
+  lt_tree t = nullptr;
+  LT_TRY(new_tree(&g0, &t));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int8_t* dep_dev = nullptr;
+  lt_status st = grow(&t->kbuf[t->cur], &t->kcap[t->cur], n);
+  hipError_t e = hipSuccess;
+  if (st == LT_OK) {
+    e = hipMalloc(&t->lim, lim.size());
+    if (e == hipSuccess) e = hipMalloc(&t->mesh_offs, sizeof(int64_t) * (nmesh + 1));
+    if (e == hipSuccess) e = hipMalloc(&dep_dev, dep.size());
+    if (e == hipSuccess) e = hipMalloc(&t->flag_tab, flag_args_size() * nmesh);
+    if (e == hipSuccess)
+      e = hipMemcpy(t->lim, lim.data(), lim.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dep_dev, dep.data(), dep.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(t->mesh_offs, offs.data(), sizeof(int64_t) * (nmesh + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+      t->g.nmesh = nmesh;
+      t->g.lim = t->lim;
+      k_uniform_batch<<<unsigned(ceil_div(n, kBlock)), kBlock, 0, s>>>(t->g, t->mesh_offs, dep_dev,
+                                                                        nmesh, n, t->kbuf[t->cur]);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = fail(LT_ERR_HIP, std::string("batch build: ") + hipGetErrorString(e));
+  }
+  if (dep_dev) (void)hipFree(dep_dev);
+  if (st != LT_OK) {
+    lt_destroy(t);
+    return st;
+  }
+  t->n_cur = n;
+  *out = t;
+  return LT_OK;
+}
+
+lt_status lt_flag_batch(lt_tree t, const lt_flag_params* per_mesh, int nmesh, int8_t* flags,
+                        void* stream) {
+  if (!t || !per_mesh || !flags) return fail(LT_ERR_ARG, "NULL argument");
+  if (nmesh != t->g.nmesh || !t->flag_tab)
+    return fail(LT_ERR_ARG, "nmesh must equal the ensemble's mesh count");
+  return launch_flag_batch(t->g, per_mesh, nmesh, t->flag_tab, t->kbuf[t->cur], t->n_cur, flags,
+                           static_cast<hipStream_t>(stream));
+}
+
+lt_status lt_mesh_offsets(lt_tree t, int64_t* offsets, void* stream) {
+  if (!t || !offsets) return fail(LT_ERR_ARG, "NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nm = t->g.nmesh;
+  if (!t->mesh_offs) LT_HIP(hipMalloc(&t->mesh_offs, sizeof(int64_t) * (nm + 1)));
+  k_mesh_offsets<<<unsigned(ceil_div(nm + 1, 64)), 64, 0, s>>>(t->g, t->kbuf[t->cur], t->n_cur, nm,
+                                                                 t->mesh_offs);
+  LT_HIP(hipGetLastError());
+  LT_HIP(hipMemcpyAsync(offsets, t->mesh_offs, sizeof(int64_t) * (nm + 1), hipMemcpyDeviceToHost, s));
+  LT_HIP(hipStreamSynchronize(s));
+  return LT_OK;
+}
+
 lt_status lt_flag(lt_tree t, const lt_flag_params* fp, int8_t* flags, void* stream) {
   if (!t || !fp || !flags) return fail(LT_ERR_ARG, "NULL argument");
+  if (t->g.nmesh > 1) return fail(LT_ERR_ARG, "an ensemble takes lt_flag_batch");
   return launch_flag(t->g, fp, t->kbuf[t->cur], t->n_cur, flags, static_cast<hipStream_t>(stream));
 }
 
@@ -763,6 +884,9 @@ void lt_destroy(lt_tree t) {
   if (t->map_src) (void)hipFree(t->map_src);
   if (t->map_kind) (void)hipFree(t->map_kind);
   if (t->status) (void)hipFree(t->status);
+  if (t->lim) (void)hipFree(t->lim);
+  if (t->flag_tab) (void)hipFree(t->flag_tab);
+  if (t->mesh_offs) (void)hipFree(t->mesh_offs);
   if (t->dctr) (void)hipFree(t->dctr);
   if (t->hctr) (void)hipHostFree(t->hctr);
   for (auto& o : t->ops) if (o) (void)hipFree(o);

@@ -34,6 +34,12 @@ lt_status fail(lt_status s, const std::string& msg);
 lt_status launch_flag(const KeyGeom& g, const lt_flag_params* fp, const uint64_t* keys, int64_t n,
                       int8_t* flags, hipStream_t stream);
 
+// Ensemble flags: per-mesh parameters copied to dev_table (flag_args_size()
+// bytes per mesh), then one launch over all leaves.
+size_t flag_args_size();
+lt_status launch_flag_batch(const KeyGeom& g, const lt_flag_params* fps, int nmesh, void* dev_table,
+                            const uint64_t* keys, int64_t n, int8_t* flags, hipStream_t stream);
+
 // Builds (once per degree) the FP64 1D transfer operators into ops.
 lt_status build_transfer_ops(int p, double** ops, hipStream_t stream);
 
@@ -106,6 +112,10 @@ struct lt_tree_s {
   int64_t map_cap = 0;
   int64_t kind_cap = 0;
   bool map_valid = false;
+
+  int8_t* lim = nullptr;        // ensemble: per-mesh {floor, ceiling}
+  void* flag_tab = nullptr;     // ensemble: per-mesh flag parameters
+  int64_t* mesh_offs = nullptr; // ensemble: first leaf of each mesh (nmesh + 1)
 
   uint64_t* status = nullptr;  // look-back tile words
   int64_t status_cap = 0;

@@ -1,0 +1,92 @@
+"""GPU: ensembles of independent trees in one key array (lt_build_batch and
+lt_flag_batch; adapt, balance, connect, map and transfer run once for all
+meshes).  Each mesh is compared with its own CPU oracle tree, which encodes
+keys at the mesh's own finest level: bit-exact keys, flags, connectivity and
+mapping, and the FP64 transfer within 1e-13 relative L2."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_06744_amd import synth
+
+from gpu_util import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def to_mesh_keys(keys, dim, d_fine, d_max_m):
+    """Re-encode ensemble keys (shared finest level, mesh bits removed) at a
+    mesh's own finest level."""
+    out = np.zeros(len(keys), dtype=np.uint64)
+    mesh_shift = d_fine.bit_length() + dim * d_fine
+    for i, k in enumerate(keys):
+        k = int(k) & ((1 << mesh_shift) - 1)
+        d, a = oracle.decode(dim, d_fine, k)
+        out[i] = oracle.encode(dim, d_max_m, d, [int(x) >> (d_fine - d_max_m) for x in a])
+    return out
+
+
+def flag_args(g, dim, nv):
+    cen = [tuple(g.uniform(-3, 3, size=3)) for _ in range(nv)]
+    r_in = float(g.uniform(1.0, 2.5))
+    return dict(centres=cen, r_in=r_in, r_out=1.2 * r_in, nodes01=synth.gl_nodes01(2),
+                lo=(-5.0,) * dim, length=10.0, dist_axes=dim, periodic_dist=bool(g.integers(2)))
+
+
+@pytest.mark.parametrize("dim,d_fine", [(3, 6), (2, 8)])
+def test_ensemble_matches_per_mesh_oracle(dim, d_fine):
+    import torch
+    import paper_2306_06744_amd as lt
+    g = synth.rng(4000 + dim)
+    M = 7
+    d_max = [int(x) for x in g.integers(d_fine - 2, d_fine + 1, size=M)]
+    d_min = [int(g.integers(1, dm - 1)) for dm in d_max]
+    depth = [int(g.integers(dmin, dmax)) for dmin, dmax in zip(d_min, d_max)]
+    print("ensemble", dim, d_fine, d_min, d_max, depth, flush=True)
+    t = lt.Tree.batch(dim, d_fine, d_min, d_max, depth)
+    O = [oracle.Tree(dim, d_min[m], d_max[m], start_depth=depth[m]) for m in range(M)]
+    fargs = [flag_args(g, dim, int(g.integers(1, 4))) for _ in range(M)]
+    p = 2
+    nvar = 3
+    for cyc in range(4):
+        offs_old = t.mesh_offsets()
+        f = t.flag_batch(fargs).cpu().numpy()
+        for m in range(M):
+            fo = O[m].flag(**fargs[m])
+            assert np.array_equal(f[offs_old[m]:offs_old[m + 1]], fo), f"flags mesh {m} cycle {cyc}"
+            O[m].adapt(fo)
+            O[m].balance()
+        t.adapt(torch.from_numpy(f).cuda())
+        t.balance()
+        offs = t.mesh_offsets()
+        keys = t.keys().cpu().numpy().view(np.uint64)
+        t.connect()
+        t.map()
+        nbr = t.nbr().cpu().numpy()
+        hang = t.hang().cpu().numpy()
+        src, kind = (a.cpu().numpy() for a in t.mapping())
+        u_old = synth.random_solution(70 + cyc, nvar, (p + 1) ** dim, offs_old[-1])
+        u_new = t.transfer(p, torch.from_numpy(u_old).cuda()).cpu().numpy()
+        hang_by_mesh = {}
+        for r in hang:
+            m = int(np.searchsorted(offs, r[0], side="right") - 1)
+            hang_by_mesh.setdefault(m, []).append(r)
+        for m in range(M):
+            a, b = offs[m], offs[m + 1]
+            assert np.array_equal(to_mesh_keys(keys[a:b], dim, d_fine, d_max[m]), O[m].keys()), \
+                f"keys mesh {m} cycle {cyc}"
+            nbr_o, hang_o = O[m].connect()
+            loc = nbr[a:b].copy()
+            loc[loc >= 0] -= a
+            assert np.array_equal(loc, nbr_o), f"nbr mesh {m}"
+            hm = np.array(hang_by_mesh.get(m, np.zeros((0, hang.shape[1] if hang.size else 2 + (1 << (dim - 1))))),
+                          dtype=np.int64).reshape(-1, 2 + (1 << (dim - 1)))
+            if len(hm):
+                hm[:, 0] -= a
+                hm[:, 2:] -= a
+            assert np.array_equal(hm, hang_o), f"hang mesh {m}"
+            so, ko = O[m].map()
+            assert np.array_equal(src[a:b] - offs_old[m], so) and np.array_equal(kind[a:b], ko), \
+                f"map mesh {m}"
+            ref = O[m].transfer(p, np.ascontiguousarray(u_old[:, :, offs_old[m]:offs_old[m + 1]]))
+            assert rel_l2(u_new[:, :, a:b], ref) <= 1e-13, f"transfer mesh {m}"
