@@ -67,6 +67,84 @@ def cpu_baseline(w, nodes):
                       f"oracle, one thread)"}
 
 
+def ensemble_variant(lt, torch, synth, seed, nvar=5, warm=8):
+    """64 independent 3D meshes (levels up to 6..9, p in {2,3}): one timed
+    cycle (after `warm` cycles, centres advected +0.1 x per cycle) of the
+    batched path -- one ensemble tree per p, every phase one launch for all of
+    its meshes -- against a loop over 64 separate trees."""
+    meshes = synth.workload_ensemble(seed)
+
+    def margs(m, cyc):
+        return dict(centres=m.centres_at(cyc), r_in=m.r_in, r_out=m.r_out,
+                    nodes01=synth.gl_nodes01(m.p), lo=(-5.0,) * 3, length=10.0, dist_axes=3,
+                    periodic_dist=False)
+
+    def cycle_tree(t, p, u_old, cyc, flag_fn):
+        f = flag_fn(cyc)
+        t.adapt(f)
+        t.balance()
+        t.connect()
+        t.map()
+        n = t.size()
+        u_new = torch.empty((nvar, (p + 1) ** 3, n), dtype=torch.float64, device="cuda")
+        t.transfer(p, u_old, u_new=u_new)
+        return u_new, n
+
+    def batched():
+        trees = []
+        for p in (2, 3):
+            grp = [m for m in meshes if m.p == p]
+            t = lt.Tree.batch(3, 9, [m.d_min for m in grp], [m.d_max for m in grp],
+                              [m.d_min for m in grp])
+            u = torch.zeros((nvar, (p + 1) ** 3, t.size()), dtype=torch.float64, device="cuda")
+            trees.append((t, p, grp, u))
+        def one(cyc):
+            total = 0
+            for i, (t, p, grp, u) in enumerate(trees):
+                u, n = cycle_tree(t, p, u, cyc, lambda c: t.flag_batch([margs(m, c) for m in grp]))
+                trees[i] = (t, p, grp, u)
+                total += n
+            return total
+        return one
+
+    def looped():
+        trees = []
+        for m in meshes:
+            t = lt.Tree.uniform(3, m.d_min, m.d_max)
+            u = torch.zeros((nvar, (m.p + 1) ** 3, t.size()), dtype=torch.float64, device="cuda")
+            trees.append([t, m, u])
+        def one(cyc):
+            total = 0
+            for rec in trees:
+                t, m, u = rec
+                a = margs(m, cyc)
+                rec[2], n = cycle_tree(t, m.p, u, cyc, lambda c: t.flag(**margs(m, c)))
+                total += n
+            return total
+        return one
+
+    out = {}
+    for name, make in (("batched", batched), ("per_mesh_loop", looped)):
+        one = make()
+        for c in range(warm):
+            n = one(c)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = one(warm)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"ms": dt * 1e3, "octants_per_s": n / dt}
+        out["leaves"] = n
+        log(f"ensemble {name}: {n} leaves, {dt * 1e3:.2f} ms")
+        del one
+        torch.cuda.empty_cache()
+    out["speedup"] = out["per_mesh_loop"]["ms"] / out["batched"]["ms"]
+    out["workload"] = ("64 independent 3D meshes [-5,5]^3, 1-4 vortices (3D distance), finest "
+                       "level U{6..9}, p U{2,3}, 5 FP64 variables, uniform start at level 3, one "
+                       f"timed cycle after {warm}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +234,7 @@ def main():
     cyc_bytes = sum(cycle_bytes(w.dim, E, *s) for s in sizes)
     variants = {}
     if not args.plain_only:
+        variants["ensemble_64"] = ensemble_variant(lt, torch, synth, 4000)
         s1, e1, t1 = run(1)
         n1 = sum(s[1] for s in s1)
         variants["split_bf16x3_transfer"] = {

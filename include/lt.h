@@ -91,6 +91,7 @@ typedef struct {
   const double* nodes01;  /* host, p+1 solution-point positions in [0,1] on one axis */
   double lo[3];           /* physical position of the domain's lowest corner         */
   double len;             /* physical edge length of the cubic domain                */
+  int raw;                /* 1: skip the d_min / d_max clamps (training labels)      */
 } lt_flag_params;
 
 /* Uniform tree of all 2^(dim*depth) octants at `depth` (d_min <= depth <= d_max
@@ -202,6 +203,56 @@ lt_status lt_view(lt_tree t, lt_field what, const void** ptr, int64_t* count);
  * type; LT_ERR_ARG if it is too small.  dst may be NULL when the field is
  * empty; LT_ERR_STATE if the field has not been computed. */
 lt_status lt_export(lt_tree t, lt_field what, void* dst, int64_t capacity, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Learned refinement indicator (form 4 of the cycle), for 3D elements of 64
+ * Gauss-Legendre points (p = 3) with 5 conserved variables.
+ *
+ * Features per element: the nodal values of each variable projected on the
+ * orthonormal tensor Legendre basis (exact with Gauss-Legendre quadrature),
+ * f = (log10(|c| + 1e-14) + 7) / 7, 320 values (variable-major, mode index
+ * x fastest), stored BF16.  Network: 320 -> 128 -> 64 -> 3 with ReLU, BF16
+ * weights and activations, FP32 accumulation on the matrix cores; classes
+ * 0 coarsen, 1 keep, 2 refine.  Parameters (FP32, host layout): W1[128][320],
+ * b1[128], W2[64][128], b2[64], W3[3][64], b3[3] (LT_MLP_NPARAM floats).
+ * ------------------------------------------------------------------------ */
+#define LT_MLP_NPARAM (128 * 320 + 128 + 64 * 128 + 64 + 3 * 64 + 3)
+typedef struct lt_mlp_s* lt_mlp;
+
+/* New model from host FP32 parameters (copied); Adam state zeroed. */
+lt_status lt_mlp_create(const float* params, lt_mlp* out);
+/* Copy the FP32 parameters and/or the last gradients (NULL to skip) to host
+ * arrays of LT_MLP_NPARAM floats.  Synchronises. */
+lt_status lt_mlp_params(lt_mlp m, float* params, float* grads, void* stream);
+/* Features of n elements into X (device BF16 [n][320]): element rows[r] of
+ * the solution u[(v*64 + i)*ld + e] (rows == NULL: elements 0..n-1). */
+lt_status lt_mlp_features(lt_mlp m, const double* u, int64_t ld, int nvar, const int32_t* rows,
+                          int64_t n, void* X, void* stream);
+/* Forward + backward of the mean softmax cross-entropy on a batch of B rows
+ * (X device BF16 [B][320], labels device int8 in {0,1,2} = coarsen / keep /
+ * refine, other values clamped into that range); the gradients are kept in
+ * the model (read with lt_mlp_params).  1 <= B <= 2^21, else LT_ERR_ARG. */
+lt_status lt_mlp_grads(lt_mlp m, const void* X, const int8_t* labels, int64_t B, void* stream);
+/* lt_mlp_grads, then one Adam step (beta 0.9 / 0.999, eps 1e-8) at rate lr. */
+lt_status lt_mlp_train_step(lt_mlp m, const void* X, const int8_t* labels, int64_t B, float lr,
+                            void* stream);
+/* Logits (device FP32 [n][3]) of n feature rows. */
+lt_status lt_mlp_infer(lt_mlp m, const void* X, int64_t n, float* logits, void* stream);
+/* Flags of the current leaves from the solution u (device FP64, ld >= n_cur):
+ * the argmax class of the network where its softmax probability is at least
+ * conf_min, else the geometric flag of `fallback`; then the depth clamps.
+ * conf (device FP32 [n_cur], may be NULL) receives the top probability. */
+lt_status lt_flag_mlp(lt_tree t, lt_mlp m, const lt_flag_params* fallback, const double* u, int64_t ld,
+                      float conf_min, int8_t* flags, float* conf, void* stream);
+/* Isentropic vortex (Section 5.2; phi = 1/2, gamma = 1.4, free stream rho = 1,
+ * u = 1, v = w = 0, p = 1) of z-extruded vortices with the given xy centres
+ * (centre[3*v + a]) and strengths, in conserved variables at the solution
+ * points of every leaf: u[(v*n_p + i)*ld + e], 5 variables in 3D (rho, rho u,
+ * rho v, rho w, E), 4 in 2D (rho, rho u, rho v, E).  Points as in lt_flag.
+ * A synthetic-input generator. */
+lt_status lt_vortex_field(lt_tree t, const lt_flag_params* where, const double* strength, double* u,
+                          int64_t ld, void* stream);
+void lt_mlp_destroy(lt_mlp m);
 
 /* Text of the calling thread's last error ("" if none). */
 const char* lt_last_error(void);

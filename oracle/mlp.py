@@ -1,0 +1,125 @@
+"""FP64 references for the learned refinement indicator.
+
+TEST INFRASTRUCTURE ONLY (imported by tests/ and the benchmark's checks).
+
+  * vortex_field: the isentropic vortex of Section 5.2 (phi = 1/2, gamma = 1.4)
+    superposed for several z-extruded vortices, on a free stream
+    (rho, u, v, w, p) = (1, 1, 0, 0, 1), in conserved variables
+    (rho, rho u, rho v, rho w, E); the perturbations are
+        du = -a/(2 pi) (y - yc) e^{phi (1 - r2)},  dv = a/(2 pi) (x - xc) e^{phi (1 - r2)},
+        dT = -a^2 (gamma - 1) / (16 phi gamma pi^2) e^{2 phi (1 - r2)},
+    with r2 the squared xy distance to the axis, T = 1 + dT, rho = T^{1/(gamma-1)},
+    p = rho^gamma.
+  * modal: coefficients of an element's Gauss-Legendre nodal values in the
+    orthonormal tensor Legendre basis (Gauss-Legendre quadrature is exact for
+    the degree-2p products, so this is the exact projection).
+  * features: log10(|c| + 1e-14) per mode and variable, scaled (f + 7) / 7.
+  * MLP 320 -> 128 -> 64 -> 3 with ReLU, softmax cross-entropy, and its
+    gradients written out by hand (checked against finite differences).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from numpy.polynomial import legendre as npleg
+
+GAMMA = 1.4
+PHI = 0.5
+
+
+def vortex_field(x, y, centres, strengths):
+    """Conserved variables (5, ...) at points (x, y), z-extruded vortices."""
+    du = np.zeros_like(x)
+    dv = np.zeros_like(x)
+    dT = np.zeros_like(x)
+    for (xc, yc), a in zip(centres, strengths):
+        dx = x - xc
+        dy = y - yc
+        r2 = dx * dx + dy * dy
+        e = np.exp(PHI * (1.0 - r2))
+        du += -a / (2 * math.pi) * dy * e
+        dv += a / (2 * math.pi) * dx * e
+        dT += -a * a * (GAMMA - 1) / (16 * PHI * GAMMA * math.pi ** 2) * e * e
+    T = 1.0 + dT
+    rho = T ** (1.0 / (GAMMA - 1.0))
+    p = rho ** GAMMA
+    u = 1.0 + du
+    v = dv
+    E = p / (GAMMA - 1.0) + 0.5 * rho * (u * u + v * v)
+    return np.stack([rho, rho * u, rho * v, np.zeros_like(x), E])
+
+
+def gl(npts):
+    x, w = npleg.leggauss(npts)
+    return x, w
+
+
+def modal_matrix_1d(p):
+    """T[n, i] = w_i * Ln(x_i), Ln orthonormal Legendre on [-1, 1]."""
+    x, w = gl(p + 1)
+    T = np.zeros((p + 1, p + 1))
+    for n in range(p + 1):
+        c = np.zeros(n + 1)
+        c[n] = 1.0
+        T[n] = w * npleg.legval(x, c) * math.sqrt((2 * n + 1) / 2.0)
+    return T
+
+
+def modal(u, dim, p):
+    """u: (..., (p+1)^dim) nodal values, x fastest -> modal coefficients
+    (same shape, mode index k = kx + (p+1)(ky + (p+1) kz))."""
+    T = modal_matrix_1d(p)
+    n1 = p + 1
+    shape = u.shape[:-1] + (n1,) * dim
+    a = u.reshape(shape)              # (..., z, y, x)
+    # apply T on every axis
+    for ax in range(dim):
+        a = np.moveaxis(np.tensordot(a, T, axes=([a.ndim - 1 - ax], [1])), -1, a.ndim - 1 - ax)
+    return a.reshape(u.shape)
+
+
+def features(coeffs):
+    """coeffs: (nvar, npts) per element (or (..., nvar, npts)) -> flat features."""
+    f = (np.log10(np.abs(coeffs) + 1e-14) + 7.0) / 7.0
+    return f.reshape(f.shape[:-2] + (-1,))
+
+
+def relu(x):
+    return np.maximum(x, 0.0)
+
+
+def forward(X, W1, b1, W2, b2, W3, b3):
+    """X: (B, 320).  Returns logits and the cache for backward."""
+    z1 = X @ W1 + b1
+    h1 = relu(z1)
+    z2 = h1 @ W2 + b2
+    h2 = relu(z2)
+    z3 = h2 @ W3 + b3
+    return z3, (X, z1, h1, z2, h2)
+
+
+def softmax(z):
+    z = z - z.max(axis=1, keepdims=True)
+    e = np.exp(z)
+    return e / e.sum(axis=1, keepdims=True)
+
+
+def loss_and_grads(X, y, W1, b1, W2, b2, W3, b3):
+    """Mean softmax cross-entropy over the batch and its gradients."""
+    z3, (X, z1, h1, z2, h2) = forward(X, W1, b1, W2, b2, W3, b3)
+    P = softmax(z3)
+    B = X.shape[0]
+    loss = -np.mean(np.log(P[np.arange(B), y]))
+    d3 = P.copy()
+    d3[np.arange(B), y] -= 1.0
+    d3 /= B
+    gW3 = h2.T @ d3
+    gb3 = d3.sum(axis=0)
+    d2 = (d3 @ W3.T) * (z2 > 0)
+    gW2 = h1.T @ d2
+    gb2 = d2.sum(axis=0)
+    d1 = (d2 @ W2.T) * (z1 > 0)
+    gW1 = X.T @ d1
+    gb1 = d1.sum(axis=0)
+    return loss, (gW1, gb1, gW2, gb2, gW3, gb3)

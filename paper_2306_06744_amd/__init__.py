@@ -25,7 +25,10 @@ STATUS = {0: "LT_OK", 1: "LT_ERR_ARG", 2: "LT_ERR_OOM", 3: "LT_ERR_HIP", 4: "LT_
 # Every symbol include/lt.h declares.
 EXPORTS = ["lt_build_uniform", "lt_build", "lt_build_batch", "lt_flag_batch", "lt_mesh_offsets",
            "lt_flag", "lt_adapt", "lt_balance", "lt_connect", "lt_map", "lt_transfer", "lt_size",
-           "lt_view", "lt_export", "lt_last_error", "lt_destroy"]
+           "lt_view", "lt_export", "lt_mlp_create", "lt_mlp_params", "lt_mlp_features",
+           "lt_mlp_grads", "lt_mlp_train_step", "lt_mlp_infer", "lt_flag_mlp", "lt_vortex_field",
+           "lt_mlp_destroy", "lt_last_error", "lt_destroy"]
+MLP_NPARAM = 128 * 320 + 128 + 64 * 128 + 64 + 3 * 64 + 3
 
 
 class LtError(RuntimeError):
@@ -44,7 +47,7 @@ class FlagParams(C.Structure):
                 ("r_in", C.c_double), ("r_out", C.c_double), ("dist_axes", C.c_int),
                 ("periodic_dist", C.c_int), ("p", C.c_int),
                 ("nodes01", C.POINTER(C.c_double)), ("lo", C.c_double * 3),
-                ("len", C.c_double)]
+                ("len", C.c_double), ("raw", C.c_int)]
 
 
 _lib = None
@@ -72,11 +75,21 @@ def lib() -> C.CDLL:
         L.lt_size.argtypes = [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
         L.lt_view.argtypes = [P, i32, C.POINTER(P), C.POINTER(i64)]
         L.lt_export.argtypes = [P, i32, P, i64, P]
+        L.lt_mlp_create.argtypes = [P, C.POINTER(P)]
+        L.lt_mlp_params.argtypes = [P, P, P, P]
+        L.lt_mlp_features.argtypes = [P, P, i64, i32, P, i64, P, P]
+        L.lt_mlp_grads.argtypes = [P, P, P, i64, P]
+        L.lt_mlp_train_step.argtypes = [P, P, P, i64, C.c_float, P]
+        L.lt_mlp_infer.argtypes = [P, P, i64, P, P]
+        L.lt_flag_mlp.argtypes = [P, P, C.POINTER(FlagParams), P, i64, C.c_float, P, P, P]
+        L.lt_vortex_field.argtypes = [P, C.POINTER(FlagParams), P, P, i64, P]
+        L.lt_mlp_destroy.argtypes = [P]
+        L.lt_mlp_destroy.restype = None
         L.lt_last_error.restype = C.c_char_p
         L.lt_destroy.argtypes = [P]
         L.lt_destroy.restype = None
         for name in EXPORTS:
-            if name not in ("lt_last_error", "lt_destroy"):
+            if name not in ("lt_last_error", "lt_destroy", "lt_mlp_destroy"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -105,7 +118,7 @@ def _dptr(t) -> C.c_void_p:
 
 
 def _flag_params(dim, centres, r_in, r_out, nodes01, lo, length, dist_axes=None,
-                 periodic_dist=False):
+                 periodic_dist=False, raw=False):
     """lt_flag_params and the ctypes arrays it points to (keep them alive)."""
     cen = (C.c_double * (3 * len(centres)))()
     for v, c in enumerate(centres):
@@ -115,7 +128,7 @@ def _flag_params(dim, centres, r_in, r_out, nodes01, lo, length, dist_axes=None,
     lo3 = (C.c_double * 3)(*([float(x) for x in lo] + [0.0] * (3 - len(lo))))
     fp = FlagParams(len(centres), C.cast(cen, C.POINTER(C.c_double)), float(r_in), float(r_out),
                     int(dist_axes or dim), int(bool(periodic_dist)), len(nodes01) - 1,
-                    C.cast(nodes, C.POINTER(C.c_double)), lo3, float(length))
+                    C.cast(nodes, C.POINTER(C.c_double)), lo3, float(length), int(bool(raw)))
     return fp, (cen, nodes)
 
 
@@ -180,13 +193,13 @@ class Tree:
 
     # ---- cycle
     def flag(self, centres, r_in, r_out, nodes01, lo, length, dist_axes=None,
-             periodic_dist=False, out=None):
+             periodic_dist=False, out=None, raw=False):
         torch = _torch()
         n = self.size()
         if out is None:
             out = torch.empty(n, dtype=torch.int8, device="cuda")
         fp, _keep = _flag_params(self.dim, centres, r_in, r_out, nodes01, lo, length, dist_axes,
-                                 periodic_dist)
+                                 periodic_dist, raw)
         _check(lib().lt_flag(self._h, C.byref(fp), _dptr(out), _stream()))
         return out
 
@@ -211,6 +224,35 @@ class Tree:
         offs = (C.c_int64 * (nm + 1))()
         _check(lib().lt_mesh_offsets(self._h, C.cast(offs, C.c_void_p), _stream()))
         return [int(x) for x in offs]
+
+    def vortex_field(self, centres, strengths, nodes01, lo, length, ld=None, out=None):
+        """Isentropic-vortex conserved variables at the solution points."""
+        torch = _torch()
+        n = self.size()
+        p = len(nodes01) - 1
+        npts = (p + 1) ** self.dim
+        nvar = 5 if self.dim == 3 else 4
+        if out is None:
+            out = torch.empty((nvar, npts, ld or n), dtype=torch.float64, device="cuda")
+        fp, keep = _flag_params(self.dim, centres, 0.0, 0.0, nodes01, lo, length)
+        st = (C.c_double * len(strengths))(*[float(a) for a in strengths])
+        _check(lib().lt_vortex_field(self._h, C.byref(fp), C.cast(st, C.c_void_p), _dptr(out),
+                                     out.shape[2], _stream()))
+        return out
+
+    def flag_mlp(self, mlp, u, centres, r_in, r_out, nodes01, lo, length, conf_min=0.9,
+                 dist_axes=None, periodic_dist=False):
+        """Learned flags with the geometric criterion as the fallback; returns
+        (flags, top softmax probability)."""
+        torch = _torch()
+        n = self.size()
+        flags = torch.empty(n, dtype=torch.int8, device="cuda")
+        conf = torch.empty(n, dtype=torch.float32, device="cuda")
+        fp, _keep = _flag_params(self.dim, centres, r_in, r_out, nodes01, lo, length, dist_axes,
+                                 periodic_dist)
+        _check(lib().lt_flag_mlp(self._h, mlp._h, C.byref(fp), _dptr(u), u.shape[2],
+                                 float(conf_min), _dptr(flags), _dptr(conf), _stream()))
+        return flags, conf
 
     def adapt(self, flags):
         torch = _torch()
@@ -271,3 +313,53 @@ class Tree:
 
     def mapping(self):
         return self.export(LT_MAP_SRC), self.export(LT_MAP_KIND)
+
+
+class MLP:
+    """Learned refinement indicator (320 -> 128 -> 64 -> 3) on the device."""
+
+    def __init__(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == MLP_NPARAM
+        h = C.c_void_p()
+        _torch()
+        _check(lib().lt_mlp_create(p.ctypes.data_as(C.c_void_p), C.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.lt_mlp_destroy(h)
+            self._h = None
+
+    def params(self, grads=False):
+        import numpy as np
+        p = np.zeros(MLP_NPARAM, dtype=np.float32)
+        g = np.zeros(MLP_NPARAM, dtype=np.float32) if grads else None
+        _check(lib().lt_mlp_params(self._h, p.ctypes.data_as(C.c_void_p),
+                                   g.ctypes.data_as(C.c_void_p) if grads else None, _stream()))
+        return (p, g) if grads else p
+
+    def features(self, u, rows=None):
+        """u: (5, 64, ld) float64 device tensor -> (n, 320) bfloat16 device tensor."""
+        torch = _torch()
+        n = rows.numel() if rows is not None else u.shape[2]
+        X = torch.empty((n, 320), dtype=torch.bfloat16, device="cuda")
+        r = _dptr(rows.to(torch.int32).contiguous()) if rows is not None else None
+        _check(lib().lt_mlp_features(self._h, _dptr(u), u.shape[2], u.shape[0], r, n, _dptr(X),
+                                     _stream()))
+        return X
+
+    def grads(self, X, labels):
+        _check(lib().lt_mlp_grads(self._h, _dptr(X), _dptr(labels), X.shape[0], _stream()))
+
+    def train_step(self, X, labels, lr):
+        _check(lib().lt_mlp_train_step(self._h, _dptr(X), _dptr(labels), X.shape[0], float(lr),
+                                       _stream()))
+
+    def logits(self, X):
+        torch = _torch()
+        out = torch.empty((X.shape[0], 3), dtype=torch.float32, device="cuda")
+        _check(lib().lt_mlp_infer(self._h, _dptr(X), X.shape[0], _dptr(out), _stream()))
+        return out

@@ -19,7 +19,7 @@ namespace {
 
 struct FlagArgs {
   KeyGeom g;
-  int p, nvort, dist_axes, periodic_dist;
+  int p, nvort, dist_axes, periodic_dist, raw;
   double lo[3], len, dx, rin2, rout2;
   double nodes[LT_MAX_DEGREE + 1];
   double c[LT_MAX_VORTICES][3];
@@ -112,10 +112,12 @@ __global__ __launch_bounds__(256) void k_flag(FlagArgs A0, const FlagArgs* __res
         }
   }
   int f = n_in > n_out ? 1 : (n_in < n_out ? -1 : 0);
-  int lo, hi;
-  depth_limits(g, key, &lo, &hi);
-  if (f == 1 && d >= hi) f = 0;
-  if (f == -1 && d <= lo) f = 0;
+  if (!A.raw) {
+    int lo, hi;
+    depth_limits(g, key, &lo, &hi);
+    if (f == 1 && d >= hi) f = 0;
+    if (f == -1 && d <= lo) f = 0;
+  }
   flags[e] = int8_t(f);
 }
 
@@ -140,6 +142,7 @@ lt_status fill_args(const KeyGeom& g, const lt_flag_params* fp, FlagArgs* out) {
   A.nvort = fp->nvort;
   A.dist_axes = fp->dist_axes;
   A.periodic_dist = fp->periodic_dist ? 1 : 0;
+  A.raw = fp->raw ? 1 : 0;
   for (int a = 0; a < 3; ++a) A.lo[a] = a < g.dim ? fp->lo[a] : 0.0;
   A.len = fp->len;
   A.dx = fp->len / double(uint64_t(1) << g.dmax);

@@ -1,0 +1,572 @@
+// lt_mlp.hip -- learned refinement indicator (form 4 of the cycle).
+//
+// Per element, the FP64 nodal solution (64 Gauss-Legendre points x 5
+// variables for p = 3 in 3D) is projected on the orthonormal tensor Legendre
+// basis (sum-factorised; Gauss-Legendre quadrature is exact for the degree-2p
+// products), each coefficient c becomes f = (log10(|c| + 1e-14) + 7) / 7, and
+// an MLP 320 -> 128 -> 64 -> 3 (ReLU, BF16 weights and activations, FP32
+// accumulation on the matrix cores) gives refine / keep / coarsen scores.
+// Below a softmax confidence threshold the element keeps the geometric flag
+// of Section 5.2.  Training runs on the device through the same GEMM kernel
+// (forward, backward, Adam on FP32 master weights).
+//
+// Also here: the isentropic vortex of Section 5.2 evaluated at the solution
+// points of a tree's leaves (z-extruded vortices superposed on the free
+// stream rho = 1, u = 1, v = w = 0, p = 1; gamma = 1.4, phi = 1/2), used to
+// make synthetic solution fields.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "tree.hpp"
+
+namespace lt {
+namespace {
+
+constexpr double kGamma = 1.4;
+constexpr double kPhi = 0.5;
+
+struct FieldArgs {
+  KeyGeom g;
+  int nvort;
+  double c[LT_MAX_VORTICES][2];
+  double a[LT_MAX_VORTICES];
+  double lo[3], dx;
+  double nodes[LT_MAX_DEGREE + 1];
+};
+
+// One thread per (element, point): conserved variables of the vortex field.
+template <int N1>
+__global__ __launch_bounds__(256) void k_vortex_field(FieldArgs A, const uint64_t* __restrict__ keys,
+                                                      int64_t n, double* __restrict__ u, int64_t ld) {
+  constexpr int NP = N1 * N1 * N1;
+  const int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int npts = A.g.dim == 3 ? NP : N1 * N1;
+  const int64_t e = id / npts;
+  const int i = int(id % npts);
+  if (e >= n) return;
+  const uint64_t key = keys[e];
+  const int d = key_depth(A.g, key);
+  uint64_t x[3];
+  demorton(A.g, key_morton(A.g, key), x);
+  const double s = double(uint64_t(1) << (A.g.dmax - d));
+  const int ix = i % N1, iy = (i / N1) % N1;
+  const double X = A.lo[0] + A.dx * (double(x[0]) + s * A.nodes[ix]);
+  const double Y = A.lo[1] + A.dx * (double(x[1]) + s * A.nodes[iy]);
+  double du = 0.0, dv = 0.0, dT = 0.0;
+  for (int v = 0; v < A.nvort; ++v) {
+    const double ddx = X - A.c[v][0], ddy = Y - A.c[v][1];
+    const double r2 = ddx * ddx + ddy * ddy;
+    const double ex = exp(kPhi * (1.0 - r2));
+    const double al = A.a[v];
+    du += -al / (2.0 * M_PI) * ddy * ex;
+    dv += al / (2.0 * M_PI) * ddx * ex;
+    dT += -al * al * (kGamma - 1.0) / (16.0 * kPhi * kGamma * M_PI * M_PI) * ex * ex;
+  }
+  const double T = 1.0 + dT;
+  const double rho = pow(T, 1.0 / (kGamma - 1.0));
+  const double p = pow(rho, kGamma);
+  const double uu = 1.0 + du, vv = dv;
+  const double E = p / (kGamma - 1.0) + 0.5 * rho * (uu * uu + vv * vv);
+  const double q[5] = {rho, rho * uu, rho * vv, 0.0, E};
+  const int nvar = A.g.dim == 3 ? 5 : 4;
+  for (int var = 0; var < nvar; ++var) {
+    const int slot = A.g.dim == 3 ? var : (var < 3 ? var : 4);  // 2D: rho, rho u, rho v, E
+    u[(int64_t(var) * npts + i) * ld + e] = q[slot];
+  }
+}
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Modal features of 64-point elements: T[n][i] = w_i L~_n(x_i) per axis
+// (orthonormal Legendre at the Gauss-Legendre points), applied on the three
+// axes; f = (log10(|c| + 1e-14) + 7) / 7 written as BF16 row [v*64 + mode]
+// of X (one row of 64*nvar per element; `rows` picks elements, or null for all).
+__global__ __launch_bounds__(256) void k_mlp_features(const double* __restrict__ T4,
+                                                      const double* __restrict__ u, int64_t ld,
+                                                      int nvar, const int32_t* __restrict__ rows,
+                                                      int64_t n, bf16* __restrict__ X) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  if (r >= n) return;
+  const int64_t e = rows ? int64_t(rows[r]) : r;
+  double a[64], b[64];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) a[i] = u[(int64_t(v) * 64 + i) * ld + e];
+  // x axis: b[z][y][n] = sum_i T[n][i] a[z][y][i]
+#pragma unroll
+  for (int zy = 0; zy < 16; ++zy)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) s += T4[m * 4 + i] * a[zy * 4 + i];
+      b[zy * 4 + m] = s;
+    }
+#pragma unroll
+  for (int z = 0; z < 4; ++z)
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s += T4[m * 4 + i] * b[(z * 4 + i) * 4 + x];
+        a[(z * 4 + m) * 4 + x] = s;
+      }
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int yx = 0; yx < 16; ++yx) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) s += T4[m * 4 + i] * a[i * 16 + yx];
+      b[m * 16 + yx] = s;
+    }
+  bf16* out = X + r * int64_t(64 * nvar) + v * 64;
+#pragma unroll
+  for (int k = 0; k < 64; ++k) out[k] = bf16(float((log10(fabs(b[k]) + 1e-14) + 7.0) / 7.0));
+}
+
+// C[m][n] = sum_k A[m][k] Bt[n][k] (+ bias[n]) on BF16 matrix cores with FP32
+// accumulation; both operands are K-contiguous.  Optional: ReLU, an FP32
+// output, a BF16 output.  One wave per 16 x 16 tile; rows/columns/depth past
+// M, N, K read as zero.
+__global__ __launch_bounds__(256) void k_gemm_nt(const bf16* __restrict__ A, int64_t lda,
+                                                 const bf16* __restrict__ Bt, int64_t ldb, int M, int N,
+                                                 int K, const float* __restrict__ bias, int relu,
+                                                 float* __restrict__ C, int64_t ldc,
+                                                 bf16* __restrict__ Cb, int64_t ldcb) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tiles_n = (N + 15) / 16;
+  const int64_t tile = int64_t(blockIdx.x) * 4 + w;
+  const int64_t tiles = int64_t((M + 15) / 16) * tiles_n;
+  if (tile >= tiles) return;
+  const int m0 = int(tile / tiles_n) * 16, n0 = int(tile % tiles_n) * 16;
+  const int r = lane & 15, kq = 8 * (lane >> 4);
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  const int am = m0 + r, bn = n0 + r;
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    bf16x8 a, b;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = k0 + kq + t;
+      a[t] = (am < M && k < K) ? A[int64_t(am) * lda + k] : bf16(0.f);
+      b[t] = (bn < N && k < K) ? Bt[int64_t(bn) * ldb + k] : bf16(0.f);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+  }
+  const int cn = n0 + (lane & 15);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int cm = m0 + 4 * (lane >> 4) + q;
+    if (cm >= M || cn >= N) continue;
+    float val = acc[q] + (bias ? bias[cn] : 0.f);
+    if (relu) val = val > 0.f ? val : 0.f;
+    if (C) C[int64_t(cm) * ldc + cn] = val;
+    if (Cb) Cb[int64_t(cm) * ldcb + cn] = bf16(val);
+  }
+}
+
+// Out[c][r] = In[r][c] (BF16 from FP32 or BF16 sources), R x Cols.
+template <class TIn>
+__global__ void k_transpose(const TIn* __restrict__ in, int64_t ldi, int R, int Cols,
+                            bf16* __restrict__ out, int64_t ldo) {
+  __shared__ float tile[32][33];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+  for (int j = ty; j < 32; j += 8) {
+    const int rr = r0 + j, cc = c0 + tx;
+    tile[j][tx] = (rr < R && cc < Cols) ? float(in[int64_t(rr) * ldi + cc]) : 0.f;
+  }
+  __syncthreads();
+  for (int j = ty; j < 32; j += 8) {
+    const int cc = c0 + j, rr = r0 + tx;
+    if (cc < Cols && rr < R) out[int64_t(cc) * ldo + rr] = bf16(tile[tx][j]);
+  }
+}
+
+// Softmax cross-entropy over 3 classes: dZ = (softmax(Z) - onehot(y)) / B and
+// the per-row loss.
+__global__ void k_xent(const float* __restrict__ Z, const int8_t* __restrict__ y, int B,
+                       float* __restrict__ dZ, float* __restrict__ loss) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const float z0 = Z[3 * b], z1 = Z[3 * b + 1], z2 = Z[3 * b + 2];
+  const float m = fmaxf(z0, fmaxf(z1, z2));
+  const float e0 = expf(z0 - m), e1 = expf(z1 - m), e2 = expf(z2 - m);
+  const float s = e0 + e1 + e2;
+  const int c = min(max(int(y[b]), 0), 2);  // labels outside {0,1,2} clamp
+  const float p[3] = {e0 / s, e1 / s, e2 / s};
+  for (int k = 0; k < 3; ++k) dZ[3 * b + k] = (p[k] - (k == c ? 1.f : 0.f)) / float(B);
+  loss[b] = -logf(p[c]);
+}
+
+// G[r][c] *= (H[r][c] > 0)  (ReLU derivative through the stored activation).
+__global__ void k_relu_mask(float* __restrict__ G, const bf16* __restrict__ H, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n && !(float(H[i]) > 0.f)) G[i] = 0.f;
+}
+
+// Column sums of an R x Cols FP32 array (bias gradients).
+__global__ void k_colsum(const float* __restrict__ G, int R, int Cols, float* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= Cols) return;
+  float s = 0.f;
+  for (int r = 0; r < R; ++r) s += G[int64_t(r) * Cols + c];
+  out[c] = s;
+}
+
+// Adam on FP32 master parameters; refreshes the BF16 copy.
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m1,
+                       float* __restrict__ m2, bf16* __restrict__ wb, int64_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float a = b1 * m1[i] + (1.f - b1) * gi;
+  const float b = b2 * m2[i] + (1.f - b2) * gi * gi;
+  m1[i] = a;
+  m2[i] = b;
+  const float wi = w[i] - lr * (a / c1) / (sqrtf(b / c2) + eps);
+  w[i] = wi;
+  if (wb) wb[i] = bf16(wi);
+}
+
+// Decision: argmax class (0 coarsen, 1 keep, 2 refine) when its softmax
+// probability reaches conf_min, else the geometric flag already in `flags`;
+// then the depth clamps.
+__global__ void k_mlp_decide(KeyGeom g, const uint64_t* __restrict__ keys, const float* __restrict__ Z,
+                             int64_t n, float conf_min, int8_t* __restrict__ flags,
+                             float* __restrict__ conf) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const float z0 = Z[3 * e], z1 = Z[3 * e + 1], z2 = Z[3 * e + 2];
+  const float m = fmaxf(z0, fmaxf(z1, z2));
+  const float e0 = expf(z0 - m), e1 = expf(z1 - m), e2 = expf(z2 - m);
+  const float s = e0 + e1 + e2;
+  int c = 0;
+  float pc = e0;
+  if (e1 > pc) { c = 1; pc = e1; }
+  if (e2 > pc) { c = 2; pc = e2; }
+  pc /= s;
+  if (conf) conf[e] = pc;
+  int f = pc >= conf_min ? c - 1 : int(flags[e]);
+  const uint64_t key = keys[e];
+  const int d = key_depth(g, key);
+  int lo, hi;
+  depth_limits(g, key, &lo, &hi);
+  if (f == 1 && d >= hi) f = 0;
+  if (f == -1 && d <= lo) f = 0;
+  flags[e] = int8_t(f);
+}
+
+inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+}  // namespace
+}  // namespace lt
+
+// ------------------------------------------------------------------- MLP state
+struct lt_mlp_s {
+  static constexpr int kIn = 320, kH1 = 128, kH2 = 64, kOut = 3;
+  int device = 0;
+  // FP32 master parameters, BF16 copies (row-major [out][in]) and transposes
+  float* P = nullptr;   // W1 b1 W2 b2 W3 b3 (FP32, contiguous)
+  float* G = nullptr;   // gradients, same layout
+  float* M1 = nullptr;  // Adam moments
+  float* M2 = nullptr;
+  __bf16* W1 = nullptr; __bf16* W2 = nullptr; __bf16* W3 = nullptr;      // [out][in]
+  __bf16* W1T = nullptr; __bf16* W2T = nullptr; __bf16* W3T = nullptr;   // [in][out]
+  double* T4 = nullptr;  // 4x4 modal matrix (p = 3)
+  int64_t step = 0;
+  // scratch sized for `cap` rows
+  int64_t cap = 0;
+  __bf16 *H1 = nullptr, *H2 = nullptr, *XT = nullptr, *H1T = nullptr, *H2T = nullptr;
+  __bf16 *D1T = nullptr, *D2T = nullptr, *D3T = nullptr, *D2b = nullptr, *D3b = nullptr;
+  float *Z3 = nullptr, *D1 = nullptr, *D2 = nullptr, *D3 = nullptr, *loss = nullptr;
+  __bf16* X = nullptr;  // features for lt_flag_mlp
+  int64_t xcap = 0;
+
+  static constexpr int64_t off_W1 = 0, off_b1 = off_W1 + int64_t(kH1) * kIn;
+  static constexpr int64_t off_W2 = off_b1 + kH1, off_b2 = off_W2 + int64_t(kH2) * kH1;
+  static constexpr int64_t off_W3 = off_b2 + kH2, off_b3 = off_W3 + int64_t(kOut) * kH2;
+  static constexpr int64_t nparam = off_b3 + kOut;
+};
+
+namespace lt {
+namespace {
+
+lt_status mlp_scratch(lt_mlp_s* m, int64_t B) {
+  if (B <= m->cap) return LT_OK;
+  auto fr = [](void* p) { if (p) (void)hipFree(p); };
+  fr(m->H1); fr(m->H2); fr(m->XT); fr(m->H1T); fr(m->H2T); fr(m->D1T); fr(m->D2T); fr(m->D3T);
+  fr(m->D2b); fr(m->D3b); fr(m->Z3); fr(m->D1); fr(m->D2); fr(m->D3); fr(m->loss);
+  const int64_t c = B + B / 4 + 64;
+  hipError_t e = hipSuccess;
+  auto al = [&](void** p, size_t bytes) { if (e == hipSuccess) e = hipMalloc(p, bytes); };
+  al((void**)&m->H1, c * 128 * 2); al((void**)&m->H2, c * 64 * 2); al((void**)&m->XT, c * 320 * 2);
+  al((void**)&m->H1T, c * 128 * 2); al((void**)&m->H2T, c * 64 * 2); al((void**)&m->D1T, c * 128 * 2);
+  al((void**)&m->D2T, c * 64 * 2); al((void**)&m->D3T, c * 3 * 2); al((void**)&m->D2b, c * 64 * 2);
+  al((void**)&m->D3b, c * 3 * 2); al((void**)&m->Z3, c * 3 * 4); al((void**)&m->D1, c * 128 * 4);
+  al((void**)&m->D2, c * 64 * 4); al((void**)&m->D3, c * 3 * 4); al((void**)&m->loss, c * 4);
+  if (e != hipSuccess) {
+    m->cap = 0;
+    return fail(LT_ERR_OOM, "MLP scratch allocation failed");
+  }
+  m->cap = c;
+  return LT_OK;
+}
+
+hipError_t gemm(const __bf16* A, int64_t lda, const __bf16* Bt, int64_t ldb, int M, int N, int K,
+                const float* bias, int relu, float* C, int64_t ldc, __bf16* Cb, int64_t ldcb,
+                hipStream_t s) {
+  const int64_t tiles = int64_t((M + 15) / 16) * ((N + 15) / 16);
+  k_gemm_nt<<<nblk(tiles, 4), 256, 0, s>>>(A, lda, Bt, ldb, M, N, K, bias, relu, C, ldc, Cb, ldcb);
+  return hipGetLastError();
+}
+
+template <class TIn>
+hipError_t transpose(const TIn* in, int64_t ldi, int R, int Cols, __bf16* out, int64_t ldo,
+                     hipStream_t s) {
+  dim3 grid(nblk(Cols, 32), nblk(R, 32));
+  k_transpose<TIn><<<grid, 256, 0, s>>>(in, ldi, R, Cols, out, ldo);
+  return hipGetLastError();
+}
+
+// BF16 copies and transposes of the weights from the FP32 masters.
+lt_status mlp_refresh(lt_mlp_s* m, hipStream_t s) {
+  const float* P = m->P;
+  hipError_t e = transpose(P + lt_mlp_s::off_W1, 320, 128, 320, m->W1T, 128, s);
+  if (e == hipSuccess) e = transpose(P + lt_mlp_s::off_W2, 128, 64, 128, m->W2T, 64, s);
+  if (e == hipSuccess) e = transpose(P + lt_mlp_s::off_W3, 64, 3, 64, m->W3T, 3, s);
+  if (e == hipSuccess) e = transpose(m->W1T, 128, 320, 128, m->W1, 320, s);
+  if (e == hipSuccess) e = transpose(m->W2T, 64, 128, 64, m->W2, 128, s);
+  if (e == hipSuccess) e = transpose(m->W3T, 3, 64, 3, m->W3, 64, s);
+  if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("MLP refresh: ") + hipGetErrorString(e));
+  return LT_OK;
+}
+
+// Forward pass on B rows of X (BF16 [B][320]); logits in Z3 (FP32 [B][3]).
+lt_status mlp_forward(lt_mlp_s* m, const __bf16* X, int64_t B, float* Z3, hipStream_t s) {
+  const float* P = m->P;
+  hipError_t e = gemm(X, 320, m->W1, 320, int(B), 128, 320, P + lt_mlp_s::off_b1, 1, nullptr, 0, m->H1, 128, s);
+  if (e == hipSuccess)
+    e = gemm(m->H1, 128, m->W2, 128, int(B), 64, 128, P + lt_mlp_s::off_b2, 1, nullptr, 0, m->H2, 64, s);
+  if (e == hipSuccess)
+    e = gemm(m->H2, 64, m->W3, 64, int(B), 3, 64, P + lt_mlp_s::off_b3, 0, Z3, 3, nullptr, 0, s);
+  if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("MLP forward: ") + hipGetErrorString(e));
+  return LT_OK;
+}
+
+// Forward + backward on one mini-batch; gradients (FP32) in m->G.
+lt_status mlp_backward(lt_mlp_s* m, const __bf16* X, const int8_t* y, int64_t B, hipStream_t s) {
+  LT_TRY_STATUS(mlp_scratch(m, B));
+  LT_TRY_STATUS(mlp_forward(m, X, B, m->Z3, s));
+  float* G = m->G;
+  const int b = int(B);
+  k_xent<<<nblk(B, 256), 256, 0, s>>>(m->Z3, y, b, m->D3, m->loss);
+  hipError_t e = hipGetLastError();
+  // layer 3: gW3 = D3^T H2, gb3 = colsum D3, D2 = (D3 W3) * [H2 > 0]
+  if (e == hipSuccess) e = transpose(m->D3, 3, b, 3, m->D3T, b, s);
+  if (e == hipSuccess) e = transpose(m->H2, 64, b, 64, m->H2T, b, s);
+  if (e == hipSuccess) e = gemm(m->D3T, b, m->H2T, b, 3, 64, b, nullptr, 0, G + lt_mlp_s::off_W3, 64, nullptr, 0, s);
+  if (e == hipSuccess) { k_colsum<<<1, 64, 0, s>>>(m->D3, b, 3, G + lt_mlp_s::off_b3); e = hipGetLastError(); }
+  if (e == hipSuccess) e = transpose(m->D3T, b, 3, b, m->D3b, 3, s);
+  if (e == hipSuccess) e = gemm(m->D3b, 3, m->W3T, 3, b, 64, 3, nullptr, 0, m->D2, 64, nullptr, 0, s);
+  if (e == hipSuccess) { k_relu_mask<<<nblk(B * 64, 256), 256, 0, s>>>(m->D2, m->H2, B * 64); e = hipGetLastError(); }
+  // layer 2: gW2 = D2^T H1, gb2, D1 = (D2 W2) * [H1 > 0]
+  if (e == hipSuccess) e = transpose(m->D2, 64, b, 64, m->D2T, b, s);
+  if (e == hipSuccess) e = transpose(m->H1, 128, b, 128, m->H1T, b, s);
+  if (e == hipSuccess) e = gemm(m->D2T, b, m->H1T, b, 64, 128, b, nullptr, 0, G + lt_mlp_s::off_W2, 128, nullptr, 0, s);
+  if (e == hipSuccess) { k_colsum<<<1, 64, 0, s>>>(m->D2, b, 64, G + lt_mlp_s::off_b2); e = hipGetLastError(); }
+  if (e == hipSuccess) e = transpose(m->D2T, b, 64, b, m->D2b, 64, s);
+  if (e == hipSuccess) e = gemm(m->D2b, 64, m->W2T, 64, b, 128, 64, nullptr, 0, m->D1, 128, nullptr, 0, s);
+  if (e == hipSuccess) { k_relu_mask<<<nblk(B * 128, 256), 256, 0, s>>>(m->D1, m->H1, B * 128); e = hipGetLastError(); }
+  // layer 1: gW1 = D1^T X, gb1
+  if (e == hipSuccess) e = transpose(m->D1, 128, b, 128, m->D1T, b, s);
+  if (e == hipSuccess) e = transpose(X, 320, b, 320, m->XT, b, s);
+  if (e == hipSuccess) e = gemm(m->D1T, b, m->XT, b, 128, 320, b, nullptr, 0, G + lt_mlp_s::off_W1, 320, nullptr, 0, s);
+  if (e == hipSuccess) { k_colsum<<<2, 64, 0, s>>>(m->D1, b, 128, G + lt_mlp_s::off_b1); e = hipGetLastError(); }
+  if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("MLP backward: ") + hipGetErrorString(e));
+  return LT_OK;
+}
+
+}  // namespace
+}  // namespace lt
+
+using namespace lt;
+
+extern "C" {
+
+lt_status lt_mlp_create(const float* params, lt_mlp* out) {
+  if (!params || !out) return fail(LT_ERR_ARG, "NULL argument");
+  lt_mlp m = new lt_mlp_s;
+  hipError_t e = hipGetDevice(&m->device);
+  const size_t np = size_t(lt_mlp_s::nparam);
+  auto al = [&](void** p, size_t bytes) { if (e == hipSuccess) e = hipMalloc(p, bytes); };
+  al((void**)&m->P, np * 4); al((void**)&m->G, np * 4); al((void**)&m->M1, np * 4); al((void**)&m->M2, np * 4);
+  al((void**)&m->W1, 128 * 320 * 2); al((void**)&m->W2, 64 * 128 * 2); al((void**)&m->W3, 3 * 64 * 2);
+  al((void**)&m->W1T, 128 * 320 * 2); al((void**)&m->W2T, 64 * 128 * 2); al((void**)&m->W3T, 3 * 64 * 2);
+  al((void**)&m->T4, 16 * 8);
+  if (e == hipSuccess) e = hipMemcpy(m->P, params, np * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(m->M1, 0, np * 4);
+  if (e == hipSuccess) e = hipMemset(m->M2, 0, np * 4);
+  if (e == hipSuccess) {
+    // modal matrix for p = 3: T[n][i] = w_i sqrt((2n+1)/2) P_n(x_i), Gauss-Legendre x_i
+    const double a = std::sqrt(3.0 / 7.0 - 2.0 / 7.0 * std::sqrt(6.0 / 5.0));
+    const double b = std::sqrt(3.0 / 7.0 + 2.0 / 7.0 * std::sqrt(6.0 / 5.0));
+    const double x[4] = {-b, -a, a, b};
+    const double wa = (18.0 + std::sqrt(30.0)) / 36.0, wb = (18.0 - std::sqrt(30.0)) / 36.0;
+    const double w[4] = {wb, wa, wa, wb};
+    double T[16];
+    for (int i = 0; i < 4; ++i) {
+      double p0 = 1.0, p1 = x[i];
+      const double pn[4] = {p0, p1, (3.0 * x[i] * p1 - p0) / 2.0,
+                            (5.0 * x[i] * ((3.0 * x[i] * p1 - p0) / 2.0) - 2.0 * p1) / 3.0};
+      for (int n = 0; n < 4; ++n) T[n * 4 + i] = w[i] * std::sqrt((2.0 * n + 1.0) / 2.0) * pn[n];
+    }
+    e = hipMemcpy(m->T4, T, sizeof(T), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    lt_mlp_destroy(m);
+    return fail(LT_ERR_HIP, std::string("MLP create: ") + hipGetErrorString(e));
+  }
+  lt_status st = mlp_refresh(m, nullptr);
+  if (st == LT_OK && hipDeviceSynchronize() != hipSuccess) st = fail(LT_ERR_HIP, "MLP create sync");
+  if (st != LT_OK) {
+    lt_mlp_destroy(m);
+    return st;
+  }
+  *out = m;
+  return LT_OK;
+}
+
+lt_status lt_mlp_params(lt_mlp m, float* params, float* grads, void* stream) {
+  if (!m) return fail(LT_ERR_ARG, "NULL model");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t bytes = size_t(lt_mlp_s::nparam) * 4;
+  if (params) LT_TRY_STATUS(hipMemcpyAsync(params, m->P, bytes, hipMemcpyDeviceToHost, s) == hipSuccess ? LT_OK : fail(LT_ERR_HIP, "copy"));
+  if (grads) LT_TRY_STATUS(hipMemcpyAsync(grads, m->G, bytes, hipMemcpyDeviceToHost, s) == hipSuccess ? LT_OK : fail(LT_ERR_HIP, "copy"));
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(LT_ERR_HIP, "sync");
+  return LT_OK;
+}
+
+lt_status lt_mlp_features(lt_mlp m, const double* u, int64_t ld, int nvar, const int32_t* rows,
+                          int64_t n, void* X, void* stream) {
+  if (!m || !u || !X || nvar != 5) return fail(LT_ERR_ARG, "features need 5 variables of 64 points");
+  if (n == 0) return LT_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  k_mlp_features<<<dim3(nblk(n, 256), unsigned(nvar)), 256, 0, s>>>(m->T4, u, ld, nvar, rows, n,
+                                                                     static_cast<__bf16*>(X));
+  if (hipGetLastError() != hipSuccess) return fail(LT_ERR_HIP, "features launch");
+  return LT_OK;
+}
+
+lt_status lt_mlp_grads(lt_mlp m, const void* X, const int8_t* labels, int64_t B, void* stream) {
+  if (!m || !X || !labels || B < 1 || B > (int64_t(1) << 21)) return fail(LT_ERR_ARG, "batch size must be in [1, 2^21]");
+  return mlp_backward(m, static_cast<const __bf16*>(X), labels, B, static_cast<hipStream_t>(stream));
+}
+
+lt_status lt_mlp_train_step(lt_mlp m, const void* X, const int8_t* labels, int64_t B, float lr,
+                            void* stream) {
+  LT_TRY_STATUS(lt_mlp_grads(m, X, labels, B, stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  m->step++;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - std::pow(b1, float(m->step)), c2 = 1.f - std::pow(b2, float(m->step));
+  k_adam<<<nblk(lt_mlp_s::nparam, 256), 256, 0, s>>>(m->P, m->G, m->M1, m->M2, nullptr,
+                                                     lt_mlp_s::nparam, lr, b1, b2, 1e-8f, c1, c2);
+  if (hipGetLastError() != hipSuccess) return fail(LT_ERR_HIP, "adam launch");
+  return mlp_refresh(m, s);
+}
+
+lt_status lt_mlp_infer(lt_mlp m, const void* X, int64_t n, float* logits, void* stream) {
+  if (!m || !X || !logits) return fail(LT_ERR_ARG, "NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int64_t b0 = 0; b0 < n; b0 += (int64_t(1) << 20)) {
+    const int64_t B = std::min<int64_t>(n - b0, int64_t(1) << 20);
+    LT_TRY_STATUS(mlp_scratch(m, B));
+    LT_TRY_STATUS(mlp_forward(m, static_cast<const __bf16*>(X) + b0 * 320, B, logits + b0 * 3, s));
+  }
+  return LT_OK;
+}
+
+lt_status lt_flag_mlp(lt_tree t, lt_mlp m, const lt_flag_params* fallback, const double* u, int64_t ld,
+                      float conf_min, int8_t* flags, float* conf, void* stream) {
+  if (!t || !m || !fallback || !u || !flags) return fail(LT_ERR_ARG, "NULL argument");
+  if (t->g.dim != 3) return fail(LT_ERR_ARG, "the learned indicator takes 3D p = 3 elements");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n = t->n_cur;
+  if (ld < n) return fail(LT_ERR_ARG, "leading dimension too small");
+  LT_TRY_STATUS(launch_flag(t->g, fallback, t->kbuf[t->cur], n, flags, s));
+  if (n == 0) return LT_OK;
+  if (m->xcap < n) {
+    if (m->X) (void)hipFree(m->X);
+    m->X = nullptr;
+    m->xcap = 0;
+    if (hipMalloc(&m->X, size_t(n) * 320 * 2) != hipSuccess) return fail(LT_ERR_OOM, "MLP features");
+    m->xcap = n;
+  }
+  float* Z = nullptr;
+  if (hipMallocAsync((void**)&Z, size_t(n) * 3 * 4, s) != hipSuccess) return fail(LT_ERR_OOM, "MLP logits");
+  lt_status st = lt_mlp_features(m, u, ld, 5, nullptr, n, m->X, stream);
+  if (st == LT_OK) st = lt_mlp_infer(m, m->X, n, Z, stream);
+  if (st == LT_OK) {
+    k_mlp_decide<<<nblk(n, 256), 256, 0, s>>>(t->g, t->kbuf[t->cur], Z, n, conf_min, flags, conf);
+    if (hipGetLastError() != hipSuccess) st = fail(LT_ERR_HIP, "decide launch");
+  }
+  (void)hipFreeAsync(Z, s);
+  return st;
+}
+
+lt_status lt_vortex_field(lt_tree t, const lt_flag_params* where, const double* strength, double* u,
+                          int64_t ld, void* stream) {
+  if (!t || !where || !strength || !u || !where->centre || !where->nodes01)
+    return fail(LT_ERR_ARG, "NULL argument");
+  if (where->nvort < 1 || where->nvort > LT_MAX_VORTICES) return fail(LT_ERR_ARG, "bad vortex count");
+  if (where->p < 0 || where->p > 3) return fail(LT_ERR_ARG, "vortex field supports p <= 3");
+  if (ld < t->n_cur) return fail(LT_ERR_ARG, "leading dimension too small");
+  FieldArgs A{};
+  A.g = t->g;
+  A.nvort = where->nvort;
+  for (int v = 0; v < where->nvort; ++v) {
+    A.c[v][0] = where->centre[3 * v];
+    A.c[v][1] = where->centre[3 * v + 1];
+    A.a[v] = strength[v];
+  }
+  for (int a = 0; a < 3; ++a) A.lo[a] = where->lo[a];
+  A.dx = where->len / double(uint64_t(1) << t->g.dmax);
+  for (int k = 0; k <= where->p; ++k) A.nodes[k] = where->nodes01[k];
+  const int n1 = where->p + 1;
+  const int64_t npts = t->g.dim == 3 ? int64_t(n1) * n1 * n1 : int64_t(n1) * n1;
+  const int64_t total = t->n_cur * npts;
+  if (total == 0) return LT_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const unsigned blocks = nblk(total, 256);
+  switch (n1) {
+    case 1: k_vortex_field<1><<<blocks, 256, 0, s>>>(A, t->kbuf[t->cur], t->n_cur, u, ld); break;
+    case 2: k_vortex_field<2><<<blocks, 256, 0, s>>>(A, t->kbuf[t->cur], t->n_cur, u, ld); break;
+    case 3: k_vortex_field<3><<<blocks, 256, 0, s>>>(A, t->kbuf[t->cur], t->n_cur, u, ld); break;
+    default: k_vortex_field<4><<<blocks, 256, 0, s>>>(A, t->kbuf[t->cur], t->n_cur, u, ld); break;
+  }
+  if (hipGetLastError() != hipSuccess) return fail(LT_ERR_HIP, "vortex field launch");
+  return LT_OK;
+}
+
+void lt_mlp_destroy(lt_mlp m) {
+  if (!m) return;
+  (void)hipDeviceSynchronize();
+  void* ptrs[] = {m->P, m->G, m->M1, m->M2, m->W1, m->W2, m->W3, m->W1T, m->W2T, m->W3T, m->T4,
+                  m->H1, m->H2, m->XT, m->H1T, m->H2T, m->D1T, m->D2T, m->D3T, m->D2b, m->D3b,
+                  m->Z3, m->D1, m->D2, m->D3, m->loss, m->X};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete m;
+}
+
+}  // extern "C"

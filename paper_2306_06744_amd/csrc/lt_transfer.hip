@@ -16,6 +16,7 @@
 // rather than by FP64 throughput.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 
 #include "tree.hpp"
@@ -240,17 +241,53 @@ __device__ inline void xy_pass(const double* Mx, const double* My, const double*
     }
 }
 
-// 3D, interpolation / projection pass.  A block of N waves covers 64
-// consecutive new elements of one variable; lane = element and wave w owns
-// z-slab w (N*N points) of the input and of the output.  The x and y passes
-// act within a slab and stay in registers; the z pass mixes slabs through
-// LDS.  A fused element needs two z rounds (children with z bit 0, then 1),
-// a refined one a single round.  Blocks of copies only leave at once (the
-// same 64 elements are seen by every wave, so the exit is block-uniform).
+// Groups of 64 consecutive new elements that hold any refined or fused
+// element, listed in order by a look-back scan (count 1 per such group).
+__global__ __launch_bounds__(kBlock) void k_group_list(const int8_t* __restrict__ kind, int64_t n,
+                                                       int64_t ngroups, int32_t* __restrict__ list,
+                                                       ScanState st) {
+  const int64_t tile = take_ticket(st);
+  const int64_t base = tile * kTile + int64_t(threadIdx.x) * kItems;
+  bool any[kItems];
+  int64_t local = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t gidx = base + k;
+    any[k] = false;
+    if (gidx >= ngroups) continue;
+    const int64_t j0 = gidx * 64;
+    if (j0 + 64 <= n) {
+      const uint64_t* w8 = reinterpret_cast<const uint64_t*>(kind + j0);
+      uint64_t acc = 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc |= w8[q];
+      any[k] = acc != 0;
+    } else {
+      for (int64_t j = j0; j < n; ++j) any[k] = any[k] || kind[j] != 0;
+    }
+    local += any[k] ? 1 : 0;
+  }
+  int64_t blk;
+  const int64_t thr = block_exclusive(local, &blk);
+  int64_t o = tile_prefix(st, tile, blk) + thr;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k)
+    if (any[k]) list[o++] = int32_t(base + k);
+}
+
+// 3D, interpolation / projection pass.  A block of N waves takes listed
+// groups of 64 consecutive new elements of one variable (grid-stride over the
+// device-side list); lane = element and wave w owns z-slab w (N*N points) of
+// the input and of the output.  The x and y passes act within a slab and stay
+// in registers; the z pass mixes slabs through LDS.  A fused element needs two
+// z rounds (children with z bit 0, then 1), a refined one a single round.
+// Copy elements are left to the copy pass.
 template <int N>
 __global__ __launch_bounds__(64 * N) void k_interp3(const double* __restrict__ ops,
                                                     const int32_t* __restrict__ src,
                                                     const int8_t* __restrict__ kind, int64_t n,
+                                                    const int32_t* __restrict__ groups,
+                                                    const int64_t* __restrict__ ngroups,
                                                     const double* __restrict__ uo, int64_t ldo,
                                                     double* __restrict__ un, int64_t ldn) {
   constexpr int NN = N * N;
@@ -258,82 +295,97 @@ __global__ __launch_bounds__(64 * N) void k_interp3(const double* __restrict__ o
   __shared__ double T[N][NN][64];
   __shared__ double M[4][NN];  // A_0, A_1, P_0, P_1
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t j = int64_t(blockIdx.x) * 64 + lane;
-  const int kd = j < n ? int(kind[j]) : 0;
-  if (__ballot(kd != 0) == 0) return;
-  const int rounds = __ballot(kd < 0) != 0 ? 2 : 1;
+  const int64_t ng = *ngroups;
+  if (int64_t(blockIdx.x) >= ng) return;
   for (int i = threadIdx.x; i < 4 * NN; i += blockDim.x) M[i / NN][i % NN] = ops[i];
   const int v = blockIdx.y;
   const double* U = uo + int64_t(v) * NP * ldo + int64_t(w) * NN * ldo;
-  const int64_t s = kd != 0 ? int64_t(src[j]) : 0;
-  const int c = kd > 0 ? kd - 1 : 0;
-  double acc[NN];
-#pragma unroll
-  for (int r = 0; r < NN; ++r) acc[r] = 0.0;
   __syncthreads();
-  for (int rz = 0; rz < rounds; ++rz) {
-    double sl[NN];
+  for (int64_t gi = blockIdx.x; gi < ng; gi += gridDim.x) {
+    const int64_t j = int64_t(groups[gi]) * 64 + lane;
+    const int kd = j < n ? int(kind[j]) : 0;
+    const int rounds = __ballot(kd < 0) != 0 ? 2 : 1;
+    const int64_t s = kd != 0 ? int64_t(src[j]) : 0;
+    const int c = kd > 0 ? kd - 1 : 0;
+    double acc[NN];
 #pragma unroll
-    for (int r = 0; r < NN; ++r) sl[r] = 0.0;
-    if (kd > 0) {
-      if (rz == 0) {
-        double in[NN];
+    for (int r = 0; r < NN; ++r) acc[r] = 0.0;
+    for (int rz = 0; rz < rounds; ++rz) {
+      double sl[NN];
 #pragma unroll
-        for (int r = 0; r < NN; ++r) in[r] = U[int64_t(r) * ldo + s];
-        xy_pass<N>(M[c & 1], M[(c >> 1) & 1], in, sl);
-      }
-    } else if (kd < 0) {
+      for (int r = 0; r < NN; ++r) sl[r] = 0.0;
+      if (kd > 0) {
+        if (rz == 0) {
+          double in[NN];
+#pragma unroll
+          for (int r = 0; r < NN; ++r) in[r] = U[int64_t(r) * ldo + s];
+          xy_pass<N>(M[c & 1], M[(c >> 1) & 1], in, sl);
+        }
+      } else if (kd < 0) {
 #pragma unroll 1
-      for (int cc = 0; cc < 4; ++cc) {
-        const int child = cc + 4 * rz;
-        double in[NN], t[NN];
+        for (int cc = 0; cc < 4; ++cc) {
+          const int child = cc + 4 * rz;
+          double in[NN], t[NN];
 #pragma unroll
-        for (int r = 0; r < NN; ++r) in[r] = U[int64_t(r) * ldo + s + child];
-        xy_pass<N>(M[2 + (cc & 1)], M[2 + (cc >> 1)], in, t);
+          for (int r = 0; r < NN; ++r) in[r] = U[int64_t(r) * ldo + s + child];
+          xy_pass<N>(M[2 + (cc & 1)], M[2 + (cc >> 1)], in, t);
 #pragma unroll
-        for (int r = 0; r < NN; ++r) sl[r] += t[r];
+          for (int r = 0; r < NN; ++r) sl[r] += t[r];
+        }
       }
+#pragma unroll
+      for (int r = 0; r < NN; ++r) T[w][r][lane] = sl[r];
+      __syncthreads();
+      if (kd > 0 && rz == 0) {
+        const double* Mz = M[(c >> 2) & 1] + w * N;
+#pragma unroll
+        for (int r = 0; r < NN; ++r) {
+          double a = 0.0;
+#pragma unroll
+          for (int k = 0; k < N; ++k) a += Mz[k] * T[k][r][lane];
+          acc[r] = a;
+        }
+      } else if (kd < 0) {
+        const double* Mz = M[2 + rz] + w * N;
+#pragma unroll
+        for (int r = 0; r < NN; ++r) {
+          double a = 0.0;
+#pragma unroll
+          for (int k = 0; k < N; ++k) a += Mz[k] * T[k][r][lane];
+          acc[r] += a;
+        }
+      }
+      __syncthreads();
     }
+    if (kd != 0) {
+      double* O = un + int64_t(v) * NP * ldn + int64_t(w) * NN * ldn + j;
 #pragma unroll
-    for (int r = 0; r < NN; ++r) T[w][r][lane] = sl[r];
-    __syncthreads();
-    if (kd > 0 && rz == 0) {
-      const double* Mz = M[(c >> 2) & 1] + w * N;
-#pragma unroll
-      for (int r = 0; r < NN; ++r) {
-        double a = 0.0;
-#pragma unroll
-        for (int k = 0; k < N; ++k) a += Mz[k] * T[k][r][lane];
-        acc[r] = a;
-      }
-    } else if (kd < 0) {
-      const double* Mz = M[2 + rz] + w * N;
-#pragma unroll
-      for (int r = 0; r < NN; ++r) {
-        double a = 0.0;
-#pragma unroll
-        for (int k = 0; k < N; ++k) a += Mz[k] * T[k][r][lane];
-        acc[r] += a;
-      }
+      for (int r = 0; r < NN; ++r) O[int64_t(r) * ldn] = acc[r];
     }
-    __syncthreads();
-  }
-  if (kd != 0) {
-    double* O = un + int64_t(v) * NP * ldn + int64_t(w) * NN * ldn + j;
-#pragma unroll
-    for (int r = 0; r < NN; ++r) O[int64_t(r) * ldn] = acc[r];
   }
 }
 
 template <int DIM, int N>
-hipError_t launch(const double* ops, const int32_t* src, const int8_t* kind, int64_t n, int nvar,
-                  const double* uo, int64_t ldo, double* un, int64_t ldn, hipStream_t s) {
+hipError_t launch(lt_tree_s* t, const double* ops, const int32_t* src, const int8_t* kind, int64_t n,
+                  int nvar, const double* uo, int64_t ldo, double* un, int64_t ldn, hipStream_t s,
+                  lt_status* st_out) {
+  *st_out = LT_OK;
   if constexpr (DIM == 3) {
-    dim3 grid(unsigned((n + 63) / 64), unsigned(nvar));
+    const int64_t ngroups = (n + 63) / 64;
+    const dim3 grid{unsigned(ngroups), unsigned(nvar), 1u};
     k_copy3<N * N * N><<<grid, 256, 0, s>>>(src, kind, n, uo, ldo, un, ldn);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_interp3<N><<<grid, 64 * N, 0, s>>>(ops, src, kind, n, uo, ldo, un, ldn);
+    *st_out = grow(&t->grp_list, &t->grp_cap, ngroups);
+    if (*st_out != LT_OK) return hipSuccess;
+    ScanState st;
+    *st_out = prep_scan(t, ngroups, s, 0, &st);
+    if (*st_out != LT_OK) return hipSuccess;
+    k_group_list<<<unsigned(st.ntiles), kBlock, 0, s>>>(kind, n, ngroups, t->grp_list, st);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 gi{unsigned(std::min<int64_t>(ngroups, 2048)), unsigned(nvar), 1u};
+    k_interp3<N><<<gi, 64 * N, 0, s>>>(ops, src, kind, n, t->grp_list, st.total, uo, ldo, un, ldn);
     return hipGetLastError();
   } else {
     dim3 grid(unsigned((n + 255) / 256), unsigned(nvar));
@@ -360,31 +412,38 @@ lt_status build_transfer_ops(int p, double** ops, hipStream_t stream) {
   return LT_OK;
 }
 
-lt_status launch_transfer(int dim, int p, const double* ops, const int32_t* src, const int8_t* kind,
-                          int64_t n, int nvar, const double* u_old, int64_t ld_old, double* u_new,
-                          int64_t ld_new, hipStream_t s) {
+lt_status launch_transfer(lt_tree_s* t, int p, const double* ops, int nvar, const double* u_old,
+                          int64_t ld_old, double* u_new, int64_t ld_new, hipStream_t s) {
+  const int dim = t->g.dim;
+  const int32_t* src = t->map_src;
+  const int8_t* kind = t->map_kind;
+  const int64_t n = t->n_cur;
   if (n == 0) return LT_OK;
   if (nvar > 65535) return fail(LT_ERR_ARG, "nvar too large");
   hipError_t e = hipErrorInvalidValue;
+  lt_status st = LT_OK;
+#define LT_L(D, NN) e = launch<D, NN>(t, ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s, &st)
   if (dim == 3) {
     switch (p) {
-      case 1: e = launch<3, 2>(ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s); break;
-      case 2: e = launch<3, 3>(ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s); break;
-      case 3: e = launch<3, 4>(ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s); break;
+      case 1: LT_L(3, 2); break;
+      case 2: LT_L(3, 3); break;
+      case 3: LT_L(3, 4); break;
       default: return fail(LT_ERR_ARG, "3D transfer supports p = 1..3");
     }
   } else {
     switch (p) {
-      case 1: e = launch<2, 2>(ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s); break;
-      case 2: e = launch<2, 3>(ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s); break;
-      case 3: e = launch<2, 4>(ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s); break;
-      case 4: e = launch<2, 5>(ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s); break;
-      case 5: e = launch<2, 6>(ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s); break;
-      case 6: e = launch<2, 7>(ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s); break;
-      case 7: e = launch<2, 8>(ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s); break;
+      case 1: LT_L(2, 2); break;
+      case 2: LT_L(2, 3); break;
+      case 3: LT_L(2, 4); break;
+      case 4: LT_L(2, 5); break;
+      case 5: LT_L(2, 6); break;
+      case 6: LT_L(2, 7); break;
+      case 7: LT_L(2, 8); break;
       default: return fail(LT_ERR_ARG, "2D transfer supports p = 1..7");
     }
   }
+#undef LT_L
+  if (st != LT_OK) return st;
   if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("transfer launch: ") + hipGetErrorString(e));
   return LT_OK;
 }

@@ -822,8 +822,7 @@ lt_status lt_transfer(lt_tree t, int p, int nvar, const double* u_old, int64_t l
   if (!t->map_valid) LT_TRY(lt_map(t, stream));
   if (precision == 1) return launch_split_transfer(t, p, nvar, u_old, ld_old, u_new, ld_new, s);
   LT_TRY(build_transfer_ops(p, &t->ops[p], s));
-  return launch_transfer(t->g.dim, p, t->ops[p], t->map_src, t->map_kind, t->n_cur, nvar, u_old,
-                         ld_old, u_new, ld_new, s);
+  return launch_transfer(t, p, t->ops[p], nvar, u_old, ld_old, u_new, ld_new, s);
 }
 
 lt_status lt_size(lt_tree t, int64_t* n_cur, int64_t* n_old, int64_t* n_hang) {
@@ -894,6 +893,7 @@ void lt_destroy(lt_tree t) {
   if (t->split_vec) (void)hipFree(t->split_vec);
   if (t->split_R) (void)hipFree(t->split_R);
   if (t->split_F) (void)hipFree(t->split_F);
+  if (t->grp_list) (void)hipFree(t->grp_list);
   delete t;
 }
 

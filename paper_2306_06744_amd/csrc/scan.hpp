@@ -42,11 +42,16 @@ constexpr uint64_t kStInc = uint64_t(2) << 62;
 constexpr uint64_t kStVal = (uint64_t(1) << 62) - 1;
 constexpr long kSpinLimit = 1L << 20;
 
-__device__ inline uint64_t ld_acquire(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// A status word carries its own value, and no tile reads data written by
+// another tile of the same launch, so the words need device-coherent access
+// but no ordering of other memory: relaxed agent-scope atomics.  (Acquire /
+// release at agent scope would write back or invalidate an XCD's whole L2 on
+// every publish and every poll.)
+__device__ inline uint64_t ld_status(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline void st_release(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ inline void st_status(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Inclusive scan of v across the 64 lanes of a wave.
@@ -96,14 +101,14 @@ __device__ inline int64_t tile_prefix(const ScanState& st, int64_t tile, int64_t
     const int lane = threadIdx.x;
     int64_t excl = 0;
     if (tile == 0) {
-      if (lane == 0) st_release(&st.status[0], kStInc | uint64_t(aggregate));
+      if (lane == 0) st_status(&st.status[0], kStInc | uint64_t(aggregate));
     } else {
-      if (lane == 0) st_release(&st.status[tile], kStAgg | uint64_t(aggregate));
+      if (lane == 0) st_status(&st.status[tile], kStAgg | uint64_t(aggregate));
       int64_t base = tile - 1;
       long spins = 0;
       for (;;) {
         const int64_t idx = base - lane;
-        const uint64_t w = idx >= 0 ? ld_acquire(&st.status[idx]) : (kStInc | 0);
+        const uint64_t w = idx >= 0 ? ld_status(&st.status[idx]) : (kStInc | 0);
         const uint64_t state = w & ~kStVal;
         const unsigned long long ready = __ballot(state != 0);
         const unsigned long long inc = __ballot(state == kStInc);
@@ -125,7 +130,7 @@ __device__ inline int64_t tile_prefix(const ScanState& st, int64_t tile, int64_t
         }
         __builtin_amdgcn_s_sleep(1);
       }
-      if (lane == 0) st_release(&st.status[tile], kStInc | uint64_t(excl + aggregate));
+      if (lane == 0) st_status(&st.status[tile], kStInc | uint64_t(excl + aggregate));
     }
     if (lane == 0) {
       if (tile == st.ntiles - 1) *st.total = excl + aggregate;

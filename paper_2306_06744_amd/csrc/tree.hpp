@@ -83,9 +83,8 @@ lt_status clear_err(lt_tree_s* t, hipStream_t stream);
 lt_status launch_split_transfer(lt_tree_s* t, int p, int nvar, const double* u_old, int64_t ld_old,
                                 double* u_new, int64_t ld_new, hipStream_t s);
 
-lt_status launch_transfer(int dim, int p, const double* ops, const int32_t* src,
-                          const int8_t* kind, int64_t n, int nvar, const double* u_old,
-                          int64_t ld_old, double* u_new, int64_t ld_new, hipStream_t stream);
+lt_status launch_transfer(lt_tree_s* t, int p, const double* ops, int nvar, const double* u_old,
+                          int64_t ld_old, double* u_new, int64_t ld_new, hipStream_t s);
 
 }  // namespace lt
 
@@ -130,4 +129,6 @@ struct lt_tree_s {
   int64_t split_R_cap = 0;
   int32_t* split_F = nullptr;   // fused parents
   int64_t split_F_cap = 0;
+  int32_t* grp_list = nullptr;  // 64-element groups holding refined/fused elements
+  int64_t grp_cap = 0;
 };

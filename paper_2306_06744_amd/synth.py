@@ -94,6 +94,69 @@ def workload_3d_extruded(seed: int = 2000) -> Workload:
                     cycles=10, advect=(0.1, 0.0, 0.0))
 
 
+@dataclass
+class EnsembleMesh:
+    """One mesh of an ensemble: 3D [-5,5]^3, uniform start at level d_min,
+    3D-distance vortex criterion (radii r_in, 1.2 r_in)."""
+    d_min: int
+    d_max: int
+    p: int
+    centres: list
+    strengths: list
+    r_in: float
+
+    @property
+    def r_out(self):
+        return 1.2 * self.r_in
+
+    def centres_at(self, cycle: int) -> list:
+        return [(c[0] + 0.1 * cycle, c[1], c[2]) for c in self.centres]
+
+
+def workload_ensemble(seed: int = 4000, nmesh: int = 64) -> list:
+    """Ensemble of independent 3D meshes: 1-4 vortices each (strength U[3,7],
+    centre U[-3,3]^3), finest level U{6..9}, p U{2,3}, uniform start at level 3.
+    The radius r_in aims each mesh at a log-uniform leaf count in [1e4, 1e6]
+    (refined volume ~ n_vort * 4/3 pi r_in^3 at the finest cell size), clipped
+    to [0.5, 2.0]; the counts reached are measured, not assumed."""
+    g = rng(seed)
+    out = []
+    for _ in range(nmesh):
+        nv = int(g.integers(1, 5))
+        d_max = int(g.integers(6, 10))
+        p = int(g.integers(2, 4))
+        target = 10.0 ** g.uniform(4.0, 6.0)
+        cell = (10.0 / 2 ** d_max) ** 3
+        r = (target * cell / (nv * 4.0 / 3.0 * math.pi)) ** (1.0 / 3.0)
+        r = float(min(max(r, 0.5), 2.0))
+        cen = [tuple(float(x) for x in g.uniform(-3.0, 3.0, size=3)) for _ in range(nv)]
+        st = [float(x) for x in g.uniform(3.0, 7.0, size=nv)]
+        out.append(EnsembleMesh(3, d_max, p, cen, st, r))
+    return out
+
+
+def mlp_init(seed: int) -> np.ndarray:
+    """He-normal initial parameters of the 320 -> 128 -> 64 -> 3 indicator
+    network, flat FP32: W1[128][320], b1[128], W2[64][128], b2[64], W3[3][64], b3[3]."""
+    g = rng(seed)
+    parts = []
+    for n_in, n_out in ((320, 128), (128, 64), (64, 3)):
+        parts.append(g.standard_normal((n_out, n_in)) * math.sqrt(2.0 / n_in))
+        parts.append(np.zeros(n_out))
+    return np.concatenate([p.reshape(-1) for p in parts]).astype(np.float32)
+
+
+def mlp_split(params: np.ndarray):
+    """Flat parameters -> (W1, b1, W2, b2, W3, b3) views ([out][in] weights)."""
+    shapes = [(128, 320), (128,), (64, 128), (64,), (3, 64), (3,)]
+    out, o = [], 0
+    for sh in shapes:
+        k = int(np.prod(sh))
+        out.append(params[o:o + k].reshape(sh))
+        o += k
+    return out
+
+
 def random_flags(seed: int, n: int, p_refine: float = 0.3, p_coarsen: float = 0.4) -> np.ndarray:
     g = rng(seed)
     r = g.random(n)

@@ -1,0 +1,134 @@
+"""GPU: the learned refinement indicator (lt_mlp_*, lt_flag_mlp) and the
+isentropic-vortex field generator (lt_vortex_field) against the FP64
+references in oracle/mlp.py."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as ref
+from paper_2306_06744_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def bf16(a):
+    import torch
+    return torch.as_tensor(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def point_coords(dim, d_max, keys, nodes, lo, length):
+    """Physical coordinates (x, y) of every solution point of every leaf."""
+    n1 = len(nodes)
+    npts = n1 ** dim
+    X = np.zeros((len(keys), npts))
+    Y = np.zeros((len(keys), npts))
+    dx = length / 2 ** d_max
+    for e, k in enumerate(keys):
+        d, a = oracle.decode(dim, d_max, int(k))
+        s = 2 ** (d_max - d)
+        for i in range(npts):
+            ix, iy = i % n1, (i // n1) % n1
+            X[e, i] = lo[0] + dx * (a[0] + s * nodes[ix])
+            Y[e, i] = lo[1] + dx * (a[1] + s * nodes[iy])
+    return X, Y
+
+
+def small_tree():
+    import torch
+    import paper_2306_06744_amd as lt
+    w = synth.workload_3d_extruded(2001)
+    t = lt.Tree.uniform(3, 3, 5)
+    o = oracle.Tree(3, 3, 5)
+    nodes = synth.gl_nodes01(3)
+    for c in range(2):
+        args = (w.centres_at(c), 3.0, 3.6, nodes, w.lo, w.length, 2, False)
+        f = o.flag(*args)
+        t.adapt(torch.from_numpy(f).cuda())
+        o.adapt(f)
+        t.balance()
+        o.balance()
+    assert np.array_equal(t.keys().cpu().numpy().view(np.uint64), o.keys())
+    return t, o, w, nodes
+
+
+def test_vortex_field_matches_reference():
+    t, o, w, nodes = small_tree()
+    cen = [(0.4, -0.3), (-1.5, 2.0)]
+    st = [5.0, 3.5]
+    u = t.vortex_field([(c[0], c[1], 0.0) for c in cen], st, nodes, w.lo, w.length).cpu().numpy()
+    X, Y = point_coords(3, 5, o.keys(), nodes, w.lo, w.length)
+    q = ref.vortex_field(X, Y, cen, st)               # (5, n, 64)
+    exp = np.transpose(q, (0, 2, 1))                  # (5, 64, n)
+    assert np.abs(u - exp).max() <= 1e-13 * np.abs(exp).max()
+
+
+def test_features_match_reference():
+    import torch
+    import paper_2306_06744_amd as lt
+    m = lt.MLP(synth.mlp_init(1))
+    g = np.random.default_rng(5)
+    n = 777
+    u = g.standard_normal((5, 64, n)) * 10.0 ** g.uniform(-9, 1, size=(5, 64, n))
+    Xg = m.features(torch.from_numpy(u).cuda()).float().cpu().numpy().astype(np.float64)
+    coeffs = ref.modal(np.transpose(u, (2, 0, 1)), 3, 3)   # (n, 5, 64)
+    Xr = ref.features(coeffs)
+    # BF16 storage of values of order 1: 2^-8 relative
+    assert np.abs(Xg - Xr).max() <= 2e-2
+    rows = torch.arange(0, n, 3, dtype=torch.int32, device="cuda")
+    Xs = m.features(torch.from_numpy(u).cuda(), rows=rows).float().cpu().numpy()
+    assert np.array_equal(Xs, Xg[::3].astype(np.float32))
+
+
+def test_gradients_match_fp64_reference():
+    import torch
+    import paper_2306_06744_amd as lt
+    params = synth.mlp_init(7)
+    m = lt.MLP(params)
+    g = np.random.default_rng(11)
+    B = 1000
+    X = g.uniform(-1.0, 1.5, size=(B, 320))
+    y = g.integers(0, 3, size=B).astype(np.int8)
+    Xb = torch.from_numpy(X).to(torch.bfloat16).cuda()
+    m.grads(Xb, torch.from_numpy(y).cuda())
+    _, G = m.params(grads=True)
+    W1, b1, W2, b2, W3, b3 = synth.mlp_split(params.astype(np.float64))
+    Xr = bf16(X)
+    _, grads = ref.loss_and_grads(Xr, y.astype(np.int64), bf16(W1).T, b1, bf16(W2).T, b2,
+                                  bf16(W3).T, b3)
+    gW1, gb1, gW2, gb2, gW3, gb3 = grads
+    Gs = synth.mlp_split(G.astype(np.float64))
+    for name, got, exp in (("W1", Gs[0], gW1.T), ("b1", Gs[1], gb1), ("W2", Gs[2], gW2.T),
+                           ("b2", Gs[3], gb2), ("W3", Gs[4], gW3.T), ("b3", Gs[5], gb3)):
+        rel = np.linalg.norm(got - exp) / np.linalg.norm(exp)
+        print(name, rel, flush=True)
+        assert rel <= 1e-2, name
+
+
+def test_training_lowers_loss_and_flags_are_valid():
+    import torch
+    import paper_2306_06744_amd as lt
+    t, o, w, nodes = small_tree()
+    m = lt.MLP(synth.mlp_init(3))
+    cen = [(w.centres[0][0], w.centres[0][1], 0.0)]
+    u = t.vortex_field(cen, [5.0], nodes, w.lo, w.length)
+    raw = t.flag(cen, 3.0, 3.6, nodes, w.lo, w.length, dist_axes=2, raw=True)
+    X = m.features(u)
+    y = (raw.to(torch.int64) + 1).to(torch.int8)
+    n = X.shape[0]
+    def loss():
+        z = m.logits(X).double()
+        return torch.nn.functional.cross_entropy(z, y.long()).item()
+    l0 = loss()
+    for step in range(150):
+        idx = torch.randint(0, n, (512,), device="cuda")
+        m.train_step(X[idx].contiguous(), y[idx].contiguous(), 3e-3)
+    l1 = loss()
+    print("loss", l0, "->", l1, flush=True)
+    assert l1 < 0.7 * l0
+    flags, conf = t.flag_mlp(m, u, cen, 3.0, 3.6, nodes, w.lo, w.length, conf_min=0.9, dist_axes=2)
+    plain = t.flag(cen, 3.0, 3.6, nodes, w.lo, w.length, dist_axes=2)
+    f, p = flags.cpu().numpy(), plain.cpu().numpy()
+    assert set(np.unique(f)) <= {-1, 0, 1}
+    low = conf.cpu().numpy() < 0.9
+    assert np.array_equal(f[low], p[low])       # fallback below the threshold
+    print("disagreement", (f != p).mean(), "fallback", low.mean(), flush=True)

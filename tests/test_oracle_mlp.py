@@ -1,0 +1,86 @@
+"""Pins for the FP64 references of the learned indicator (oracle/mlp.py)."""
+import math
+
+import numpy as np
+import pytest
+from numpy.polynomial import legendre as npleg
+
+from oracle import mlp
+
+
+def test_vortex_closed_forms():
+    a = 5.0
+    rho = mlp.vortex_field(np.array([0.0]), np.array([0.0]), [(0.0, 0.0)], [a])
+    dT = -a * a * 0.4 / (16 * 0.5 * 1.4 * math.pi ** 2) * math.exp(1.0)
+    T = 1 + dT
+    r = T ** 2.5
+    assert abs(rho[0, 0] - r) < 1e-14                 # density on the axis
+    assert abs(rho[1, 0] - r) < 1e-14                 # rho*u = rho (u = 1 on the axis)
+    assert abs(rho[2, 0]) < 1e-15                     # no v on the axis
+    far = mlp.vortex_field(np.array([40.0]), np.array([-30.0]), [(0.0, 0.0)], [a])[:, 0]
+    np.testing.assert_allclose(far, [1.0, 1.0, 0.0, 0.0, 1.0 / 0.4 + 0.5], atol=1e-14)
+
+
+def test_vortex_is_isentropic_and_rotational():
+    g = np.random.default_rng(0)
+    x, y = g.uniform(-4, 4, size=(2, 500))
+    q = mlp.vortex_field(x, y, [(0.3, -0.2), (1.0, 2.0)], [4.0, 6.0])
+    rho = q[0]
+    u, v = q[1] / rho, q[2] / rho
+    p = (q[4] - 0.5 * rho * (u * u + v * v)) * 0.4
+    np.testing.assert_allclose(p / rho ** 1.4, 1.0, rtol=1e-12)
+    # one vortex: the velocity perturbation is tangential with |dv| ~ r e^{phi(1-r^2)}
+    q = mlp.vortex_field(x, y, [(0.0, 0.0)], [5.0])
+    du, dv = q[1] / q[0] - 1.0, q[2] / q[0]
+    np.testing.assert_allclose(du * x + dv * y, 0.0, atol=1e-13)
+    r2 = x * x + y * y
+    # (rho u)/rho - 1 cancels to ~1e-16 absolute where the perturbation is small
+    np.testing.assert_allclose(np.hypot(du, dv), 5 / (2 * math.pi) * np.sqrt(r2) * np.exp(0.5 * (1 - r2)),
+                               rtol=1e-9, atol=1e-14)
+
+
+@pytest.mark.parametrize("dim,p", [(2, 3), (3, 3), (3, 2)])
+def test_modal_exact_and_parseval(dim, p):
+    x, w = np.polynomial.legendre.leggauss(p + 1)
+    n1 = p + 1
+    pts = np.array(np.meshgrid(*([x] * dim), indexing="ij")).reshape(dim, -1)[::-1]  # x fastest
+    W = np.ones(1)
+    for _ in range(dim):
+        W = np.kron(w, W)
+    for k in range(n1 ** dim):
+        kk = [(k // n1 ** a) % n1 for a in range(dim)]
+        val = np.ones(pts.shape[1])
+        for a in range(dim):
+            c = np.zeros(kk[a] + 1)
+            c[kk[a]] = 1.0
+            val *= npleg.legval(pts[a], c) * math.sqrt((2 * kk[a] + 1) / 2.0)
+        cf = mlp.modal(val[None, :], dim, p)[0]
+        e = np.zeros(n1 ** dim)
+        e[k] = 1.0
+        np.testing.assert_allclose(cf, e, atol=1e-13)
+    u = np.random.default_rng(1).standard_normal(n1 ** dim)
+    c = mlp.modal(u[None, :], dim, p)[0]
+    assert abs((c * c).sum() - (W * u * u).sum()) < 1e-12
+
+
+def test_mlp_gradients_match_finite_differences():
+    g = np.random.default_rng(2)
+    B = 7
+    X = g.standard_normal((B, 320))
+    y = g.integers(0, 3, size=B)
+    params = [g.standard_normal((320, 128)) * 0.05, g.standard_normal(128) * 0.1,
+              g.standard_normal((128, 64)) * 0.1, g.standard_normal(64) * 0.1,
+              g.standard_normal((64, 3)) * 0.1, g.standard_normal(3) * 0.1]
+    loss, grads = mlp.loss_and_grads(X, y, *params)
+    h = 1e-6
+    for pi, (P, G) in enumerate(zip(params, grads)):
+        flat = P.reshape(-1)
+        for idx in g.choice(flat.size, size=min(12, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp, _ = mlp.loss_and_grads(X, y, *params)
+            flat[idx] = old - h
+            lm, _ = mlp.loss_and_grads(X, y, *params)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - G.reshape(-1)[idx]) <= 1e-6 * max(1.0, abs(fd)), (pi, idx)
