@@ -145,6 +145,26 @@ def ensemble_variant(lt, torch, synth, seed, nvar=5, warm=8):
     return out
 
 
+def plain_copy_gbs(torch, stream, nbytes, reps=5):
+    """Rate of a plain contiguous device-to-device copy moving the same bytes
+    (nbytes read + nbytes written): the practical ceiling of a copy-bound
+    kernel on this GPU, reported beside the roofline."""
+    n = max(1, nbytes // 8)
+    a = torch.empty(n, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for _ in range(reps):
+        b.copy_(a)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    del a, b
+    return 2 * n * 8 / (ms * 1e-3) / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,6 +251,7 @@ def main():
     total_new = sum(s[1] for s in sizes)
     tr_bytes = [E * n_old + (E + 5) * n_new for n_old, n_new, _ in sizes]
     achieved = sum(tr_bytes) / (sum(tr_ms) * 1e-3) / 1e9
+    copy_ceiling = plain_copy_gbs(torch, stream, sum(tr_bytes) // (2 * len(tr_bytes)))
     cyc_bytes = sum(cycle_bytes(w.dim, E, *s) for s in sizes)
     variants = {}
     if not args.plain_only:
@@ -274,6 +295,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
+            "plain_copy_GBs": copy_ceiling,
         },
         "variants": variants,
     }

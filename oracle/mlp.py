@@ -15,7 +15,9 @@ TEST INFRASTRUCTURE ONLY (imported by tests/ and the benchmark's checks).
     the degree-2p products, so this is the exact projection).
   * features: log10(|c| + 1e-14) per mode and variable, scaled (f + 7) / 7.
   * MLP 320 -> 128 -> 64 -> 3 with ReLU, softmax cross-entropy, and its
-    gradients written out by hand (checked against finite differences).
+    gradients written out by hand (checked against finite differences); an
+    optional storage map on the hidden activations models a network that
+    keeps them in a narrower format.
 """
 from __future__ import annotations
 
@@ -89,12 +91,17 @@ def relu(x):
     return np.maximum(x, 0.0)
 
 
-def forward(X, W1, b1, W2, b2, W3, b3):
-    """X: (B, 320).  Returns logits and the cache for backward."""
+def forward(X, W1, b1, W2, b2, W3, b3, store=None):
+    """X: (B, 320).  Returns logits and the cache for backward.
+
+    ``store`` (optional) maps each hidden activation to the value the network
+    keeps and passes on (e.g. rounding to a storage format); the backward
+    pass then differentiates through it as the identity."""
+    st = store if store is not None else (lambda a: a)
     z1 = X @ W1 + b1
-    h1 = relu(z1)
+    h1 = st(relu(z1))
     z2 = h1 @ W2 + b2
-    h2 = relu(z2)
+    h2 = st(relu(z2))
     z3 = h2 @ W3 + b3
     return z3, (X, z1, h1, z2, h2)
 
@@ -105,9 +112,10 @@ def softmax(z):
     return e / e.sum(axis=1, keepdims=True)
 
 
-def loss_and_grads(X, y, W1, b1, W2, b2, W3, b3):
-    """Mean softmax cross-entropy over the batch and its gradients."""
-    z3, (X, z1, h1, z2, h2) = forward(X, W1, b1, W2, b2, W3, b3)
+def loss_and_grads(X, y, W1, b1, W2, b2, W3, b3, store=None):
+    """Mean softmax cross-entropy over the batch and its gradients (``store``
+    as in forward)."""
+    z3, (X, z1, h1, z2, h2) = forward(X, W1, b1, W2, b2, W3, b3, store)
     P = softmax(z3)
     B = X.shape[0]
     loss = -np.mean(np.log(P[np.arange(B), y]))

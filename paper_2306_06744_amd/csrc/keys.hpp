@@ -217,6 +217,43 @@ __device__ inline int64_t last_le_near(const uint64_t* __restrict__ keys, int64_
   return lo;
 }
 
+// Radix directory over a sorted key array: bucket c covers the keys
+// [c << shift, (c + 1) << shift), and d[c] is the index of the last key
+// <= c << shift (-1 if none), for c = 0 .. nb; d[nb] = n - 1.  The leaf
+// holding a probe then lies in [d[c], d[c + 1]] for c = probe >> shift, so a
+// search reads two adjacent words and bisects a range of a few leaves
+// instead of walking the whole array.
+struct KeyDir {
+  const int32_t* d;
+  int shift;
+  int64_t nb;
+};
+
+// Last index with keys[i] <= probe (-1 if none), through the directory.
+__device__ inline int64_t dir_last_le(const uint64_t* __restrict__ keys, int64_t n, const KeyDir& D,
+                                      uint64_t probe) {
+  const uint64_t c = probe >> D.shift;
+  int64_t lo, hi;
+  if (c >= uint64_t(D.nb)) {
+    lo = D.d[D.nb];
+    hi = n;
+  } else {
+    lo = D.d[c];
+    hi = int64_t(D.d[c + 1]) + 1;
+  }
+  // keep every probe inside [0, n) whatever the directory holds
+  lo = lo < -1 ? -1 : (lo > n - 1 ? n - 1 : lo);
+  hi = hi > n ? n : (hi < lo + 1 ? lo + 1 : hi);
+  while (hi - lo > 1) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (keys[mid] <= probe)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
 // First index with keys[i] >= probe (n if none).
 __device__ inline int64_t lower_bound(const uint64_t* __restrict__ keys, int64_t n, uint64_t probe) {
   int64_t lo = 0, hi = n;

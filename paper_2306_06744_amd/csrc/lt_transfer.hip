@@ -189,31 +189,73 @@ __global__ __launch_bounds__(256) void k_transfer(const double* __restrict__ ops
   for (int i = 0; i < NP; ++i) O[i * ldn + j] = acc[i];
 }
 
-// 3D, copy pass.  A block of 4 waves covers 64 consecutive new elements of one
-// variable; lane = element, and the waves stride over the point rows, so each
-// lane keeps NP/4 independent loads in flight.  Only copy elements do work.
-template <int NP>
+// Blocks are dealt to the XCDs round-robin (block b to XCD b % 8); this
+// permutation gives each XCD one contiguous run of chunks, so the cache lines
+// two neighbouring chunks share are fetched into one L2 only.
+__device__ inline int64_t xcd_chunk(int64_t b, int64_t nblocks) {
+  const int64_t q = nblocks >> 3, r = nblocks & 7;
+  const int64_t x = b & 7, k = b >> 3;
+  return x * q + (x < r ? x : r) + k;
+}
+
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
+
+// 3D, copy pass.  A block of 4 waves covers 64 * EPL consecutive new elements
+// of one variable; each lane owns EPL consecutive elements, and the waves
+// stride over the point rows, so each lane keeps NP/4 independent loads in
+// flight.  Two copied elements whose sources are adjacent move as one 16-byte
+// access; the output is written with streaming (non-temporal) stores.
+template <int NP, int EPL>
 __global__ __launch_bounds__(256) void k_copy3(const int32_t* __restrict__ src,
                                                const int8_t* __restrict__ kind, int64_t n,
                                                const double* __restrict__ uo, int64_t ldo,
                                                double* __restrict__ un, int64_t ldn) {
+  static_assert(EPL == 1 || EPL == 2, "one or two elements per lane");
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t j = int64_t(blockIdx.x) * 64 + lane;
-  if (j >= n || kind[j] != 0) return;
-  const int v = blockIdx.y;
-  const double* U = uo + int64_t(v) * NP * ldo + src[j];
-  double* O = un + int64_t(v) * NP * ldn + j;
-  constexpr int R = (NP + 3) / 4;
-  double t[R];
+  const int64_t j0 = (xcd_chunk(blockIdx.x, gridDim.x) * 64 + lane) * EPL;
+  bool cp[EPL];
+  int64_t sj[EPL];
+  bool any = false;
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int i = w + 4 * r;
-    if (i < NP) t[r] = U[int64_t(i) * ldo];
+  for (int e = 0; e < EPL; ++e) {
+    const int64_t j = j0 + e;
+    cp[e] = j < n && kind[j] == 0;
+    sj[e] = cp[e] ? int64_t(src[j]) : 0;
+    any = any || cp[e];
+  }
+  if (!any) return;
+  const int v = blockIdx.y;
+  const double* U = uo + int64_t(v) * NP * ldo;
+  double* O = un + int64_t(v) * NP * ldn;
+  constexpr int R = (NP + 3) / 4;
+  if (EPL == 2 && cp[0] && cp[EPL - 1] && sj[EPL - 1] == sj[0] + 1) {
+    d2u t[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = w + 4 * r;
+      if (i < NP) t[r] = *reinterpret_cast<const d2u*>(U + int64_t(i) * ldo + sj[0]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = w + 4 * r;
+      if (i < NP) __builtin_nontemporal_store(t[r], reinterpret_cast<d2u*>(O + int64_t(i) * ldn + j0));
+    }
+    return;
   }
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int i = w + 4 * r;
-    if (i < NP) O[int64_t(i) * ldn] = t[r];
+  for (int e = 0; e < EPL; ++e) {
+    if (!cp[e]) continue;
+    double t[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = w + 4 * r;
+      if (i < NP) t[r] = U[int64_t(i) * ldo + sj[e]];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = w + 4 * r;
+      if (i < NP) __builtin_nontemporal_store(t[r], O + int64_t(i) * ldn + j0 + e);
+    }
   }
 }
 
@@ -372,8 +414,8 @@ hipError_t launch(lt_tree_s* t, const double* ops, const int32_t* src, const int
   *st_out = LT_OK;
   if constexpr (DIM == 3) {
     const int64_t ngroups = (n + 63) / 64;
-    const dim3 grid{unsigned(ngroups), unsigned(nvar), 1u};
-    k_copy3<N * N * N><<<grid, 256, 0, s>>>(src, kind, n, uo, ldo, un, ldn);
+    const dim3 grid{unsigned((n + 127) / 128), unsigned(nvar), 1u};
+    k_copy3<N * N * N, 2><<<grid, 256, 0, s>>>(src, kind, n, uo, ldo, un, ldn);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     *st_out = grow(&t->grp_list, &t->grp_cap, ngroups);

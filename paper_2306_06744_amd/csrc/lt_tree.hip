@@ -214,45 +214,83 @@ __global__ __launch_bounds__(kBlock) void k_adapt(KeyGeom g, const uint64_t* __r
 // restricted to face / face+edge neighbours for the weaker balance kinds.
 // Such a leaf gets bit 0 (split); L gets bit 1 (check again next pass).
 // Only leaves with bit 2 (new or re-checked) are examined unless check_all.
+template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_balance_mark(KeyGeom g, const uint64_t* __restrict__ keys,
-                                                         int64_t n, uint32_t* mark, int check_all,
-                                                         DevCtr* ctr) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (!check_all && !(mark[i] & 4u)) return;
-  const uint64_t key = keys[i];
-  const int d = key_depth(g, key);
-  if (d < 2) return;
+                                                         int64_t n, KeyDir D, uint32_t* mark,
+                                                         int check_all, DevCtr* ctr) {
+  // 2^DIM lanes per leaf, lane `sub` (1 .. 2^DIM - 1) probes one searching key.
+  constexpr int SL = 1 << DIM;
+  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t i = tid / SL;
+  const int sub = int(tid % SL);
+  const int lane = threadIdx.x & 63;
+  bool viol = false, fresh = false;
   const int limit = g.balance == 0 ? 1 : (g.balance == 1 ? 2 : 3);
-  uint64_t x[3];
-  demorton(g, key_morton(g, key), x);
-  const uint64_t mhi = key_mesh_bits(g, key) >> g.mb;
-  const uint64_t S = uint64_t(1) << (g.dmax - d + 1);  // parent size
-  uint64_t pa[3];
-  int b[3];
-  for (int a = 0; a < 3; ++a) {
-    pa[a] = x[a] & ~(S - 1);
-    b[a] = int((x[a] >> (g.dmax - d)) & 1);
-  }
-  unsigned long long fresh_marks = 0;
-  bool self = false;
-  const int nc = g.nchild();
-  for (int sub = 1; sub < nc; ++sub) {
-    if (__popc(unsigned(sub)) > limit) continue;
-    uint64_t q[3] = {pa[0], pa[1], pa[2]};
-    bool ok = true;
-    for (int a = 0; a < g.dim; ++a)
-      if ((sub >> a) & 1) ok = ok && shift_coord(g, a, pa[a], b[a] ? int64_t(S) : -int64_t(S), &q[a]);
-    if (!ok) continue;
-    const int64_t j = last_le_near(keys, n, point_key(g, morton(g, q) | mhi), i);
-    if (j >= 0 && key_depth(g, keys[j]) < d - 1) {
-      const uint32_t was = atomicOr(&mark[j], 1u);
-      if (!(was & 1u)) fresh_marks++;
-      self = true;
+  if (i < n && sub != 0 && __popc(unsigned(sub)) <= limit && (check_all || (mark[i] & 4u))) {
+    const uint64_t key = keys[i];
+    const int d = key_depth(g, key);
+    if (d >= 2) {
+      uint64_t x[3];
+      demorton(g, key_morton(g, key), x);
+      const uint64_t mhi = key_mesh_bits(g, key) >> g.mb;
+      const uint64_t S = uint64_t(1) << (g.dmax - d + 1);  // parent size
+      uint64_t q[3] = {0, 0, 0};
+      bool ok = true;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        const uint64_t pa = x[a] & ~(S - 1);
+        q[a] = pa;
+        if ((sub >> a) & 1) {
+          const bool up = (x[a] >> (g.dmax - d)) & 1;
+          ok = ok && shift_coord(g, a, pa, up ? int64_t(S) : -int64_t(S), &q[a]);
+        }
+      }
+      if (ok) {
+        const int64_t j = dir_last_le(keys, n, D, point_key(g, morton(g, q) | mhi));
+        if (j >= 0 && key_depth(g, keys[j]) < d - 1) {
+          const uint32_t was = atomicOr(&mark[j], 1u);
+          fresh = !(was & 1u);
+          viol = true;
+        }
+      }
     }
   }
-  if (self) atomicOr(&mark[i], 2u);
-  if (fresh_marks) atomicAdd(&ctr->nmarked, fresh_marks);
+  const uint64_t vb = __ballot(viol);
+  const uint64_t fb = __ballot(fresh);
+  if (sub == 0 && i < n && ((vb >> lane) & ((uint64_t(1) << SL) - 1))) atomicOr(&mark[i], 2u);
+  if (lane == 0 && fb) atomicAdd(&ctr->nmarked, (unsigned long long)__popcll(fb));
+}
+
+// Radix directory of a sorted key array (see KeyDir): leaf i owns the
+// buckets c with keys[i] <= c << shift < keys[i + 1].  Short spans are
+// written by their own lane, long ones (coarse leaves) by the whole wave.
+__global__ __launch_bounds__(256) void k_build_dir(const uint64_t* __restrict__ keys, int64_t n,
+                                                   int shift, int64_t nb, int32_t* __restrict__ d) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  auto ceil_sh = [shift](uint64_t k) -> int64_t {
+    const uint64_t mask = (uint64_t(1) << shift) - 1;
+    return int64_t(k >> shift) + ((k & mask) ? 1 : 0);
+  };
+  int64_t c0 = 0, c1 = 0;
+  if (i < n) {
+    c0 = ceil_sh(keys[i]);
+    c1 = i + 1 < n ? ceil_sh(keys[i + 1]) : nb + 1;
+    c1 = c1 < nb + 1 ? c1 : nb + 1;
+    c0 = c0 < c1 ? c0 : c1;
+    if (i == 0)
+      for (int64_t c = 0, e = c0; c < e; ++c) d[c] = -1;
+  }
+  const bool big = c1 - c0 > 8;
+  if (!big)
+    for (int64_t c = c0; c < c1; ++c) d[c] = int32_t(i);
+  uint64_t bm = __ballot(big);
+  while (bm) {
+    const int l = __ffsll((unsigned long long)bm) - 1;
+    bm &= bm - 1;
+    const int64_t a = __shfl(c0, l), b = __shfl(c1, l), v = __shfl(i, l);
+    for (int64_t c = a + lane; c < b; c += 64) d[c] = int32_t(v);
+  }
 }
 
 // 2:1 balance, refinement pass: split bit-0 leaves one level, in order.  The
@@ -312,72 +350,92 @@ __global__ __launch_bounds__(kBlock) void k_balance_refine(KeyGeom g, const uint
 // means that leaf holds the whole box; deeper means the box is subdivided and
 // e is the coarse side of a hanging face, whose 2^(dim-1) fine leaves are the
 // box's children on the side facing e.
-__global__ __launch_bounds__(kBlock) void k_connect(KeyGeom g, const uint64_t* __restrict__ keys,
-                                                    int64_t n, int32_t* __restrict__ nbr,
-                                                    int32_t* __restrict__ hang, int64_t cap_rows,
-                                                    ScanState st) {
+//
+// Pass 1: one lane per (leaf, face), 2^DIM lanes per leaf (2D: 4, 3D: 8, two
+// idle); nbr rows are written coalesced and each leaf's hanging faces become
+// a bit mask.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_connect_faces(KeyGeom g, const uint64_t* __restrict__ keys,
+                                                       int64_t n, KeyDir D, int32_t* __restrict__ nbr,
+                                                       uint8_t* __restrict__ hmask) {
+  constexpr int SL = 1 << DIM, NF = 2 * DIM;
+  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t e = tid / SL;
+  const int f = int(tid % SL);
+  const int lane = threadIdx.x & 63;
+  bool hanging = false;
+  if (e < n && f < NF) {
+    const uint64_t key = keys[e];
+    const int d = key_depth(g, key);
+    uint64_t x[3];
+    demorton(g, key_morton(g, key), x);
+    const uint64_t mhi = key_mesh_bits(g, key) >> g.mb;
+    const int64_t sz = int64_t(1) << (g.dmax - d);
+    const int a = f >> 1;
+    uint64_t q[3] = {x[0], x[1], x[2]};
+    int32_t v;
+    if (!shift_coord(g, a, x[a], (f & 1) ? sz : -sz, &q[a])) {
+      v = -2;
+    } else {
+      const int64_t j = dir_last_le(keys, n, D, point_key(g, morton(g, q) | mhi));
+      if (j < 0) {
+        v = -2;  // unreachable for a complete tree (keys[0] has anchor 0)
+      } else if (key_depth(g, keys[j]) <= d) {
+        v = int32_t(j);
+      } else {
+        v = -1;
+        hanging = true;
+      }
+    }
+    nbr[e * NF + f] = v;
+  }
+  const uint64_t hb = __ballot(hanging);
+  if (f == 0 && e < n) hmask[e] = uint8_t((hb >> lane) & ((1u << SL) - 1));
+}
+
+// Pass 2: hanging-face rows in (leaf, face) order: count from the masks,
+// decoupled look-back scan, then each row's 2^(dim-1) fine leaves.
+__global__ __launch_bounds__(kBlock) void k_connect_hang(KeyGeom g, const uint64_t* __restrict__ keys,
+                                                         int64_t n, KeyDir D,
+                                                         const uint8_t* __restrict__ hmask,
+                                                         int32_t* __restrict__ hang, int64_t cap_rows,
+                                                         ScanState st) {
   const int64_t tile = take_ticket(st);
   const int64_t base = tile * kTile + int64_t(threadIdx.x) * kItems;
   const int nf = 2 * g.dim;
   const int nh = 1 << (g.dim - 1);
   const int width = 2 + nh;
-  unsigned hm[kItems];
-  int64_t local = 0;
-#pragma unroll
-  for (int k = 0; k < kItems; ++k) {
-    const int64_t e = base + k;
-    hm[k] = 0;
-    if (e >= n) continue;
-    const uint64_t key = keys[e];
-    const int d = key_depth(g, key);
-    uint64_t x[3];
-    demorton(g, key_morton(g, key), x);
-    const uint64_t mhi = key_mesh_bits(g, key) >> g.mb;
-    const int64_t s = int64_t(1) << (g.dmax - d);
-    for (int f = 0; f < nf; ++f) {
-      const int a = f >> 1;
-      uint64_t q[3] = {x[0], x[1], x[2]};
-      int32_t v;
-      if (!shift_coord(g, a, x[a], (f & 1) ? s : -s, &q[a])) {
-        v = -2;
-      } else {
-        const int64_t j = last_le_near(keys, n, point_key(g, morton(g, q) | mhi), e);
-        if (j < 0) {
-          v = -2;  // unreachable for a complete tree (keys[0] has anchor 0)
-        } else if (key_depth(g, keys[j]) <= d) {
-          v = int32_t(j);
-        } else {
-          v = -1;
-          hm[k] |= 1u << f;
-        }
-      }
-      nbr[e * nf + f] = v;
-    }
-    local += __popc(hm[k]);
+  uint64_t hm8 = 0;  // kItems masks, one byte each
+  if (base + kItems <= n) {
+    hm8 = *reinterpret_cast<const uint64_t*>(hmask + base);
+  } else {
+    for (int k = 0; k < kItems; ++k)
+      if (base + k < n) hm8 |= uint64_t(hmask[base + k]) << (8 * k);
   }
+  const int64_t local = __popcll(hm8);
   int64_t blk;
   const int64_t thr = block_exclusive(local, &blk);
   int64_t o = tile_prefix(st, tile, blk) + thr;
   unsigned err = 0;
-#pragma unroll
-  for (int k = 0; k < kItems; ++k) {
-    if (!hm[k]) continue;
+  for (int k = 0; k < kItems && hm8; ++k) {
+    const unsigned hm = unsigned(hm8 >> (8 * k)) & 0xffu;
+    if (!hm) continue;
     const int64_t e = base + k;
     const uint64_t key = keys[e];
     const int d = key_depth(g, key);
     uint64_t x[3];
     demorton(g, key_morton(g, key), x);
     const uint64_t mhi = key_mesh_bits(g, key) >> g.mb;
-    const int64_t s = int64_t(1) << (g.dmax - d);
+    const int64_t sz = int64_t(1) << (g.dmax - d);
     for (int f = 0; f < nf; ++f) {
-      if (!((hm[k] >> f) & 1u)) continue;
-      if (o >= cap_rows) {  // table too small: the host grows it and runs again
+      if (!((hm >> f) & 1u)) continue;
+      if (o >= cap_rows) {  // table too small: the host grows it and runs this pass again
         o++;
         continue;
       }
       const int a = f >> 1, side = f & 1;
       uint64_t q[3] = {x[0], x[1], x[2]};
-      shift_coord(g, a, x[a], side ? s : -s, &q[a]);
+      shift_coord(g, a, x[a], side ? sz : -sz, &q[a]);
       const uint64_t mq = morton(g, q) | mhi;
       int32_t* row = hang + o * width;
       row[0] = int32_t(e);
@@ -390,7 +448,7 @@ __global__ __launch_bounds__(kBlock) void k_connect(KeyGeom g, const uint64_t* _
           ++j;
         }
         const uint64_t ck = child_key(g, mq, d, c);
-        const int64_t idx = last_le_near(keys, n, ck, e);
+        const int64_t idx = dir_last_le(keys, n, D, ck);
         if (idx < 0 || keys[idx] != ck) {
           err |= ERR_UNBALANCED;
           row[2 + slot] = -1;
@@ -520,9 +578,42 @@ lt_status new_tree(const lt_geom* geom, lt_tree* out) {
 }
 
 void invalidate(lt_tree t) {
+  t->dir_valid = false;
   t->conn_valid = false;
   t->n_hang = -1;
   t->map_valid = false;
+}
+
+// Radix directory of the current keys (see KeyDir): about one bucket per
+// two leaves (2^10 .. 2^24 buckets) over the range the keys can take.
+lt_status ensure_dir(lt_tree t, hipStream_t s, KeyDir* D) {
+  const int64_t n = t->n_cur;
+  if (!t->dir_valid) {
+    int kb = t->g.mesh_shift;
+    if (t->g.nmesh > 1) {
+      int mbits = 0;
+      while ((int64_t(1) << mbits) < t->g.nmesh) ++mbits;
+      kb += mbits;
+    }
+    kb = std::min(kb, 64);
+    int L = 0;
+    while (L < 62 && (int64_t(1) << L) < n) ++L;
+    L = std::max(10, std::min(24, L - 1));
+    L = std::min(L, kb);
+    t->dir_shift = kb - L;
+    t->dir_nb = int64_t(1) << L;
+    LT_TRY(grow(&t->dir, &t->dir_cap, t->dir_nb + 1));
+    if (n > 0) {
+      k_build_dir<<<unsigned(ceil_div(n, 256)), 256, 0, s>>>(t->kbuf[t->cur], n, t->dir_shift,
+                                                             t->dir_nb, t->dir);
+      LT_HIP(hipGetLastError());
+    }
+    t->dir_valid = true;
+  }
+  D->d = t->dir;
+  D->shift = t->dir_shift;
+  D->nb = t->dir_nb;
+  return LT_OK;
 }
 
 lt_status do_map(lt_tree t, hipStream_t stream) {
@@ -745,9 +836,18 @@ lt_status lt_balance(lt_tree t, void* stream) {
   int64_t expect_total = -1;
   for (int pass = 0;; ++pass) {
     if (pass > max_pass) return fail(LT_ERR_INTERNAL, "balance did not converge");
-    k_balance_mark<<<unsigned(ceil_div(t->n_cur, kBlock)), kBlock, 0, s>>>(
-        t->g, t->kbuf[t->cur], t->n_cur, t->mbuf[mi], pass == 0 ? 1 : 0, t->dctr);
-    LT_HIP(hipGetLastError());
+    KeyDir D;
+    LT_TRY(ensure_dir(t, s, &D));
+    if (t->n_cur > 0) {
+      const unsigned blocks = unsigned(ceil_div(t->n_cur * t->g.nchild(), kBlock));
+      if (t->g.dim == 3)
+        k_balance_mark<3><<<blocks, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], t->n_cur, D,
+                                                    t->mbuf[mi], pass == 0 ? 1 : 0, t->dctr);
+      else
+        k_balance_mark<2><<<blocks, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], t->n_cur, D,
+                                                    t->mbuf[mi], pass == 0 ? 1 : 0, t->dctr);
+      LT_HIP(hipGetLastError());
+    }
     LT_TRY(read_ctr(t, s));
     if (t->hctr->err) return fail(LT_ERR_INTERNAL, "device check failed in lt_balance");
     if (expect_total >= 0 && t->hctr->total != expect_total)
@@ -780,13 +880,26 @@ lt_status lt_connect(lt_tree t, void* stream) {
   const int nf = 2 * t->g.dim;
   const int width = 2 + (1 << (t->g.dim - 1));
   LT_TRY(grow(&t->nbr, &t->nbr_cap, n * nf));
-  if (t->hang_cap < 1024) LT_TRY(grow(&t->hang, &t->hang_cap, int64_t(1024) * width));
+  LT_TRY(grow(&t->hmask, &t->hmask_cap, n + kItems));
+  // initial table: one row per 64 leaves (the hanging faces sit on the
+  // refinement fronts, a small fraction of all faces)
+  LT_TRY(grow(&t->hang, &t->hang_cap, std::max<int64_t>(1024, n / 64) * width));
+  KeyDir D;
+  LT_TRY(ensure_dir(t, s, &D));
+  if (n > 0) {
+    const unsigned blocks = unsigned(ceil_div(n * t->g.nchild(), 256));
+    if (t->g.dim == 3)
+      k_connect_faces<3><<<blocks, 256, 0, s>>>(t->g, t->kbuf[t->cur], n, D, t->nbr, t->hmask);
+    else
+      k_connect_faces<2><<<blocks, 256, 0, s>>>(t->g, t->kbuf[t->cur], n, D, t->nbr, t->hmask);
+    LT_HIP(hipGetLastError());
+  }
   for (int attempt = 0; attempt < 2; ++attempt) {
     const int64_t cap_rows = t->hang_cap / width;
     ScanState st;
     LT_TRY(prep_scan(t, n, s, 1, &st));
-    k_connect<<<unsigned(st.ntiles), kBlock, 0, s>>>(t->g, t->kbuf[t->cur], n, t->nbr, t->hang,
-                                                      cap_rows, st);
+    k_connect_hang<<<unsigned(st.ntiles), kBlock, 0, s>>>(t->g, t->kbuf[t->cur], n, D, t->hmask,
+                                                           t->hang, cap_rows, st);
     LT_HIP(hipGetLastError());
     LT_TRY(read_ctr(t, s));
     if (t->hctr->err & ERR_UNBALANCED)
@@ -798,7 +911,7 @@ lt_status lt_connect(lt_tree t, void* stream) {
       t->conn_valid = true;
       return LT_OK;
     }
-    // The hanging-face table overflowed: grow it to the exact size and rerun.
+    // The hanging-face table overflowed: grow it and emit the rows again.
     LT_TRY(grow(&t->hang, &t->hang_cap, rows * width));
   }
   return fail(LT_ERR_INTERNAL, "hanging-face table overflowed twice");
@@ -879,6 +992,8 @@ void lt_destroy(lt_tree t) {
   for (auto& b : t->kbuf) if (b) (void)hipFree(b);
   for (auto& b : t->mbuf) if (b) (void)hipFree(b);
   if (t->nbr) (void)hipFree(t->nbr);
+  if (t->hmask) (void)hipFree(t->hmask);
+  if (t->dir) (void)hipFree(t->dir);
   if (t->hang) (void)hipFree(t->hang);
   if (t->map_src) (void)hipFree(t->map_src);
   if (t->map_kind) (void)hipFree(t->map_kind);

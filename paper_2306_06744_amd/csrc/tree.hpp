@@ -100,8 +100,16 @@ struct lt_tree_s {
   uint32_t* mbuf[2] = {nullptr, nullptr};  // balance marks, ping-pong
   int64_t mcap[2] = {0, 0};
 
+  int32_t* dir = nullptr;       // radix directory of the current keys
+  int64_t dir_cap = 0;
+  int dir_shift = 0;
+  int64_t dir_nb = 0;
+  bool dir_valid = false;
+
   int32_t* nbr = nullptr;
   int64_t nbr_cap = 0;
+  uint8_t* hmask = nullptr;     // per leaf: faces that are the coarse side of a hanging face
+  int64_t hmask_cap = 0;
   int32_t* hang = nullptr;
   int64_t hang_cap = 0;  // rows
   bool conn_valid = false;

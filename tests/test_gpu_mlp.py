@@ -80,6 +80,12 @@ def test_features_match_reference():
 
 
 def test_gradients_match_fp64_reference():
+    """The device network keeps inputs, weights and hidden activations in
+    BF16 and accumulates in FP32.  Against the FP64 network with the same
+    BF16 storage the gradients agree to the rounding of the back-propagated
+    errors (BF16, unit roundoff 2^-8): <= 1e-2 relative L2 per tensor.
+    Against the plain FP64 network (activations unrounded) the gap is bounded
+    by 2^-8 times the cancellation of the batch sum, ||sum |d||x| || / ||g||."""
     import torch
     import paper_2306_06744_amd as lt
     params = synth.mlp_init(7)
@@ -93,15 +99,26 @@ def test_gradients_match_fp64_reference():
     _, G = m.params(grads=True)
     W1, b1, W2, b2, W3, b3 = synth.mlp_split(params.astype(np.float64))
     Xr = bf16(X)
-    _, grads = ref.loss_and_grads(Xr, y.astype(np.int64), bf16(W1).T, b1, bf16(W2).T, b2,
-                                  bf16(W3).T, b3)
-    gW1, gb1, gW2, gb2, gW3, gb3 = grads
+    w = (Xr, y.astype(np.int64), bf16(W1).T, b1, bf16(W2).T, b2, bf16(W3).T, b3)
+    _, grads_st = ref.loss_and_grads(*w, store=bf16)
+    _, grads = ref.loss_and_grads(*w)
+    # cancellation factor of the first layer's batch sum (plain network)
+    _, (_, z1, h1, z2, h2) = ref.forward(*w[:1], *w[2:])
+    P = ref.softmax(h2 @ w[6] + b3)
+    P[np.arange(B), y] -= 1.0
+    d1 = ((P / B) @ w[6].T * (z2 > 0)) @ w[4].T * (z1 > 0)
+    kappa = np.linalg.norm(np.abs(d1).T @ np.abs(Xr)) / np.linalg.norm(grads[0])
     Gs = synth.mlp_split(G.astype(np.float64))
-    for name, got, exp in (("W1", Gs[0], gW1.T), ("b1", Gs[1], gb1), ("W2", Gs[2], gW2.T),
-                           ("b2", Gs[3], gb2), ("W3", Gs[4], gW3.T), ("b3", Gs[5], gb3)):
+    names = ("W1", "b1", "W2", "b2", "W3", "b3")
+    for i, name in enumerate(names):
+        got = Gs[i]
+        exp_st = grads_st[i].T if grads_st[i].ndim == 2 else grads_st[i]
+        exp = grads[i].T if grads[i].ndim == 2 else grads[i]
+        rel_st = np.linalg.norm(got - exp_st) / np.linalg.norm(exp_st)
         rel = np.linalg.norm(got - exp) / np.linalg.norm(exp)
-        print(name, rel, flush=True)
-        assert rel <= 1e-2, name
+        print(name, "vs BF16-storage", rel_st, "vs plain", rel, "kappa", kappa, flush=True)
+        assert rel_st <= 1e-2, name
+        assert rel <= 2.0 ** -8 * kappa, name
 
 
 def test_training_lowers_loss_and_flags_are_valid():

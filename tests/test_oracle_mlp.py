@@ -84,3 +84,33 @@ def test_mlp_gradients_match_finite_differences():
             flat[idx] = old
             fd = (lp - lm) / (2 * h)
             assert abs(fd - G.reshape(-1)[idx]) <= 1e-6 * max(1.0, abs(fd)), (pi, idx)
+
+
+def test_stored_activation_gradients():
+    """With a storage map on the activations: identity gives the plain
+    gradients; with rounding, the last layer's gradients (which do not pass
+    through the map) still match finite differences exactly."""
+    g = np.random.default_rng(3)
+    B = 9
+    X = g.standard_normal((B, 320))
+    y = g.integers(0, 3, size=B)
+    params = [g.standard_normal((320, 128)) * 0.05, g.standard_normal(128) * 0.1,
+              g.standard_normal((128, 64)) * 0.1, g.standard_normal(64) * 0.1,
+              g.standard_normal((64, 3)) * 0.1, g.standard_normal(3) * 0.1]
+    l0, g0 = mlp.loss_and_grads(X, y, *params)
+    l1, g1 = mlp.loss_and_grads(X, y, *params, store=lambda a: a)
+    assert l0 == l1 and all(np.array_equal(a, b) for a, b in zip(g0, g1))
+    rnd = lambda a: np.round(a * 64.0) / 64.0          # a coarse storage grid
+    loss, grads = mlp.loss_and_grads(X, y, *params, store=rnd)
+    assert abs(loss - l0) > 1e-6                        # the map does act
+    h = 1e-6
+    for pi in (4, 5):
+        flat = params[pi].reshape(-1)
+        for idx in range(flat.size):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp, _ = mlp.loss_and_grads(X, y, *params, store=rnd)
+            flat[idx] = old - h
+            lm, _ = mlp.loss_and_grads(X, y, *params, store=rnd)
+            flat[idx] = old
+            assert abs((lp - lm) / (2 * h) - grads[pi].reshape(-1)[idx]) <= 1e-7
