@@ -394,17 +394,14 @@ __global__ __launch_bounds__(256) void k_connect_faces(KeyGeom g, const uint64_t
 }
 
 // Pass 2: hanging-face rows in (leaf, face) order: count from the masks,
-// decoupled look-back scan, then each row's 2^(dim-1) fine leaves.
-__global__ __launch_bounds__(kBlock) void k_connect_hang(KeyGeom g, const uint64_t* __restrict__ keys,
-                                                         int64_t n, KeyDir D,
-                                                         const uint8_t* __restrict__ hmask,
-                                                         int32_t* __restrict__ hang, int64_t cap_rows,
-                                                         ScanState st) {
+// decoupled look-back scan, then each row's leaf and face.
+__global__ __launch_bounds__(kBlock) void k_connect_rows(const uint8_t* __restrict__ hmask, int64_t n,
+                                                         int dim, int32_t* __restrict__ hang,
+                                                         int64_t cap_rows, ScanState st) {
   const int64_t tile = take_ticket(st);
   const int64_t base = tile * kTile + int64_t(threadIdx.x) * kItems;
-  const int nf = 2 * g.dim;
-  const int nh = 1 << (g.dim - 1);
-  const int width = 2 + nh;
+  const int nf = 2 * dim;
+  const int width = 2 + (1 << (dim - 1));
   uint64_t hm8 = 0;  // kItems masks, one byte each
   if (base + kItems <= n) {
     hm8 = *reinterpret_cast<const uint64_t*>(hmask + base);
@@ -412,54 +409,67 @@ __global__ __launch_bounds__(kBlock) void k_connect_hang(KeyGeom g, const uint64
     for (int k = 0; k < kItems; ++k)
       if (base + k < n) hm8 |= uint64_t(hmask[base + k]) << (8 * k);
   }
-  const int64_t local = __popcll(hm8);
   int64_t blk;
-  const int64_t thr = block_exclusive(local, &blk);
+  const int64_t thr = block_exclusive(__popcll(hm8), &blk);
   int64_t o = tile_prefix(st, tile, blk) + thr;
-  unsigned err = 0;
   for (int k = 0; k < kItems && hm8; ++k) {
     const unsigned hm = unsigned(hm8 >> (8 * k)) & 0xffu;
-    if (!hm) continue;
-    const int64_t e = base + k;
-    const uint64_t key = keys[e];
-    const int d = key_depth(g, key);
-    uint64_t x[3];
-    demorton(g, key_morton(g, key), x);
-    const uint64_t mhi = key_mesh_bits(g, key) >> g.mb;
-    const int64_t sz = int64_t(1) << (g.dmax - d);
     for (int f = 0; f < nf; ++f) {
       if (!((hm >> f) & 1u)) continue;
-      if (o >= cap_rows) {  // table too small: the host grows it and runs this pass again
-        o++;
-        continue;
-      }
-      const int a = f >> 1, side = f & 1;
-      uint64_t q[3] = {x[0], x[1], x[2]};
-      shift_coord(g, a, x[a], side ? sz : -sz, &q[a]);
-      const uint64_t mq = morton(g, q) | mhi;
-      int32_t* row = hang + o * width;
-      row[0] = int32_t(e);
-      row[1] = f;
-      for (int slot = 0; slot < nh; ++slot) {
-        int c = (1 - side) << a, j = 0;
-        for (int t = 0; t < g.dim; ++t) {
-          if (t == a) continue;
-          c |= ((slot >> j) & 1) << t;
-          ++j;
-        }
-        const uint64_t ck = child_key(g, mq, d, c);
-        const int64_t idx = dir_last_le(keys, n, D, ck);
-        if (idx < 0 || keys[idx] != ck) {
-          err |= ERR_UNBALANCED;
-          row[2 + slot] = -1;
-        } else {
-          row[2 + slot] = int32_t(idx);
-        }
+      if (o < cap_rows) {  // else the host grows the table and runs this pass again
+        hang[o * width] = int32_t(base + k);
+        hang[o * width + 1] = f;
       }
       o++;
     }
   }
-  if (err) atomicOr(st.err, err);
+}
+
+// Pass 3: one lane per (row, slot): the fine leaf of the hanging face.  Slot
+// bits are the tangential child bits in axis order, lower axis first; the
+// fine leaves are the children of the same-size box on the side facing e.
+__global__ __launch_bounds__(256) void k_connect_fine(KeyGeom g, const uint64_t* __restrict__ keys,
+                                                      int64_t n, KeyDir D, int32_t* __restrict__ hang,
+                                                      const int64_t* total, int64_t cap_rows,
+                                                      unsigned* err) {
+  const int nh = 1 << (g.dim - 1);
+  const int width = 2 + nh;
+  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t r = tid / nh;
+  const int slot = int(tid % nh);
+  const int64_t rows = *total < cap_rows ? *total : cap_rows;  // rows the table holds
+  if (r >= rows) return;
+  int32_t* row = hang + r * width;
+  const int64_t e = row[0];
+  const int f = row[1];
+  if (e < 0 || e >= n || f < 0 || f >= 2 * g.dim) {
+    atomicOr(err, ERR_UNBALANCED);
+    row[2 + slot] = -1;
+    return;
+  }
+  const uint64_t key = keys[e];
+  const int d = key_depth(g, key);
+  uint64_t x[3];
+  demorton(g, key_morton(g, key), x);
+  const uint64_t mhi = key_mesh_bits(g, key) >> g.mb;
+  const int64_t sz = int64_t(1) << (g.dmax - d);
+  const int a = f >> 1, side = f & 1;
+  uint64_t q[3] = {x[0], x[1], x[2]};
+  shift_coord(g, a, x[a], side ? sz : -sz, &q[a]);
+  int c = (1 - side) << a, j = 0;
+  for (int t = 0; t < g.dim; ++t) {
+    if (t == a) continue;
+    c |= ((slot >> j) & 1) << t;
+    ++j;
+  }
+  const uint64_t ck = child_key(g, morton(g, q) | mhi, d, c);
+  const int64_t idx = dir_last_le(keys, n, D, ck);
+  if (idx < 0 || keys[idx] != ck) {
+    atomicOr(err, ERR_UNBALANCED);
+    row[2 + slot] = -1;
+  } else {
+    row[2 + slot] = int32_t(idx);
+  }
 }
 
 // Old -> new mapping (Section 4.2): lower bound of each new key in the old tree.
@@ -894,27 +904,32 @@ lt_status lt_connect(lt_tree t, void* stream) {
       k_connect_faces<2><<<blocks, 256, 0, s>>>(t->g, t->kbuf[t->cur], n, D, t->nbr, t->hmask);
     LT_HIP(hipGetLastError());
   }
-  for (int attempt = 0; attempt < 2; ++attempt) {
+  const int nh = 1 << (t->g.dim - 1);
+  int64_t rows = -1;
+  for (int attempt = 0; attempt < 2 && rows < 0; ++attempt) {
     const int64_t cap_rows = t->hang_cap / width;
     ScanState st;
     LT_TRY(prep_scan(t, n, s, 1, &st));
-    k_connect_hang<<<unsigned(st.ntiles), kBlock, 0, s>>>(t->g, t->kbuf[t->cur], n, D, t->hmask,
-                                                           t->hang, cap_rows, st);
+    k_connect_rows<<<unsigned(st.ntiles), kBlock, 0, s>>>(t->hmask, n, t->g.dim, t->hang, cap_rows,
+                                                           st);
+    LT_HIP(hipGetLastError());
+    // fine leaves of the rows the table holds (the row count stays on the device)
+    k_connect_fine<<<unsigned(ceil_div(cap_rows * nh, 256)), 256, 0, s>>>(
+        t->g, t->kbuf[t->cur], n, D, t->hang, &t->dctr->total, cap_rows, &t->dctr->err);
     LT_HIP(hipGetLastError());
     LT_TRY(read_ctr(t, s));
     if (t->hctr->err & ERR_UNBALANCED)
       return fail(LT_ERR_UNBALANCED, "tree is not 2:1 balanced across a face");
     if (t->hctr->err) return fail(LT_ERR_INTERNAL, "device check failed in lt_connect");
-    const int64_t rows = t->hctr->total;
-    if (rows <= cap_rows) {
-      t->n_hang = rows;
-      t->conn_valid = true;
-      return LT_OK;
-    }
-    // The hanging-face table overflowed: grow it and emit the rows again.
-    LT_TRY(grow(&t->hang, &t->hang_cap, rows * width));
+    if (t->hctr->total <= cap_rows)
+      rows = t->hctr->total;
+    else  // the hanging-face table overflowed: grow it and emit the rows again
+      LT_TRY(grow(&t->hang, &t->hang_cap, t->hctr->total * width));
   }
-  return fail(LT_ERR_INTERNAL, "hanging-face table overflowed twice");
+  if (rows < 0) return fail(LT_ERR_INTERNAL, "hanging-face table overflowed twice");
+  t->n_hang = rows;
+  t->conn_valid = true;
+  return LT_OK;
 }
 
 lt_status lt_map(lt_tree t, void* stream) {
