@@ -185,7 +185,8 @@ lt_status lt_map(lt_tree t, void* stream);
  *                (Gauss-Legendre quadrature mean) equal the FP64 one; copies
  *                are exact.  Needs 64 points per element (dim 3 with p = 3,
  *                or dim 2 with p = 7).  Relative L2 error ~1e-7 against FP64.
- * Other values return LT_ERR_ARG.  Asynchronous (unless the mapping was stale). */
+ * Other values return LT_ERR_ARG, as does nvar * n_p outside [1, 65535].
+ * Asynchronous (unless the mapping was stale). */
 lt_status lt_transfer(lt_tree t, int p, int nvar, const double* u_old, int64_t ld_old,
                       double* u_new, int64_t ld_new, int precision, void* stream);
 

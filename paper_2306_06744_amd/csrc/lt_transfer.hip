@@ -200,62 +200,59 @@ __device__ inline int64_t xcd_chunk(int64_t b, int64_t nblocks) {
 
 typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
 
-// 3D, copy pass.  A block of 4 waves covers 64 * EPL consecutive new elements
-// of one variable; each lane owns EPL consecutive elements, and the waves
-// stride over the point rows, so each lane keeps NP/4 independent loads in
-// flight.  Two copied elements whose sources are adjacent move as one 16-byte
-// access; the output is written with streaming (non-temporal) stores.
-template <int NP, int EPL>
+// Copy runs.  Between the refinement fronts the new elements are copies of
+// consecutive old elements, so src[j] - j is constant over long runs.  A
+// chunk of kCopyChunk new elements that lies inside one such run is "pure":
+// its source offset is one word, and the copy of that chunk needs no
+// per-element map reads.  cdelta[c] = src[j] - j for a pure chunk, else
+// kImpure.
+constexpr int kCopyChunk = 512;
+constexpr int64_t kImpure = INT64_MIN;
+
+__global__ __launch_bounds__(256) void k_copy_chunks(const int32_t* __restrict__ src,
+                                                     const int8_t* __restrict__ kind, int64_t n,
+                                                     int64_t* __restrict__ cdelta) {
+  const int64_t c = blockIdx.x;
+  const int64_t j0 = c * kCopyChunk;
+  const bool head = kind[j0] == 0;
+  const int64_t ref = head ? int64_t(src[j0]) - j0 : 0;
+  bool ok = head;
+#pragma unroll
+  for (int e = 0; e < kCopyChunk / 256; ++e) {
+    const int64_t j = j0 + int64_t(threadIdx.x) * (kCopyChunk / 256) + e;
+    if (j < n) ok = ok && kind[j] == 0 && int64_t(src[j]) - j == ref;
+  }
+  ok = __syncthreads_and(ok);
+  if (threadIdx.x == 0) cdelta[c] = ok ? ref : kImpure;
+}
+
+// 3D, copy pass.  One block moves one point row (variable v, point i) of one
+// chunk: 256 lanes x two elements.  Pure chunks read one offset and move
+// 16-byte pairs like a plain copy; impure chunks read the map per element and
+// move only the copy elements.  Output stores are streaming (non-temporal).
 __global__ __launch_bounds__(256) void k_copy3(const int32_t* __restrict__ src,
                                                const int8_t* __restrict__ kind, int64_t n,
+                                               const int64_t* __restrict__ cdelta,
                                                const double* __restrict__ uo, int64_t ldo,
                                                double* __restrict__ un, int64_t ldn) {
-  static_assert(EPL == 1 || EPL == 2, "one or two elements per lane");
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t j0 = (xcd_chunk(blockIdx.x, gridDim.x) * 64 + lane) * EPL;
-  bool cp[EPL];
-  int64_t sj[EPL];
-  bool any = false;
-#pragma unroll
-  for (int e = 0; e < EPL; ++e) {
-    const int64_t j = j0 + e;
-    cp[e] = j < n && kind[j] == 0;
-    sj[e] = cp[e] ? int64_t(src[j]) : 0;
-    any = any || cp[e];
-  }
-  if (!any) return;
-  const int v = blockIdx.y;
-  const double* U = uo + int64_t(v) * NP * ldo;
-  double* O = un + int64_t(v) * NP * ldn;
-  constexpr int R = (NP + 3) / 4;
-  if (EPL == 2 && cp[0] && cp[EPL - 1] && sj[EPL - 1] == sj[0] + 1) {
-    d2u t[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = w + 4 * r;
-      if (i < NP) t[r] = *reinterpret_cast<const d2u*>(U + int64_t(i) * ldo + sj[0]);
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = w + 4 * r;
-      if (i < NP) __builtin_nontemporal_store(t[r], reinterpret_cast<d2u*>(O + int64_t(i) * ldn + j0));
+  const int64_t c = xcd_chunk(blockIdx.x, gridDim.x);
+  const int64_t j = c * kCopyChunk + int64_t(threadIdx.x) * 2;
+  const double* U = uo + int64_t(blockIdx.y) * ldo;
+  double* O = un + int64_t(blockIdx.y) * ldn;
+  const int64_t dl = cdelta[c];
+  if (dl != kImpure) {
+    if (j + 1 < n) {
+      const d2u t = *reinterpret_cast<const d2u*>(U + j + dl);
+      __builtin_nontemporal_store(t, reinterpret_cast<d2u*>(O + j));
+    } else if (j < n) {
+      __builtin_nontemporal_store(U[j + dl], O + j);
     }
     return;
   }
 #pragma unroll
-  for (int e = 0; e < EPL; ++e) {
-    if (!cp[e]) continue;
-    double t[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = w + 4 * r;
-      if (i < NP) t[r] = U[int64_t(i) * ldo + sj[e]];
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = w + 4 * r;
-      if (i < NP) __builtin_nontemporal_store(t[r], O + int64_t(i) * ldn + j0 + e);
-    }
+  for (int e = 0; e < 2; ++e) {
+    const int64_t jj = j + e;
+    if (jj < n && kind[jj] == 0) __builtin_nontemporal_store(U[src[jj]], O + jj);
   }
 }
 
@@ -414,8 +411,14 @@ hipError_t launch(lt_tree_s* t, const double* ops, const int32_t* src, const int
   *st_out = LT_OK;
   if constexpr (DIM == 3) {
     const int64_t ngroups = (n + 63) / 64;
-    const dim3 grid{unsigned((n + 127) / 128), unsigned(nvar), 1u};
-    k_copy3<N * N * N, 2><<<grid, 256, 0, s>>>(src, kind, n, uo, ldo, un, ldn);
+    if (n > 0) {
+      const int64_t nchunks = (n + kCopyChunk - 1) / kCopyChunk;
+      *st_out = grow(&t->copy_delta, &t->copy_delta_cap, nchunks);
+      if (*st_out != LT_OK) return hipSuccess;
+      k_copy_chunks<<<unsigned(nchunks), 256, 0, s>>>(src, kind, n, t->copy_delta);
+      const dim3 grid{unsigned(nchunks), unsigned(nvar * N * N * N), 1u};
+      k_copy3<<<grid, 256, 0, s>>>(src, kind, n, t->copy_delta, uo, ldo, un, ldn);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     *st_out = grow(&t->grp_list, &t->grp_cap, ngroups);
@@ -461,7 +464,10 @@ lt_status launch_transfer(lt_tree_s* t, int p, const double* ops, int nvar, cons
   const int8_t* kind = t->map_kind;
   const int64_t n = t->n_cur;
   if (n == 0) return LT_OK;
-  if (nvar > 65535) return fail(LT_ERR_ARG, "nvar too large");
+  int64_t npts = 1;
+  for (int a = 0; a < dim; ++a) npts *= p + 1;
+  if (nvar < 1 || int64_t(nvar) * npts > 65535)
+    return fail(LT_ERR_ARG, "nvar * (p+1)^dim must be in [1, 65535]");
   hipError_t e = hipErrorInvalidValue;
   lt_status st = LT_OK;
 #define LT_L(D, NN) e = launch<D, NN>(t, ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s, &st)

@@ -1023,6 +1023,7 @@ void lt_destroy(lt_tree t) {
   if (t->split_vec) (void)hipFree(t->split_vec);
   if (t->split_R) (void)hipFree(t->split_R);
   if (t->split_F) (void)hipFree(t->split_F);
+  if (t->copy_delta) (void)hipFree(t->copy_delta);
   if (t->grp_list) (void)hipFree(t->grp_list);
   delete t;
 }

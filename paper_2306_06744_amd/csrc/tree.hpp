@@ -139,4 +139,6 @@ struct lt_tree_s {
   int64_t split_F_cap = 0;
   int32_t* grp_list = nullptr;  // 64-element groups holding refined/fused elements
   int64_t grp_cap = 0;
+  int64_t* copy_delta = nullptr;  // per copy chunk: source offset of a pure run, or a flag
+  int64_t copy_delta_cap = 0;
 };
