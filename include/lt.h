@@ -255,6 +255,18 @@ lt_status lt_vortex_field(lt_tree t, const lt_flag_params* where, const double* 
                           int64_t ld, void* stream);
 void lt_mlp_destroy(lt_mlp m);
 
+/* Modal-energy indicator (the criterion used when no vortex centre is known,
+ * and the baseline the learned indicator is measured against): the density
+ * u[(0 * n_p + i) * ld + e] (variable 0, device FP64) of each leaf is projected
+ * on the orthonormal tensor Legendre basis at the Gauss-Legendre points;
+ * s = (energy of the modes whose highest per-axis degree is p) / (total
+ * energy).  flag = +1 if log10 s > tau_refine, -1 if log10 s < tau_coarsen,
+ * else 0 (0 for an all-zero density), then the d_max / d_min clamps of
+ * lt_flag.  p in 1..3; tau_coarsen <= tau_refine.  flags: device int8
+ * [n_cur].  Asynchronous. */
+lt_status lt_flag_modal(lt_tree t, int p, const double* u, int64_t ld, double tau_refine,
+                        double tau_coarsen, int8_t* flags, void* stream);
+
 /* Text of the calling thread's last error ("" if none). */
 const char* lt_last_error(void);
 

@@ -1,4 +1,5 @@
-"""FP64 references for the learned refinement indicator.
+"""FP64 references for the learned refinement indicator and for the
+modal-energy indicator it is measured against.
 
 TEST INFRASTRUCTURE ONLY (imported by tests/ and the benchmark's checks).
 
@@ -14,6 +15,13 @@ TEST INFRASTRUCTURE ONLY (imported by tests/ and the benchmark's checks).
     orthonormal tensor Legendre basis (Gauss-Legendre quadrature is exact for
     the degree-2p products, so this is the exact projection).
   * features: log10(|c| + 1e-14) per mode and variable, scaled (f + 7) / 7.
+  * modal_energy / modal_flags: the fraction of the density's modal energy in
+    the modes whose highest per-axis degree is p, and the thresholded flag
+    (+1 above log10 tau_r, -1 below log10 tau_c, else 0; all-zero density 0),
+    with the refinement ceiling / coarsening floor clamps.  The thresholds
+    are calibrated by this project, not taken from the paper (parity of the
+    thresholds themselves is unpinned; the indicator's arithmetic is pinned
+    by closed forms).
   * MLP 320 -> 128 -> 64 -> 3 with ReLU, softmax cross-entropy, and its
     gradients written out by hand (checked against finite differences); an
     optional storage map on the hidden activations models a network that
@@ -131,3 +139,29 @@ def loss_and_grads(X, y, W1, b1, W2, b2, W3, b3, store=None):
     gW1 = X.T @ d1
     gb1 = d1.sum(axis=0)
     return loss, (gW1, gb1, gW2, gb2, gW3, gb3)
+
+
+def modal_energy(rho, dim, p):
+    """rho: (n, (p+1)^dim) nodal density -> (top-mode energy, total energy)."""
+    c = modal(rho, dim, p)
+    n1 = p + 1
+    k = np.arange(n1 ** dim)
+    top = np.zeros(n1 ** dim, dtype=bool)
+    for a in range(dim):
+        top |= (k // n1 ** a) % n1 == p
+    e = c * c
+    return e[:, top].sum(axis=1), e.sum(axis=1)
+
+
+def modal_flags(rho, depth, d_min, d_max, dim, p, tau_r, tau_c):
+    """Modal-energy flags with the depth clamps (depth: (n,) ints)."""
+    top, tot = modal_energy(rho, dim, p)
+    f = np.zeros(len(tot), dtype=np.int8)
+    nz = tot > 0
+    with np.errstate(divide="ignore"):
+        ls = np.where(nz, np.log10(np.where(nz, top, 1.0) / np.where(nz, tot, 1.0)), 0.0)
+    f[nz & (ls > tau_r)] = 1
+    f[nz & (ls < tau_c)] = -1
+    f[(f == 1) & (depth >= d_max)] = 0
+    f[(f == -1) & (depth <= d_min)] = 0
+    return f, ls

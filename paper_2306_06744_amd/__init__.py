@@ -27,7 +27,7 @@ EXPORTS = ["lt_build_uniform", "lt_build", "lt_build_batch", "lt_flag_batch", "l
            "lt_flag", "lt_adapt", "lt_balance", "lt_connect", "lt_map", "lt_transfer", "lt_size",
            "lt_view", "lt_export", "lt_mlp_create", "lt_mlp_params", "lt_mlp_features",
            "lt_mlp_grads", "lt_mlp_train_step", "lt_mlp_infer", "lt_flag_mlp", "lt_vortex_field",
-           "lt_mlp_destroy", "lt_last_error", "lt_destroy"]
+           "lt_flag_modal", "lt_mlp_destroy", "lt_last_error", "lt_destroy"]
 MLP_NPARAM = 128 * 320 + 128 + 64 * 128 + 64 + 3 * 64 + 3
 
 
@@ -83,6 +83,7 @@ def lib() -> C.CDLL:
         L.lt_mlp_infer.argtypes = [P, P, i64, P, P]
         L.lt_flag_mlp.argtypes = [P, P, C.POINTER(FlagParams), P, i64, C.c_float, P, P, P]
         L.lt_vortex_field.argtypes = [P, C.POINTER(FlagParams), P, P, i64, P]
+        L.lt_flag_modal.argtypes = [P, i32, P, i64, C.c_double, C.c_double, P, P]
         L.lt_mlp_destroy.argtypes = [P]
         L.lt_mlp_destroy.restype = None
         L.lt_last_error.restype = C.c_char_p
@@ -253,6 +254,15 @@ class Tree:
         _check(lib().lt_flag_mlp(self._h, mlp._h, C.byref(fp), _dptr(u), u.shape[2],
                                  float(conf_min), _dptr(flags), _dptr(conf), _stream()))
         return flags, conf
+
+    def flag_modal(self, p, u, tau_refine, tau_coarsen, out=None):
+        """Modal-energy flags from the density (variable 0) of u (nvar, n_p, ld)."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.size(), dtype=torch.int8, device="cuda")
+        _check(lib().lt_flag_modal(self._h, int(p), _dptr(u), u.shape[2], float(tau_refine),
+                                   float(tau_coarsen), _dptr(out), _stream()))
+        return out
 
     def adapt(self, flags):
         torch = _torch()

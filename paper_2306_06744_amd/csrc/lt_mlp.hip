@@ -266,7 +266,118 @@ __global__ void k_mlp_decide(KeyGeom g, const uint64_t* __restrict__ keys, const
   flags[e] = int8_t(f);
 }
 
+// Modal-energy indicator: the density's nodal values become coefficients in
+// the orthonormal tensor Legendre basis (matrix T per axis, sum-factorised);
+// s = energy of the modes whose highest per-axis degree is p over the total
+// energy; +1 if log10 s > tau_r, -1 if log10 s < tau_c, else 0 (all-zero
+// density: 0); then the depth clamps.
+struct ModalT {
+  double T[16];  // T[n * N1 + i]
+};
+
+template <int N1, int DIM>
+__global__ __launch_bounds__(256) void k_flag_modal(KeyGeom g, const uint64_t* __restrict__ keys,
+                                                    int64_t n, ModalT M, const double* __restrict__ u,
+                                                    int64_t ld, double tau_r, double tau_c,
+                                                    int8_t* __restrict__ flags) {
+  constexpr int NP = DIM == 3 ? N1 * N1 * N1 : N1 * N1;
+  constexpr int NZ = DIM == 3 ? N1 : 1;
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double a[NP], b[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) a[i] = u[int64_t(i) * ld + e];
+  // x: b[zy][m] = sum_i T[m][i] a[zy][i]
+#pragma unroll
+  for (int zy = 0; zy < NP / N1; ++zy)
+#pragma unroll
+    for (int m = 0; m < N1; ++m) {
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < N1; ++i) acc += M.T[m * N1 + i] * a[zy * N1 + i];
+      b[zy * N1 + m] = acc;
+    }
+  // y: a[z][m][x] = sum_i T[m][i] b[z][i][x]
+#pragma unroll
+  for (int z = 0; z < NZ; ++z)
+#pragma unroll
+    for (int m = 0; m < N1; ++m)
+#pragma unroll
+      for (int x = 0; x < N1; ++x) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < N1; ++i) acc += M.T[m * N1 + i] * b[(z * N1 + i) * N1 + x];
+        a[(z * N1 + m) * N1 + x] = acc;
+      }
+  if (DIM == 3) {
+    // z: b[m][yx] = sum_i T[m][i] a[i][yx]
+#pragma unroll
+    for (int m = 0; m < N1; ++m)
+#pragma unroll
+      for (int yx = 0; yx < N1 * N1; ++yx) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < N1; ++i) acc += M.T[m * N1 + i] * a[i * N1 * N1 + yx];
+        b[m * N1 * N1 + yx] = acc;
+      }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NP; ++k) b[k] = a[k];
+  }
+  double tot = 0.0, top = 0.0;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const int kx = k % N1, ky = (k / N1) % N1, kz = DIM == 3 ? k / (N1 * N1) : 0;
+    const double c2 = b[k] * b[k];
+    tot += c2;
+    if (kx == N1 - 1 || ky == N1 - 1 || kz == N1 - 1) top += c2;
+  }
+  int f = 0;
+  if (tot > 0.0) {
+    const double ls = log10(top / tot);  // -inf when the top modes vanish
+    f = ls > tau_r ? 1 : (ls < tau_c ? -1 : 0);
+  }
+  const uint64_t key = keys[e];
+  const int d = key_depth(g, key);
+  int lo, hi;
+  depth_limits(g, key, &lo, &hi);
+  if (f == 1 && d >= hi) f = 0;
+  if (f == -1 && d <= lo) f = 0;
+  flags[e] = int8_t(f);
+}
+
 inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+// T[n][i] = w_i sqrt((2n+1)/2) P_n(x_i) at the p+1 Gauss-Legendre points
+// (closed forms, p <= 3): the orthonormal-Legendre projection per axis.
+bool modal_matrix(int p, double* T) {
+  double x[4], w[4];
+  if (p == 1) {
+    const double r = 1.0 / std::sqrt(3.0);
+    x[0] = -r; x[1] = r; w[0] = w[1] = 1.0;
+  } else if (p == 2) {
+    const double r = std::sqrt(3.0 / 5.0);
+    x[0] = -r; x[1] = 0.0; x[2] = r;
+    w[0] = w[2] = 5.0 / 9.0; w[1] = 8.0 / 9.0;
+  } else if (p == 3) {
+    const double a = std::sqrt(3.0 / 7.0 - 2.0 / 7.0 * std::sqrt(6.0 / 5.0));
+    const double b = std::sqrt(3.0 / 7.0 + 2.0 / 7.0 * std::sqrt(6.0 / 5.0));
+    x[0] = -b; x[1] = -a; x[2] = a; x[3] = b;
+    w[0] = w[3] = (18.0 - std::sqrt(30.0)) / 36.0;
+    w[1] = w[2] = (18.0 + std::sqrt(30.0)) / 36.0;
+  } else {
+    return false;
+  }
+  const int n1 = p + 1;
+  for (int i = 0; i < n1; ++i) {
+    double P[4];
+    P[0] = 1.0;
+    P[1] = x[i];
+    for (int k = 2; k < n1; ++k) P[k] = ((2.0 * k - 1.0) * x[i] * P[k - 1] - (k - 1.0) * P[k - 2]) / k;
+    for (int m = 0; m < n1; ++m) T[m * n1 + i] = w[i] * std::sqrt((2.0 * m + 1.0) / 2.0) * P[m];
+  }
+  return true;
+}
 
 }  // namespace
 }  // namespace lt
@@ -417,19 +528,8 @@ lt_status lt_mlp_create(const float* params, lt_mlp* out) {
   if (e == hipSuccess) e = hipMemset(m->M1, 0, np * 4);
   if (e == hipSuccess) e = hipMemset(m->M2, 0, np * 4);
   if (e == hipSuccess) {
-    // modal matrix for p = 3: T[n][i] = w_i sqrt((2n+1)/2) P_n(x_i), Gauss-Legendre x_i
-    const double a = std::sqrt(3.0 / 7.0 - 2.0 / 7.0 * std::sqrt(6.0 / 5.0));
-    const double b = std::sqrt(3.0 / 7.0 + 2.0 / 7.0 * std::sqrt(6.0 / 5.0));
-    const double x[4] = {-b, -a, a, b};
-    const double wa = (18.0 + std::sqrt(30.0)) / 36.0, wb = (18.0 - std::sqrt(30.0)) / 36.0;
-    const double w[4] = {wb, wa, wa, wb};
     double T[16];
-    for (int i = 0; i < 4; ++i) {
-      double p0 = 1.0, p1 = x[i];
-      const double pn[4] = {p0, p1, (3.0 * x[i] * p1 - p0) / 2.0,
-                            (5.0 * x[i] * ((3.0 * x[i] * p1 - p0) / 2.0) - 2.0 * p1) / 3.0};
-      for (int n = 0; n < 4; ++n) T[n * 4 + i] = w[i] * std::sqrt((2.0 * n + 1.0) / 2.0) * pn[n];
-    }
+    modal_matrix(3, T);
     e = hipMemcpy(m->T4, T, sizeof(T), hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) {
@@ -555,6 +655,30 @@ lt_status lt_vortex_field(lt_tree t, const lt_flag_params* where, const double* 
     default: k_vortex_field<4><<<blocks, 256, 0, s>>>(A, t->kbuf[t->cur], t->n_cur, u, ld); break;
   }
   if (hipGetLastError() != hipSuccess) return fail(LT_ERR_HIP, "vortex field launch");
+  return LT_OK;
+}
+
+lt_status lt_flag_modal(lt_tree t, int p, const double* u, int64_t ld, double tau_refine,
+                        double tau_coarsen, int8_t* flags, void* stream) {
+  if (!t || !u || !flags) return fail(LT_ERR_ARG, "NULL argument");
+  if (p < 1 || p > 3) return fail(LT_ERR_ARG, "modal indicator supports p = 1..3");
+  if (ld < t->n_cur) return fail(LT_ERR_ARG, "leading dimension too small");
+  if (!(tau_coarsen <= tau_refine)) return fail(LT_ERR_ARG, "need tau_coarsen <= tau_refine");
+  const int64_t n = t->n_cur;
+  if (n == 0) return LT_OK;
+  ModalT M{};
+  modal_matrix(p, M.T);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const unsigned blocks = nblk(n, 256);
+  const uint64_t* keys = t->kbuf[t->cur];
+#define LT_M(N1, D) k_flag_modal<N1, D><<<blocks, 256, 0, s>>>(t->g, keys, n, M, u, ld, tau_refine, tau_coarsen, flags)
+  if (t->g.dim == 3) {
+    if (p == 1) LT_M(2, 3); else if (p == 2) LT_M(3, 3); else LT_M(4, 3);
+  } else {
+    if (p == 1) LT_M(2, 2); else if (p == 2) LT_M(3, 2); else LT_M(4, 2);
+  }
+#undef LT_M
+  if (hipGetLastError() != hipSuccess) return fail(LT_ERR_HIP, "modal indicator launch");
   return LT_OK;
 }
 

@@ -341,24 +341,6 @@ __global__ __launch_bounds__(64 * NC) void k_split_fuse(
   }
 }
 
-// Copy pass for 64-point elements (as in the FP64 path).
-__global__ __launch_bounds__(256) void k_split_copy(const int32_t* __restrict__ src,
-                                                    const int8_t* __restrict__ kind, int64_t n,
-                                                    const double* __restrict__ uo, int64_t ldo,
-                                                    double* __restrict__ un, int64_t ldn) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t j = int64_t(blockIdx.x) * 64 + lane;
-  if (j >= n || kind[j] != 0) return;
-  const int v = blockIdx.y;
-  const double* U = uo + int64_t(v) * kNP * ldo + src[j];
-  double* O = un + int64_t(v) * kNP * ldn + j;
-  double t[kNP / 4];
-#pragma unroll
-  for (int r = 0; r < kNP / 4; ++r) t[r] = U[int64_t(w + 4 * r) * ldo];
-#pragma unroll
-  for (int r = 0; r < kNP / 4; ++r) O[int64_t(w + 4 * r) * ldn] = t[r];
-}
-
 }  // namespace
 
 lt_status launch_split_transfer(lt_tree_s* t, int p, int nvar, const double* u_old, int64_t ld_old,
@@ -366,7 +348,7 @@ lt_status launch_split_transfer(lt_tree_s* t, int p, int nvar, const double* u_o
   const int dim = t->g.dim;
   if (!((dim == 3 && p == 3) || (dim == 2 && p == 7)))
     return fail(LT_ERR_ARG, "split precision needs 64 points per element (3D p=3 or 2D p=7)");
-  if (nvar > 65535) return fail(LT_ERR_ARG, "nvar too large");
+  if (nvar < 1 || int64_t(nvar) * kNP > 65535) return fail(LT_ERR_ARG, "nvar * 64 must be in [1, 65535]");
   const int nc = 1 << dim, n1 = p + 1;
   LT_TRY_STATUS(build_transfer_ops(p, &t->ops[p], s));
   if (!t->split_frags) {
@@ -399,8 +381,7 @@ lt_status launch_split_transfer(lt_tree_s* t, int p, int nvar, const double* u_o
   const bf16x8* fr = static_cast<const bf16x8*>(t->split_frags);
   const bf16x8* fI = fr;
   const bf16x8* fP = fr + size_t(nc) * 3 * kMT * kKS * 64;
-  const dim3 gc(unsigned((n + 63) / 64), unsigned(nvar));
-  k_split_copy<<<gc, 256, 0, s>>>(t->map_src, t->map_kind, n, u_old, ld_old, u_new, ld_new);
+  LT_TRY_STATUS(launch_copy(t, int64_t(nvar) * kNP, u_old, ld_old, u_new, ld_new, s));
   const int64_t max_ref_tiles = (n / nc + kTC - 1) / kTC + 1;
   const int64_t max_fuse_tiles = (n + kTC - 1) / kTC + 1;
   const dim3 gr(unsigned(std::min<int64_t>(max_ref_tiles, 2048)), unsigned(nvar));

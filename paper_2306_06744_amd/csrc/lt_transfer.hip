@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void k_copy_chunks(const int32_t* __restrict__
   if (threadIdx.x == 0) cdelta[c] = ok ? ref : kImpure;
 }
 
-// 3D, copy pass.  One block moves one point row (variable v, point i) of one
+// Copy pass (COPY elements).  One block moves one point row (variable v, point i) of one
 // chunk: 256 lanes x two elements.  Pure chunks read one offset and move
 // 16-byte pairs like a plain copy; impure chunks read the map per element and
 // move only the copy elements.  Output stores are streaming (non-temporal).
@@ -411,16 +411,9 @@ hipError_t launch(lt_tree_s* t, const double* ops, const int32_t* src, const int
   *st_out = LT_OK;
   if constexpr (DIM == 3) {
     const int64_t ngroups = (n + 63) / 64;
-    if (n > 0) {
-      const int64_t nchunks = (n + kCopyChunk - 1) / kCopyChunk;
-      *st_out = grow(&t->copy_delta, &t->copy_delta_cap, nchunks);
-      if (*st_out != LT_OK) return hipSuccess;
-      k_copy_chunks<<<unsigned(nchunks), 256, 0, s>>>(src, kind, n, t->copy_delta);
-      const dim3 grid{unsigned(nchunks), unsigned(nvar * N * N * N), 1u};
-      k_copy3<<<grid, 256, 0, s>>>(src, kind, n, t->copy_delta, uo, ldo, un, ldn);
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    *st_out = launch_copy(t, nvar * N * N * N, uo, ldo, un, ldn, s);
+    if (*st_out != LT_OK) return hipSuccess;
+    hipError_t e = hipSuccess;
     *st_out = grow(&t->grp_list, &t->grp_cap, ngroups);
     if (*st_out != LT_OK) return hipSuccess;
     ScanState st;
@@ -440,6 +433,21 @@ hipError_t launch(lt_tree_s* t, const double* ops, const int32_t* src, const int
 }
 
 }  // namespace
+
+lt_status launch_copy(lt_tree_s* t, int64_t rows, const double* uo, int64_t ldo, double* un,
+                      int64_t ldn, hipStream_t s) {
+  const int64_t n = t->n_cur;
+  if (n == 0) return LT_OK;
+  if (rows < 1 || rows > 65535) return fail(LT_ERR_ARG, "copy pass: rows out of range");
+  const int64_t nchunks = (n + kCopyChunk - 1) / kCopyChunk;
+  LT_TRY_STATUS(grow(&t->copy_delta, &t->copy_delta_cap, nchunks));
+  k_copy_chunks<<<unsigned(nchunks), 256, 0, s>>>(t->map_src, t->map_kind, n, t->copy_delta);
+  const dim3 grid{unsigned(nchunks), unsigned(rows), 1u};
+  k_copy3<<<grid, 256, 0, s>>>(t->map_src, t->map_kind, n, t->copy_delta, uo, ldo, un, ldn);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("copy pass launch: ") + hipGetErrorString(e));
+  return LT_OK;
+}
 
 lt_status build_transfer_ops(int p, double** ops, hipStream_t stream) {
   if (*ops) return LT_OK;

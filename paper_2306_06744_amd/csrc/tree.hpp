@@ -86,6 +86,11 @@ lt_status launch_split_transfer(lt_tree_s* t, int p, int nvar, const double* u_o
 lt_status launch_transfer(lt_tree_s* t, int p, const double* ops, int nvar, const double* u_old,
                           int64_t ld_old, double* u_new, int64_t ld_new, hipStream_t s);
 
+// COPY elements of the current mapping, all `rows` point rows (nvar * n_p);
+// asynchronous.
+lt_status launch_copy(lt_tree_s* t, int64_t rows, const double* uo, int64_t ldo, double* un,
+                      int64_t ldn, hipStream_t s);
+
 }  // namespace lt
 
 struct lt_tree_s {

@@ -114,3 +114,54 @@ def test_stored_activation_gradients():
             lm, _ = mlp.loss_and_grads(X, y, *params, store=rnd)
             flat[idx] = old
             assert abs((lp - lm) / (2 * h) - grads[pi].reshape(-1)[idx]) <= 1e-7
+
+
+def _mode_field(dim, p, degs, scale=1.0):
+    """Nodal values at the Gauss-Legendre points of the tensor orthonormal
+    Legendre mode with per-axis degrees `degs` (x fastest)."""
+    x, _ = np.polynomial.legendre.leggauss(p + 1)
+    n1 = p + 1
+    val = np.ones(n1 ** dim)
+    for i in range(n1 ** dim):
+        for a in range(dim):
+            c = np.zeros(degs[a] + 1)
+            c[degs[a]] = 1.0
+            val[i] *= npleg.legval(x[(i // n1 ** a) % n1], c) * math.sqrt((2 * degs[a] + 1) / 2.0)
+    return scale * val
+
+
+@pytest.mark.parametrize("dim,p", [(2, 2), (3, 3), (3, 1), (2, 3)])
+def test_modal_energy_single_modes(dim, p):
+    """One tensor mode: all its energy is 'top' iff its highest degree is p."""
+    import itertools
+    for degs in itertools.product(range(p + 1), repeat=dim):
+        rho = _mode_field(dim, p, degs, 2.5)[None, :]
+        top, tot = mlp.modal_energy(rho, dim, p)
+        assert abs(tot[0] - 6.25) < 1e-12
+        exp = 6.25 if max(degs) == p else 0.0
+        assert abs(top[0] - exp) < 1e-12, degs
+
+
+def test_modal_energy_two_modes_and_flags():
+    """rho = a L0 + b Ltop: s = b^2 / (a^2 + b^2); thresholds and clamps."""
+    dim, p = 3, 3
+    a0 = _mode_field(dim, p, (0, 0, 0))
+    at = _mode_field(dim, p, (1, 3, 0))
+    rows, s_exp = [], []
+    for a, b in ((1.0, 1e-1), (1.0, 1e-3), (1.0, 1e-6), (2.0, 0.0), (0.0, 0.0)):
+        rows.append(a * a0 + b * at)
+        s_exp.append(b * b / (a * a + b * b) if a or b else None)
+    rho = np.array(rows)
+    top, tot = mlp.modal_energy(rho, dim, p)
+    for k, s in enumerate(s_exp):
+        if s is None:
+            assert tot[k] == 0.0
+        else:
+            # a rounding-level leak (~1e-16) of the mean into the top coefficient
+            assert abs(top[k] / tot[k] - s) <= 1e-12 * s + 1e-20
+    depth = np.array([5, 5, 5, 5, 5])
+    f, ls = mlp.modal_flags(rho, depth, 3, 7, dim, p, tau_r=-4.0, tau_c=-8.0)
+    # log10 s = -2, -6, -12, -inf, (zero field)
+    assert list(f) == [1, 0, -1, -1, 0]
+    f, _ = mlp.modal_flags(rho, np.array([7, 7, 3, 3, 5]), 3, 7, dim, p, tau_r=-4.0, tau_c=-8.0)
+    assert list(f) == [0, 0, 0, 0, 0]                   # clamped at d_max / d_min
