@@ -94,6 +94,21 @@ def workload_3d_extruded(seed: int = 2000) -> Workload:
                     cycles=10, advect=(0.1, 0.0, 0.0))
 
 
+def workload_3d_large(seed: int = 3000) -> Workload:
+    """3D, [-5,5]^3, uniform level 4, max level 10, p=3, 5 variables, four
+    vortices (strength U[3,7], centre U[-3,3]^3, 3D distance).  The radius
+    aims at ~8M leaves: four balls of radius r_in filled at the finest cell
+    size (10/1024)^3 hold 8e6 cells for r_in ~ 0.76; r_out = 1.2 r_in.  Seven
+    adaptations at fixed centres take the uniform level-4 mesh to level 10."""
+    g = rng(seed)
+    cen = [tuple(float(x) for x in g.uniform(-3.0, 3.0, size=3)) for _ in range(4)]
+    st = [float(x) for x in g.uniform(3.0, 7.0, size=4)]
+    cell = (10.0 / 2 ** 10) ** 3
+    r = (8e6 * cell / (4 * 4.0 / 3.0 * math.pi)) ** (1.0 / 3.0)
+    return Workload("3d_large_p3_l4-10", 3, 4, 10, 3, 5, (-5.0, -5.0, -5.0), 10.0, r, 1.2 * r, 3,
+                    False, centres=cen, strengths=st, cycles=7)
+
+
 @dataclass
 class EnsembleMesh:
     """One mesh of an ensemble: 3D [-5,5]^3, uniform start at level d_min,
