@@ -225,6 +225,35 @@ def chosen_cycle(lt, torch, synth, w, nodes, stream, steps, warmup, u, cap, E):
     }
 
 
+TRAFFIC_SUMMARY = os.path.join("profiles", "transfer_3d_p3_l4-7_traffic.md")
+TRANSFER_SOURCES = ("paper_2306_06744_amd/csrc/lt_transfer.hip", "paper_2306_06744_amd/csrc/scan.hpp")
+
+
+def measured_traffic():
+    """HBM bytes per transfer launch from the committed rocprofv3 --pmc
+    summary (FETCH_SIZE and WRITE_SIZE, calibrated by a plain copy), or None
+    when the transfer sources have changed since those counters were taken."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        text = open(os.path.join(here, TRAFFIC_SUMMARY)).read()
+        h = hashlib.sha256()
+        for f in TRANSFER_SOURCES:
+            h.update(open(os.path.join(here, f), "rb").read())
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        for key in ("traffic_bytes_per_launch", "algorithmic_bytes_per_launch", "source_sha256"):
+            if line.startswith(key + ":"):
+                vals[key] = line.split(":", 1)[1].split()[0]
+    if vals.get("source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in vals:
+        return None
+    return {"bytes_per_launch": float(vals["traffic_bytes_per_launch"]),
+            "algorithmic_bytes_per_launch": float(vals["algorithmic_bytes_per_launch"]),
+            "source": TRAFFIC_SUMMARY}
+
+
 def plain_copy_gbs(torch, stream, nbytes, reps=5):
     """Rate of a plain contiguous device-to-device copy moving the same bytes
     (nbytes read + nbytes written): the practical ceiling of a copy-bound
@@ -332,6 +361,7 @@ def main():
     tr_bytes = [E * n_old + (E + 5) * n_new for n_old, n_new, _ in sizes]
     achieved = sum(tr_bytes) / (sum(tr_ms) * 1e-3) / 1e9
     copy_ceiling = plain_copy_gbs(torch, stream, sum(tr_bytes) // (2 * len(tr_bytes)))
+    traffic = measured_traffic()
     cyc_bytes = sum(cycle_bytes(w.dim, E, *s) for s in sizes)
     variants = {}
     if not args.plain_only:
@@ -376,7 +406,10 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic["bytes_per_launch"] if traffic else None,
+            "traffic_per_algorithmic": (traffic["bytes_per_launch"] /
+                                        traffic["algorithmic_bytes_per_launch"]) if traffic else None,
+            "traffic_source": traffic["source"] if traffic else None,
             "plain_copy_GBs": copy_ceiling,
         },
         "variants": variants,

@@ -85,8 +85,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Modal features of 64-point elements: T[n][i] = w_i L~_n(x_i) per axis
 // (orthonormal Legendre at the Gauss-Legendre points), applied on the three
-// axes; f = (log10(|c| + 1e-14) + 7) / 7 written as BF16 row [v*64 + mode]
-// of X (one row of 64*nvar per element; `rows` picks elements, or null for all).
+// axes in place; f = (log10(|c| + 1e-14) + 7) / 7 written as BF16 row
+// [v*64 + mode] of X (one row of 64*nvar per element; `rows` picks elements,
+// or null for all).  The coefficients are FP64; the logarithm is taken in
+// FP32 since its result is stored in BF16.
 __global__ __launch_bounds__(256) void k_mlp_features(const double* __restrict__ T4,
                                                       const double* __restrict__ u, int64_t ld,
                                                       int nvar, const int32_t* __restrict__ rows,
@@ -95,42 +97,38 @@ __global__ __launch_bounds__(256) void k_mlp_features(const double* __restrict__
   const int v = blockIdx.y;
   if (r >= n) return;
   const int64_t e = rows ? int64_t(rows[r]) : r;
-  double a[64], b[64];
+  double T[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) T[i] = T4[i];
+  double a[64];
 #pragma unroll
   for (int i = 0; i < 64; ++i) a[i] = u[(int64_t(v) * 64 + i) * ld + e];
-  // x axis: b[z][y][n] = sum_i T[n][i] a[z][y][i]
+  // one axis at a time, each line of 4 values transformed in place
 #pragma unroll
-  for (int zy = 0; zy < 16; ++zy)
+  for (int axis = 0; axis < 3; ++axis) {
+    const int st = axis == 0 ? 1 : (axis == 1 ? 4 : 16);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      double s = 0.0;
+    for (int line = 0; line < 16; ++line) {
+      // base index of this line: the two other axes' coordinates
+      const int base = axis == 0 ? line * 4 : (axis == 1 ? (line / 4) * 16 + (line % 4) : line);
+      const double x0 = a[base], x1 = a[base + st], x2 = a[base + 2 * st], x3 = a[base + 3 * st];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) s += T4[m * 4 + i] * a[zy * 4 + i];
-      b[zy * 4 + m] = s;
+      for (int m = 0; m < 4; ++m)
+        a[base + m * st] = T[m * 4] * x0 + T[m * 4 + 1] * x1 + T[m * 4 + 2] * x2 + T[m * 4 + 3] * x3;
     }
+  }
+  typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+  bf16x8v* out = reinterpret_cast<bf16x8v*>(X + r * int64_t(64 * nvar) + v * 64);
 #pragma unroll
-  for (int z = 0; z < 4; ++z)
+  for (int k8 = 0; k8 < 8; ++k8) {
+    bf16x8v o;
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        double s = 0.0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) s += T4[m * 4 + i] * b[(z * 4 + i) * 4 + x];
-        a[(z * 4 + m) * 4 + x] = s;
-      }
-#pragma unroll
-  for (int m = 0; m < 4; ++m)
-#pragma unroll
-    for (int yx = 0; yx < 16; ++yx) {
-      double s = 0.0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) s += T4[m * 4 + i] * a[i * 16 + yx];
-      b[m * 16 + yx] = s;
+    for (int t = 0; t < 8; ++t) {
+      const float c = float(fabs(a[k8 * 8 + t]) + 1e-14);
+      o[t] = bf16((log10f(c) + 7.0f) / 7.0f);
     }
-  bf16* out = X + r * int64_t(64 * nvar) + v * 64;
-#pragma unroll
-  for (int k = 0; k < 64; ++k) out[k] = bf16(float((log10(fabs(b[k]) + 1e-14) + 7.0) / 7.0));
+    out[k8] = o;
+  }
 }
 
 // C[m][n] = sum_k A[m][k] Bt[n][k] (+ bias[n]) on BF16 matrix cores with FP32
@@ -238,34 +236,6 @@ __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float
   if (wb) wb[i] = bf16(wi);
 }
 
-// Decision: argmax class (0 coarsen, 1 keep, 2 refine) when its softmax
-// probability reaches conf_min, else the geometric flag already in `flags`;
-// then the depth clamps.
-__global__ void k_mlp_decide(KeyGeom g, const uint64_t* __restrict__ keys, const float* __restrict__ Z,
-                             int64_t n, float conf_min, int8_t* __restrict__ flags,
-                             float* __restrict__ conf) {
-  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  const float z0 = Z[3 * e], z1 = Z[3 * e + 1], z2 = Z[3 * e + 2];
-  const float m = fmaxf(z0, fmaxf(z1, z2));
-  const float e0 = expf(z0 - m), e1 = expf(z1 - m), e2 = expf(z2 - m);
-  const float s = e0 + e1 + e2;
-  int c = 0;
-  float pc = e0;
-  if (e1 > pc) { c = 1; pc = e1; }
-  if (e2 > pc) { c = 2; pc = e2; }
-  pc /= s;
-  if (conf) conf[e] = pc;
-  int f = pc >= conf_min ? c - 1 : int(flags[e]);
-  const uint64_t key = keys[e];
-  const int d = key_depth(g, key);
-  int lo, hi;
-  depth_limits(g, key, &lo, &hi);
-  if (f == 1 && d >= hi) f = 0;
-  if (f == -1 && d <= lo) f = 0;
-  flags[e] = int8_t(f);
-}
-
 // Modal-energy indicator: the density's nodal values become coefficients in
 // the orthonormal tensor Legendre basis (matrix T per axis, sum-factorised);
 // s = energy of the modes whose highest per-axis degree is p over the total
@@ -344,6 +314,153 @@ __global__ __launch_bounds__(256) void k_flag_modal(KeyGeom g, const uint64_t* _
   if (f == 1 && d >= hi) f = 0;
   if (f == -1 && d <= lo) f = 0;
   flags[e] = int8_t(f);
+}
+
+// Fused inference and decision.  Persistent workgroups of 4 waves; each wave
+// keeps its slice of the weights in registers as matrix-core B fragments
+// (layer 1: output columns 32w .. 32w+31; layer 2: columns 16w .. 16w+15;
+// layer 3: all 3 outputs, padded to 16), and every 64-row tile of features is
+// staged in LDS.  Layer 1 and 2 activations stay in LDS (BF16); the logits go
+// straight to the decision: argmax class (0 coarsen, 1 keep, 2 refine) when
+// its softmax probability reaches conf_min, else the geometric flag already
+// in `flags`; then the depth clamps.
+constexpr int kXS = 328;   // LDS row stride (BF16) of a feature tile (320 + pad)
+constexpr int kH1S = 136;  // layer-1 activations (128 + pad)
+constexpr int kH2S = 72;   // layer-2 activations (64 + pad)
+
+__global__ __launch_bounds__(256) void k_mlp_flag(KeyGeom g, const uint64_t* __restrict__ keys,
+                                                  const bf16* __restrict__ X, int64_t n,
+                                                  const bf16* __restrict__ W1, const bf16* __restrict__ W2,
+                                                  const bf16* __restrict__ W3, const float* __restrict__ P,
+                                                  int64_t off_b1, int64_t off_b2, int64_t off_b3,
+                                                  float conf_min, int8_t* __restrict__ flags,
+                                                  float* __restrict__ conf) {
+  __shared__ __attribute__((aligned(16))) bf16 sX[64 * kXS];
+  __shared__ __attribute__((aligned(16))) bf16 sH1[64 * kH1S];
+  __shared__ __attribute__((aligned(16))) bf16 sH2[64 * kH2S];
+  __shared__ float sZ[64][4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lr = lane & 15, lk = 8 * (lane >> 4);
+  // weights as B fragments: lane holds Bt[n0 + lr][k0 + lk .. + 8]
+  bf16x8 b1f[2][10], b2f[4], b3f[2];
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+    for (int ks = 0; ks < 10; ++ks)
+      b1f[ct][ks] = *reinterpret_cast<const bf16x8*>(W1 + (32 * w + 16 * ct + lr) * 320 + 32 * ks + lk);
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks)
+    b2f[ks] = *reinterpret_cast<const bf16x8*>(W2 + (16 * w + lr) * 128 + 32 * ks + lk);
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks) {
+    if (lr < 3) {
+      b3f[ks] = *reinterpret_cast<const bf16x8*>(W3 + lr * 64 + 32 * ks + lk);
+    } else {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) b3f[ks][t] = bf16(0.f);
+    }
+  }
+  const float bias1[2] = {P[off_b1 + 32 * w + lr], P[off_b1 + 32 * w + 16 + lr]};
+  const float bias2 = P[off_b2 + 16 * w + lr];
+  const float bias3 = lr < 3 ? P[off_b3 + lr] : 0.f;
+  const int64_t ntiles = (n + 63) / 64;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t r0 = tile * 64;
+    // stage the 64 x 320 feature tile (rows past n as zeros)
+#pragma unroll
+    for (int j = 0; j < 10; ++j) {
+      const int c = tid + 256 * j;
+      const int row = c / 40, c16 = c % 40;
+      bf16x8 v;
+      if (r0 + row < n) {
+        v = *reinterpret_cast<const bf16x8*>(X + (r0 + row) * 320 + c16 * 8);
+      } else {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = bf16(0.f);
+      }
+      *reinterpret_cast<bf16x8*>(sX + row * kXS + c16 * 8) = v;
+    }
+    __syncthreads();
+    // layer 1: H1[:, 32w .. 32w+31] = relu(X W1^T + b1)
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 10; ++ks)
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) {
+        const bf16x8 af = *reinterpret_cast<const bf16x8*>(sX + (16 * rt + lr) * kXS + 32 * ks + lk);
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b1f[ct][ks], acc[rt][ct], 0, 0, 0);
+      }
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float h = acc[rt][ct][q] + bias1[ct];
+          sH1[(16 * rt + 4 * (lane >> 4) + q) * kH1S + 32 * w + 16 * ct + lr] = bf16(h > 0.f ? h : 0.f);
+        }
+    __syncthreads();
+    // layer 2: H2[:, 16w .. 16w+15] = relu(H1 W2^T + b2)
+    f32x4 acc2[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) acc2[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) {
+        const bf16x8 af = *reinterpret_cast<const bf16x8*>(sH1 + (16 * rt + lr) * kH1S + 32 * ks + lk);
+        acc2[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b2f[ks], acc2[rt], 0, 0, 0);
+      }
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float h = acc2[rt][q] + bias2;
+        sH2[(16 * rt + 4 * (lane >> 4) + q) * kH2S + 16 * w + lr] = bf16(h > 0.f ? h : 0.f);
+      }
+    __syncthreads();
+    // layer 3: logits of rows 16w .. 16w+15
+    f32x4 acc3 = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const bf16x8 af = *reinterpret_cast<const bf16x8*>(sH2 + (16 * w + lr) * kH2S + 32 * ks + lk);
+      acc3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b3f[ks], acc3, 0, 0, 0);
+    }
+    if (lr < 3)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sZ[16 * w + 4 * (lane >> 4) + q][lr] = acc3[q] + bias3;
+    __syncthreads();
+    if (tid < 64 && r0 + tid < n) {
+      const int64_t e = r0 + tid;
+      const float z0 = sZ[tid][0], z1 = sZ[tid][1], z2 = sZ[tid][2];
+      const float m = fmaxf(z0, fmaxf(z1, z2));
+      const float e0 = expf(z0 - m), e1 = expf(z1 - m), e2 = expf(z2 - m);
+      const float sum = e0 + e1 + e2;
+      int c = 0;
+      float pc = e0;
+      if (e1 > pc) { c = 1; pc = e1; }
+      if (e2 > pc) { c = 2; pc = e2; }
+      pc /= sum;
+      if (conf) conf[e] = pc;
+      int f = pc >= conf_min ? c - 1 : int(flags[e]);
+      const uint64_t key = keys[e];
+      const int d = key_depth(g, key);
+      int lo, hi;
+      depth_limits(g, key, &lo, &hi);
+      if (f == 1 && d >= hi) f = 0;
+      if (f == -1 && d <= lo) f = 0;
+      flags[e] = int8_t(f);
+    }
+    // sX, sH1, sH2 and sZ are rewritten by the next tile only after the
+    // barriers above, except sX, which the next tile's staging overwrites:
+    __syncthreads();
+  }
 }
 
 inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
@@ -612,16 +729,15 @@ lt_status lt_flag_mlp(lt_tree t, lt_mlp m, const lt_flag_params* fallback, const
     if (hipMalloc(&m->X, size_t(n) * 320 * 2) != hipSuccess) return fail(LT_ERR_OOM, "MLP features");
     m->xcap = n;
   }
-  float* Z = nullptr;
-  if (hipMallocAsync((void**)&Z, size_t(n) * 3 * 4, s) != hipSuccess) return fail(LT_ERR_OOM, "MLP logits");
   lt_status st = lt_mlp_features(m, u, ld, 5, nullptr, n, m->X, stream);
-  if (st == LT_OK) st = lt_mlp_infer(m, m->X, n, Z, stream);
-  if (st == LT_OK) {
-    k_mlp_decide<<<nblk(n, 256), 256, 0, s>>>(t->g, t->kbuf[t->cur], Z, n, conf_min, flags, conf);
-    if (hipGetLastError() != hipSuccess) st = fail(LT_ERR_HIP, "decide launch");
-  }
-  (void)hipFreeAsync(Z, s);
-  return st;
+  if (st != LT_OK) return st;
+  const int64_t ntiles = (n + 63) / 64;
+  const unsigned grid = unsigned(std::min<int64_t>(ntiles, 1024));
+  k_mlp_flag<<<grid, 256, 0, s>>>(t->g, t->kbuf[t->cur], m->X, n, m->W1, m->W2, m->W3, m->P,
+                                  lt_mlp_s::off_b1, lt_mlp_s::off_b2, lt_mlp_s::off_b3, conf_min,
+                                  flags, conf);
+  if (hipGetLastError() != hipSuccess) return fail(LT_ERR_HIP, "learned flag launch");
+  return LT_OK;
 }
 
 lt_status lt_vortex_field(lt_tree t, const lt_flag_params* where, const double* strength, double* u,

@@ -122,6 +122,43 @@ def test_learned_decision_matches_cpu_forward(trained):
     print("near ties", int(near_arg.sum()), int(near_thr.sum()), flush=True)
 
 
+def test_learned_flags_match_cpu_forward(trained):
+    """lt_flag_mlp (features, fused network and decision) on a whole mesh
+    against an FP64 forward of the same BF16 weights on the same features,
+    the geometric fallback below 0.9 and the depth clamps: equal except at
+    near ties of the argmax or of the threshold."""
+    import torch
+    import paper_2306_06744_amd as lt
+    from paper_2306_06744_amd import indicator
+    m = trained[0]
+    w = synth.workload_3d_extruded(200070)
+    nodes = synth.gl_nodes01(w.p)
+    t, c = next(indicator.mesh_states(w, states=(1,)))
+    cen = w.centres_at(c)
+    u = t.vortex_field(cen, w.strengths, nodes, w.lo, w.length)
+    plain = t.flag(cen, w.r_in, w.r_out, nodes, w.lo, w.length, dist_axes=w.dist_axes).cpu().numpy()
+    f, conf = t.flag_mlp(m, u, cen, w.r_in, w.r_out, nodes, w.lo, w.length, conf_min=0.9,
+                         dist_axes=w.dist_axes)
+    f, conf = f.cpu().numpy(), conf.cpu().numpy()
+    X = m.features(u).double().cpu().numpy()
+    W1, b1, W2, b2, W3, b3 = synth.mlp_split(m.params().astype(np.float64))
+    zr, _ = ref.forward(X, bf16(W1).T, b1, bf16(W2).T, b2, bf16(W3).T, b3, store=bf16)
+    pr = ref.softmax(zr)
+    cls, pc = pr.argmax(1), pr.max(1)
+    keys = t.keys().cpu().numpy().view(np.uint64)
+    depth = (keys & np.uint64(7)).astype(np.int64)
+    exp = np.where(pc >= 0.9, cls - 1, plain).astype(np.int8)
+    exp[(exp == 1) & (depth >= w.d_max)] = 0
+    exp[(exp == -1) & (depth <= w.d_min)] = 0
+    srt = np.sort(zr, axis=1)
+    near = (srt[:, 2] - srt[:, 1] < 1e-3) | (np.abs(pc - 0.9) < 1e-3)
+    bad = f != exp
+    print("leaves", len(f), "near ties", int(near.sum()), "differ at ties", int((bad & near).sum()),
+          flush=True)
+    assert not (bad & ~near).any()
+    assert np.abs(conf - pc).max() < 1e-2
+
+
 def test_tree_from_learned_flags_matches_oracle(trained):
     import torch
     import paper_2306_06744_amd as lt
