@@ -145,7 +145,7 @@ def ensemble_variant(lt, torch, synth, seed, nvar=5, warm=8):
     return out
 
 
-def chosen_cycle(lt, torch, synth, w, nodes, stream, steps, warmup, u, cap, E):
+def chosen_cycle(lt, torch, synth, w, nodes, stream, steps, warmup, u, cap, E, train_seeds=2000):
     """The chosen cycle on the same workload: learned flags (network trained
     here on the device over 2000 seeded fields, geometric fallback below 0.9
     confidence) and the split-precision BF16 x 3 transfer.  Each cycle first
@@ -158,7 +158,8 @@ def chosen_cycle(lt, torch, synth, w, nodes, stream, steps, warmup, u, cap, E):
     tau = json.load(open(os.path.join(here, "tests", "golden", "modal_tau.json")))["3d_p3"]
     m = lt.MLP(synth.mlp_init(11))
     t0 = time.perf_counter()
-    X, y = indicator.training_set(m, seeds=indicator.TRAIN_SEEDS)
+    seeds = indicator.TRAIN_SEEDS[:train_seeds]
+    X, y = indicator.training_set(m, seeds=seeds)
     rows = int(X.shape[0])
     l0, l1 = indicator.train(m, X, y, steps=3000, batch=4096, lr=2e-3)
     del X, y
@@ -214,8 +215,7 @@ def chosen_cycle(lt, torch, synth, w, nodes, stream, steps, warmup, u, cap, E):
         "roofline": {"bound": "hbm", "kernel": "split BF16 x 3 transfer (copy + MFMA interpolation)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS},
-        "indicator": {"train_rows": rows, "train_seeds": [indicator.TRAIN_SEEDS[0],
-                                                          indicator.TRAIN_SEEDS[-1]],
+        "indicator": {"train_rows": rows, "train_seeds": [seeds[0], seeds[-1]],
                       "loss_first_last_100": [l0, l1], "train_s": train_s,
                       "heldout_seeds": [indicator.HELDOUT_SEEDS[0], indicator.HELDOUT_SEEDS[-1]],
                       "disagreement": held},
@@ -283,6 +283,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-only", action="store_true",
                     help="time only the plain FP64 cycle (skip the split-precision variant)")
+    ap.add_argument("--variants", default="ensemble,split,chosen",
+                    help="comma-separated variants to run after the plain cycle "
+                         "(ensemble, split, chosen; empty for none)")
+    ap.add_argument("--train-seeds", type=int, default=2000,
+                    help="training fields of the learned indicator (chosen variant)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed region, one plain device-to-device copy of this many "
                          "MiB (a known-size reference for HBM byte counters)")
@@ -364,12 +369,16 @@ def main():
     traffic = measured_traffic()
     cyc_bytes = sum(cycle_bytes(w.dim, E, *s) for s in sizes)
     variants = {}
-    if not args.plain_only:
+    which = set() if args.plain_only else {v for v in args.variants.split(",") if v}
+    if "ensemble" in which:
         variants["ensemble_64"] = ensemble_variant(lt, torch, synth, 4000)
+    if "chosen" in which:
+        variants["chosen_learned_split"] = chosen_cycle(lt, torch, synth, w, nodes, stream,
+                                                        args.steps, args.warmup, u, cap, E,
+                                                        args.train_seeds)
+    if "split" in which:
         s1, e1, t1 = run(1)
         n1 = sum(s[1] for s in s1)
-        variants["chosen_learned_split"] = chosen_cycle(lt, torch, synth, w, nodes, stream,
-                                                        args.steps, args.warmup, u, cap, E)
         variants["split_bf16x3_transfer"] = {
             "value": n1 / e1, "unit": "octants/s", "ms_per_step": e1 * 1e3 / args.steps,
             "transfer_ms_mean": sum(t1) / len(t1),

@@ -85,49 +85,67 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Modal features of 64-point elements: T[n][i] = w_i L~_n(x_i) per axis
 // (orthonormal Legendre at the Gauss-Legendre points), applied on the three
-// axes in place; f = (log10(|c| + 1e-14) + 7) / 7 written as BF16 row
-// [v*64 + mode] of X (one row of 64*nvar per element; `rows` picks elements,
-// or null for all).  The coefficients are FP64; the logarithm is taken in
-// FP32 since its result is stored in BF16.
+// axes; f = (log10(|c| + 1e-14) + 7) / 7 written as BF16 row [v*64 + mode]
+// of X (one row of 64*nvar per element; `rows` picks elements, or null for
+// all).  A block covers 64 elements of one variable with four lanes per
+// element, one z-slab each: x and y passes in registers, the z pass through
+// LDS.  Coefficients are FP64; the logarithm is taken in FP32, its result
+// being stored in BF16.
 __global__ __launch_bounds__(256) void k_mlp_features(const double* __restrict__ T4,
                                                       const double* __restrict__ u, int64_t ld,
                                                       int nvar, const int32_t* __restrict__ rows,
                                                       int64_t n, bf16* __restrict__ X) {
-  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  constexpr int kS = 65;  // LDS stride (doubles) of one element's 64 values
+  __shared__ double sA[64 * kS];
+  const int el = threadIdx.x & 63, z = threadIdx.x >> 6;
   const int v = blockIdx.y;
-  if (r >= n) return;
-  const int64_t e = rows ? int64_t(rows[r]) : r;
+  const int64_t r = int64_t(blockIdx.x) * 64 + el;
+  const bool live = r < n;
+  const int64_t e = live ? (rows ? int64_t(rows[r]) : r) : 0;
   double T[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) T[i] = T4[i];
-  double a[64];
+  double a[16];
 #pragma unroll
-  for (int i = 0; i < 64; ++i) a[i] = u[(int64_t(v) * 64 + i) * ld + e];
-  // one axis at a time, each line of 4 values transformed in place
+  for (int i = 0; i < 16; ++i) a[i] = live ? u[(int64_t(v) * 64 + z * 16 + i) * ld + e] : 0.0;
+  // x pass (stride 1) then y pass (stride 4) on the 4 x 4 slab
 #pragma unroll
-  for (int axis = 0; axis < 3; ++axis) {
-    const int st = axis == 0 ? 1 : (axis == 1 ? 4 : 16);
+  for (int pass = 0; pass < 2; ++pass) {
+    const int st = pass == 0 ? 1 : 4;
 #pragma unroll
-    for (int line = 0; line < 16; ++line) {
-      // base index of this line: the two other axes' coordinates
-      const int base = axis == 0 ? line * 4 : (axis == 1 ? (line / 4) * 16 + (line % 4) : line);
+    for (int line = 0; line < 4; ++line) {
+      const int base = pass == 0 ? line * 4 : line;
       const double x0 = a[base], x1 = a[base + st], x2 = a[base + 2 * st], x3 = a[base + 3 * st];
 #pragma unroll
       for (int m = 0; m < 4; ++m)
         a[base + m * st] = T[m * 4] * x0 + T[m * 4 + 1] * x1 + T[m * 4 + 2] * x2 + T[m * 4 + 3] * x3;
     }
   }
-  typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
-  bf16x8v* out = reinterpret_cast<bf16x8v*>(X + r * int64_t(64 * nvar) + v * 64);
 #pragma unroll
-  for (int k8 = 0; k8 < 8; ++k8) {
+  for (int i = 0; i < 16; ++i) sA[el * kS + z * 16 + i] = a[i];
+  __syncthreads();
+  // z pass: this lane now produces output slab m = z of its element
+  const int m = z;
+  double c[16];
+#pragma unroll
+  for (int yx = 0; yx < 16; ++yx) {
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc += T[m * 4 + i] * sA[el * kS + i * 16 + yx];
+    c[yx] = acc;
+  }
+  if (!live) return;
+  typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+  bf16x8v* out = reinterpret_cast<bf16x8v*>(X + r * int64_t(64 * nvar) + v * 64 + m * 16);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
     bf16x8v o;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-      const float c = float(fabs(a[k8 * 8 + t]) + 1e-14);
-      o[t] = bf16((log10f(c) + 7.0f) / 7.0f);
+      const float cc = float(fabs(c[h * 8 + t]) + 1e-14);
+      o[t] = bf16((log10f(cc) + 7.0f) / 7.0f);
     }
-    out[k8] = o;
+    out[h] = o;
   }
 }
 
@@ -316,41 +334,46 @@ __global__ __launch_bounds__(256) void k_flag_modal(KeyGeom g, const uint64_t* _
   flags[e] = int8_t(f);
 }
 
-// Fused inference and decision.  Persistent workgroups of 4 waves; each wave
-// keeps its slice of the weights in registers as matrix-core B fragments
-// (layer 1: output columns 32w .. 32w+31; layer 2: columns 16w .. 16w+15;
-// layer 3: all 3 outputs, padded to 16), and every 64-row tile of features is
-// staged in LDS.  Layer 1 and 2 activations stay in LDS (BF16); the logits go
+// Fused inference and decision.  Workgroups of 8 waves hold W1 and W2 in
+// LDS; each wave runs its own 16-row tiles: the feature rows come straight
+// from memory as matrix-core A fragments (the next tile's are loaded while
+// the current one computes), layer-1 and layer-2 activations pass through a
+// per-wave LDS patch (BF16), W3 sits in registers, and the logits go
 // straight to the decision: argmax class (0 coarsen, 1 keep, 2 refine) when
 // its softmax probability reaches conf_min, else the geometric flag already
 // in `flags`; then the depth clamps.
-constexpr int kXS = 328;   // LDS row stride (BF16) of a feature tile (320 + pad)
-constexpr int kH1S = 136;  // layer-1 activations (128 + pad)
+constexpr int kW1S = 328;  // LDS row stride (BF16) of W1 (320 + pad)
+constexpr int kW2S = 136;  // W2 (128 + pad)
+constexpr int kH1S = 136;  // layer-1 activations of a wave's 16 rows (128 + pad)
 constexpr int kH2S = 72;   // layer-2 activations (64 + pad)
+constexpr int kFlagWaves = 8;
 
-__global__ __launch_bounds__(256) void k_mlp_flag(KeyGeom g, const uint64_t* __restrict__ keys,
-                                                  const bf16* __restrict__ X, int64_t n,
-                                                  const bf16* __restrict__ W1, const bf16* __restrict__ W2,
-                                                  const bf16* __restrict__ W3, const float* __restrict__ P,
-                                                  int64_t off_b1, int64_t off_b2, int64_t off_b3,
-                                                  float conf_min, int8_t* __restrict__ flags,
-                                                  float* __restrict__ conf) {
-  __shared__ __attribute__((aligned(16))) bf16 sX[64 * kXS];
-  __shared__ __attribute__((aligned(16))) bf16 sH1[64 * kH1S];
-  __shared__ __attribute__((aligned(16))) bf16 sH2[64 * kH2S];
-  __shared__ float sZ[64][4];
+__global__ __launch_bounds__(64 * kFlagWaves) void k_mlp_flag(
+    KeyGeom g, const uint64_t* __restrict__ keys, const bf16* __restrict__ X, int64_t n,
+    const bf16* __restrict__ W1, const bf16* __restrict__ W2, const bf16* __restrict__ W3,
+    const float* __restrict__ P, int64_t off_b1, int64_t off_b2, int64_t off_b3, float conf_min,
+    int8_t* __restrict__ flags, float* __restrict__ conf) {
+  __shared__ __attribute__((aligned(16))) bf16 sW1[128 * kW1S];
+  __shared__ __attribute__((aligned(16))) bf16 sW2[64 * kW2S];
+  __shared__ __attribute__((aligned(16))) bf16 sH1[kFlagWaves][16 * kH1S];
+  __shared__ __attribute__((aligned(16))) bf16 sH2[kFlagWaves][16 * kH2S];
+  __shared__ float sZ[kFlagWaves][16][4];
+  __shared__ float sB[128 + 64 + 4];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = 8 * (lane >> 4);
-  // weights as B fragments: lane holds Bt[n0 + lr][k0 + lk .. + 8]
-  bf16x8 b1f[2][10], b2f[4], b3f[2];
-#pragma unroll
-  for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-    for (int ks = 0; ks < 10; ++ks)
-      b1f[ct][ks] = *reinterpret_cast<const bf16x8*>(W1 + (32 * w + 16 * ct + lr) * 320 + 32 * ks + lk);
-#pragma unroll
-  for (int ks = 0; ks < 4; ++ks)
-    b2f[ks] = *reinterpret_cast<const bf16x8*>(W2 + (16 * w + lr) * 128 + 32 * ks + lk);
+  for (int c = tid; c < 128 * 40; c += 64 * kFlagWaves) {
+    const int row = c / 40, c16 = c % 40;
+    *reinterpret_cast<bf16x8*>(sW1 + row * kW1S + c16 * 8) =
+        *reinterpret_cast<const bf16x8*>(W1 + row * 320 + c16 * 8);
+  }
+  for (int c = tid; c < 64 * 16; c += 64 * kFlagWaves) {
+    const int row = c / 16, c16 = c % 16;
+    *reinterpret_cast<bf16x8*>(sW2 + row * kW2S + c16 * 8) =
+        *reinterpret_cast<const bf16x8*>(W2 + row * 128 + c16 * 8);
+  }
+  for (int c = tid; c < 128 + 64 + 3; c += 64 * kFlagWaves)
+    sB[c] = c < 128 ? P[off_b1 + c] : (c < 192 ? P[off_b2 + c - 128] : P[off_b3 + c - 192]);
+  bf16x8 b3f[2];
 #pragma unroll
   for (int ks = 0; ks < 2; ++ks) {
     if (lr < 3) {
@@ -360,87 +383,85 @@ __global__ __launch_bounds__(256) void k_mlp_flag(KeyGeom g, const uint64_t* __r
       for (int t = 0; t < 8; ++t) b3f[ks][t] = bf16(0.f);
     }
   }
-  const float bias1[2] = {P[off_b1 + 32 * w + lr], P[off_b1 + 32 * w + 16 + lr]};
-  const float bias2 = P[off_b2 + 16 * w + lr];
-  const float bias3 = lr < 3 ? P[off_b3 + lr] : 0.f;
-  const int64_t ntiles = (n + 63) / 64;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t r0 = tile * 64;
-    // stage the 64 x 320 feature tile (rows past n as zeros)
+  __syncthreads();
+  bf16* H1 = sH1[w];
+  bf16* H2 = sH2[w];
+  const int64_t ntiles = (n + 15) / 16;
+  const int64_t stride = int64_t(gridDim.x) * kFlagWaves;
+  auto load_a = [&](int64_t t, bf16x8* af) {
+    const int64_t row = t * 16 + lr;
 #pragma unroll
-    for (int j = 0; j < 10; ++j) {
-      const int c = tid + 256 * j;
-      const int row = c / 40, c16 = c % 40;
-      bf16x8 v;
-      if (r0 + row < n) {
-        v = *reinterpret_cast<const bf16x8*>(X + (r0 + row) * 320 + c16 * 8);
+    for (int ks = 0; ks < 10; ++ks) {
+      if (t < ntiles && row < n) {
+        af[ks] = *reinterpret_cast<const bf16x8*>(X + row * 320 + 32 * ks + lk);
       } else {
 #pragma unroll
-        for (int t = 0; t < 8; ++t) v[t] = bf16(0.f);
+        for (int q = 0; q < 8; ++q) af[ks][q] = bf16(0.f);
       }
-      *reinterpret_cast<bf16x8*>(sX + row * kXS + c16 * 8) = v;
     }
-    __syncthreads();
-    // layer 1: H1[:, 32w .. 32w+31] = relu(X W1^T + b1)
-    f32x4 acc[4][2];
+  };
+  bf16x8 a_cur[10], a_nxt[10];
+  // The round loop is uniform over the workgroup (every wave reaches every
+  // barrier); a wave whose tile lies past the end computes on zeros and
+  // writes nothing.
+  const int64_t base0 = int64_t(blockIdx.x) * kFlagWaves;
+  load_a(base0 + w, a_cur);
+  for (int64_t base = base0; base < ntiles; base += stride) {
+    const int64_t tile = base + w;
+    load_a(tile + stride, a_nxt);
+    // layer 1: H1 = relu(X W1^T + b1), 16 rows x 128
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
+    for (int ct = 0; ct < 8; ++ct) {
+      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int ks = 0; ks < 10; ++ks)
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt) {
-        const bf16x8 af = *reinterpret_cast<const bf16x8*>(sX + (16 * rt + lr) * kXS + 32 * ks + lk);
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
-          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b1f[ct][ks], acc[rt][ct], 0, 0, 0);
+      for (int ks = 0; ks < 10; ++ks) {
+        const bf16x8 bf = *reinterpret_cast<const bf16x8*>(sW1 + (16 * ct + lr) * kW1S + 32 * ks + lk);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_cur[ks], bf, acc, 0, 0, 0);
       }
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float h = acc[rt][ct][q] + bias1[ct];
-          sH1[(16 * rt + 4 * (lane >> 4) + q) * kH1S + 32 * w + 16 * ct + lr] = bf16(h > 0.f ? h : 0.f);
-        }
-    __syncthreads();
-    // layer 2: H2[:, 16w .. 16w+15] = relu(H1 W2^T + b2)
-    f32x4 acc2[4];
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt) acc2[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks)
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt) {
-        const bf16x8 af = *reinterpret_cast<const bf16x8*>(sH1 + (16 * rt + lr) * kH1S + 32 * ks + lk);
-        acc2[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b2f[ks], acc2[rt], 0, 0, 0);
-      }
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
+      const float bias = sB[16 * ct + lr];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const float h = acc2[rt][q] + bias2;
-        sH2[(16 * rt + 4 * (lane >> 4) + q) * kH2S + 16 * w + lr] = bf16(h > 0.f ? h : 0.f);
+        const float h = acc[q] + bias;
+        H1[(4 * (lane >> 4) + q) * kH1S + 16 * ct + lr] = bf16(h > 0.f ? h : 0.f);
       }
+    }
     __syncthreads();
-    // layer 3: logits of rows 16w .. 16w+15
+    // layer 2: H2 = relu(H1 W2^T + b2), 16 rows x 64
+    bf16x8 h1f[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) h1f[ks] = *reinterpret_cast<const bf16x8*>(H1 + lr * kH1S + 32 * ks + lk);
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const bf16x8 bf = *reinterpret_cast<const bf16x8*>(sW2 + (16 * ct + lr) * kW2S + 32 * ks + lk);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h1f[ks], bf, acc, 0, 0, 0);
+      }
+      const float bias = sB[128 + 16 * ct + lr];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float h = acc[q] + bias;
+        H2[(4 * (lane >> 4) + q) * kH2S + 16 * ct + lr] = bf16(h > 0.f ? h : 0.f);
+      }
+    }
+    __syncthreads();
+    // layer 3: logits, 16 rows x 3 (padded to 16)
     f32x4 acc3 = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
-      const bf16x8 af = *reinterpret_cast<const bf16x8*>(sH2 + (16 * w + lr) * kH2S + 32 * ks + lk);
+      const bf16x8 af = *reinterpret_cast<const bf16x8*>(H2 + lr * kH2S + 32 * ks + lk);
       acc3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b3f[ks], acc3, 0, 0, 0);
     }
     if (lr < 3)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) sZ[16 * w + 4 * (lane >> 4) + q][lr] = acc3[q] + bias3;
+      for (int q = 0; q < 4; ++q) sZ[w][4 * (lane >> 4) + q][lr] = acc3[q] + sB[192 + lr];
     __syncthreads();
-    if (tid < 64 && r0 + tid < n) {
-      const int64_t e = r0 + tid;
-      const float z0 = sZ[tid][0], z1 = sZ[tid][1], z2 = sZ[tid][2];
-      const float m = fmaxf(z0, fmaxf(z1, z2));
-      const float e0 = expf(z0 - m), e1 = expf(z1 - m), e2 = expf(z2 - m);
+    const int64_t e = tile * 16 + lane;
+    if (lane < 16 && e < n) {
+      const float z0 = sZ[w][lane][0], z1 = sZ[w][lane][1], z2 = sZ[w][lane][2];
+      const float mx = fmaxf(z0, fmaxf(z1, z2));
+      const float e0 = expf(z0 - mx), e1 = expf(z1 - mx), e2 = expf(z2 - mx);
       const float sum = e0 + e1 + e2;
       int c = 0;
       float pc = e0;
@@ -457,9 +478,8 @@ __global__ __launch_bounds__(256) void k_mlp_flag(KeyGeom g, const uint64_t* __r
       if (f == -1 && d <= lo) f = 0;
       flags[e] = int8_t(f);
     }
-    // sX, sH1, sH2 and sZ are rewritten by the next tile only after the
-    // barriers above, except sX, which the next tile's staging overwrites:
-    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 10; ++ks) a_cur[ks] = a_nxt[ks];
   }
 }
 
@@ -678,8 +698,8 @@ lt_status lt_mlp_features(lt_mlp m, const double* u, int64_t ld, int nvar, const
   if (!m || !u || !X || nvar != 5) return fail(LT_ERR_ARG, "features need 5 variables of 64 points");
   if (n == 0) return LT_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  k_mlp_features<<<dim3(nblk(n, 256), unsigned(nvar)), 256, 0, s>>>(m->T4, u, ld, nvar, rows, n,
-                                                                     static_cast<__bf16*>(X));
+  k_mlp_features<<<dim3(nblk(n, 64), unsigned(nvar)), 256, 0, s>>>(m->T4, u, ld, nvar, rows, n,
+                                                                    static_cast<__bf16*>(X));
   if (hipGetLastError() != hipSuccess) return fail(LT_ERR_HIP, "features launch");
   return LT_OK;
 }
@@ -731,9 +751,9 @@ lt_status lt_flag_mlp(lt_tree t, lt_mlp m, const lt_flag_params* fallback, const
   }
   lt_status st = lt_mlp_features(m, u, ld, 5, nullptr, n, m->X, stream);
   if (st != LT_OK) return st;
-  const int64_t ntiles = (n + 63) / 64;
-  const unsigned grid = unsigned(std::min<int64_t>(ntiles, 1024));
-  k_mlp_flag<<<grid, 256, 0, s>>>(t->g, t->kbuf[t->cur], m->X, n, m->W1, m->W2, m->W3, m->P,
+  const int64_t ntiles = (n + 16 * kFlagWaves - 1) / (16 * kFlagWaves);
+  const unsigned grid = unsigned(std::min<int64_t>(ntiles, 256));
+  k_mlp_flag<<<grid, 64 * kFlagWaves, 0, s>>>(t->g, t->kbuf[t->cur], m->X, n, m->W1, m->W2, m->W3, m->P,
                                   lt_mlp_s::off_b1, lt_mlp_s::off_b2, lt_mlp_s::off_b3, conf_min,
                                   flags, conf);
   if (hipGetLastError() != hipSuccess) return fail(LT_ERR_HIP, "learned flag launch");
