@@ -254,6 +254,49 @@ def measured_traffic():
             "source": TRAFFIC_SUMMARY}
 
 
+def graph_cycle(lt, torch, synth, w, nodes, stream, steps, warmup, u, cap, E, passes=4):
+    """The plain FP64 cycle captured once in a hipGraph (lt_cycle_*): warm-up
+    cycles eagerly, then the graph is created at the current tree and replayed
+    for the timed cycles (one host synchronisation per cycle)."""
+    t = lt.Tree.uniform(w.dim, w.d_min, w.d_max)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2000)
+    cur = 0
+    u[0][:, :, : t.size()].normal_(generator=g)
+
+    def fa(c):
+        return dict(centres=w.centres_at(c), r_in=w.r_in, r_out=w.r_out, nodes01=nodes, lo=w.lo,
+                    length=w.length, dist_axes=w.dist_axes, periodic_dist=w.periodic_dist)
+
+    for c in range(warmup):
+        t.adapt(t.flag(**fa(c)))
+        t.balance()
+        t.connect()
+        t.map()
+        t.transfer(w.p, u[cur], u_new=u[1 - cur])
+        cur = 1 - cur
+    torch.cuda.synchronize()
+    pair = [u[cur], u[1 - cur]]
+    cyc = lt.Cycle(t, w.p, w.nvar, cap, pair, fa(warmup), balance_passes=passes)
+    torch.cuda.synchronize()
+    sizes = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        n_old = t.size()
+        cyc.run(fa(warmup + k))
+        sizes.append((n_old, t.size()))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    runs, eager, recap = cyc.stats()
+    del cyc, t
+    total = sum(b for _, b in sizes)
+    return {"value": total / elapsed, "unit": "octants/s", "ms_per_step": elapsed * 1e3 / steps,
+            "balance_passes": passes, "runs": runs, "eager_finishes": eager, "recaptures": recap,
+            "capacity": cap,
+            "note": "same cycle, captured once in a hipGraph; host wall clock around the timed "
+                    "cycles (one synchronisation per cycle)"}
+
+
 def plain_copy_gbs(torch, stream, nbytes, reps=5):
     """Rate of a plain contiguous device-to-device copy moving the same bytes
     (nbytes read + nbytes written): the practical ceiling of a copy-bound
@@ -283,9 +326,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-only", action="store_true",
                     help="time only the plain FP64 cycle (skip the split-precision variant)")
-    ap.add_argument("--variants", default="ensemble,split,chosen",
+    ap.add_argument("--variants", default="graph,ensemble,split,chosen",
                     help="comma-separated variants to run after the plain cycle "
-                         "(ensemble, split, chosen; empty for none)")
+                         "(graph, ensemble, split, chosen; empty for none)")
     ap.add_argument("--train-seeds", type=int, default=2000,
                     help="training fields of the learned indicator (chosen variant)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -370,6 +413,9 @@ def main():
     cyc_bytes = sum(cycle_bytes(w.dim, E, *s) for s in sizes)
     variants = {}
     which = set() if args.plain_only else {v for v in args.variants.split(",") if v}
+    if "graph" in which:
+        variants["graph_plain"] = graph_cycle(lt, torch, synth, w, nodes, stream, args.steps,
+                                              args.warmup, u, cap, E)
     if "ensemble" in which:
         variants["ensemble_64"] = ensemble_variant(lt, torch, synth, 4000)
     if "chosen" in which:

@@ -47,7 +47,8 @@ typedef enum {
   LT_ERR_INVALID_TREE = 5, /* keys not strictly ascending / not a complete linear tree */
   LT_ERR_UNBALANCED = 6,   /* a step that needs a 2:1-balanced tree found it is not    */
   LT_ERR_STATE = 7,        /* call order violated (e.g. lt_map before any lt_adapt)    */
-  LT_ERR_INTERNAL = 8      /* a device-side consistency check failed                   */
+  LT_ERR_INTERNAL = 8,     /* a device-side consistency check failed                   */
+  LT_ERR_CAPACITY = 9      /* a captured cycle outgrew the capacity it was created with  */
 } lt_status;
 
 /* Export / view selectors. */
@@ -266,6 +267,58 @@ void lt_mlp_destroy(lt_mlp m);
  * [n_cur].  Asynchronous. */
 lt_status lt_flag_modal(lt_tree t, int p, const double* u, int64_t ld, double tau_refine,
                         double tau_coarsen, int8_t* flags, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Captured cycles (form 2 of the cycle): the whole plain cycle -- flags of
+ * Section 5.2, adaptation (Section 4.1), balance (Section 3.2), connectivity
+ * (Section 3.3), mapping and FP64 transfer (Section 4.2) -- recorded once in
+ * a hipGraph whose kernels keep every count on the device, then replayed with
+ * one host synchronisation per cycle instead of one per size readback.
+ *
+ * The graph is sized for `capacity` leaves: every tree buffer is allocated for
+ * it at creation, and u[0], u[1] (caller-owned device FP64 arrays, layout as
+ * lt_transfer with ld = capacity) hold the solution alternately.  Balance runs
+ * `balance_passes` one-level passes (even, >= 2) and a check pass.
+ * flag_template (host, nmesh entries, nmesh = the tree's mesh count) fixes the
+ * degree p of the flag points, the geometry and the criterion's form; each run
+ * passes the cycle's own parameters (e.g. advected centres) with the same p.
+ * Supports precision 0 (FP64) transfers of 3D p 1..3 and 2D p 1..7. */
+typedef struct lt_cycle_s* lt_cycle;
+typedef struct {
+  int p;                  /* transfer degree                                        */
+  int nvar;               /* variables; nvar * (p+1)^dim <= 65535                   */
+  int64_t capacity;       /* leaves the graph's buffers hold (>= current leaves)     */
+  int balance_passes;     /* fixed balance passes in the graph: even, 2..64          */
+  double* u[2];           /* device solution arrays, ld = capacity                  */
+  int nmesh;              /* flag parameter sets per run (the tree's mesh count)     */
+  const lt_flag_params* flag_template;  /* host, nmesh entries                      */
+} lt_cycle_desc;
+
+/* Allocates the tree's buffers for d->capacity (keeping its leaves; the
+ * pre-adapt snapshot is dropped), builds the transfer operators and captures
+ * two graphs (u[0] -> u[1] and u[1] -> u[0]).  Synchronises.  The tree must
+ * not be used by other calls while the cycle exists, except lt_size, lt_view
+ * and lt_export.  LT_ERR_ARG for an invalid descriptor. */
+lt_status lt_cycle_create(lt_tree t, const lt_cycle_desc* d, void* stream, lt_cycle* out);
+
+/* One cycle with flag parameters fp (host, nmesh entries, same p as the
+ * template).  On return *u_index is the index of the array now holding the
+ * solution (the other one held it before).  Synchronises once.
+ * If the fixed balance passes did not reach the 2:1 fixpoint, the cycle is
+ * finished by the eager calls (same result) and the graphs are recaptured
+ * when buffers had to grow.  If a size passed the capacity, the tree is
+ * restored to its state before the call and LT_ERR_CAPACITY is returned
+ * (create a new cycle with a larger capacity); if that happens while
+ * finishing eagerly, the tree holds the new leaves but u was not
+ * transferred.  Other device check failures give LT_ERR_INTERNAL. */
+lt_status lt_cycle_run(lt_cycle c, const lt_flag_params* fp, void* stream, int* u_index);
+
+/* Host counters of a cycle: runs, runs whose balance was finished by the
+ * eager calls, and recaptures.  Any pointer may be NULL. */
+lt_status lt_cycle_stats(lt_cycle c, int64_t* runs, int64_t* eager_finishes, int64_t* recaptures);
+
+/* Frees the graphs and the cycle's own buffers (not the tree). */
+void lt_cycle_destroy(lt_cycle c);
 
 /* Text of the calling thread's last error ("" if none). */
 const char* lt_last_error(void);

@@ -20,14 +20,15 @@ LT_MAX_DEGREE = 7
 
 STATUS = {0: "LT_OK", 1: "LT_ERR_ARG", 2: "LT_ERR_OOM", 3: "LT_ERR_HIP", 4: "LT_ERR_DEPTH",
           5: "LT_ERR_INVALID_TREE", 6: "LT_ERR_UNBALANCED", 7: "LT_ERR_STATE",
-          8: "LT_ERR_INTERNAL"}
+          8: "LT_ERR_INTERNAL", 9: "LT_ERR_CAPACITY"}
 
 # Every symbol include/lt.h declares.
 EXPORTS = ["lt_build_uniform", "lt_build", "lt_build_batch", "lt_flag_batch", "lt_mesh_offsets",
            "lt_flag", "lt_adapt", "lt_balance", "lt_connect", "lt_map", "lt_transfer", "lt_size",
            "lt_view", "lt_export", "lt_mlp_create", "lt_mlp_params", "lt_mlp_features",
            "lt_mlp_grads", "lt_mlp_train_step", "lt_mlp_infer", "lt_flag_mlp", "lt_vortex_field",
-           "lt_flag_modal", "lt_mlp_destroy", "lt_last_error", "lt_destroy"]
+           "lt_flag_modal", "lt_mlp_destroy", "lt_cycle_create", "lt_cycle_run",
+           "lt_cycle_stats", "lt_cycle_destroy", "lt_last_error", "lt_destroy"]
 MLP_NPARAM = 128 * 320 + 128 + 64 * 128 + 64 + 3 * 64 + 3
 
 
@@ -48,6 +49,12 @@ class FlagParams(C.Structure):
                 ("periodic_dist", C.c_int), ("p", C.c_int),
                 ("nodes01", C.POINTER(C.c_double)), ("lo", C.c_double * 3),
                 ("len", C.c_double), ("raw", C.c_int)]
+
+
+class CycleDesc(C.Structure):
+    _fields_ = [("p", C.c_int), ("nvar", C.c_int), ("capacity", C.c_int64),
+                ("balance_passes", C.c_int), ("u", C.c_void_p * 2), ("nmesh", C.c_int),
+                ("flag_template", C.POINTER(FlagParams))]
 
 
 _lib = None
@@ -86,11 +93,16 @@ def lib() -> C.CDLL:
         L.lt_flag_modal.argtypes = [P, i32, P, i64, C.c_double, C.c_double, P, P]
         L.lt_mlp_destroy.argtypes = [P]
         L.lt_mlp_destroy.restype = None
+        L.lt_cycle_create.argtypes = [P, C.POINTER(CycleDesc), P, C.POINTER(P)]
+        L.lt_cycle_run.argtypes = [P, C.POINTER(FlagParams), P, C.POINTER(i32)]
+        L.lt_cycle_stats.argtypes = [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+        L.lt_cycle_destroy.argtypes = [P]
+        L.lt_cycle_destroy.restype = None
         L.lt_last_error.restype = C.c_char_p
         L.lt_destroy.argtypes = [P]
         L.lt_destroy.restype = None
         for name in EXPORTS:
-            if name not in ("lt_last_error", "lt_destroy", "lt_mlp_destroy"):
+            if name not in ("lt_last_error", "lt_destroy", "lt_mlp_destroy", "lt_cycle_destroy"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -373,3 +385,55 @@ class MLP:
         out = torch.empty((X.shape[0], 3), dtype=torch.float32, device="cuda")
         _check(lib().lt_mlp_infer(self._h, _dptr(X), X.shape[0], _dptr(out), _stream()))
         return out
+
+
+class Cycle:
+    """The whole plain cycle captured in a hipGraph over a tree (lt_cycle_*).
+
+    ``u`` is a pair of device FP64 arrays (nvar, n_p, capacity); ``flag`` maps a
+    cycle to the flag arguments of ``Tree.flag`` (a dict per mesh for an
+    ensemble).  ``run(cycle)`` returns the index of the array now holding the
+    solution."""
+
+    def __init__(self, tree, p, nvar, capacity, u, flag_args, balance_passes=4):
+        self.tree = tree
+        self._u = u
+        per = flag_args if isinstance(flag_args, (list, tuple)) else [flag_args]
+        self._keep = []
+        arr = (FlagParams * len(per))()
+        for m, a in enumerate(per):
+            fp, keep = _flag_params(tree.dim, **a)
+            arr[m] = fp
+            self._keep.append(keep)
+        d = CycleDesc()
+        d.p, d.nvar, d.capacity, d.balance_passes = int(p), int(nvar), int(capacity), int(balance_passes)
+        d.u[0], d.u[1] = _dptr(u[0]), _dptr(u[1])
+        d.nmesh = len(per)
+        d.flag_template = arr
+        h = C.c_void_p()
+        _check(lib().lt_cycle_create(tree._h, C.byref(d), _stream(), C.byref(h)))
+        self._h = h
+
+    def run(self, flag_args):
+        per = flag_args if isinstance(flag_args, (list, tuple)) else [flag_args]
+        arr = (FlagParams * len(per))()
+        keep = []
+        for m, a in enumerate(per):
+            fp, k = _flag_params(self.tree.dim, **a)
+            arr[m] = fp
+            keep.append(k)
+        ui = C.c_int(-1)
+        _check(lib().lt_cycle_run(self._h, arr, _stream(), C.byref(ui)))
+        return ui.value
+
+    def stats(self):
+        """(runs, runs finished eagerly, recaptures)."""
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().lt_cycle_stats(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.lt_cycle_destroy(h)
+            self._h = None

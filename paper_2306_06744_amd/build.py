@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "liblt.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["lt_tree.hip", "lt_flag.hip", "lt_transfer.hip", "lt_split.hip", "lt_mlp.hip"]
+SOURCES = ["lt_tree.hip", "lt_flag.hip", "lt_transfer.hip", "lt_split.hip", "lt_mlp.hip", "lt_cycle.hip"]
 NO_CONTRACT = {"lt_flag.hip"}
 HEADERS = ["keys.hpp", "scan.hpp", "tree.hpp"]
 

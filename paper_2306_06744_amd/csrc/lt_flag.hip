@@ -30,10 +30,10 @@ struct FlagArgs {
 // For an ensemble (tab != null) each element takes the parameters of its mesh.
 template <int N1>
 __global__ __launch_bounds__(256) void k_flag(FlagArgs A0, const FlagArgs* __restrict__ tab,
-                                              const uint64_t* __restrict__ keys, int64_t n,
+                                              const uint64_t* __restrict__ keys, Count cn,
                                               int8_t* __restrict__ flags) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= n) return;
+  if (e >= cn.get()) return;
   const KeyGeom& g = A0.g;
   const uint64_t key = keys[e];
   const FlagArgs& A = tab ? tab[key_mesh(g, key)] : A0;
@@ -122,9 +122,9 @@ __global__ __launch_bounds__(256) void k_flag(FlagArgs A0, const FlagArgs* __res
 }
 
 template <int N1>
-hipError_t launch(const FlagArgs& A, const FlagArgs* tab, const uint64_t* keys, int64_t n, int8_t* flags,
+hipError_t launch(const FlagArgs& A, const FlagArgs* tab, const uint64_t* keys, Count n, int8_t* flags,
                   hipStream_t s) {
-  const unsigned blocks = unsigned((n + 255) / 256);
+  const unsigned blocks = unsigned((n.n + 255) / 256);
   k_flag<N1><<<blocks, 256, 0, s>>>(A, tab, keys, n, flags);
   return hipGetLastError();
 }
@@ -155,7 +155,7 @@ lt_status fill_args(const KeyGeom& g, const lt_flag_params* fp, FlagArgs* out) {
   return LT_OK;
 }
 
-hipError_t dispatch(int n1, const FlagArgs& A, const FlagArgs* tab, const uint64_t* keys, int64_t n,
+hipError_t dispatch(int n1, const FlagArgs& A, const FlagArgs* tab, const uint64_t* keys, Count n,
                     int8_t* flags, hipStream_t stream) {
   switch (n1) {
     case 1: return launch<1>(A, tab, keys, n, flags, stream);
@@ -176,7 +176,7 @@ lt_status launch_flag(const KeyGeom& g, const lt_flag_params* fp, const uint64_t
   FlagArgs A;
   LT_TRY_STATUS(fill_args(g, fp, &A));
   if (n == 0) return LT_OK;
-  const hipError_t e = dispatch(fp->p + 1, A, nullptr, keys, n, flags, stream);
+  const hipError_t e = dispatch(fp->p + 1, A, nullptr, keys, Count{n, nullptr}, flags, stream);
   if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("flag launch: ") + hipGetErrorString(e));
   return LT_OK;
 }
@@ -195,7 +195,31 @@ lt_status launch_flag_batch(const KeyGeom& g, const lt_flag_params* fps, int nme
   hipError_t e = hipMemcpyAsync(dev_table, H.data(), sizeof(FlagArgs) * nmesh, hipMemcpyHostToDevice,
                                 stream);
   if (e == hipSuccess && n > 0)
-    e = dispatch(fps[0].p + 1, H[0], static_cast<const FlagArgs*>(dev_table), keys, n, flags, stream);
+    e = dispatch(fps[0].p + 1, H[0], static_cast<const FlagArgs*>(dev_table), keys, Count{n, nullptr},
+                 flags, stream);
+  if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("flag launch: ") + hipGetErrorString(e));
+  return LT_OK;
+}
+
+// Host table of per-mesh parameters (validated) for a later upload.
+lt_status fill_flag_table(const KeyGeom& g, const lt_flag_params* fps, int nmesh, void* host_table) {
+  FlagArgs* H = static_cast<FlagArgs*>(host_table);
+  for (int m = 0; m < nmesh; ++m) {
+    LT_TRY_STATUS(fill_args(g, &fps[m], &H[m]));
+    if (fps[m].p != fps[0].p) return fail(LT_ERR_ARG, "every mesh of an ensemble flag call needs the same p");
+  }
+  return LT_OK;
+}
+
+// Flags from the parameters in dev_table (one entry per mesh), over a count
+// that may live on the device; fp0 fixes the degree and the geometry.
+lt_status launch_flag_table(const KeyGeom& g, const lt_flag_params* fp0, const void* dev_table,
+                            const uint64_t* keys, Count n, int8_t* flags, hipStream_t stream) {
+  FlagArgs A;
+  LT_TRY_STATUS(fill_args(g, fp0, &A));
+  if (n.n == 0) return LT_OK;
+  const hipError_t e = dispatch(fp0->p + 1, A, static_cast<const FlagArgs*>(dev_table), keys, n, flags,
+                                stream);
   if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("flag launch: ") + hipGetErrorString(e));
   return LT_OK;
 }

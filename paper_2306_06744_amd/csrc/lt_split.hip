@@ -377,7 +377,7 @@ lt_status launch_split_transfer(lt_tree_s* t, int p, int nvar, const double* u_o
   LT_TRY_STATUS(grow(&t->split_F, &t->split_F_cap, n));
   ScanState st;
   LT_TRY_STATUS(prep_scan(t, n, s, 0, &st));
-  k_split_lists<<<unsigned(st.ntiles), kBlock, 0, s>>>(t->map_kind, n, t->split_R, t->split_F, st);
+  k_split_lists<<<grid_tiles(st), kBlock, 0, s>>>(t->map_kind, n, t->split_R, t->split_F, st);
   const bf16x8* fr = static_cast<const bf16x8*>(t->split_frags);
   const bf16x8* fI = fr;
   const bf16x8* fP = fr + size_t(nc) * 3 * kMT * kKS * 64;

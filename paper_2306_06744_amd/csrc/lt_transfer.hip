@@ -144,9 +144,10 @@ __device__ inline void tensor_apply(const double* __restrict__ Mx, const double*
 template <int DIM, int N>
 __global__ __launch_bounds__(256) void k_transfer(const double* __restrict__ ops,
                                                   const int32_t* __restrict__ src,
-                                                  const int8_t* __restrict__ kind, int64_t n,
+                                                  const int8_t* __restrict__ kind, Count cn,
                                                   const double* __restrict__ uo, int64_t ldo,
                                                   double* __restrict__ un, int64_t ldn) {
+  const int64_t n = cn.get();
   constexpr int NP = DIM == 3 ? N * N * N : N * N;
   constexpr int NC = 1 << DIM;
   const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -210,10 +211,15 @@ constexpr int kCopyChunk = 512;
 constexpr int64_t kImpure = INT64_MIN;
 
 __global__ __launch_bounds__(256) void k_copy_chunks(const int32_t* __restrict__ src,
-                                                     const int8_t* __restrict__ kind, int64_t n,
+                                                     const int8_t* __restrict__ kind, Count cn,
                                                      int64_t* __restrict__ cdelta) {
+  const int64_t n = cn.get();
   const int64_t c = blockIdx.x;
   const int64_t j0 = c * kCopyChunk;
+  if (j0 >= n) {  // launches sized for a capacity: chunks past the end
+    if (threadIdx.x == 0) cdelta[c] = kImpure;
+    return;
+  }
   const bool head = kind[j0] == 0;
   const int64_t ref = head ? int64_t(src[j0]) - j0 : 0;
   bool ok = head;
@@ -231,11 +237,13 @@ __global__ __launch_bounds__(256) void k_copy_chunks(const int32_t* __restrict__
 // 16-byte pairs like a plain copy; impure chunks read the map per element and
 // move only the copy elements.  Output stores are streaming (non-temporal).
 __global__ __launch_bounds__(256) void k_copy3(const int32_t* __restrict__ src,
-                                               const int8_t* __restrict__ kind, int64_t n,
+                                               const int8_t* __restrict__ kind, Count cn,
                                                const int64_t* __restrict__ cdelta,
                                                const double* __restrict__ uo, int64_t ldo,
                                                double* __restrict__ un, int64_t ldn) {
+  const int64_t n = cn.get();
   const int64_t c = xcd_chunk(blockIdx.x, gridDim.x);
+  if (c * kCopyChunk >= n) return;
   const int64_t j = c * kCopyChunk + int64_t(threadIdx.x) * 2;
   const double* U = uo + int64_t(blockIdx.y) * ldo;
   double* O = un + int64_t(blockIdx.y) * ldn;
@@ -282,10 +290,12 @@ __device__ inline void xy_pass(const double* Mx, const double* My, const double*
 
 // Groups of 64 consecutive new elements that hold any refined or fused
 // element, listed in order by a look-back scan (count 1 per such group).
-__global__ __launch_bounds__(kBlock) void k_group_list(const int8_t* __restrict__ kind, int64_t n,
-                                                       int64_t ngroups, int32_t* __restrict__ list,
-                                                       ScanState st) {
+__global__ __launch_bounds__(kBlock) void k_group_list(const int8_t* __restrict__ kind, Count cn,
+                                                       int32_t* __restrict__ list, ScanState st) {
   const int64_t tile = take_ticket(st);
+  if (tile >= scan_tiles(st)) return;
+  const int64_t n = cn.get();
+  const int64_t ngroups = st.items.get();
   const int64_t base = tile * kTile + int64_t(threadIdx.x) * kItems;
   bool any[kItems];
   int64_t local = 0;
@@ -324,7 +334,7 @@ __global__ __launch_bounds__(kBlock) void k_group_list(const int8_t* __restrict_
 template <int N>
 __global__ __launch_bounds__(64 * N) void k_interp3(const double* __restrict__ ops,
                                                     const int32_t* __restrict__ src,
-                                                    const int8_t* __restrict__ kind, int64_t n,
+                                                    const int8_t* __restrict__ kind, Count cn,
                                                     const int32_t* __restrict__ groups,
                                                     const int64_t* __restrict__ ngroups,
                                                     const double* __restrict__ uo, int64_t ldo,
@@ -334,6 +344,7 @@ __global__ __launch_bounds__(64 * N) void k_interp3(const double* __restrict__ o
   __shared__ double T[N][NN][64];
   __shared__ double M[4][NN];  // A_0, A_1, P_0, P_1
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t n = cn.get();
   const int64_t ng = *ngroups;
   if (int64_t(blockIdx.x) >= ng) return;
   for (int i = threadIdx.x; i < 4 * NN; i += blockDim.x) M[i / NN][i % NN] = ops[i];
@@ -405,13 +416,13 @@ __global__ __launch_bounds__(64 * N) void k_interp3(const double* __restrict__ o
 }
 
 template <int DIM, int N>
-hipError_t launch(lt_tree_s* t, const double* ops, const int32_t* src, const int8_t* kind, int64_t n,
-                  int nvar, const double* uo, int64_t ldo, double* un, int64_t ldn, hipStream_t s,
-                  lt_status* st_out) {
+hipError_t launch(lt_tree_s* t, const double* ops, const int32_t* src, const int8_t* kind, Count n,
+                  const int64_t* ngroups_dev, int nvar, const double* uo, int64_t ldo, double* un,
+                  int64_t ldn, hipStream_t s, lt_status* st_out) {
   *st_out = LT_OK;
   if constexpr (DIM == 3) {
-    const int64_t ngroups = (n + 63) / 64;
-    *st_out = launch_copy(t, nvar * N * N * N, uo, ldo, un, ldn, s);
+    const int64_t ngroups = (n.n + 63) / 64;
+    *st_out = launch_copy(t, n, nvar * N * N * N, uo, ldo, un, ldn, s);
     if (*st_out != LT_OK) return hipSuccess;
     hipError_t e = hipSuccess;
     *st_out = grow(&t->grp_list, &t->grp_cap, ngroups);
@@ -419,14 +430,15 @@ hipError_t launch(lt_tree_s* t, const double* ops, const int32_t* src, const int
     ScanState st;
     *st_out = prep_scan(t, ngroups, s, 0, &st);
     if (*st_out != LT_OK) return hipSuccess;
-    k_group_list<<<unsigned(st.ntiles), kBlock, 0, s>>>(kind, n, ngroups, t->grp_list, st);
+    st.items.p = ngroups_dev;
+    k_group_list<<<grid_tiles(st), kBlock, 0, s>>>(kind, n, t->grp_list, st);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 gi{unsigned(std::min<int64_t>(ngroups, 2048)), unsigned(nvar), 1u};
+    const dim3 gi{unsigned(std::max<int64_t>(1, std::min<int64_t>(ngroups, 2048))), unsigned(nvar), 1u};
     k_interp3<N><<<gi, 64 * N, 0, s>>>(ops, src, kind, n, t->grp_list, st.total, uo, ldo, un, ldn);
     return hipGetLastError();
   } else {
-    dim3 grid(unsigned((n + 255) / 256), unsigned(nvar));
+    dim3 grid(unsigned((n.n + 255) / 256), unsigned(nvar));
     k_transfer<DIM, N><<<grid, 256, 0, s>>>(ops, src, kind, n, uo, ldo, un, ldn);
     return hipGetLastError();
   }
@@ -434,12 +446,11 @@ hipError_t launch(lt_tree_s* t, const double* ops, const int32_t* src, const int
 
 }  // namespace
 
-lt_status launch_copy(lt_tree_s* t, int64_t rows, const double* uo, int64_t ldo, double* un,
-                      int64_t ldn, hipStream_t s) {
-  const int64_t n = t->n_cur;
-  if (n == 0) return LT_OK;
+lt_status launch_copy(lt_tree_s* t, Count n, int64_t rows, const double* uo, int64_t ldo,
+                      double* un, int64_t ldn, hipStream_t s) {
+  if (n.n == 0) return LT_OK;
   if (rows < 1 || rows > 65535) return fail(LT_ERR_ARG, "copy pass: rows out of range");
-  const int64_t nchunks = (n + kCopyChunk - 1) / kCopyChunk;
+  const int64_t nchunks = (n.n + kCopyChunk - 1) / kCopyChunk;
   LT_TRY_STATUS(grow(&t->copy_delta, &t->copy_delta_cap, nchunks));
   k_copy_chunks<<<unsigned(nchunks), 256, 0, s>>>(t->map_src, t->map_kind, n, t->copy_delta);
   const dim3 grid{unsigned(nchunks), unsigned(rows), 1u};
@@ -465,20 +476,31 @@ lt_status build_transfer_ops(int p, double** ops, hipStream_t stream) {
   return LT_OK;
 }
 
+lt_status launch_copy(lt_tree_s* t, int64_t rows, const double* uo, int64_t ldo, double* un,
+                      int64_t ldn, hipStream_t s) {
+  return launch_copy(t, Count{t->n_cur, nullptr}, rows, uo, ldo, un, ldn, s);
+}
+
 lt_status launch_transfer(lt_tree_s* t, int p, const double* ops, int nvar, const double* u_old,
                           int64_t ld_old, double* u_new, int64_t ld_new, hipStream_t s) {
+  return launch_transfer(t, Count{t->n_cur, nullptr}, nullptr, p, ops, nvar, u_old, ld_old, u_new,
+                         ld_new, s);
+}
+
+lt_status launch_transfer(lt_tree_s* t, Count n, const int64_t* ngroups_dev, int p,
+                          const double* ops, int nvar, const double* u_old, int64_t ld_old,
+                          double* u_new, int64_t ld_new, hipStream_t s) {
   const int dim = t->g.dim;
   const int32_t* src = t->map_src;
   const int8_t* kind = t->map_kind;
-  const int64_t n = t->n_cur;
-  if (n == 0) return LT_OK;
+  if (n.n == 0) return LT_OK;
   int64_t npts = 1;
   for (int a = 0; a < dim; ++a) npts *= p + 1;
   if (nvar < 1 || int64_t(nvar) * npts > 65535)
     return fail(LT_ERR_ARG, "nvar * (p+1)^dim must be in [1, 65535]");
   hipError_t e = hipErrorInvalidValue;
   lt_status st = LT_OK;
-#define LT_L(D, NN) e = launch<D, NN>(t, ops, src, kind, n, nvar, u_old, ld_old, u_new, ld_new, s, &st)
+#define LT_L(D, NN) e = launch<D, NN>(t, ops, src, kind, n, ngroups_dev, nvar, u_old, ld_old, u_new, ld_new, s, &st)
   if (dim == 3) {
     switch (p) {
       case 1: LT_L(3, 2); break;

@@ -132,10 +132,12 @@ __global__ void k_validate(KeyGeom g, const uint64_t* __restrict__ keys, int64_t
 // complete all -1 family -> parent, other members of such a family -> nothing,
 // everything else -> itself.
 __global__ __launch_bounds__(kBlock) void k_adapt(KeyGeom g, const uint64_t* __restrict__ in,
-                                                  const int8_t* __restrict__ flags, int64_t n,
+                                                  const int8_t* __restrict__ flags,
                                                   uint64_t* __restrict__ out, int64_t cap,
                                                   ScanState st) {
   const int64_t tile = take_ticket(st);
+  if (tile >= scan_tiles(st)) return;
+  const int64_t n = st.items.get();
   const int64_t base = tile * kTile + int64_t(threadIdx.x) * kItems;
   const int nc = g.nchild();
   uint64_t key[kItems];
@@ -216,8 +218,9 @@ __global__ __launch_bounds__(kBlock) void k_adapt(KeyGeom g, const uint64_t* __r
 // Only leaves with bit 2 (new or re-checked) are examined unless check_all.
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_balance_mark(KeyGeom g, const uint64_t* __restrict__ keys,
-                                                         int64_t n, KeyDir D, uint32_t* mark,
+                                                         Count cn, KeyDir D, uint32_t* mark,
                                                          int check_all, DevCtr* ctr) {
+  const int64_t n = cn.get();
   // 2^DIM lanes per leaf, lane `sub` (1 .. 2^DIM - 1) probes one searching key.
   constexpr int SL = 1 << DIM;
   const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -264,8 +267,9 @@ __global__ __launch_bounds__(kBlock) void k_balance_mark(KeyGeom g, const uint64
 // Radix directory of a sorted key array (see KeyDir): leaf i owns the
 // buckets c with keys[i] <= c << shift < keys[i + 1].  Short spans are
 // written by their own lane, long ones (coarse leaves) by the whole wave.
-__global__ __launch_bounds__(256) void k_build_dir(const uint64_t* __restrict__ keys, int64_t n,
+__global__ __launch_bounds__(256) void k_build_dir(const uint64_t* __restrict__ keys, Count cn,
                                                    int shift, int64_t nb, int32_t* __restrict__ d) {
+  const int64_t n = cn.get();
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
   auto ceil_sh = [shift](uint64_t k) -> int64_t {
@@ -297,11 +301,13 @@ __global__ __launch_bounds__(256) void k_build_dir(const uint64_t* __restrict__ 
 // new mark array holds bit 2 for leaves to examine next pass: the children of
 // split leaves and the leaves that found a violation.
 __global__ __launch_bounds__(kBlock) void k_balance_refine(KeyGeom g, const uint64_t* __restrict__ in,
-                                                           const uint32_t* __restrict__ mark, int64_t n,
+                                                           const uint32_t* __restrict__ mark,
                                                            uint64_t* __restrict__ out,
                                                            uint32_t* __restrict__ mark_out, int64_t cap,
                                                            ScanState st) {
   const int64_t tile = take_ticket(st);
+  if (tile >= scan_tiles(st)) return;
+  const int64_t n = st.items.get();
   const int64_t base = tile * kTile + int64_t(threadIdx.x) * kItems;
   const int nc = g.nchild();
   uint32_t w[kItems];
@@ -356,8 +362,9 @@ __global__ __launch_bounds__(kBlock) void k_balance_refine(KeyGeom g, const uint
 // a bit mask.
 template <int DIM>
 __global__ __launch_bounds__(256) void k_connect_faces(KeyGeom g, const uint64_t* __restrict__ keys,
-                                                       int64_t n, KeyDir D, int32_t* __restrict__ nbr,
+                                                       Count cn, KeyDir D, int32_t* __restrict__ nbr,
                                                        uint8_t* __restrict__ hmask) {
+  const int64_t n = cn.get();
   constexpr int SL = 1 << DIM, NF = 2 * DIM;
   const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t e = tid / SL;
@@ -395,10 +402,12 @@ __global__ __launch_bounds__(256) void k_connect_faces(KeyGeom g, const uint64_t
 
 // Pass 2: hanging-face rows in (leaf, face) order: count from the masks,
 // decoupled look-back scan, then each row's leaf and face.
-__global__ __launch_bounds__(kBlock) void k_connect_rows(const uint8_t* __restrict__ hmask, int64_t n,
-                                                         int dim, int32_t* __restrict__ hang,
-                                                         int64_t cap_rows, ScanState st) {
+__global__ __launch_bounds__(kBlock) void k_connect_rows(const uint8_t* __restrict__ hmask, int dim,
+                                                         int32_t* __restrict__ hang, int64_t cap_rows,
+                                                         ScanState st) {
   const int64_t tile = take_ticket(st);
+  if (tile >= scan_tiles(st)) return;
+  const int64_t n = st.items.get();
   const int64_t base = tile * kTile + int64_t(threadIdx.x) * kItems;
   const int nf = 2 * dim;
   const int width = 2 + (1 << (dim - 1));
@@ -429,9 +438,10 @@ __global__ __launch_bounds__(kBlock) void k_connect_rows(const uint8_t* __restri
 // bits are the tangential child bits in axis order, lower axis first; the
 // fine leaves are the children of the same-size box on the side facing e.
 __global__ __launch_bounds__(256) void k_connect_fine(KeyGeom g, const uint64_t* __restrict__ keys,
-                                                      int64_t n, KeyDir D, int32_t* __restrict__ hang,
+                                                      Count cn, KeyDir D, int32_t* __restrict__ hang,
                                                       const int64_t* total, int64_t cap_rows,
                                                       unsigned* err) {
+  const int64_t n = cn.get();
   const int nh = 1 << (g.dim - 1);
   const int width = 2 + nh;
   const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -474,9 +484,10 @@ __global__ __launch_bounds__(256) void k_connect_fine(KeyGeom g, const uint64_t*
 
 // Old -> new mapping (Section 4.2): lower bound of each new key in the old tree.
 __global__ __launch_bounds__(kBlock) void k_map(KeyGeom g, const uint64_t* __restrict__ old_keys,
-                                                int64_t n_old, const uint64_t* __restrict__ keys,
-                                                int64_t n, int32_t* __restrict__ src,
+                                                Count cn_old, const uint64_t* __restrict__ keys,
+                                                Count cn, int32_t* __restrict__ src,
                                                 int8_t* __restrict__ kind, unsigned* err) {
+  const int64_t n_old = cn_old.get(), n = cn.get();
   const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const uint64_t key = keys[j];
@@ -506,13 +517,31 @@ __global__ __launch_bounds__(kBlock) void k_map(KeyGeom g, const uint64_t* __res
       return;
     }
   }
-  src[j] = -1;
+  // fits none of the three cases (the old tree was not balanced): report it;
+  // the entry stays a valid index so that a captured transfer reads in bounds
+  src[j] = 0;
   kind[j] = 0;
   atomicOr(err, ERR_MAP);
 }
 
 // ------------------------------------------------------------------ host helpers
 }  // namespace
+
+void dir_params(const KeyGeom& g, int64_t n, int* shift, int64_t* nb) {
+  int kb = g.mesh_shift;
+  if (g.nmesh > 1) {
+    int mbits = 0;
+    while ((int64_t(1) << mbits) < g.nmesh) ++mbits;
+    kb += mbits;
+  }
+  kb = std::min(kb, 64);
+  int L = 0;
+  while (L < 62 && (int64_t(1) << L) < n) ++L;
+  L = std::max(10, std::min(24, L - 1));
+  L = std::min(L, kb);
+  *shift = kb - L;
+  *nb = int64_t(1) << L;
+}
 
 lt_status prep_scan(lt_tree t, int64_t n_items, hipStream_t stream, int clear_err, ScanState* st) {
   const int64_t ntiles = std::max<int64_t>(1, ceil_div(n_items, kTile));
@@ -524,7 +553,7 @@ lt_status prep_scan(lt_tree t, int64_t n_items, hipStream_t stream, int clear_er
   st->ticket = &t->dctr->ticket;
   st->err = &t->dctr->err;
   st->total = &t->dctr->total;
-  st->ntiles = ntiles;
+  st->items = Count{n_items, nullptr};
   return LT_OK;
 }
 
@@ -599,23 +628,11 @@ void invalidate(lt_tree t) {
 lt_status ensure_dir(lt_tree t, hipStream_t s, KeyDir* D) {
   const int64_t n = t->n_cur;
   if (!t->dir_valid) {
-    int kb = t->g.mesh_shift;
-    if (t->g.nmesh > 1) {
-      int mbits = 0;
-      while ((int64_t(1) << mbits) < t->g.nmesh) ++mbits;
-      kb += mbits;
-    }
-    kb = std::min(kb, 64);
-    int L = 0;
-    while (L < 62 && (int64_t(1) << L) < n) ++L;
-    L = std::max(10, std::min(24, L - 1));
-    L = std::min(L, kb);
-    t->dir_shift = kb - L;
-    t->dir_nb = int64_t(1) << L;
+    dir_params(t->g, n, &t->dir_shift, &t->dir_nb);
     LT_TRY(grow(&t->dir, &t->dir_cap, t->dir_nb + 1));
     if (n > 0) {
-      k_build_dir<<<unsigned(ceil_div(n, 256)), 256, 0, s>>>(t->kbuf[t->cur], n, t->dir_shift,
-                                                             t->dir_nb, t->dir);
+      k_build_dir<<<unsigned(ceil_div(n, 256)), 256, 0, s>>>(t->kbuf[t->cur], Count{n, nullptr},
+                                                             t->dir_shift, t->dir_nb, t->dir);
       LT_HIP(hipGetLastError());
     }
     t->dir_valid = true;
@@ -633,8 +650,8 @@ lt_status do_map(lt_tree t, hipStream_t stream) {
   LT_TRY(clear_err(t, stream));
   if (t->n_cur > 0)
     k_map<<<unsigned(ceil_div(t->n_cur, kBlock)), kBlock, 0, stream>>>(
-        t->g, t->kbuf[t->old], t->n_old, t->kbuf[t->cur], t->n_cur, t->map_src, t->map_kind,
-        &t->dctr->err);
+        t->g, t->kbuf[t->old], Count{t->n_old, nullptr}, t->kbuf[t->cur], Count{t->n_cur, nullptr},
+        t->map_src, t->map_kind, &t->dctr->err);
   LT_HIP(hipGetLastError());
   LT_TRY(read_ctr(t, stream));
   if (t->hctr->err & ERR_MAP)
@@ -644,6 +661,107 @@ lt_status do_map(lt_tree t, hipStream_t stream) {
   t->map_valid = true;
   return LT_OK;
 }
+
+// ---------------------------------------------------------- captured cycles
+// Single-thread bookkeeping kernels of a cycle whose counts stay on the device.
+__global__ void k_commit(int64_t* dst, const int64_t* src, int64_t cap, unsigned* err) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int64_t v = *src;
+  if (v > cap) atomicOr(err, ERR_CAPACITY);
+  *dst = v > cap ? cap : v;
+}
+
+__global__ void k_copy_count(int64_t* dst, const int64_t* src) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
+__global__ void k_groups_of(int64_t* dst, const int64_t* n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = (*n + 63) / 64;
+}
+
+__global__ void k_check_marks(DevCtr* ctr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && ctr->nmarked != 0) atomicOr(&ctr->err, ERR_BALANCE_PASSES);
+}
+
+__global__ void k_copy_keys(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst, Count cn,
+                            const unsigned* err) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (*err != 0) return;  // keep the pre-cycle keys for the host's recovery
+  if (i < cn.get()) dst[i] = src[i];
+}
+
+}  // namespace
+
+lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
+  const KeyGeom& g = t->g;
+  const int64_t C = r.cap;
+  int64_t* S = r.dsz;
+  uint64_t* K0 = t->kbuf[0];
+  uint64_t* K[2] = {t->kbuf[1], t->kbuf[2]};
+  const unsigned nb256 = unsigned(ceil_div(C, 256));
+  const unsigned nlanes = unsigned(ceil_div(C * g.nchild(), 256));
+  unsigned* err = &t->dctr->err;
+  int8_t* F = t->map_kind;  // the flags live in the kind array until the mapping overwrites it
+  // flags (parameters from the device table)
+  LT_TRY(launch_flag_table(g, &r.fp0, t->flag_tab, K0, Count{C, &S[0]}, F, s));
+  k_copy_count<<<1, 64, 0, s>>>(&S[1], &S[0]);
+  // adapt K0 -> K[0]
+  ScanState st;
+  LT_TRY(prep_scan(t, C, s, 1, &st));
+  st.items.p = &S[1];
+  k_adapt<<<grid_tiles(st), kBlock, 0, s>>>(g, K0, F, K[0], C, st);
+  k_commit<<<1, 64, 0, s>>>(&S[0], &t->dctr->total, C, err);
+  LT_HIP(hipGetLastError());
+  // balance: fixed passes, then a check
+  const KeyDir D{t->dir, r.dir_shift, r.dir_nb};
+  k_fill_u32<<<nb256, 256, 0, s>>>(t->mbuf[0], C, 0u);
+  int ki = 0, mi = 0;
+  for (int pass = 0; pass <= r.passes; ++pass) {
+    k_build_dir<<<nb256, 256, 0, s>>>(K[ki], Count{C, &S[0]}, r.dir_shift, r.dir_nb, t->dir);
+    if (g.dim == 3)
+      k_balance_mark<3><<<nlanes, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi],
+                                                  pass == 0 ? 1 : 0, t->dctr);
+    else
+      k_balance_mark<2><<<nlanes, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi],
+                                                  pass == 0 ? 1 : 0, t->dctr);
+    if (pass == r.passes) break;
+    LT_TRY(prep_scan(t, C, s, 0, &st));
+    st.items.p = &S[0];
+    k_balance_refine<<<grid_tiles(st), kBlock, 0, s>>>(g, K[ki], t->mbuf[mi], K[1 - ki],
+                                                        t->mbuf[1 - mi], C, st);
+    k_commit<<<1, 64, 0, s>>>(&S[0], &t->dctr->total, C, err);
+    ki = 1 - ki;
+    mi = 1 - mi;
+  }
+  k_check_marks<<<1, 64, 0, s>>>(t->dctr);
+  LT_HIP(hipGetLastError());
+  if (ki != 0) return fail(LT_ERR_ARG, "balance passes of a captured cycle must be even");
+  // connect (the directory of K[0] was built by the check pass)
+  if (g.dim == 3)
+    k_connect_faces<3><<<nlanes, 256, 0, s>>>(g, K[0], Count{C, &S[0]}, D, t->nbr, t->hmask);
+  else
+    k_connect_faces<2><<<nlanes, 256, 0, s>>>(g, K[0], Count{C, &S[0]}, D, t->nbr, t->hmask);
+  LT_TRY(prep_scan(t, C, s, 0, &st));
+  st.items.p = &S[0];
+  k_connect_rows<<<grid_tiles(st), kBlock, 0, s>>>(t->hmask, g.dim, t->hang, r.hang_rows, st);
+  const int nh = 1 << (g.dim - 1);
+  k_connect_fine<<<unsigned(ceil_div(r.hang_rows * nh, 256)), 256, 0, s>>>(
+      g, K[0], Count{C, &S[0]}, D, t->hang, &t->dctr->total, r.hang_rows, err);
+  k_commit<<<1, 64, 0, s>>>(&S[2], &t->dctr->total, r.hang_rows, err);
+  // map
+  k_map<<<unsigned(ceil_div(C, kBlock)), kBlock, 0, s>>>(g, K0, Count{C, &S[1]}, K[0], Count{C, &S[0]},
+                                                         t->map_src, t->map_kind, err);
+  LT_HIP(hipGetLastError());
+  // transfer
+  k_groups_of<<<1, 64, 0, s>>>(&S[3], &S[0]);
+  LT_TRY(launch_transfer(t, Count{C, &S[0]}, &S[3], r.p, r.ops, r.nvar, r.uo, C, r.un, C, s));
+  // the new keys become the next cycle's input
+  k_copy_keys<<<nb256, 256, 0, s>>>(K[0], K0, Count{C, &S[0]}, err);
+  LT_HIP(hipGetLastError());
+  return LT_OK;
+}
+
+namespace {
 
 }  // namespace
 }  // namespace lt
@@ -813,8 +931,8 @@ lt_status lt_adapt(lt_tree t, const int8_t* flags, void* stream) {
   LT_TRY(grow(&t->kbuf[t->tmp], &t->kcap[t->tmp], n * t->g.nchild()));
   ScanState st;
   LT_TRY(prep_scan(t, n, s, 1, &st));
-  k_adapt<<<unsigned(st.ntiles), kBlock, 0, s>>>(t->g, t->kbuf[t->cur], flags, n, t->kbuf[t->tmp],
-                                                   t->kcap[t->tmp], st);
+  k_adapt<<<grid_tiles(st), kBlock, 0, s>>>(t->g, t->kbuf[t->cur], flags, t->kbuf[t->tmp],
+                                              t->kcap[t->tmp], st);
   LT_HIP(hipGetLastError());
   LT_TRY(read_ctr(t, s));
   if (t->hctr->err & ERR_BAD_FLAG) return fail(LT_ERR_ARG, "flags must be -1, 0 or 1");
@@ -851,11 +969,11 @@ lt_status lt_balance(lt_tree t, void* stream) {
     if (t->n_cur > 0) {
       const unsigned blocks = unsigned(ceil_div(t->n_cur * t->g.nchild(), kBlock));
       if (t->g.dim == 3)
-        k_balance_mark<3><<<blocks, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], t->n_cur, D,
-                                                    t->mbuf[mi], pass == 0 ? 1 : 0, t->dctr);
+        k_balance_mark<3><<<blocks, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], Count{t->n_cur, nullptr},
+                                                    D, t->mbuf[mi], pass == 0 ? 1 : 0, t->dctr);
       else
-        k_balance_mark<2><<<blocks, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], t->n_cur, D,
-                                                    t->mbuf[mi], pass == 0 ? 1 : 0, t->dctr);
+        k_balance_mark<2><<<blocks, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], Count{t->n_cur, nullptr},
+                                                    D, t->mbuf[mi], pass == 0 ? 1 : 0, t->dctr);
       LT_HIP(hipGetLastError());
     }
     LT_TRY(read_ctr(t, s));
@@ -870,9 +988,8 @@ lt_status lt_balance(lt_tree t, void* stream) {
     ScanState st;
     LT_TRY(prep_scan(t, t->n_cur, s, 0, &st));  // also zeroes the mark count for the next pass
     const int64_t cap = std::min(t->kcap[t->tmp], t->mcap[1 - mi]);
-    k_balance_refine<<<unsigned(st.ntiles), kBlock, 0, s>>>(t->g, t->kbuf[t->cur], t->mbuf[mi],
-                                                             t->n_cur, t->kbuf[t->tmp],
-                                                             t->mbuf[1 - mi], cap, st);
+    k_balance_refine<<<grid_tiles(st), kBlock, 0, s>>>(t->g, t->kbuf[t->cur], t->mbuf[mi],
+                                                        t->kbuf[t->tmp], t->mbuf[1 - mi], cap, st);
     LT_HIP(hipGetLastError());
     expect_total = n_new;
     std::swap(t->cur, t->tmp);
@@ -899,9 +1016,11 @@ lt_status lt_connect(lt_tree t, void* stream) {
   if (n > 0) {
     const unsigned blocks = unsigned(ceil_div(n * t->g.nchild(), 256));
     if (t->g.dim == 3)
-      k_connect_faces<3><<<blocks, 256, 0, s>>>(t->g, t->kbuf[t->cur], n, D, t->nbr, t->hmask);
+      k_connect_faces<3><<<blocks, 256, 0, s>>>(t->g, t->kbuf[t->cur], Count{n, nullptr}, D, t->nbr,
+                                                t->hmask);
     else
-      k_connect_faces<2><<<blocks, 256, 0, s>>>(t->g, t->kbuf[t->cur], n, D, t->nbr, t->hmask);
+      k_connect_faces<2><<<blocks, 256, 0, s>>>(t->g, t->kbuf[t->cur], Count{n, nullptr}, D, t->nbr,
+                                                t->hmask);
     LT_HIP(hipGetLastError());
   }
   const int nh = 1 << (t->g.dim - 1);
@@ -910,12 +1029,12 @@ lt_status lt_connect(lt_tree t, void* stream) {
     const int64_t cap_rows = t->hang_cap / width;
     ScanState st;
     LT_TRY(prep_scan(t, n, s, 1, &st));
-    k_connect_rows<<<unsigned(st.ntiles), kBlock, 0, s>>>(t->hmask, n, t->g.dim, t->hang, cap_rows,
-                                                           st);
+    k_connect_rows<<<grid_tiles(st), kBlock, 0, s>>>(t->hmask, t->g.dim, t->hang, cap_rows, st);
     LT_HIP(hipGetLastError());
     // fine leaves of the rows the table holds (the row count stays on the device)
     k_connect_fine<<<unsigned(ceil_div(cap_rows * nh, 256)), 256, 0, s>>>(
-        t->g, t->kbuf[t->cur], n, D, t->hang, &t->dctr->total, cap_rows, &t->dctr->err);
+        t->g, t->kbuf[t->cur], Count{n, nullptr}, D, t->hang, &t->dctr->total, cap_rows,
+        &t->dctr->err);
     LT_HIP(hipGetLastError());
     LT_TRY(read_ctr(t, s));
     if (t->hctr->err & ERR_UNBALANCED)

@@ -27,15 +27,31 @@ enum : unsigned {
   ERR_INVALID_TREE = 1u << 3,
   ERR_MAP = 1u << 4,
   ERR_CAPACITY = 1u << 5,
+  ERR_BALANCE_PASSES = 1u << 6,  // a captured cycle's fixed balance passes did not converge
+};
+
+// A number of items known either on the host (p null) or only on the device
+// (p points at it; the launch is then sized for the capacity n).
+struct Count {
+  int64_t n;
+  const int64_t* p;
+  __device__ int64_t get() const { return p ? *p : n; }
 };
 
 struct ScanState {
-  uint64_t* status;       // one word per tile
+  uint64_t* status;       // one word per tile of the launch
   unsigned long long* ticket;
   unsigned* err;
   int64_t* total;         // written by the last tile: sum of all counts
-  int64_t ntiles;
+  Count items;            // items scanned; tiles = max(1, ceil(items / kTile))
 };
+
+// Tiles that hold items (>= 1).  Launches sized for a capacity have more
+// workgroups than this; the extra ones take a ticket and leave at once.
+__device__ inline int64_t scan_tiles(const ScanState& st) {
+  const int64_t n = st.items.get();
+  return n > 0 ? (n + kTile - 1) / kTile : 1;
+}
 
 constexpr uint64_t kStAgg = uint64_t(1) << 62;
 constexpr uint64_t kStInc = uint64_t(2) << 62;
@@ -133,12 +149,18 @@ __device__ inline int64_t tile_prefix(const ScanState& st, int64_t tile, int64_t
       if (lane == 0) st_status(&st.status[tile], kStInc | uint64_t(excl + aggregate));
     }
     if (lane == 0) {
-      if (tile == st.ntiles - 1) *st.total = excl + aggregate;
+      if (tile == scan_tiles(st) - 1) *st.total = excl + aggregate;
       s_prefix = excl;
     }
   }
   __syncthreads();
   return s_prefix;
+}
+
+// Workgroups of a scan launch: one per tile of the (host) item count or capacity.
+inline unsigned grid_tiles(const ScanState& st) {
+  const int64_t n = st.items.n;
+  return unsigned(n > 0 ? (n + kTile - 1) / kTile : 1);
 }
 
 __device__ inline int64_t take_ticket(const ScanState& st) {

@@ -40,6 +40,35 @@ size_t flag_args_size();
 lt_status launch_flag_batch(const KeyGeom& g, const lt_flag_params* fps, int nmesh, void* dev_table,
                             const uint64_t* keys, int64_t n, int8_t* flags, hipStream_t stream);
 
+// Validated per-mesh flag parameters written to host_table (flag_args_size()
+// bytes per mesh), and flags from a device copy of such a table over a count
+// that may live on the device (captured cycles).
+lt_status fill_flag_table(const KeyGeom& g, const lt_flag_params* fps, int nmesh, void* host_table);
+lt_status launch_flag_table(const KeyGeom& g, const lt_flag_params* fp0, const void* dev_table,
+                            const uint64_t* keys, Count n, int8_t* flags, hipStream_t stream);
+
+// One whole cycle recorded on a stream with every count kept on the device
+// (for capture in a graph): flags from the device table, adapt kbuf[0] ->
+// kbuf[1], `passes` (even) balance passes between kbuf[1] and kbuf[2] and a
+// check pass, connect, map, transfer uo -> un, then the new keys copied back
+// to kbuf[0] (skipped when an error bit is set).  dsz[0] = leaves,
+// dsz[1] = leaves before the cycle, dsz[2] = hanging rows, dsz[3] = groups of
+// 64 leaves.  Every buffer must already hold `cap` leaves (no allocation).
+struct CycleRec {
+  int64_t cap;        // leaves
+  int64_t hang_rows;  // rows of the hanging-face table
+  int passes;
+  int p, nvar;
+  const double* uo;
+  double* un;
+  lt_flag_params fp0;  // degree and geometry of the flags (the centres come from the table)
+  int64_t* dsz;
+  const double* ops;
+  int dir_shift;
+  int64_t dir_nb;
+};
+lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s);
+
 // Builds (once per degree) the FP64 1D transfer operators into ops.
 lt_status build_transfer_ops(int p, double** ops, hipStream_t stream);
 
@@ -78,6 +107,8 @@ lt_status prep_scan(lt_tree_s* t, int64_t n_items, hipStream_t stream, int clear
 lt_status read_ctr(lt_tree_s* t, hipStream_t stream);
 // Zero the counters and the error word.
 lt_status clear_err(lt_tree_s* t, hipStream_t stream);
+// Key-directory size for n leaves: 2^L buckets of 2^shift key values.
+void dir_params(const KeyGeom& g, int64_t n, int* shift, int64_t* nb);
 
 // Split-precision (BF16 x 3 on MFMA, FP64 cell means) transfer; asynchronous.
 lt_status launch_split_transfer(lt_tree_s* t, int p, int nvar, const double* u_old, int64_t ld_old,
@@ -90,6 +121,15 @@ lt_status launch_transfer(lt_tree_s* t, int p, const double* ops, int nvar, cons
 // asynchronous.
 lt_status launch_copy(lt_tree_s* t, int64_t rows, const double* uo, int64_t ldo, double* un,
                       int64_t ldn, hipStream_t s);
+lt_status launch_copy(lt_tree_s* t, Count n, int64_t rows, const double* uo, int64_t ldo,
+                      double* un, int64_t ldn, hipStream_t s);
+
+// Transfer over n new leaves given as a Count (a device count with the
+// launch sized for its capacity n.n); ngroups_dev, when set, holds
+// ceil(count / 64) on the device.  Asynchronous; no host synchronisation.
+lt_status launch_transfer(lt_tree_s* t, Count n, const int64_t* ngroups_dev, int p,
+                          const double* ops, int nvar, const double* u_old, int64_t ld_old,
+                          double* u_new, int64_t ld_new, hipStream_t s);
 
 }  // namespace lt
 
