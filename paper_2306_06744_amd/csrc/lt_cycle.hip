@@ -244,16 +244,16 @@ lt_status lt_cycle_run(lt_cycle c, const lt_flag_params* fp, void* stream, int* 
   }
   // The keys before the cycle are intact in kbuf[0] (the final copy is
   // skipped on any error).
-  if (err & ~(ERR_CAPACITY | ERR_BALANCE_PASSES)) {
-    t->n_cur = c->hsz[1];
-    t->dir_valid = t->conn_valid = t->map_valid = false;
-    return fail(LT_ERR_INTERNAL, "device check failed in a captured cycle");
-  }
-  if (err & ERR_CAPACITY) {
+  if (err & ERR_CAPACITY) {  // later checks failing on truncated arrays are its consequences
     t->n_cur = c->hsz[1];
     t->dir_valid = t->conn_valid = t->map_valid = false;
     t->n_hang = -1;
     return fail(LT_ERR_CAPACITY, "a captured cycle outgrew its capacity; the tree is unchanged");
+  }
+  if (err & ~ERR_BALANCE_PASSES) {
+    t->n_cur = c->hsz[1];
+    t->dir_valid = t->conn_valid = t->map_valid = false;
+    return fail(LT_ERR_INTERNAL, "device check failed in a captured cycle");
   }
   // The fixed balance passes stopped short of the fixpoint: finish eagerly
   // from the partly balanced keys in kbuf[1].

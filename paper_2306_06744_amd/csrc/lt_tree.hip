@@ -219,81 +219,96 @@ __global__ __launch_bounds__(kBlock) void k_adapt(KeyGeom g, const uint64_t* __r
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_balance_mark(KeyGeom g, const uint64_t* __restrict__ keys,
                                                          Count cn, KeyDir D, uint32_t* mark,
-                                                         int check_all, DevCtr* ctr) {
-  const int64_t n = cn.get();
-  // 2^DIM lanes per leaf, lane `sub` (1 .. 2^DIM - 1) probes one searching key.
+                                                         int check_all, DevCtr* ctr,
+                                                         const unsigned* conv) {
+  // 2^DIM lanes per leaf, lane `sub` (1 .. 2^DIM - 1) probes one searching key;
+  // waves stride over the (leaf, sub) pairs.  `conv` (captured cycles): the
+  // fixpoint was already reached, nothing to examine.
+  if (conv && *conv) return;
   constexpr int SL = 1 << DIM;
-  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t i = tid / SL;
-  const int sub = int(tid % SL);
+  const int64_t n = cn.get();
+  const int64_t lanes = n * SL;
   const int lane = threadIdx.x & 63;
-  bool viol = false, fresh = false;
   const int limit = g.balance == 0 ? 1 : (g.balance == 1 ? 2 : 3);
-  if (i < n && sub != 0 && __popc(unsigned(sub)) <= limit && (check_all || (mark[i] & 4u))) {
-    const uint64_t key = keys[i];
-    const int d = key_depth(g, key);
-    if (d >= 2) {
-      uint64_t x[3];
-      demorton(g, key_morton(g, key), x);
-      const uint64_t mhi = key_mesh_bits(g, key) >> g.mb;
-      const uint64_t S = uint64_t(1) << (g.dmax - d + 1);  // parent size
-      uint64_t q[3] = {0, 0, 0};
-      bool ok = true;
+  unsigned long long nfresh = 0;
+  for (int64_t wb = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63); wb < lanes;
+       wb += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t tid = wb + lane;
+    const int64_t i = tid / SL;
+    const int sub = int(tid % SL);
+    bool viol = false, fresh = false;
+    if (i < n && sub != 0 && __popc(unsigned(sub)) <= limit && (check_all || (mark[i] & 4u))) {
+      const uint64_t key = keys[i];
+      const int d = key_depth(g, key);
+      if (d >= 2) {
+        uint64_t x[3];
+        demorton(g, key_morton(g, key), x);
+        const uint64_t mhi = key_mesh_bits(g, key) >> g.mb;
+        const uint64_t S = uint64_t(1) << (g.dmax - d + 1);  // parent size
+        uint64_t q[3] = {0, 0, 0};
+        bool ok = true;
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) {
-        const uint64_t pa = x[a] & ~(S - 1);
-        q[a] = pa;
-        if ((sub >> a) & 1) {
-          const bool up = (x[a] >> (g.dmax - d)) & 1;
-          ok = ok && shift_coord(g, a, pa, up ? int64_t(S) : -int64_t(S), &q[a]);
+        for (int a = 0; a < DIM; ++a) {
+          const uint64_t pa = x[a] & ~(S - 1);
+          q[a] = pa;
+          if ((sub >> a) & 1) {
+            const bool up = (x[a] >> (g.dmax - d)) & 1;
+            ok = ok && shift_coord(g, a, pa, up ? int64_t(S) : -int64_t(S), &q[a]);
+          }
         }
-      }
-      if (ok) {
-        const int64_t j = dir_last_le(keys, n, D, point_key(g, morton(g, q) | mhi));
-        if (j >= 0 && key_depth(g, keys[j]) < d - 1) {
-          const uint32_t was = atomicOr(&mark[j], 1u);
-          fresh = !(was & 1u);
-          viol = true;
+        if (ok) {
+          const int64_t j = dir_last_le(keys, n, D, point_key(g, morton(g, q) | mhi));
+          if (j >= 0 && key_depth(g, keys[j]) < d - 1) {
+            const uint32_t was = atomicOr(&mark[j], 1u);
+            fresh = !(was & 1u);
+            viol = true;
+          }
         }
       }
     }
+    const uint64_t vb = __ballot(viol);
+    const uint64_t fb = __ballot(fresh);
+    if (sub == 0 && i < n && ((vb >> lane) & ((uint64_t(1) << SL) - 1))) atomicOr(&mark[i], 2u);
+    nfresh += __popcll(fb);
   }
-  const uint64_t vb = __ballot(viol);
-  const uint64_t fb = __ballot(fresh);
-  if (sub == 0 && i < n && ((vb >> lane) & ((uint64_t(1) << SL) - 1))) atomicOr(&mark[i], 2u);
-  if (lane == 0 && fb) atomicAdd(&ctr->nmarked, (unsigned long long)__popcll(fb));
+  if (lane == 0 && nfresh) atomicAdd(&ctr->nmarked, nfresh);
 }
 
 // Radix directory of a sorted key array (see KeyDir): leaf i owns the
 // buckets c with keys[i] <= c << shift < keys[i + 1].  Short spans are
 // written by their own lane, long ones (coarse leaves) by the whole wave.
 __global__ __launch_bounds__(256) void k_build_dir(const uint64_t* __restrict__ keys, Count cn,
-                                                   int shift, int64_t nb, int32_t* __restrict__ d) {
+                                                   int shift, int64_t nb, int32_t* __restrict__ d,
+                                                   const unsigned* conv) {
+  if (conv && *conv) return;  // captured cycles: keys unchanged since the last build
   const int64_t n = cn.get();
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
   auto ceil_sh = [shift](uint64_t k) -> int64_t {
     const uint64_t mask = (uint64_t(1) << shift) - 1;
     return int64_t(k >> shift) + ((k & mask) ? 1 : 0);
   };
-  int64_t c0 = 0, c1 = 0;
-  if (i < n) {
-    c0 = ceil_sh(keys[i]);
-    c1 = i + 1 < n ? ceil_sh(keys[i + 1]) : nb + 1;
-    c1 = c1 < nb + 1 ? c1 : nb + 1;
-    c0 = c0 < c1 ? c0 : c1;
-    if (i == 0)
-      for (int64_t c = 0, e = c0; c < e; ++c) d[c] = -1;
-  }
-  const bool big = c1 - c0 > 8;
-  if (!big)
-    for (int64_t c = c0; c < c1; ++c) d[c] = int32_t(i);
-  uint64_t bm = __ballot(big);
-  while (bm) {
-    const int l = __ffsll((unsigned long long)bm) - 1;
-    bm &= bm - 1;
-    const int64_t a = __shfl(c0, l), b = __shfl(c1, l), v = __shfl(i, l);
-    for (int64_t c = a + lane; c < b; c += 64) d[c] = int32_t(v);
+  for (int64_t wb = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63); wb < n;
+       wb += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t i = wb + lane;
+    int64_t c0 = 0, c1 = 0;
+    if (i < n) {
+      c0 = ceil_sh(keys[i]);
+      c1 = i + 1 < n ? ceil_sh(keys[i + 1]) : nb + 1;
+      c1 = c1 < nb + 1 ? c1 : nb + 1;
+      c0 = c0 < c1 ? c0 : c1;
+      if (i == 0)
+        for (int64_t c = 0, e = c0; c < e; ++c) d[c] = -1;
+    }
+    const bool big = c1 - c0 > 8;
+    if (!big)
+      for (int64_t c = c0; c < c1; ++c) d[c] = int32_t(i);
+    uint64_t bm = __ballot(big);
+    while (bm) {
+      const int l = __ffsll((unsigned long long)bm) - 1;
+      bm &= bm - 1;
+      const int64_t a = __shfl(c0, l), b = __shfl(c1, l), v = __shfl(i, l);
+      for (int64_t c = a + lane; c < b; c += 64) d[c] = int32_t(v);
+    }
   }
 }
 
@@ -304,7 +319,21 @@ __global__ __launch_bounds__(kBlock) void k_balance_refine(KeyGeom g, const uint
                                                            const uint32_t* __restrict__ mark,
                                                            uint64_t* __restrict__ out,
                                                            uint32_t* __restrict__ mark_out, int64_t cap,
-                                                           ScanState st) {
+                                                           ScanState st, const unsigned* conv) {
+  if (conv && *conv) {
+    // captured cycles past the fixpoint: the pass is the identity, a plain copy
+    const int64_t n = st.items.get();
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int64_t i = int64_t(blockIdx.x) * kTile + int64_t(k) * kBlock + threadIdx.x;
+      if (i < n) {
+        out[i] = in[i];
+        mark_out[i] = 0u;
+      }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *st.total = n;
+    return;
+  }
   const int64_t tile = take_ticket(st);
   if (tile >= scan_tiles(st)) return;
   const int64_t n = st.items.get();
@@ -364,40 +393,44 @@ template <int DIM>
 __global__ __launch_bounds__(256) void k_connect_faces(KeyGeom g, const uint64_t* __restrict__ keys,
                                                        Count cn, KeyDir D, int32_t* __restrict__ nbr,
                                                        uint8_t* __restrict__ hmask) {
-  const int64_t n = cn.get();
   constexpr int SL = 1 << DIM, NF = 2 * DIM;
-  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t e = tid / SL;
-  const int f = int(tid % SL);
+  const int64_t n = cn.get();
+  const int64_t lanes = n * SL;
   const int lane = threadIdx.x & 63;
-  bool hanging = false;
-  if (e < n && f < NF) {
-    const uint64_t key = keys[e];
-    const int d = key_depth(g, key);
-    uint64_t x[3];
-    demorton(g, key_morton(g, key), x);
-    const uint64_t mhi = key_mesh_bits(g, key) >> g.mb;
-    const int64_t sz = int64_t(1) << (g.dmax - d);
-    const int a = f >> 1;
-    uint64_t q[3] = {x[0], x[1], x[2]};
-    int32_t v;
-    if (!shift_coord(g, a, x[a], (f & 1) ? sz : -sz, &q[a])) {
-      v = -2;
-    } else {
-      const int64_t j = dir_last_le(keys, n, D, point_key(g, morton(g, q) | mhi));
-      if (j < 0) {
-        v = -2;  // unreachable for a complete tree (keys[0] has anchor 0)
-      } else if (key_depth(g, keys[j]) <= d) {
-        v = int32_t(j);
+  for (int64_t wb = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63); wb < lanes;
+       wb += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t tid = wb + lane;
+    const int64_t e = tid / SL;
+    const int f = int(tid % SL);
+    bool hanging = false;
+    if (e < n && f < NF) {
+      const uint64_t key = keys[e];
+      const int d = key_depth(g, key);
+      uint64_t x[3];
+      demorton(g, key_morton(g, key), x);
+      const uint64_t mhi = key_mesh_bits(g, key) >> g.mb;
+      const int64_t sz = int64_t(1) << (g.dmax - d);
+      const int a = f >> 1;
+      uint64_t q[3] = {x[0], x[1], x[2]};
+      int32_t v;
+      if (!shift_coord(g, a, x[a], (f & 1) ? sz : -sz, &q[a])) {
+        v = -2;
       } else {
-        v = -1;
-        hanging = true;
+        const int64_t j = dir_last_le(keys, n, D, point_key(g, morton(g, q) | mhi));
+        if (j < 0) {
+          v = -2;  // unreachable for a complete tree (keys[0] has anchor 0)
+        } else if (key_depth(g, keys[j]) <= d) {
+          v = int32_t(j);
+        } else {
+          v = -1;
+          hanging = true;
+        }
       }
+      nbr[e * NF + f] = v;
     }
-    nbr[e * NF + f] = v;
+    const uint64_t hb = __ballot(hanging);
+    if (f == 0 && e < n) hmask[e] = uint8_t((hb >> lane) & ((1u << SL) - 1));
   }
-  const uint64_t hb = __ballot(hanging);
-  if (f == 0 && e < n) hmask[e] = uint8_t((hb >> lane) & ((1u << SL) - 1));
 }
 
 // Pass 2: hanging-face rows in (leaf, face) order: count from the masks,
@@ -483,13 +516,9 @@ __global__ __launch_bounds__(256) void k_connect_fine(KeyGeom g, const uint64_t*
 }
 
 // Old -> new mapping (Section 4.2): lower bound of each new key in the old tree.
-__global__ __launch_bounds__(kBlock) void k_map(KeyGeom g, const uint64_t* __restrict__ old_keys,
-                                                Count cn_old, const uint64_t* __restrict__ keys,
-                                                Count cn, int32_t* __restrict__ src,
-                                                int8_t* __restrict__ kind, unsigned* err) {
-  const int64_t n_old = cn_old.get(), n = cn.get();
-  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+__device__ inline void map_one(KeyGeom g, const uint64_t* __restrict__ old_keys, int64_t n_old,
+                               const uint64_t* __restrict__ keys, int64_t j, int32_t* __restrict__ src,
+                               int8_t* __restrict__ kind, unsigned* err) {
   const uint64_t key = keys[j];
   const int64_t B = lower_bound(old_keys, n_old, key);
   const int d = key_depth(g, key);
@@ -523,6 +552,17 @@ __global__ __launch_bounds__(kBlock) void k_map(KeyGeom g, const uint64_t* __res
   kind[j] = 0;
   atomicOr(err, ERR_MAP);
 }
+
+__global__ __launch_bounds__(kBlock) void k_map(KeyGeom g, const uint64_t* __restrict__ old_keys,
+                                                Count cn_old, const uint64_t* __restrict__ keys,
+                                                Count cn, int32_t* __restrict__ src,
+                                                int8_t* __restrict__ kind, unsigned* err) {
+  const int64_t n_old = cn_old.get(), n = cn.get();
+  for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < n;
+       j += int64_t(gridDim.x) * blockDim.x)
+    map_one(g, old_keys, n_old, keys, j, src, kind, err);
+}
+
 
 // ------------------------------------------------------------------ host helpers
 }  // namespace
@@ -632,7 +672,7 @@ lt_status ensure_dir(lt_tree t, hipStream_t s, KeyDir* D) {
     LT_TRY(grow(&t->dir, &t->dir_cap, t->dir_nb + 1));
     if (n > 0) {
       k_build_dir<<<unsigned(ceil_div(n, 256)), 256, 0, s>>>(t->kbuf[t->cur], Count{n, nullptr},
-                                                             t->dir_shift, t->dir_nb, t->dir);
+                                                             t->dir_shift, t->dir_nb, t->dir, nullptr);
       LT_HIP(hipGetLastError());
     }
     t->dir_valid = true;
@@ -671,8 +711,18 @@ __global__ void k_commit(int64_t* dst, const int64_t* src, int64_t cap, unsigned
   *dst = v > cap ? cap : v;
 }
 
-__global__ void k_copy_count(int64_t* dst, const int64_t* src) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+// Start of a captured cycle: leaves before the cycle <- current leaves; the
+// balance fixpoint not yet reached.
+__global__ void k_cycle_begin(int64_t* S, DevCtr* ctr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    S[1] = S[0];
+    ctr->conv = 0;
+  }
+}
+
+// After a balance marking pass: no fresh marks means the fixpoint.
+__global__ void k_converge(DevCtr* ctr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && ctr->nmarked == 0) ctr->conv = 1;
 }
 
 __global__ void k_groups_of(int64_t* dst, const int64_t* n) {
@@ -699,12 +749,16 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
   uint64_t* K0 = t->kbuf[0];
   uint64_t* K[2] = {t->kbuf[1], t->kbuf[2]};
   const unsigned nb256 = unsigned(ceil_div(C, 256));
-  const unsigned nlanes = unsigned(ceil_div(C * g.nchild(), 256));
+  // the search kernels stride over their work: a bounded grid, whatever the capacity
+  constexpr int64_t kStrideGrid = 4096;
+  const unsigned nlanes = unsigned(std::min<int64_t>(ceil_div(C * g.nchild(), 256), kStrideGrid));
+  const unsigned nleaf = unsigned(std::min<int64_t>(ceil_div(C, 256), kStrideGrid));
+  const unsigned* conv = &t->dctr->conv;
   unsigned* err = &t->dctr->err;
   int8_t* F = t->map_kind;  // the flags live in the kind array until the mapping overwrites it
   // flags (parameters from the device table)
   LT_TRY(launch_flag_table(g, &r.fp0, t->flag_tab, K0, Count{C, &S[0]}, F, s));
-  k_copy_count<<<1, 64, 0, s>>>(&S[1], &S[0]);
+  k_cycle_begin<<<1, 64, 0, s>>>(S, t->dctr);
   // adapt K0 -> K[0]
   ScanState st;
   LT_TRY(prep_scan(t, C, s, 1, &st));
@@ -717,18 +771,19 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
   k_fill_u32<<<nb256, 256, 0, s>>>(t->mbuf[0], C, 0u);
   int ki = 0, mi = 0;
   for (int pass = 0; pass <= r.passes; ++pass) {
-    k_build_dir<<<nb256, 256, 0, s>>>(K[ki], Count{C, &S[0]}, r.dir_shift, r.dir_nb, t->dir);
+    k_build_dir<<<nleaf, 256, 0, s>>>(K[ki], Count{C, &S[0]}, r.dir_shift, r.dir_nb, t->dir, conv);
     if (g.dim == 3)
       k_balance_mark<3><<<nlanes, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi],
-                                                  pass == 0 ? 1 : 0, t->dctr);
+                                                  pass == 0 ? 1 : 0, t->dctr, conv);
     else
       k_balance_mark<2><<<nlanes, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi],
-                                                  pass == 0 ? 1 : 0, t->dctr);
+                                                  pass == 0 ? 1 : 0, t->dctr, conv);
     if (pass == r.passes) break;
+    k_converge<<<1, 64, 0, s>>>(t->dctr);
     LT_TRY(prep_scan(t, C, s, 0, &st));
     st.items.p = &S[0];
     k_balance_refine<<<grid_tiles(st), kBlock, 0, s>>>(g, K[ki], t->mbuf[mi], K[1 - ki],
-                                                        t->mbuf[1 - mi], C, st);
+                                                        t->mbuf[1 - mi], C, st, conv);
     k_commit<<<1, 64, 0, s>>>(&S[0], &t->dctr->total, C, err);
     ki = 1 - ki;
     mi = 1 - mi;
@@ -749,8 +804,8 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
       g, K[0], Count{C, &S[0]}, D, t->hang, &t->dctr->total, r.hang_rows, err);
   k_commit<<<1, 64, 0, s>>>(&S[2], &t->dctr->total, r.hang_rows, err);
   // map
-  k_map<<<unsigned(ceil_div(C, kBlock)), kBlock, 0, s>>>(g, K0, Count{C, &S[1]}, K[0], Count{C, &S[0]},
-                                                         t->map_src, t->map_kind, err);
+  k_map<<<nleaf, kBlock, 0, s>>>(g, K0, Count{C, &S[1]}, K[0], Count{C, &S[0]}, t->map_src,
+                                  t->map_kind, err);
   LT_HIP(hipGetLastError());
   // transfer
   k_groups_of<<<1, 64, 0, s>>>(&S[3], &S[0]);
@@ -970,10 +1025,10 @@ lt_status lt_balance(lt_tree t, void* stream) {
       const unsigned blocks = unsigned(ceil_div(t->n_cur * t->g.nchild(), kBlock));
       if (t->g.dim == 3)
         k_balance_mark<3><<<blocks, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], Count{t->n_cur, nullptr},
-                                                    D, t->mbuf[mi], pass == 0 ? 1 : 0, t->dctr);
+                                                    D, t->mbuf[mi], pass == 0 ? 1 : 0, t->dctr, nullptr);
       else
         k_balance_mark<2><<<blocks, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], Count{t->n_cur, nullptr},
-                                                    D, t->mbuf[mi], pass == 0 ? 1 : 0, t->dctr);
+                                                    D, t->mbuf[mi], pass == 0 ? 1 : 0, t->dctr, nullptr);
       LT_HIP(hipGetLastError());
     }
     LT_TRY(read_ctr(t, s));
@@ -989,7 +1044,8 @@ lt_status lt_balance(lt_tree t, void* stream) {
     LT_TRY(prep_scan(t, t->n_cur, s, 0, &st));  // also zeroes the mark count for the next pass
     const int64_t cap = std::min(t->kcap[t->tmp], t->mcap[1 - mi]);
     k_balance_refine<<<grid_tiles(st), kBlock, 0, s>>>(t->g, t->kbuf[t->cur], t->mbuf[mi],
-                                                        t->kbuf[t->tmp], t->mbuf[1 - mi], cap, st);
+                                                        t->kbuf[t->tmp], t->mbuf[1 - mi], cap, st,
+                                                        nullptr);
     LT_HIP(hipGetLastError());
     expect_total = n_new;
     std::swap(t->cur, t->tmp);

@@ -15,7 +15,7 @@ namespace lt {
 // Small device-side counters, read back in one copy.
 struct DevCtr {
   unsigned err;
-  unsigned pad;
+  unsigned conv;  // captured cycles: the balance fixpoint was reached this cycle
   int64_t total;
   unsigned long long nmarked;
   unsigned long long ticket;

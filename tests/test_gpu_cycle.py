@@ -130,3 +130,41 @@ def test_captured_ensemble_cycle_matches_eager():
         print("ensemble cycle", c, G.size(), cyc.stats(), flush=True)
         compare(G, E, u[ui], uE, E.size())
     del cyc
+
+
+def test_captured_cycle_finishes_long_ripples_eagerly():
+    """Four vortices refined to level 8 over a level-4 background leave a
+    five-level staircase around each; moving the vortices ripples the 2:1
+    splits down the staircase over several passes.  With two captured passes
+    the run finishes such cycles eagerly, with the same result."""
+    import torch
+    import paper_2306_06744_amd as lt
+    w = synth.workload_3d_large(3001)
+    w.d_max = 8
+    w.p = 2
+    nodes = synth.gl_nodes01(w.p)
+    E = lt.Tree.uniform(3, w.d_min, w.d_max)
+    G = lt.Tree.uniform(3, w.d_min, w.d_max)
+
+    def fa(c):
+        return dict(centres=[(x + 0.06 * c, y - 0.04 * c, z) for x, y, z in w.centres], r_in=w.r_in,
+                    r_out=w.r_out, nodes01=nodes, lo=w.lo, length=w.length, dist_axes=3)
+
+    for c in range(5):
+        for t in (E, G):
+            t.adapt(t.flag(**fa(0)))
+            t.balance()
+    cap = 8 * G.size()
+    u = [torch.zeros((2, 27, cap), dtype=torch.float64, device="cuda") for _ in range(2)]
+    u[0][:, :, :G.size()] = torch.randn((2, 27, G.size()), dtype=torch.float64, device="cuda")
+    uE = u[0][:, :, :E.size()].clone()
+    cyc = lt.Cycle(G, 2, 2, cap, u, fa(1), balance_passes=2)
+    for c in range(1, 7):
+        ui = cyc.run(fa(c))
+        uE = eager_cycle(E, fa(c), 2, uE)
+        torch.cuda.synchronize()
+        print("ripple cycle", c, G.size(), cyc.stats(), flush=True)
+        compare(G, E, u[ui], uE, E.size())
+    runs, eager, recap = cyc.stats()
+    assert eager >= 1
+    del cyc
