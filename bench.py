@@ -254,7 +254,7 @@ def measured_traffic():
             "source": TRAFFIC_SUMMARY}
 
 
-def graph_cycle(lt, torch, synth, w, nodes, stream, steps, warmup, u, cap, E, passes=4):
+def graph_cycle(lt, torch, synth, w, nodes, stream, steps, warmup, u, cap, E, passes=2):
     """The plain FP64 cycle captured once in a hipGraph (lt_cycle_*): warm-up
     cycles eagerly, then the graph is created at the current tree and replayed
     for the timed cycles (one host synchronisation per cycle)."""
@@ -277,7 +277,9 @@ def graph_cycle(lt, torch, synth, w, nodes, stream, steps, warmup, u, cap, E, pa
         cur = 1 - cur
     torch.cuda.synchronize()
     pair = [u[cur], u[1 - cur]]
-    cyc = lt.Cycle(t, w.p, w.nvar, cap, pair, fa(warmup), balance_passes=passes)
+    # capacity: the leaves now plus 25% headroom (the timed cycles grow ~3%)
+    capacity = min(cap, int(t.size() * 1.25))
+    cyc = lt.Cycle(t, w.p, w.nvar, capacity, pair, fa(warmup), balance_passes=passes)
     torch.cuda.synchronize()
     sizes = []
     t0 = time.perf_counter()
@@ -292,7 +294,7 @@ def graph_cycle(lt, torch, synth, w, nodes, stream, steps, warmup, u, cap, E, pa
     total = sum(b for _, b in sizes)
     return {"value": total / elapsed, "unit": "octants/s", "ms_per_step": elapsed * 1e3 / steps,
             "balance_passes": passes, "runs": runs, "eager_finishes": eager, "recaptures": recap,
-            "capacity": cap,
+            "capacity": capacity,
             "note": "same cycle, captured once in a hipGraph; host wall clock around the timed "
                     "cycles (one synchronisation per cycle)"}
 

@@ -277,7 +277,8 @@ lt_status lt_flag_modal(lt_tree t, int p, const double* u, int64_t ld, double ta
  *
  * The graph is sized for `capacity` leaves: every tree buffer is allocated for
  * it at creation, and u[0], u[1] (caller-owned device FP64 arrays, layout as
- * lt_transfer with ld = capacity) hold the solution alternately.  Balance runs
+ * lt_transfer with a leading dimension ld >= capacity) hold the solution
+ * alternately.  Balance runs
  * `balance_passes` one-level passes (even, >= 2) and a check pass.
  * flag_template (host, nmesh entries, nmesh = the tree's mesh count) fixes the
  * degree p of the flag points, the geometry and the criterion's form; each run
@@ -288,8 +289,9 @@ typedef struct {
   int p;                  /* transfer degree                                        */
   int nvar;               /* variables; nvar * (p+1)^dim <= 65535                   */
   int64_t capacity;       /* leaves the graph's buffers hold (>= current leaves)     */
+  int64_t ld;             /* leading dimension of u[0], u[1] (>= capacity)          */
   int balance_passes;     /* fixed balance passes in the graph: even, 2..64          */
-  double* u[2];           /* device solution arrays, ld = capacity                  */
+  double* u[2];           /* device solution arrays [nvar][(p+1)^dim][ld]           */
   int nmesh;              /* flag parameter sets per run (the tree's mesh count)     */
   const lt_flag_params* flag_template;  /* host, nmesh entries                      */
 } lt_cycle_desc;

@@ -52,7 +52,7 @@ class FlagParams(C.Structure):
 
 
 class CycleDesc(C.Structure):
-    _fields_ = [("p", C.c_int), ("nvar", C.c_int), ("capacity", C.c_int64),
+    _fields_ = [("p", C.c_int), ("nvar", C.c_int), ("capacity", C.c_int64), ("ld", C.c_int64),
                 ("balance_passes", C.c_int), ("u", C.c_void_p * 2), ("nmesh", C.c_int),
                 ("flag_template", C.POINTER(FlagParams))]
 
@@ -390,7 +390,7 @@ class MLP:
 class Cycle:
     """The whole plain cycle captured in a hipGraph over a tree (lt_cycle_*).
 
-    ``u`` is a pair of device FP64 arrays (nvar, n_p, capacity); ``flag`` maps a
+    ``u`` is a pair of device FP64 arrays (nvar, n_p, ld >= capacity); ``flag`` maps a
     cycle to the flag arguments of ``Tree.flag`` (a dict per mesh for an
     ensemble).  ``run(cycle)`` returns the index of the array now holding the
     solution."""
@@ -407,6 +407,8 @@ class Cycle:
             self._keep.append(keep)
         d = CycleDesc()
         d.p, d.nvar, d.capacity, d.balance_passes = int(p), int(nvar), int(capacity), int(balance_passes)
+        d.ld = int(u[0].shape[2])
+        assert u[1].shape == u[0].shape
         d.u[0], d.u[1] = _dptr(u[0]), _dptr(u[1])
         d.nmesh = len(per)
         d.flag_template = arr

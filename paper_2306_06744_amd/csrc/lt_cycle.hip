@@ -124,6 +124,7 @@ lt_status capture(lt_cycle c) {
     r.nvar = c->d.nvar;
     r.uo = c->d.u[q];
     r.un = c->d.u[1 - q];
+    r.ld = c->d.ld;
     r.fp0 = c->tmpl[0];
     r.dsz = c->dsz;
     r.ops = t->ops[c->d.p];
@@ -176,6 +177,7 @@ lt_status lt_cycle_create(lt_tree t, const lt_cycle_desc* d, void* stream, lt_cy
   if (d->nvar < 1 || int64_t(d->nvar) * npts > 65535) return fail(LT_ERR_ARG, "nvar out of range");
   if (d->capacity < std::max<int64_t>(t->n_cur, 1) || d->capacity > (int64_t(1) << 31) - 1)
     return fail(LT_ERR_ARG, "capacity must hold the current leaves and stay below 2^31");
+  if (d->ld < d->capacity) return fail(LT_ERR_ARG, "ld must be at least the capacity");
   for (int m = 0; m < d->nmesh; ++m)
     if (d->flag_template[m].p != d->flag_template[0].p) return fail(LT_ERR_ARG, "flag templates need one p");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -273,8 +275,8 @@ lt_status lt_cycle_run(lt_cycle c, const lt_flag_params* fp, void* stream, int* 
   LT_TRY_STATUS(lt_map(t, stream));
   if (t->n_cur > c->d.capacity)
     return fail(LT_ERR_CAPACITY, "the cycle outgrew its capacity while finishing eagerly; u not transferred");
-  LT_TRY_STATUS(lt_transfer(t, c->d.p, c->d.nvar, c->d.u[q], c->d.capacity, c->d.u[1 - q],
-                            c->d.capacity, 0, stream));
+  LT_TRY_STATUS(lt_transfer(t, c->d.p, c->d.nvar, c->d.u[q], c->d.ld, c->d.u[1 - q], c->d.ld, 0,
+                            stream));
   if (t->cur != 0) {
     if (hipMemcpyAsync(t->kbuf[0], t->kbuf[t->cur], size_t(t->n_cur) * 8, hipMemcpyDeviceToDevice, s) !=
         hipSuccess)

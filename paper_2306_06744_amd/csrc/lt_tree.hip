@@ -52,10 +52,14 @@ namespace {
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ------------------------------------------------------------------ kernels
-__global__ void k_clear_scan(uint64_t* status, int64_t ntiles, DevCtr* ctr, int clear_err) {
+// Zero the look-back words and counters before a scan.  converge (captured
+// cycles, after a balance marking pass): no fresh marks means the fixpoint.
+__global__ void k_clear_scan(uint64_t* status, int64_t ntiles, DevCtr* ctr, int clear_err,
+                             int converge) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < ntiles) status[i] = 0;
   if (i == 0) {
+    if (converge && ctr->nmarked == 0) ctr->conv = 1;
     ctr->ticket = 0;
     ctr->total = 0;
     ctr->nmarked = 0;
@@ -331,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_balance_refine(KeyGeom g, const uint
         mark_out[i] = 0u;
       }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) *st.total = n;
+    if (blockIdx.x == 0 && threadIdx.x == 0) publish_total(st, n);
     return;
   }
   const int64_t tile = take_ticket(st);
@@ -583,17 +587,19 @@ void dir_params(const KeyGeom& g, int64_t n, int* shift, int64_t* nb) {
   *nb = int64_t(1) << L;
 }
 
-lt_status prep_scan(lt_tree t, int64_t n_items, hipStream_t stream, int clear_err, ScanState* st) {
+lt_status prep_scan(lt_tree t, int64_t n_items, hipStream_t stream, int flags, ScanState* st) {
   const int64_t ntiles = std::max<int64_t>(1, ceil_div(n_items, kTile));
   LT_TRY(grow(&t->status, &t->status_cap, ntiles));
   k_clear_scan<<<unsigned(ceil_div(ntiles, 256)), 256, 0, stream>>>(t->status, ntiles, t->dctr,
-                                                                      clear_err);
+                                                                      flags & 1, (flags >> 1) & 1);
   LT_HIP(hipGetLastError());
   st->status = t->status;
   st->ticket = &t->dctr->ticket;
   st->err = &t->dctr->err;
   st->total = &t->dctr->total;
   st->items = Count{n_items, nullptr};
+  st->commit = nullptr;
+  st->commit_cap = 0;
   return LT_OK;
 }
 
@@ -604,7 +610,7 @@ lt_status read_ctr(lt_tree t, hipStream_t stream) {
 }
 
 lt_status clear_err(lt_tree t, hipStream_t stream) {
-  k_clear_scan<<<1, 64, 0, stream>>>(t->status, 0, t->dctr, 1);
+  k_clear_scan<<<1, 64, 0, stream>>>(t->status, 0, t->dctr, 1, 0);
   LT_HIP(hipGetLastError());
   return LT_OK;
 }
@@ -704,12 +710,6 @@ lt_status do_map(lt_tree t, hipStream_t stream) {
 
 // ---------------------------------------------------------- captured cycles
 // Single-thread bookkeeping kernels of a cycle whose counts stay on the device.
-__global__ void k_commit(int64_t* dst, const int64_t* src, int64_t cap, unsigned* err) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int64_t v = *src;
-  if (v > cap) atomicOr(err, ERR_CAPACITY);
-  *dst = v > cap ? cap : v;
-}
 
 // Start of a captured cycle: leaves before the cycle <- current leaves; the
 // balance fixpoint not yet reached.
@@ -720,10 +720,6 @@ __global__ void k_cycle_begin(int64_t* S, DevCtr* ctr) {
   }
 }
 
-// After a balance marking pass: no fresh marks means the fixpoint.
-__global__ void k_converge(DevCtr* ctr) {
-  if (threadIdx.x == 0 && blockIdx.x == 0 && ctr->nmarked == 0) ctr->conv = 1;
-}
 
 __global__ void k_groups_of(int64_t* dst, const int64_t* n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *dst = (*n + 63) / 64;
@@ -763,8 +759,9 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
   ScanState st;
   LT_TRY(prep_scan(t, C, s, 1, &st));
   st.items.p = &S[1];
+  st.commit = &S[0];
+  st.commit_cap = C;
   k_adapt<<<grid_tiles(st), kBlock, 0, s>>>(g, K0, F, K[0], C, st);
-  k_commit<<<1, 64, 0, s>>>(&S[0], &t->dctr->total, C, err);
   LT_HIP(hipGetLastError());
   // balance: fixed passes, then a check
   const KeyDir D{t->dir, r.dir_shift, r.dir_nb};
@@ -779,12 +776,12 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
       k_balance_mark<2><<<nlanes, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi],
                                                   pass == 0 ? 1 : 0, t->dctr, conv);
     if (pass == r.passes) break;
-    k_converge<<<1, 64, 0, s>>>(t->dctr);
-    LT_TRY(prep_scan(t, C, s, 0, &st));
+    LT_TRY(prep_scan(t, C, s, 2, &st));  // also records convergence
     st.items.p = &S[0];
+    st.commit = &S[0];
+    st.commit_cap = C;
     k_balance_refine<<<grid_tiles(st), kBlock, 0, s>>>(g, K[ki], t->mbuf[mi], K[1 - ki],
                                                         t->mbuf[1 - mi], C, st, conv);
-    k_commit<<<1, 64, 0, s>>>(&S[0], &t->dctr->total, C, err);
     ki = 1 - ki;
     mi = 1 - mi;
   }
@@ -798,18 +795,19 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
     k_connect_faces<2><<<nlanes, 256, 0, s>>>(g, K[0], Count{C, &S[0]}, D, t->nbr, t->hmask);
   LT_TRY(prep_scan(t, C, s, 0, &st));
   st.items.p = &S[0];
+  st.commit = &S[2];  // rows past the table's capacity raise ERR_CAPACITY
+  st.commit_cap = r.hang_rows;
   k_connect_rows<<<grid_tiles(st), kBlock, 0, s>>>(t->hmask, g.dim, t->hang, r.hang_rows, st);
   const int nh = 1 << (g.dim - 1);
   k_connect_fine<<<unsigned(ceil_div(r.hang_rows * nh, 256)), 256, 0, s>>>(
       g, K[0], Count{C, &S[0]}, D, t->hang, &t->dctr->total, r.hang_rows, err);
-  k_commit<<<1, 64, 0, s>>>(&S[2], &t->dctr->total, r.hang_rows, err);
   // map
   k_map<<<nleaf, kBlock, 0, s>>>(g, K0, Count{C, &S[1]}, K[0], Count{C, &S[0]}, t->map_src,
                                   t->map_kind, err);
   LT_HIP(hipGetLastError());
   // transfer
   k_groups_of<<<1, 64, 0, s>>>(&S[3], &S[0]);
-  LT_TRY(launch_transfer(t, Count{C, &S[0]}, &S[3], r.p, r.ops, r.nvar, r.uo, C, r.un, C, s));
+  LT_TRY(launch_transfer(t, Count{C, &S[0]}, &S[3], r.p, r.ops, r.nvar, r.uo, r.ld, r.un, r.ld, s));
   // the new keys become the next cycle's input
   k_copy_keys<<<nb256, 256, 0, s>>>(K[0], K0, Count{C, &S[0]}, err);
   LT_HIP(hipGetLastError());

@@ -44,7 +44,18 @@ struct ScanState {
   unsigned* err;
   int64_t* total;         // written by the last tile: sum of all counts
   Count items;            // items scanned; tiles = max(1, ceil(items / kTile))
+  int64_t* commit;        // optional (captured cycles): also receives min(total, commit_cap),
+  int64_t commit_cap;     // with ERR_CAPACITY raised when the total exceeds it
 };
+
+// The last tile's publication of the total (and of its clamped copy).
+__device__ inline void publish_total(const ScanState& st, int64_t v) {
+  *st.total = v;
+  if (st.commit) {
+    if (v > st.commit_cap) atomicOr(st.err, ERR_CAPACITY);
+    *st.commit = v > st.commit_cap ? st.commit_cap : v;
+  }
+}
 
 // Tiles that hold items (>= 1).  Launches sized for a capacity have more
 // workgroups than this; the extra ones take a ticket and leave at once.
@@ -149,7 +160,7 @@ __device__ inline int64_t tile_prefix(const ScanState& st, int64_t tile, int64_t
       if (lane == 0) st_status(&st.status[tile], kStInc | uint64_t(excl + aggregate));
     }
     if (lane == 0) {
-      if (tile == scan_tiles(st) - 1) *st.total = excl + aggregate;
+      if (tile == scan_tiles(st) - 1) publish_total(st, excl + aggregate);
       s_prefix = excl;
     }
   }

@@ -61,6 +61,7 @@ struct CycleRec {
   int p, nvar;
   const double* uo;
   double* un;
+  int64_t ld;          // leading dimension of uo and un
   lt_flag_params fp0;  // degree and geometry of the flags (the centres come from the table)
   int64_t* dsz;
   const double* ops;
