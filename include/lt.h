@@ -296,8 +296,9 @@ typedef struct {
   const lt_flag_params* flag_template;  /* host, nmesh entries                      */
 } lt_cycle_desc;
 
-/* Allocates the tree's buffers for d->capacity (keeping its leaves; the
- * pre-adapt snapshot is dropped), builds the transfer operators and captures
+/* Balances the tree if it is not known to be balanced, allocates its
+ * buffers for d->capacity (keeping its leaves; the pre-adapt snapshot is
+ * dropped), builds the transfer operators and captures
  * two graphs (u[0] -> u[1] and u[1] -> u[0]).  Synchronises.  The tree must
  * not be used by other calls while the cycle exists, except lt_size, lt_view
  * and lt_export.  LT_ERR_ARG for an invalid descriptor. */

@@ -198,6 +198,7 @@ lt_status lt_cycle_create(lt_tree t, const lt_cycle_desc* d, void* stream, lt_cy
       hipHostMalloc(&c->hsz, 4 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(&c->flag_host, flag_args_size() * size_t(c->nmesh), hipHostMallocDefault) != hipSuccess)
     st = fail(LT_ERR_OOM, "cycle state");
+  if (st == LT_OK && !t->balanced) st = lt_balance(t, stream);  // the graph starts from a balanced tree
   if (st == LT_OK) st = reserve(c, s);
   if (st == LT_OK) st = fill_flag_table(t->g, c->tmpl.data(), 1, c->flag_host);  // validate the template
   if (st == LT_OK) st = upload_count(c, s);
@@ -237,6 +238,8 @@ lt_status lt_cycle_run(lt_cycle c, const lt_flag_params* fp, void* stream, int* 
     t->tmp = 1;
     t->old = 2;
     t->has_old = false;  // the pre-cycle keys were overwritten by the new ones
+    t->balanced = true;
+    t->adapt_marks = false;
     t->conn_valid = true;
     t->map_valid = true;
     t->dir_valid = false;

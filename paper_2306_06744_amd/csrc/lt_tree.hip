@@ -135,10 +135,16 @@ __global__ void k_validate(KeyGeom g, const uint64_t* __restrict__ keys, int64_t
 // Adaptation (Section 4.1).  Per leaf: +1 -> 2^dim children, first leaf of a
 // complete all -1 family -> parent, other members of such a family -> nothing,
 // everything else -> itself.
+// Balance marks written by adapt (see the marking pass): the children of a
+// refined leaf are to be examined, a fused parent is to be checked against
+// finer neighbours; every other leaf is balanced with its neighbours already.
+constexpr uint32_t kMarkExamine = 4u;
+constexpr uint32_t kMarkFused = 16u;
+
 __global__ __launch_bounds__(kBlock) void k_adapt(KeyGeom g, const uint64_t* __restrict__ in,
                                                   const int8_t* __restrict__ flags,
                                                   uint64_t* __restrict__ out, int64_t cap,
-                                                  ScanState st) {
+                                                  ScanState st, uint32_t* __restrict__ marks) {
   const int64_t tile = take_ticket(st);
   if (tile >= scan_tiles(st)) return;
   const int64_t n = st.items.get();
@@ -202,11 +208,16 @@ __global__ __launch_bounds__(kBlock) void k_adapt(KeyGeom g, const uint64_t* __r
     const int d = key_depth(g, kk);
     if (a == 0) {
       out[o] = kk;
+      if (marks) marks[o] = 0u;
     } else if (a == 2) {
       out[o] = make_key(g, key_m(g, kk), d - 1);
+      if (marks) marks[o] = kMarkFused;
     } else {
       const uint64_t m = key_m(g, kk);
-      for (int c = 0; c < nc; ++c) out[o + c] = child_key(g, m, d, c);
+      for (int c = 0; c < nc; ++c) {
+        out[o + c] = child_key(g, m, d, c);
+        if (marks) marks[o + c] = kMarkExamine;
+      }
     }
     o += cnt;
   }
@@ -274,6 +285,62 @@ __global__ __launch_bounds__(kBlock) void k_balance_mark(KeyGeom g, const uint64
     const uint64_t fb = __ballot(fresh);
     if (sub == 0 && i < n && ((vb >> lane) & ((uint64_t(1) << SL) - 1))) atomicOr(&mark[i], 2u);
     nfresh += __popcll(fb);
+  }
+  if (lane == 0 && nfresh) atomicAdd(&ctr->nmarked, nfresh);
+}
+
+// 2:1 balance after adaptation, fused parents.  A parent P (depth D) that
+// replaced 2^dim balanced leaves can touch leaves of depth D+2 (never deeper,
+// never coarser than D-1 -- the leaves it replaced were balanced); those sit
+// in the shell of depth-(D+2) cells around P.  One wave takes each fused
+// parent of its 64-leaf window, its lanes probe the shell cells (per the
+// balance kind: cells across faces only, or also edges, or also corners) and
+// P is marked for splitting if a probe finds a depth-(D+2) leaf.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_balance_fused(KeyGeom g, const uint64_t* __restrict__ keys,
+                                                          Count cn, KeyDir D, uint32_t* mark,
+                                                          DevCtr* ctr) {
+  constexpr int W = 6;                                   // cells per axis: -1 .. 4
+  constexpr int NCELL = DIM == 3 ? W * W * W : W * W;
+  const int64_t n = cn.get();
+  const int lane = threadIdx.x & 63;
+  const int limit = g.balance == 0 ? 1 : (g.balance == 1 ? 2 : 3);
+  unsigned long long nfresh = 0;
+  for (int64_t wb = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63); wb < n;
+       wb += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t me = wb + lane;
+    uint64_t todo = __ballot(me < n && (mark[me] & kMarkFused));
+    while (todo) {
+      const int l = __ffsll((unsigned long long)todo) - 1;
+      todo &= todo - 1;
+      const int64_t i = wb + l;
+      const uint64_t key = keys[i];
+      const int d = key_depth(g, key);
+      bool viol = false;
+      if (d + 2 <= g.dmax) {
+        uint64_t x[3];
+        demorton(g, key_morton(g, key), x);
+        const uint64_t mhi = key_mesh_bits(g, key) >> g.mb;
+        const int64_t q4 = int64_t(1) << (g.dmax - d - 2);  // cell size
+        for (int cidx = lane; cidx < NCELL && !viol; cidx += 64) {
+          int off[3] = {cidx % W - 1, (cidx / W) % W - 1, DIM == 3 ? cidx / (W * W) - 1 : 0};
+          int outside = 0;
+          for (int a = 0; a < DIM; ++a) outside += (off[a] < 0 || off[a] > 3) ? 1 : 0;
+          if (outside == 0 || outside > limit) continue;
+          uint64_t q[3] = {x[0], x[1], x[2]};
+          bool ok = true;
+          for (int a = 0; a < DIM && ok; ++a)
+            ok = shift_coord(g, a, x[a], int64_t(off[a]) * q4, &q[a]);
+          if (!ok) continue;
+          const int64_t j = dir_last_le(keys, n, D, point_key(g, morton(g, q) | mhi));
+          if (j >= 0 && key_depth(g, keys[j]) >= d + 2) viol = true;
+        }
+      }
+      if (__ballot(viol) && lane == 0) {
+        const uint32_t was = atomicOr(&mark[i], 1u);
+        if (!(was & 1u)) nfresh++;
+      }
+    }
   }
   if (lane == 0 && nfresh) atomicAdd(&ctr->nmarked, nfresh);
 }
@@ -761,20 +828,27 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
   st.items.p = &S[1];
   st.commit = &S[0];
   st.commit_cap = C;
-  k_adapt<<<grid_tiles(st), kBlock, 0, s>>>(g, K0, F, K[0], C, st);
+  k_adapt<<<grid_tiles(st), kBlock, 0, s>>>(g, K0, F, K[0], C, st, t->mbuf[0]);
   LT_HIP(hipGetLastError());
   // balance: fixed passes, then a check
+  // (the tree entering the cycle is balanced, so adapt's marks restrict the
+  // first pass to new children and fused parents)
   const KeyDir D{t->dir, r.dir_shift, r.dir_nb};
-  k_fill_u32<<<nb256, 256, 0, s>>>(t->mbuf[0], C, 0u);
   int ki = 0, mi = 0;
   for (int pass = 0; pass <= r.passes; ++pass) {
     k_build_dir<<<nleaf, 256, 0, s>>>(K[ki], Count{C, &S[0]}, r.dir_shift, r.dir_nb, t->dir, conv);
+    if (pass == 0) {
+      if (g.dim == 3)
+        k_balance_fused<3><<<nleaf, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi], t->dctr);
+      else
+        k_balance_fused<2><<<nleaf, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi], t->dctr);
+    }
     if (g.dim == 3)
-      k_balance_mark<3><<<nlanes, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi],
-                                                  pass == 0 ? 1 : 0, t->dctr, conv);
+      k_balance_mark<3><<<nlanes, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi], 0,
+                                                  t->dctr, conv);
     else
-      k_balance_mark<2><<<nlanes, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi],
-                                                  pass == 0 ? 1 : 0, t->dctr, conv);
+      k_balance_mark<2><<<nlanes, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi], 0,
+                                                  t->dctr, conv);
     if (pass == r.passes) break;
     LT_TRY(prep_scan(t, C, s, 2, &st));  // also records convergence
     st.items.p = &S[0];
@@ -852,6 +926,7 @@ lt_status lt_build_uniform(const lt_geom* geom, int depth, void* stream, lt_tree
     return fail(LT_ERR_HIP, std::string("uniform build: ") + hipGetErrorString(e));
   }
   t->n_cur = n;
+  t->balanced = true;  // uniform per mesh
   *out = t;
   return LT_OK;
 }
@@ -945,6 +1020,7 @@ lt_status lt_build_batch(const lt_geom* geom, int nmesh, const int* d_min, const
     return st;
   }
   t->n_cur = n;
+  t->balanced = true;  // uniform per mesh
   *out = t;
   return LT_OK;
 }
@@ -982,10 +1058,13 @@ lt_status lt_adapt(lt_tree t, const int8_t* flags, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t n = t->n_cur;
   LT_TRY(grow(&t->kbuf[t->tmp], &t->kcap[t->tmp], n * t->g.nchild()));
+  // From a balanced tree, adapt also writes the first balance pass's marks.
+  const bool marks = t->balanced;
+  if (marks) LT_TRY(grow(&t->mbuf[0], &t->mcap[0], t->kcap[t->tmp]));
   ScanState st;
   LT_TRY(prep_scan(t, n, s, 1, &st));
   k_adapt<<<grid_tiles(st), kBlock, 0, s>>>(t->g, t->kbuf[t->cur], flags, t->kbuf[t->tmp],
-                                              t->kcap[t->tmp], st);
+                                              t->kcap[t->tmp], st, marks ? t->mbuf[0] : nullptr);
   LT_HIP(hipGetLastError());
   LT_TRY(read_ctr(t, s));
   if (t->hctr->err & ERR_BAD_FLAG) return fail(LT_ERR_ARG, "flags must be -1, 0 or 1");
@@ -999,6 +1078,8 @@ lt_status lt_adapt(lt_tree t, const int8_t* flags, void* stream) {
   t->n_cur = t->hctr->total;
   t->has_old = true;
   invalidate(t);
+  t->balanced = false;
+  t->adapt_marks = marks;
   return LT_OK;
 }
 
@@ -1008,10 +1089,16 @@ lt_status lt_balance(lt_tree t, void* stream) {
   // One host readback per pass (the number of leaves to split).  The refine
   // pass's own consistency checks land in the error word and are read with
   // the next pass's count.
+  // The first pass examines every leaf, or -- right after adapt of a
+  // balanced tree -- only the new children and the fused parents.
   int mi = 0;
-  LT_TRY(grow(&t->mbuf[mi], &t->mcap[mi], t->n_cur));
-  k_fill_u32<<<unsigned(ceil_div(t->n_cur, 256)), 256, 0, s>>>(t->mbuf[mi], t->n_cur, 0u);
-  LT_HIP(hipGetLastError());
+  const bool restricted = t->adapt_marks && t->mcap[0] >= t->n_cur;
+  t->adapt_marks = false;
+  if (!restricted) {
+    LT_TRY(grow(&t->mbuf[mi], &t->mcap[mi], t->n_cur));
+    k_fill_u32<<<unsigned(ceil_div(t->n_cur, 256)), 256, 0, s>>>(t->mbuf[mi], t->n_cur, 0u);
+    LT_HIP(hipGetLastError());
+  }
   LT_TRY(clear_err(t, s));
   const int max_pass = 4 * t->g.dmax + 16;
   int64_t expect_total = -1;
@@ -1021,12 +1108,21 @@ lt_status lt_balance(lt_tree t, void* stream) {
     LT_TRY(ensure_dir(t, s, &D));
     if (t->n_cur > 0) {
       const unsigned blocks = unsigned(ceil_div(t->n_cur * t->g.nchild(), kBlock));
+      const int all = pass == 0 && !restricted ? 1 : 0;
+      const Count cn{t->n_cur, nullptr};
+      if (pass == 0 && restricted) {
+        const unsigned fb = unsigned(ceil_div(t->n_cur, kBlock));
+        if (t->g.dim == 3)
+          k_balance_fused<3><<<fb, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], cn, D, t->mbuf[mi], t->dctr);
+        else
+          k_balance_fused<2><<<fb, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], cn, D, t->mbuf[mi], t->dctr);
+      }
       if (t->g.dim == 3)
-        k_balance_mark<3><<<blocks, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], Count{t->n_cur, nullptr},
-                                                    D, t->mbuf[mi], pass == 0 ? 1 : 0, t->dctr, nullptr);
+        k_balance_mark<3><<<blocks, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], cn, D, t->mbuf[mi], all,
+                                                    t->dctr, nullptr);
       else
-        k_balance_mark<2><<<blocks, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], Count{t->n_cur, nullptr},
-                                                    D, t->mbuf[mi], pass == 0 ? 1 : 0, t->dctr, nullptr);
+        k_balance_mark<2><<<blocks, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], cn, D, t->mbuf[mi], all,
+                                                    t->dctr, nullptr);
       LT_HIP(hipGetLastError());
     }
     LT_TRY(read_ctr(t, s));
@@ -1051,6 +1147,7 @@ lt_status lt_balance(lt_tree t, void* stream) {
     mi = 1 - mi;
     invalidate(t);
   }
+  t->balanced = true;
   return LT_OK;
 }
 

@@ -142,6 +142,8 @@ struct lt_tree_s {
   int cur = 0, tmp = 1, old = 2;  // roles of the three key buffers
   int64_t n_cur = 0, n_old = -1, n_hang = -1;
   bool has_old = false;
+  bool balanced = false;     // the current leaves are known to be 2:1 balanced
+  bool adapt_marks = false;  // mbuf[0] holds adapt's marks for the first balance pass
 
   uint32_t* mbuf[2] = {nullptr, nullptr};  // balance marks, ping-pong
   int64_t mcap[2] = {0, 0};
