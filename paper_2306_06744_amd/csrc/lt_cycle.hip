@@ -80,6 +80,7 @@ lt_status reserve(lt_cycle c, hipStream_t s) {
   LT_TRY_STATUS(grow(&t->mbuf[1], &t->mcap[1], C));
   LT_TRY_STATUS(grow(&t->nbr, &t->nbr_cap, C * 2 * dim));
   LT_TRY_STATUS(grow(&t->hmask, &t->hmask_cap, C + kItems));
+  LT_TRY_STATUS(grow(&t->fused, &t->fused_cap, C));
   c->hang_rows = std::max<int64_t>(1024, C / 16);
   LT_TRY_STATUS(grow(&t->hang, &t->hang_cap, c->hang_rows * (2 + (1 << (dim - 1)))));
   c->hang_rows = t->hang_cap / (2 + (1 << (dim - 1)));
@@ -264,7 +265,8 @@ lt_status lt_cycle_run(lt_cycle c, const lt_flag_params* fp, void* stream, int* 
   // from the partly balanced keys in kbuf[1].
   c->eager_finishes++;
   void* before[] = {t->kbuf[0], t->kbuf[1], t->kbuf[2], t->mbuf[0], t->mbuf[1], t->nbr, t->hmask,
-                    t->hang, t->map_src, t->map_kind, t->dir, t->status, t->copy_delta, t->grp_list};
+                    t->hang, t->map_src, t->map_kind, t->dir, t->status, t->copy_delta, t->grp_list,
+                    t->fused};
   t->old = 0;
   t->cur = 1;
   t->tmp = 2;
@@ -294,7 +296,8 @@ lt_status lt_cycle_run(lt_cycle c, const lt_flag_params* fp, void* stream, int* 
   if (u_index) *u_index = c->parity;
   LT_TRY_STATUS(upload_count(c, s));
   void* after[] = {t->kbuf[0], t->kbuf[1], t->kbuf[2], t->mbuf[0], t->mbuf[1], t->nbr, t->hmask,
-                   t->hang, t->map_src, t->map_kind, t->dir, t->status, t->copy_delta, t->grp_list};
+                   t->hang, t->map_src, t->map_kind, t->dir, t->status, t->copy_delta, t->grp_list,
+                   t->fused};
   if (std::memcmp(before, after, sizeof(before)) != 0) {
     // buffers moved: size everything for the capacity again and recapture
     c->recaptures++;

@@ -63,6 +63,7 @@ __global__ void k_clear_scan(uint64_t* status, int64_t ntiles, DevCtr* ctr, int 
     ctr->ticket = 0;
     ctr->total = 0;
     ctr->nmarked = 0;
+    ctr->nfused = 0;
     if (clear_err) ctr->err = 0;
   }
 }
@@ -292,57 +293,75 @@ __global__ __launch_bounds__(kBlock) void k_balance_mark(KeyGeom g, const uint64
 // 2:1 balance after adaptation, fused parents.  A parent P (depth D) that
 // replaced 2^dim balanced leaves can touch leaves of depth D+2 (never deeper,
 // never coarser than D-1 -- the leaves it replaced were balanced); those sit
-// in the shell of depth-(D+2) cells around P.  One wave takes each fused
-// parent of its 64-leaf window, its lanes probe the shell cells (per the
-// balance kind: cells across faces only, or also edges, or also corners) and
-// P is marked for splitting if a probe finds a depth-(D+2) leaf.
-template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_balance_fused(KeyGeom g, const uint64_t* __restrict__ keys,
-                                                          Count cn, KeyDir D, uint32_t* mark,
-                                                          DevCtr* ctr) {
-  constexpr int W = 6;                                   // cells per axis: -1 .. 4
-  constexpr int NCELL = DIM == 3 ? W * W * W : W * W;
+// in the shell of depth-(D+2) cells around P.  First the fused parents are
+// listed (any order), then one lane per (parent, shell cell) -- per the
+// balance kind, cells across faces only, or also edges, or also corners --
+// probes its cell and marks P for splitting on a depth-(D+2) leaf.
+__global__ __launch_bounds__(kBlock) void k_fused_list(Count cn, const uint32_t* __restrict__ mark,
+                                                       int32_t* __restrict__ list, DevCtr* ctr) {
   const int64_t n = cn.get();
   const int lane = threadIdx.x & 63;
-  const int limit = g.balance == 0 ? 1 : (g.balance == 1 ? 2 : 3);
-  unsigned long long nfresh = 0;
   for (int64_t wb = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63); wb < n;
        wb += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t me = wb + lane;
-    uint64_t todo = __ballot(me < n && (mark[me] & kMarkFused));
-    while (todo) {
-      const int l = __ffsll((unsigned long long)todo) - 1;
-      todo &= todo - 1;
-      const int64_t i = wb + l;
-      const uint64_t key = keys[i];
-      const int d = key_depth(g, key);
-      bool viol = false;
-      if (d + 2 <= g.dmax) {
-        uint64_t x[3];
-        demorton(g, key_morton(g, key), x);
-        const uint64_t mhi = key_mesh_bits(g, key) >> g.mb;
-        const int64_t q4 = int64_t(1) << (g.dmax - d - 2);  // cell size
-        for (int cidx = lane; cidx < NCELL && !viol; cidx += 64) {
-          int off[3] = {cidx % W - 1, (cidx / W) % W - 1, DIM == 3 ? cidx / (W * W) - 1 : 0};
-          int outside = 0;
-          for (int a = 0; a < DIM; ++a) outside += (off[a] < 0 || off[a] > 3) ? 1 : 0;
-          if (outside == 0 || outside > limit) continue;
-          uint64_t q[3] = {x[0], x[1], x[2]};
-          bool ok = true;
-          for (int a = 0; a < DIM && ok; ++a)
-            ok = shift_coord(g, a, x[a], int64_t(off[a]) * q4, &q[a]);
-          if (!ok) continue;
-          const int64_t j = dir_last_le(keys, n, D, point_key(g, morton(g, q) | mhi));
-          if (j >= 0 && key_depth(g, keys[j]) >= d + 2) viol = true;
-        }
-      }
-      if (__ballot(viol) && lane == 0) {
-        const uint32_t was = atomicOr(&mark[i], 1u);
-        if (!(was & 1u)) nfresh++;
-      }
+    const int64_t i = wb + lane;
+    const bool f = i < n && (mark[i] & kMarkFused);
+    const uint64_t b = __ballot(f);
+    if (!b) continue;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&ctr->nfused, (unsigned long long)__popcll(b));
+    base = __shfl(base, 0);
+    if (f) list[base + __popcll(b & ((uint64_t(1) << lane) - 1))] = int32_t(i);
+  }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_fused_probe(KeyGeom g, const uint64_t* __restrict__ keys,
+                                                        Count cn, KeyDir D,
+                                                        const int32_t* __restrict__ list, uint32_t* mark,
+                                                        DevCtr* ctr) {
+  constexpr int W = 6;  // cells per axis around P: -1 .. 4 in units of a depth-(D+2) cell
+  constexpr int NCELL = DIM == 3 ? W * W * W : W * W;
+  const int64_t n = cn.get();
+  const int64_t work = int64_t(ctr->nfused) * NCELL;
+  const int limit = g.balance == 0 ? 1 : (g.balance == 1 ? 2 : 3);
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < work;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t i = list[t / NCELL];
+    const int cidx = int(t % NCELL);
+    const int off[3] = {cidx % W - 1, (cidx / W) % W - 1, DIM == 3 ? cidx / (W * W) - 1 : 0};
+    int outside = 0;
+    for (int a = 0; a < DIM; ++a) outside += (off[a] < 0 || off[a] > 3) ? 1 : 0;
+    if (outside == 0 || outside > limit || i < 0 || i >= n) continue;
+    const uint64_t key = keys[i];
+    const int d = key_depth(g, key);
+    if (d + 2 > g.dmax) continue;
+    uint64_t x[3];
+    demorton(g, key_morton(g, key), x);
+    const uint64_t mhi = key_mesh_bits(g, key) >> g.mb;
+    const int64_t q4 = int64_t(1) << (g.dmax - d - 2);
+    uint64_t q[3] = {x[0], x[1], x[2]};
+    bool ok = true;
+    for (int a = 0; a < DIM && ok; ++a) ok = shift_coord(g, a, x[a], int64_t(off[a]) * q4, &q[a]);
+    if (!ok) continue;
+    const int64_t j = dir_last_le(keys, n, D, point_key(g, morton(g, q) | mhi));
+    if (j >= 0 && key_depth(g, keys[j]) >= d + 2) {
+      const uint32_t was = atomicOr(&mark[i], 1u);
+      if (!(was & 1u)) atomicAdd(&ctr->nmarked, 1ull);
     }
   }
-  if (lane == 0 && nfresh) atomicAdd(&ctr->nmarked, nfresh);
+}
+
+// The fused-parent check of the first balance pass after adaptation.
+hipError_t launch_fused_check(const KeyGeom& g, const uint64_t* keys, Count cn, const KeyDir& D,
+                              uint32_t* mark, int32_t* list, DevCtr* ctr, hipStream_t s) {
+  constexpr int64_t kGrid = 2048;
+  const unsigned lb = unsigned(std::max<int64_t>(1, std::min<int64_t>(ceil_div(cn.n, kBlock), kGrid)));
+  k_fused_list<<<lb, kBlock, 0, s>>>(cn, mark, list, ctr);
+  if (g.dim == 3)
+    k_fused_probe<3><<<unsigned(kGrid), kBlock, 0, s>>>(g, keys, cn, D, list, mark, ctr);
+  else
+    k_fused_probe<2><<<unsigned(kGrid), kBlock, 0, s>>>(g, keys, cn, D, list, mark, ctr);
+  return hipGetLastError();
 }
 
 // Radix directory of a sorted key array (see KeyDir): leaf i owns the
@@ -837,12 +856,7 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
   int ki = 0, mi = 0;
   for (int pass = 0; pass <= r.passes; ++pass) {
     k_build_dir<<<nleaf, 256, 0, s>>>(K[ki], Count{C, &S[0]}, r.dir_shift, r.dir_nb, t->dir, conv);
-    if (pass == 0) {
-      if (g.dim == 3)
-        k_balance_fused<3><<<nleaf, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi], t->dctr);
-      else
-        k_balance_fused<2><<<nleaf, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi], t->dctr);
-    }
+    if (pass == 0) LT_HIP(launch_fused_check(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi], t->fused, t->dctr, s));
     if (g.dim == 3)
       k_balance_mark<3><<<nlanes, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi], 0,
                                                   t->dctr, conv);
@@ -1111,11 +1125,8 @@ lt_status lt_balance(lt_tree t, void* stream) {
       const int all = pass == 0 && !restricted ? 1 : 0;
       const Count cn{t->n_cur, nullptr};
       if (pass == 0 && restricted) {
-        const unsigned fb = unsigned(ceil_div(t->n_cur, kBlock));
-        if (t->g.dim == 3)
-          k_balance_fused<3><<<fb, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], cn, D, t->mbuf[mi], t->dctr);
-        else
-          k_balance_fused<2><<<fb, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], cn, D, t->mbuf[mi], t->dctr);
+        LT_TRY(grow(&t->fused, &t->fused_cap, t->n_cur));
+        LT_HIP(launch_fused_check(t->g, t->kbuf[t->cur], cn, D, t->mbuf[mi], t->fused, t->dctr, s));
       }
       if (t->g.dim == 3)
         k_balance_mark<3><<<blocks, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], cn, D, t->mbuf[mi], all,
@@ -1278,6 +1289,7 @@ void lt_destroy(lt_tree t) {
   for (auto& b : t->mbuf) if (b) (void)hipFree(b);
   if (t->nbr) (void)hipFree(t->nbr);
   if (t->hmask) (void)hipFree(t->hmask);
+  if (t->fused) (void)hipFree(t->fused);
   if (t->dir) (void)hipFree(t->dir);
   if (t->hang) (void)hipFree(t->hang);
   if (t->map_src) (void)hipFree(t->map_src);

@@ -19,6 +19,7 @@ struct DevCtr {
   int64_t total;
   unsigned long long nmarked;
   unsigned long long ticket;
+  unsigned long long nfused;  // fused parents listed for the first balance pass
 };
 
 void set_error(const std::string& msg);
@@ -158,6 +159,8 @@ struct lt_tree_s {
   int64_t nbr_cap = 0;
   uint8_t* hmask = nullptr;     // per leaf: faces that are the coarse side of a hanging face
   int64_t hmask_cap = 0;
+  int32_t* fused = nullptr;     // fused parents of the last adaptation (first balance pass)
+  int64_t fused_cap = 0;
   int32_t* hang = nullptr;
   int64_t hang_cap = 0;  // rows
   bool conn_valid = false;
