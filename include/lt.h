@@ -283,7 +283,10 @@ lt_status lt_flag_modal(lt_tree t, int p, const double* u, int64_t ld, double ta
  * flag_template (host, nmesh entries, nmesh = the tree's mesh count) fixes the
  * degree p of the flag points, the geometry and the criterion's form; each run
  * passes the cycle's own parameters (e.g. advected centres) with the same p.
- * Supports precision 0 (FP64) transfers of 3D p 1..3 and 2D p 1..7. */
+ * The transfer may be FP64 (3D p 1..3, 2D p 1..7) or split precision
+ * (64 points per element), and the flags geometric or learned (lt_flag_mlp:
+ * the network over the geometric fallback below conf_min; the network's
+ * weights are read at each replay, so training between runs takes effect). */
 typedef struct lt_cycle_s* lt_cycle;
 typedef struct {
   int p;                  /* transfer degree                                        */
@@ -294,6 +297,9 @@ typedef struct {
   double* u[2];           /* device solution arrays [nvar][(p+1)^dim][ld]           */
   int nmesh;              /* flag parameter sets per run (the tree's mesh count)     */
   const lt_flag_params* flag_template;  /* host, nmesh entries                      */
+  int precision;          /* transfer as lt_transfer: 0 FP64, 1 split (64 points)    */
+  struct lt_mlp_s* mlp;   /* learned flags over the geometric fallback (lt_flag_mlp  */
+  float conf_min;         /*   semantics; 3D p 3, 5 variables), or NULL             */
 } lt_cycle_desc;
 
 /* Balances the tree if it is not known to be balanced, allocates its

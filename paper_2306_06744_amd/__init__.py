@@ -54,7 +54,8 @@ class FlagParams(C.Structure):
 class CycleDesc(C.Structure):
     _fields_ = [("p", C.c_int), ("nvar", C.c_int), ("capacity", C.c_int64), ("ld", C.c_int64),
                 ("balance_passes", C.c_int), ("u", C.c_void_p * 2), ("nmesh", C.c_int),
-                ("flag_template", C.POINTER(FlagParams))]
+                ("flag_template", C.POINTER(FlagParams)), ("precision", C.c_int),
+                ("mlp", C.c_void_p), ("conf_min", C.c_float)]
 
 
 _lib = None
@@ -395,7 +396,8 @@ class Cycle:
     ensemble).  ``run(cycle)`` returns the index of the array now holding the
     solution."""
 
-    def __init__(self, tree, p, nvar, capacity, u, flag_args, balance_passes=4):
+    def __init__(self, tree, p, nvar, capacity, u, flag_args, balance_passes=4, precision=0,
+                 mlp=None, conf_min=0.9):
         self.tree = tree
         self._u = u
         per = flag_args if isinstance(flag_args, (list, tuple)) else [flag_args]
@@ -412,6 +414,10 @@ class Cycle:
         d.u[0], d.u[1] = _dptr(u[0]), _dptr(u[1])
         d.nmesh = len(per)
         d.flag_template = arr
+        d.precision = int(precision)
+        d.mlp = mlp._h.value if mlp is not None else None
+        d.conf_min = float(conf_min)
+        self._mlp = mlp
         h = C.c_void_p()
         _check(lib().lt_cycle_create(tree._h, C.byref(d), _stream(), C.byref(h)))
         self._h = h

@@ -96,6 +96,12 @@ lt_status reserve(lt_cycle c, hipStream_t s) {
       return fail(LT_ERR_OOM, "flag table");
   }
   LT_TRY_STATUS(build_transfer_ops(c->d.p, &t->ops[c->d.p], s));
+  if (c->d.precision == 1) {
+    LT_TRY_STATUS(prepare_split(t, c->d.p, s));
+    LT_TRY_STATUS(grow(&t->split_R, &t->split_R_cap, C));
+    LT_TRY_STATUS(grow(&t->split_F, &t->split_F_cap, C));
+  }
+  if (c->d.mlp) LT_TRY_STATUS(mlp_reserve(c->d.mlp, C));
   if (hipStreamSynchronize(s) != hipSuccess) return fail(LT_ERR_HIP, "sync");
   return LT_OK;
 }
@@ -129,6 +135,9 @@ lt_status capture(lt_cycle c) {
     r.fp0 = c->tmpl[0];
     r.dsz = c->dsz;
     r.ops = t->ops[c->d.p];
+    r.precision = c->d.precision;
+    r.mlp = c->d.mlp;
+    r.conf_min = c->d.conf_min;
     r.dir_shift = c->dir_shift;
     r.dir_nb = c->dir_nb;
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -181,6 +190,11 @@ lt_status lt_cycle_create(lt_tree t, const lt_cycle_desc* d, void* stream, lt_cy
   if (d->ld < d->capacity) return fail(LT_ERR_ARG, "ld must be at least the capacity");
   for (int m = 0; m < d->nmesh; ++m)
     if (d->flag_template[m].p != d->flag_template[0].p) return fail(LT_ERR_ARG, "flag templates need one p");
+  if (d->precision != 0 && d->precision != 1) return fail(LT_ERR_ARG, "precision must be 0 or 1");
+  if (d->precision == 1 && !((dim == 3 && d->p == 3) || (dim == 2 && d->p == 7)))
+    return fail(LT_ERR_ARG, "split precision needs 64 points per element");
+  if (d->mlp && (dim != 3 || d->p != 3 || d->nvar != 5))
+    return fail(LT_ERR_ARG, "learned flags need 3D p = 3 elements with 5 variables");
   hipStream_t s = static_cast<hipStream_t>(stream);
   lt_cycle c = new lt_cycle_s;
   c->t = t;
@@ -280,8 +294,8 @@ lt_status lt_cycle_run(lt_cycle c, const lt_flag_params* fp, void* stream, int* 
   LT_TRY_STATUS(lt_map(t, stream));
   if (t->n_cur > c->d.capacity)
     return fail(LT_ERR_CAPACITY, "the cycle outgrew its capacity while finishing eagerly; u not transferred");
-  LT_TRY_STATUS(lt_transfer(t, c->d.p, c->d.nvar, c->d.u[q], c->d.ld, c->d.u[1 - q], c->d.ld, 0,
-                            stream));
+  LT_TRY_STATUS(lt_transfer(t, c->d.p, c->d.nvar, c->d.u[q], c->d.ld, c->d.u[1 - q], c->d.ld,
+                            c->d.precision, stream));
   if (t->cur != 0) {
     if (hipMemcpyAsync(t->kbuf[0], t->kbuf[t->cur], size_t(t->n_cur) * 8, hipMemcpyDeviceToDevice, s) !=
         hipSuccess)

@@ -94,8 +94,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_mlp_features(const double* __restrict__ T4,
                                                       const double* __restrict__ u, int64_t ld,
                                                       int nvar, const int32_t* __restrict__ rows,
-                                                      int64_t n, bf16* __restrict__ X) {
+                                                      Count cn, bf16* __restrict__ X) {
   constexpr int kS = 65;  // LDS stride (doubles) of one element's 64 values
+  const int64_t n = cn.get();
   __shared__ double sA[64 * kS];
   const int el = threadIdx.x & 63, z = threadIdx.x >> 6;
   const int v = blockIdx.y;
@@ -349,7 +350,7 @@ constexpr int kH2S = 72;   // layer-2 activations (64 + pad)
 constexpr int kFlagWaves = 8;
 
 __global__ __launch_bounds__(64 * kFlagWaves) void k_mlp_flag(
-    KeyGeom g, const uint64_t* __restrict__ keys, const bf16* __restrict__ X, int64_t n,
+    KeyGeom g, const uint64_t* __restrict__ keys, const bf16* __restrict__ X, Count cn,
     const bf16* __restrict__ W1, const bf16* __restrict__ W2, const bf16* __restrict__ W3,
     const float* __restrict__ P, int64_t off_b1, int64_t off_b2, int64_t off_b3, float conf_min,
     int8_t* __restrict__ flags, float* __restrict__ conf) {
@@ -359,6 +360,7 @@ __global__ __launch_bounds__(64 * kFlagWaves) void k_mlp_flag(
   __shared__ __attribute__((aligned(16))) bf16 sH2[kFlagWaves][16 * kH2S];
   __shared__ float sZ[kFlagWaves][16][4];
   __shared__ float sB[128 + 64 + 4];
+  const int64_t n = cn.get();
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = 8 * (lane >> 4);
   for (int c = tid; c < 128 * 40; c += 64 * kFlagWaves) {
@@ -647,6 +649,35 @@ lt_status mlp_backward(lt_mlp_s* m, const __bf16* X, const int8_t* y, int64_t B,
 }  // namespace
 }  // namespace lt
 
+namespace lt {
+
+lt_status mlp_reserve(lt_mlp m, int64_t n) {
+  if (m->xcap >= n) return LT_OK;
+  if (m->X) (void)hipFree(m->X);
+  m->X = nullptr;
+  m->xcap = 0;
+  if (hipMalloc(&m->X, size_t(n) * 320 * 2) != hipSuccess) return fail(LT_ERR_OOM, "MLP features");
+  m->xcap = n;
+  return LT_OK;
+}
+
+lt_status launch_mlp_flag(lt_tree_s* t, lt_mlp m, Count n, const double* u, int64_t ld, float conf_min,
+                          int8_t* flags, float* conf, hipStream_t s) {
+  if (t->g.dim != 3) return fail(LT_ERR_ARG, "the learned indicator takes 3D p = 3 elements");
+  if (n.n == 0) return LT_OK;
+  if (m->xcap < n.n) return fail(LT_ERR_ARG, "feature buffer smaller than the leaves");
+  k_mlp_features<<<dim3(nblk(n.n, 64), 5u), 256, 0, s>>>(m->T4, u, ld, 5, nullptr, n, m->X);
+  const int64_t ntiles = (n.n + 16 * kFlagWaves - 1) / (16 * kFlagWaves);
+  const unsigned grid = unsigned(std::min<int64_t>(ntiles, 256));
+  k_mlp_flag<<<grid, 64 * kFlagWaves, 0, s>>>(t->g, t->kbuf[t->cur], m->X, n, m->W1, m->W2, m->W3, m->P,
+                                              lt_mlp_s::off_b1, lt_mlp_s::off_b2, lt_mlp_s::off_b3,
+                                              conf_min, flags, conf);
+  if (hipGetLastError() != hipSuccess) return fail(LT_ERR_HIP, "learned flag launch");
+  return LT_OK;
+}
+
+}  // namespace lt
+
 using namespace lt;
 
 extern "C" {
@@ -698,7 +729,8 @@ lt_status lt_mlp_features(lt_mlp m, const double* u, int64_t ld, int nvar, const
   if (!m || !u || !X || nvar != 5) return fail(LT_ERR_ARG, "features need 5 variables of 64 points");
   if (n == 0) return LT_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  k_mlp_features<<<dim3(nblk(n, 64), unsigned(nvar)), 256, 0, s>>>(m->T4, u, ld, nvar, rows, n,
+  k_mlp_features<<<dim3(nblk(n, 64), unsigned(nvar)), 256, 0, s>>>(m->T4, u, ld, nvar, rows,
+                                                                    Count{n, nullptr},
                                                                     static_cast<__bf16*>(X));
   if (hipGetLastError() != hipSuccess) return fail(LT_ERR_HIP, "features launch");
   return LT_OK;
@@ -742,22 +774,8 @@ lt_status lt_flag_mlp(lt_tree t, lt_mlp m, const lt_flag_params* fallback, const
   if (ld < n) return fail(LT_ERR_ARG, "leading dimension too small");
   LT_TRY_STATUS(launch_flag(t->g, fallback, t->kbuf[t->cur], n, flags, s));
   if (n == 0) return LT_OK;
-  if (m->xcap < n) {
-    if (m->X) (void)hipFree(m->X);
-    m->X = nullptr;
-    m->xcap = 0;
-    if (hipMalloc(&m->X, size_t(n) * 320 * 2) != hipSuccess) return fail(LT_ERR_OOM, "MLP features");
-    m->xcap = n;
-  }
-  lt_status st = lt_mlp_features(m, u, ld, 5, nullptr, n, m->X, stream);
-  if (st != LT_OK) return st;
-  const int64_t ntiles = (n + 16 * kFlagWaves - 1) / (16 * kFlagWaves);
-  const unsigned grid = unsigned(std::min<int64_t>(ntiles, 256));
-  k_mlp_flag<<<grid, 64 * kFlagWaves, 0, s>>>(t->g, t->kbuf[t->cur], m->X, n, m->W1, m->W2, m->W3, m->P,
-                                  lt_mlp_s::off_b1, lt_mlp_s::off_b2, lt_mlp_s::off_b3, conf_min,
-                                  flags, conf);
-  if (hipGetLastError() != hipSuccess) return fail(LT_ERR_HIP, "learned flag launch");
-  return LT_OK;
+  LT_TRY_STATUS(mlp_reserve(m, n));
+  return launch_mlp_flag(t, m, Count{n, nullptr}, u, ld, conf_min, flags, conf, s);
 }
 
 lt_status lt_vortex_field(lt_tree t, const lt_flag_params* where, const double* strength, double* u,

@@ -108,10 +108,12 @@ __global__ void k_build_split_vec(const double* __restrict__ ops1d, int n1, int 
 // Work lists from the mapping: R = first child of each refined family (kind
 // 1), F = each fused parent (kind -1), in new-leaf order.  One scan carries
 // both counts packed as nR + (nF << 31).
-__global__ __launch_bounds__(kBlock) void k_split_lists(const int8_t* __restrict__ kind, int64_t n,
+__global__ __launch_bounds__(kBlock) void k_split_lists(const int8_t* __restrict__ kind,
                                                         int32_t* __restrict__ R,
                                                         int32_t* __restrict__ F, ScanState st) {
   const int64_t tile = take_ticket(st);
+  if (tile >= scan_tiles(st)) return;
+  const int64_t n = st.items.get();
   const int64_t base = tile * kTile + int64_t(threadIdx.x) * kItems;
   int8_t kd[kItems];
   int64_t local = 0;
@@ -343,12 +345,10 @@ __global__ __launch_bounds__(64 * NC) void k_split_fuse(
 
 }  // namespace
 
-lt_status launch_split_transfer(lt_tree_s* t, int p, int nvar, const double* u_old, int64_t ld_old,
-                                double* u_new, int64_t ld_new, hipStream_t s) {
+lt_status prepare_split(lt_tree_s* t, int p, hipStream_t s) {
   const int dim = t->g.dim;
   if (!((dim == 3 && p == 3) || (dim == 2 && p == 7)))
     return fail(LT_ERR_ARG, "split precision needs 64 points per element (3D p=3 or 2D p=7)");
-  if (nvar < 1 || int64_t(nvar) * kNP > 65535) return fail(LT_ERR_ARG, "nvar * 64 must be in [1, 65535]");
   const int nc = 1 << dim, n1 = p + 1;
   LT_TRY_STATUS(build_transfer_ops(p, &t->ops[p], s));
   if (!t->split_frags) {
@@ -371,17 +371,32 @@ lt_status launch_split_transfer(lt_tree_s* t, int p, int nvar, const double* u_o
     t->split_frags = q;
     t->split_vec = static_cast<double*>(qv);
   }
-  const int64_t n = t->n_cur;
+  return LT_OK;
+}
+
+lt_status launch_split_transfer(lt_tree_s* t, int p, int nvar, const double* u_old, int64_t ld_old,
+                                double* u_new, int64_t ld_new, hipStream_t s) {
+  return launch_split_transfer(t, Count{t->n_cur, nullptr}, p, nvar, u_old, ld_old, u_new, ld_new, s);
+}
+
+lt_status launch_split_transfer(lt_tree_s* t, Count cn, int p, int nvar, const double* u_old,
+                                int64_t ld_old, double* u_new, int64_t ld_new, hipStream_t s) {
+  const int dim = t->g.dim;
+  if (nvar < 1 || int64_t(nvar) * kNP > 65535) return fail(LT_ERR_ARG, "nvar * 64 must be in [1, 65535]");
+  LT_TRY_STATUS(prepare_split(t, p, s));
+  const int nc = 1 << dim;
+  const int64_t n = cn.n;  // leaves, or the capacity of a launch whose count lives on the device
   if (n == 0) return LT_OK;
   LT_TRY_STATUS(grow(&t->split_R, &t->split_R_cap, n));
   LT_TRY_STATUS(grow(&t->split_F, &t->split_F_cap, n));
   ScanState st;
   LT_TRY_STATUS(prep_scan(t, n, s, 0, &st));
-  k_split_lists<<<grid_tiles(st), kBlock, 0, s>>>(t->map_kind, n, t->split_R, t->split_F, st);
+  st.items.p = cn.p;
+  k_split_lists<<<grid_tiles(st), kBlock, 0, s>>>(t->map_kind, t->split_R, t->split_F, st);
   const bf16x8* fr = static_cast<const bf16x8*>(t->split_frags);
   const bf16x8* fI = fr;
   const bf16x8* fP = fr + size_t(nc) * 3 * kMT * kKS * 64;
-  LT_TRY_STATUS(launch_copy(t, int64_t(nvar) * kNP, u_old, ld_old, u_new, ld_new, s));
+  LT_TRY_STATUS(launch_copy(t, cn, int64_t(nvar) * kNP, u_old, ld_old, u_new, ld_new, s));
   const int64_t max_ref_tiles = (n / nc + kTC - 1) / kTC + 1;
   const int64_t max_fuse_tiles = (n + kTC - 1) / kTC + 1;
   const dim3 gr(unsigned(std::min<int64_t>(max_ref_tiles, 2048)), unsigned(nvar));

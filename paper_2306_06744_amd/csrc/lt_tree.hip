@@ -840,6 +840,8 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
   int8_t* F = t->map_kind;  // the flags live in the kind array until the mapping overwrites it
   // flags (parameters from the device table)
   LT_TRY(launch_flag_table(g, &r.fp0, t->flag_tab, K0, Count{C, &S[0]}, F, s));
+  if (r.mlp)  // learned flags, the geometric ones as the fallback below conf_min
+    LT_TRY(launch_mlp_flag(t, r.mlp, Count{C, &S[0]}, r.uo, r.ld, r.conf_min, F, nullptr, s));
   k_cycle_begin<<<1, 64, 0, s>>>(S, t->dctr);
   // adapt K0 -> K[0]
   ScanState st;
@@ -894,8 +896,12 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
                                   t->map_kind, err);
   LT_HIP(hipGetLastError());
   // transfer
-  k_groups_of<<<1, 64, 0, s>>>(&S[3], &S[0]);
-  LT_TRY(launch_transfer(t, Count{C, &S[0]}, &S[3], r.p, r.ops, r.nvar, r.uo, r.ld, r.un, r.ld, s));
+  if (r.precision == 1) {
+    LT_TRY(launch_split_transfer(t, Count{C, &S[0]}, r.p, r.nvar, r.uo, r.ld, r.un, r.ld, s));
+  } else {
+    k_groups_of<<<1, 64, 0, s>>>(&S[3], &S[0]);
+    LT_TRY(launch_transfer(t, Count{C, &S[0]}, &S[3], r.p, r.ops, r.nvar, r.uo, r.ld, r.un, r.ld, s));
+  }
   // the new keys become the next cycle's input
   k_copy_keys<<<nb256, 256, 0, s>>>(K[0], K0, Count{C, &S[0]}, err);
   LT_HIP(hipGetLastError());

@@ -66,6 +66,9 @@ struct CycleRec {
   lt_flag_params fp0;  // degree and geometry of the flags (the centres come from the table)
   int64_t* dsz;
   const double* ops;
+  int precision;       // transfer: 0 FP64, 1 split
+  lt_mlp mlp;          // learned flags (null: geometric only)
+  float conf_min;
   int dir_shift;
   int64_t dir_nb;
 };
@@ -115,6 +118,17 @@ void dir_params(const KeyGeom& g, int64_t n, int* shift, int64_t* nb);
 // Split-precision (BF16 x 3 on MFMA, FP64 cell means) transfer; asynchronous.
 lt_status launch_split_transfer(lt_tree_s* t, int p, int nvar, const double* u_old, int64_t ld_old,
                                 double* u_new, int64_t ld_new, hipStream_t s);
+lt_status launch_split_transfer(lt_tree_s* t, Count n, int p, int nvar, const double* u_old,
+                                int64_t ld_old, double* u_new, int64_t ld_new, hipStream_t s);
+// One-time split operator build (before capture).
+lt_status prepare_split(lt_tree_s* t, int p, hipStream_t s);
+
+// Learned flags over a count that may live on the device: features of u
+// (5 variables x 64 points), the fused network and the decision over the
+// geometric flags already in `flags`.  mlp_reserve sizes the feature buffer.
+lt_status mlp_reserve(lt_mlp m, int64_t n);
+lt_status launch_mlp_flag(lt_tree_s* t, lt_mlp m, Count n, const double* u, int64_t ld, float conf_min,
+                          int8_t* flags, float* conf, hipStream_t s);
 
 lt_status launch_transfer(lt_tree_s* t, int p, const double* ops, int nvar, const double* u_old,
                           int64_t ld_old, double* u_new, int64_t ld_new, hipStream_t s);

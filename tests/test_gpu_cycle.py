@@ -168,3 +168,41 @@ def test_captured_cycle_finishes_long_ripples_eagerly():
     runs, eager, recap = cyc.stats()
     assert eager >= 1
     del cyc
+
+
+def test_captured_chosen_cycle_matches_eager():
+    """Learned flags (network over the geometric fallback) and the split
+    transfer, captured, against the same calls made eagerly."""
+    import torch
+    import paper_2306_06744_amd as lt
+    w = synth.workload_3d_extruded(2007)
+    nodes = synth.gl_nodes01(3)
+    m = lt.MLP(synth.mlp_init(21))
+    E = lt.Tree.uniform(3, w.d_min, w.d_max)
+    G = lt.Tree.uniform(3, w.d_min, w.d_max)
+    for c in range(2):
+        for t in (E, G):
+            t.adapt(t.flag(**flag_args(w, c, nodes)))
+            t.balance()
+    cap = 4_000_000
+    u = [torch.zeros((5, 64, cap), dtype=torch.float64, device="cuda") for _ in range(2)]
+    cyc = lt.Cycle(G, 3, 5, cap, u, flag_args(w, 2, nodes), balance_passes=2, precision=1, mlp=m)
+    cur = 0
+    for c in range(2, 6):
+        fa = flag_args(w, c, nodes)
+        cen = w.centres_at(c)
+        G.vortex_field(cen, w.strengths, nodes, w.lo, w.length, out=u[cur])
+        uE = E.vortex_field(cen, w.strengths, nodes, w.lo, w.length)
+        assert bool((u[cur][:, :, :E.size()] == uE).all())
+        cur = cyc.run(fa)
+        f, _ = E.flag_mlp(m, uE, cen, w.r_in, w.r_out, nodes, w.lo, w.length, conf_min=0.9,
+                          dist_axes=w.dist_axes)
+        E.adapt(f)
+        E.balance()
+        E.connect()
+        E.map()
+        uE = E.transfer(3, uE, precision=1)
+        torch.cuda.synchronize()
+        print("chosen cycle", c, G.size(), cyc.stats(), flush=True)
+        compare(G, E, u[cur], uE, E.size())
+    del cyc
