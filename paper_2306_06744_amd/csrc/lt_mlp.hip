@@ -485,6 +485,202 @@ __global__ __launch_bounds__(64 * kFlagWaves) void k_mlp_flag(
   }
 }
 
+// Features and network in one pass (learned flags over a whole mesh).  The
+// same workgroup shape as k_mlp_flag, but each wave builds its 16 rows of
+// features itself: lane group g (lanes 16g .. 16g+15, one element each)
+// loads z-slab g of the element's 64 values of one variable, transforms it
+// along x and y in registers, and the z pass combines the four slabs over
+// three rotation rounds of cross-lane exchange (round r: lane group g sends
+// its row my = (g + r) mod 4 and receives slab (g - r) mod 4 of row my = g),
+// so lane group g ends with the coefficients of row my = g.  The 64 BF16
+// features of a variable are staged in the wave's LDS patch and read back as
+// matrix-core A fragments.  No feature array is written to memory.
+__device__ inline double pick4(const double* a, int row, int x) {
+  const double r0 = a[x], r1 = a[4 + x], r2 = a[8 + x], r3 = a[12 + x];
+  return row == 0 ? r0 : (row == 1 ? r1 : (row == 2 ? r2 : r3));
+}
+
+__global__ __launch_bounds__(64 * kFlagWaves) void k_mlp_flag_fused(
+    KeyGeom g, const uint64_t* __restrict__ keys, const double* __restrict__ u, int64_t ld, Count cn,
+    const double* __restrict__ T4, const bf16* __restrict__ W1, const bf16* __restrict__ W2,
+    const bf16* __restrict__ W3, const float* __restrict__ P, int64_t off_b1, int64_t off_b2,
+    int64_t off_b3, float conf_min, int8_t* __restrict__ flags, float* __restrict__ conf) {
+  constexpr int kFS = 72;  // staging row stride (BF16) of one element's 64 features
+  __shared__ __attribute__((aligned(16))) bf16 sW1[128 * kW1S];
+  __shared__ __attribute__((aligned(16))) bf16 sW2[64 * kW2S];
+  __shared__ __attribute__((aligned(16))) bf16 sH1[kFlagWaves][16 * kH1S];
+  __shared__ __attribute__((aligned(16))) bf16 sH2[kFlagWaves][16 * kH2S];
+  __shared__ float sZ[kFlagWaves][16][4];
+  __shared__ float sB[128 + 64 + 4];
+  const int64_t n = cn.get();
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4, lk = 8 * lg;
+  for (int c = tid; c < 128 * 40; c += 64 * kFlagWaves) {
+    const int row = c / 40, c16 = c % 40;
+    *reinterpret_cast<bf16x8*>(sW1 + row * kW1S + c16 * 8) =
+        *reinterpret_cast<const bf16x8*>(W1 + row * 320 + c16 * 8);
+  }
+  for (int c = tid; c < 64 * 16; c += 64 * kFlagWaves) {
+    const int row = c / 16, c16 = c % 16;
+    *reinterpret_cast<bf16x8*>(sW2 + row * kW2S + c16 * 8) =
+        *reinterpret_cast<const bf16x8*>(W2 + row * 128 + c16 * 8);
+  }
+  for (int c = tid; c < 128 + 64 + 3; c += 64 * kFlagWaves)
+    sB[c] = c < 128 ? P[off_b1 + c] : (c < 192 ? P[off_b2 + c - 128] : P[off_b3 + c - 192]);
+  bf16x8 b3f[2];
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks) {
+    if (lr < 3) {
+      b3f[ks] = *reinterpret_cast<const bf16x8*>(W3 + lr * 64 + 32 * ks + lk);
+    } else {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) b3f[ks][t] = bf16(0.f);
+    }
+  }
+  double T[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) T[i] = T4[i];
+  __syncthreads();
+  bf16* H1 = sH1[w];
+  bf16* H2 = sH2[w];
+  bf16* FS = sH1[w];  // feature staging shares the layer-1 patch (used one after the other)
+  const int64_t ntiles = (n + 15) / 16;
+  const int64_t stride = int64_t(gridDim.x) * kFlagWaves;
+  // The round loop is uniform over the workgroup (every wave reaches every
+  // barrier); a wave whose tile lies past the end computes on zeros and
+  // writes nothing.
+  for (int64_t base = int64_t(blockIdx.x) * kFlagWaves; base < ntiles; base += stride) {
+    const int64_t tile = base + w;
+    const int64_t e = tile * 16 + lr;
+    const bool live = tile < ntiles && e < n;
+    // layer 1 accumulates variable by variable: acc[ct] += X[:, 64v .. 64v+63] W1^T
+    f32x4 acc1[8];
+#pragma unroll
+    for (int ct = 0; ct < 8; ++ct) acc1[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int v = 0; v < 5; ++v) {
+      double a[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) a[i] = live ? u[(int64_t(v) * 64 + lg * 16 + i) * ld + e] : 0.0;
+#pragma unroll
+      for (int pass = 0; pass < 2; ++pass) {
+        const int st = pass == 0 ? 1 : 4;
+#pragma unroll
+        for (int line = 0; line < 4; ++line) {
+          const int b0 = pass == 0 ? line * 4 : line;
+          const double x0 = a[b0], x1 = a[b0 + st], x2 = a[b0 + 2 * st], x3 = a[b0 + 3 * st];
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+            a[b0 + m * st] = T[m * 4] * x0 + T[m * 4 + 1] * x1 + T[m * 4 + 2] * x2 + T[m * 4 + 3] * x3;
+        }
+      }
+      // a[my*4 + mx] = slab lg's partial coefficients; z pass over the 4 slabs
+      double c[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) c[i] = 0.0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int z = (lg - r) & 3;         // slab received this round
+        const int row = (lg + r) & 3;       // row sent this round
+        const int srcl = z * 16 + lr;
+        double val[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          const double sendv = pick4(a, row, x);
+          val[x] = r == 0 ? sendv : __shfl(sendv, srcl);
+        }
+#pragma unroll
+        for (int mz = 0; mz < 4; ++mz) {
+          const double tz = z == 0 ? T[mz * 4] : (z == 1 ? T[mz * 4 + 1] : (z == 2 ? T[mz * 4 + 2] : T[mz * 4 + 3]));
+#pragma unroll
+          for (int x = 0; x < 4; ++x) c[mz * 4 + x] += tz * val[x];
+        }
+      }
+      __syncthreads();  // the previous variable's fragments have been read
+#pragma unroll
+      for (int mz = 0; mz < 4; ++mz)
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          const float cc = float(fabs(c[mz * 4 + x]) + 1e-14);
+          FS[lr * kFS + mz * 16 + lg * 4 + x] = bf16((log10f(cc) + 7.0f) / 7.0f);
+        }
+      __syncthreads();
+      bf16x8 af[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) af[h] = *reinterpret_cast<const bf16x8*>(FS + lr * kFS + 32 * h + lk);
+#pragma unroll
+      for (int ct = 0; ct < 8; ++ct)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const bf16x8 bf =
+              *reinterpret_cast<const bf16x8*>(sW1 + (16 * ct + lr) * kW1S + 64 * v + 32 * h + lk);
+          acc1[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[h], bf, acc1[ct], 0, 0, 0);
+        }
+    }
+    __syncthreads();  // staging reads done before layer 1 writes the patch
+#pragma unroll
+    for (int ct = 0; ct < 8; ++ct) {
+      const float bias = sB[16 * ct + lr];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float hv = acc1[ct][q] + bias;
+        H1[(4 * lg + q) * kH1S + 16 * ct + lr] = bf16(hv > 0.f ? hv : 0.f);
+      }
+    }
+    __syncthreads();
+    bf16x8 h1f[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) h1f[ks] = *reinterpret_cast<const bf16x8*>(H1 + lr * kH1S + 32 * ks + lk);
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const bf16x8 bf = *reinterpret_cast<const bf16x8*>(sW2 + (16 * ct + lr) * kW2S + 32 * ks + lk);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h1f[ks], bf, acc, 0, 0, 0);
+      }
+      const float bias = sB[128 + 16 * ct + lr];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float hv = acc[q] + bias;
+        H2[(4 * lg + q) * kH2S + 16 * ct + lr] = bf16(hv > 0.f ? hv : 0.f);
+      }
+    }
+    __syncthreads();
+    f32x4 acc3 = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(H2 + lr * kH2S + 32 * ks + lk);
+      acc3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b3f[ks], acc3, 0, 0, 0);
+    }
+    if (lr < 3)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sZ[w][4 * lg + q][lr] = acc3[q] + sB[192 + lr];
+    __syncthreads();
+    const int64_t eo = tile * 16 + lane;
+    if (lane < 16 && tile < ntiles && eo < n) {
+      const float z0 = sZ[w][lane][0], z1 = sZ[w][lane][1], z2 = sZ[w][lane][2];
+      const float mx = fmaxf(z0, fmaxf(z1, z2));
+      const float e0 = expf(z0 - mx), e1 = expf(z1 - mx), e2 = expf(z2 - mx);
+      const float sum = e0 + e1 + e2;
+      int cls = 0;
+      float pc = e0;
+      if (e1 > pc) { cls = 1; pc = e1; }
+      if (e2 > pc) { cls = 2; pc = e2; }
+      pc /= sum;
+      if (conf) conf[eo] = pc;
+      int f = pc >= conf_min ? cls - 1 : int(flags[eo]);
+      const uint64_t key = keys[eo];
+      const int d = key_depth(g, key);
+      int lo, hi;
+      depth_limits(g, key, &lo, &hi);
+      if (f == 1 && d >= hi) f = 0;
+      if (f == -1 && d <= lo) f = 0;
+      flags[eo] = int8_t(f);
+    }
+  }
+}
+
 inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
 // T[n][i] = w_i sqrt((2n+1)/2) P_n(x_i) at the p+1 Gauss-Legendre points
@@ -665,13 +861,11 @@ lt_status launch_mlp_flag(lt_tree_s* t, lt_mlp m, Count n, const double* u, int6
                           int8_t* flags, float* conf, hipStream_t s) {
   if (t->g.dim != 3) return fail(LT_ERR_ARG, "the learned indicator takes 3D p = 3 elements");
   if (n.n == 0) return LT_OK;
-  if (m->xcap < n.n) return fail(LT_ERR_ARG, "feature buffer smaller than the leaves");
-  k_mlp_features<<<dim3(nblk(n.n, 64), 5u), 256, 0, s>>>(m->T4, u, ld, 5, nullptr, n, m->X);
   const int64_t ntiles = (n.n + 16 * kFlagWaves - 1) / (16 * kFlagWaves);
   const unsigned grid = unsigned(std::min<int64_t>(ntiles, 256));
-  k_mlp_flag<<<grid, 64 * kFlagWaves, 0, s>>>(t->g, t->kbuf[t->cur], m->X, n, m->W1, m->W2, m->W3, m->P,
-                                              lt_mlp_s::off_b1, lt_mlp_s::off_b2, lt_mlp_s::off_b3,
-                                              conf_min, flags, conf);
+  k_mlp_flag_fused<<<grid, 64 * kFlagWaves, 0, s>>>(t->g, t->kbuf[t->cur], u, ld, n, m->T4, m->W1, m->W2,
+                                                    m->W3, m->P, lt_mlp_s::off_b1, lt_mlp_s::off_b2,
+                                                    lt_mlp_s::off_b3, conf_min, flags, conf);
   if (hipGetLastError() != hipSuccess) return fail(LT_ERR_HIP, "learned flag launch");
   return LT_OK;
 }
