@@ -335,155 +335,17 @@ __global__ __launch_bounds__(256) void k_flag_modal(KeyGeom g, const uint64_t* _
   flags[e] = int8_t(f);
 }
 
-// Fused inference and decision.  Workgroups of 8 waves hold W1 and W2 in
-// LDS; each wave runs its own 16-row tiles: the feature rows come straight
-// from memory as matrix-core A fragments (the next tile's are loaded while
-// the current one computes), layer-1 and layer-2 activations pass through a
-// per-wave LDS patch (BF16), W3 sits in registers, and the logits go
-// straight to the decision: argmax class (0 coarsen, 1 keep, 2 refine) when
-// its softmax probability reaches conf_min, else the geometric flag already
-// in `flags`; then the depth clamps.
+// Learned flags over a mesh: workgroups of 8 waves hold W1 and W2 in LDS;
+// each wave runs its own 16-element tiles, with its activations in a
+// per-wave LDS patch (BF16), W3 in registers, and the logits going straight
+// to the decision: argmax class (0 coarsen, 1 keep, 2 refine) when its
+// softmax probability reaches conf_min, else the geometric flag already in
+// `flags`; then the depth clamps.
 constexpr int kW1S = 328;  // LDS row stride (BF16) of W1 (320 + pad)
 constexpr int kW2S = 136;  // W2 (128 + pad)
 constexpr int kH1S = 136;  // layer-1 activations of a wave's 16 rows (128 + pad)
 constexpr int kH2S = 72;   // layer-2 activations (64 + pad)
 constexpr int kFlagWaves = 8;
-
-__global__ __launch_bounds__(64 * kFlagWaves) void k_mlp_flag(
-    KeyGeom g, const uint64_t* __restrict__ keys, const bf16* __restrict__ X, Count cn,
-    const bf16* __restrict__ W1, const bf16* __restrict__ W2, const bf16* __restrict__ W3,
-    const float* __restrict__ P, int64_t off_b1, int64_t off_b2, int64_t off_b3, float conf_min,
-    int8_t* __restrict__ flags, float* __restrict__ conf) {
-  __shared__ __attribute__((aligned(16))) bf16 sW1[128 * kW1S];
-  __shared__ __attribute__((aligned(16))) bf16 sW2[64 * kW2S];
-  __shared__ __attribute__((aligned(16))) bf16 sH1[kFlagWaves][16 * kH1S];
-  __shared__ __attribute__((aligned(16))) bf16 sH2[kFlagWaves][16 * kH2S];
-  __shared__ float sZ[kFlagWaves][16][4];
-  __shared__ float sB[128 + 64 + 4];
-  const int64_t n = cn.get();
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int lr = lane & 15, lk = 8 * (lane >> 4);
-  for (int c = tid; c < 128 * 40; c += 64 * kFlagWaves) {
-    const int row = c / 40, c16 = c % 40;
-    *reinterpret_cast<bf16x8*>(sW1 + row * kW1S + c16 * 8) =
-        *reinterpret_cast<const bf16x8*>(W1 + row * 320 + c16 * 8);
-  }
-  for (int c = tid; c < 64 * 16; c += 64 * kFlagWaves) {
-    const int row = c / 16, c16 = c % 16;
-    *reinterpret_cast<bf16x8*>(sW2 + row * kW2S + c16 * 8) =
-        *reinterpret_cast<const bf16x8*>(W2 + row * 128 + c16 * 8);
-  }
-  for (int c = tid; c < 128 + 64 + 3; c += 64 * kFlagWaves)
-    sB[c] = c < 128 ? P[off_b1 + c] : (c < 192 ? P[off_b2 + c - 128] : P[off_b3 + c - 192]);
-  bf16x8 b3f[2];
-#pragma unroll
-  for (int ks = 0; ks < 2; ++ks) {
-    if (lr < 3) {
-      b3f[ks] = *reinterpret_cast<const bf16x8*>(W3 + lr * 64 + 32 * ks + lk);
-    } else {
-#pragma unroll
-      for (int t = 0; t < 8; ++t) b3f[ks][t] = bf16(0.f);
-    }
-  }
-  __syncthreads();
-  bf16* H1 = sH1[w];
-  bf16* H2 = sH2[w];
-  const int64_t ntiles = (n + 15) / 16;
-  const int64_t stride = int64_t(gridDim.x) * kFlagWaves;
-  auto load_a = [&](int64_t t, bf16x8* af) {
-    const int64_t row = t * 16 + lr;
-#pragma unroll
-    for (int ks = 0; ks < 10; ++ks) {
-      if (t < ntiles && row < n) {
-        af[ks] = *reinterpret_cast<const bf16x8*>(X + row * 320 + 32 * ks + lk);
-      } else {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) af[ks][q] = bf16(0.f);
-      }
-    }
-  };
-  bf16x8 a_cur[10], a_nxt[10];
-  // The round loop is uniform over the workgroup (every wave reaches every
-  // barrier); a wave whose tile lies past the end computes on zeros and
-  // writes nothing.
-  const int64_t base0 = int64_t(blockIdx.x) * kFlagWaves;
-  load_a(base0 + w, a_cur);
-  for (int64_t base = base0; base < ntiles; base += stride) {
-    const int64_t tile = base + w;
-    load_a(tile + stride, a_nxt);
-    // layer 1: H1 = relu(X W1^T + b1), 16 rows x 128
-#pragma unroll
-    for (int ct = 0; ct < 8; ++ct) {
-      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ks = 0; ks < 10; ++ks) {
-        const bf16x8 bf = *reinterpret_cast<const bf16x8*>(sW1 + (16 * ct + lr) * kW1S + 32 * ks + lk);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_cur[ks], bf, acc, 0, 0, 0);
-      }
-      const float bias = sB[16 * ct + lr];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float h = acc[q] + bias;
-        H1[(4 * (lane >> 4) + q) * kH1S + 16 * ct + lr] = bf16(h > 0.f ? h : 0.f);
-      }
-    }
-    __syncthreads();
-    // layer 2: H2 = relu(H1 W2^T + b2), 16 rows x 64
-    bf16x8 h1f[4];
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) h1f[ks] = *reinterpret_cast<const bf16x8*>(H1 + lr * kH1S + 32 * ks + lk);
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        const bf16x8 bf = *reinterpret_cast<const bf16x8*>(sW2 + (16 * ct + lr) * kW2S + 32 * ks + lk);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h1f[ks], bf, acc, 0, 0, 0);
-      }
-      const float bias = sB[128 + 16 * ct + lr];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float h = acc[q] + bias;
-        H2[(4 * (lane >> 4) + q) * kH2S + 16 * ct + lr] = bf16(h > 0.f ? h : 0.f);
-      }
-    }
-    __syncthreads();
-    // layer 3: logits, 16 rows x 3 (padded to 16)
-    f32x4 acc3 = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      const bf16x8 af = *reinterpret_cast<const bf16x8*>(H2 + lr * kH2S + 32 * ks + lk);
-      acc3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b3f[ks], acc3, 0, 0, 0);
-    }
-    if (lr < 3)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) sZ[w][4 * (lane >> 4) + q][lr] = acc3[q] + sB[192 + lr];
-    __syncthreads();
-    const int64_t e = tile * 16 + lane;
-    if (lane < 16 && e < n) {
-      const float z0 = sZ[w][lane][0], z1 = sZ[w][lane][1], z2 = sZ[w][lane][2];
-      const float mx = fmaxf(z0, fmaxf(z1, z2));
-      const float e0 = expf(z0 - mx), e1 = expf(z1 - mx), e2 = expf(z2 - mx);
-      const float sum = e0 + e1 + e2;
-      int c = 0;
-      float pc = e0;
-      if (e1 > pc) { c = 1; pc = e1; }
-      if (e2 > pc) { c = 2; pc = e2; }
-      pc /= sum;
-      if (conf) conf[e] = pc;
-      int f = pc >= conf_min ? c - 1 : int(flags[e]);
-      const uint64_t key = keys[e];
-      const int d = key_depth(g, key);
-      int lo, hi;
-      depth_limits(g, key, &lo, &hi);
-      if (f == 1 && d >= hi) f = 0;
-      if (f == -1 && d <= lo) f = 0;
-      flags[e] = int8_t(f);
-    }
-#pragma unroll
-    for (int ks = 0; ks < 10; ++ks) a_cur[ks] = a_nxt[ks];
-  }
-}
 
 // Features and network in one pass (learned flags over a whole mesh).  The
 // same workgroup shape as k_mlp_flag, but each wave builds its 16 rows of
@@ -495,6 +357,15 @@ __global__ __launch_bounds__(64 * kFlagWaves) void k_mlp_flag(
 // so lane group g ends with the coefficients of row my = g.  The 64 BF16
 // features of a variable are staged in the wave's LDS patch and read back as
 // matrix-core A fragments.  No feature array is written to memory.
+// Orders one wave's LDS writes before its later LDS reads by other lanes of
+// the same wave (the patches below are private to a wave; the wave's LDS
+// operations execute in program order, the fences keep the compiler's order).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ inline double pick4(const double* a, int row, int x) {
   const double r0 = a[x], r1 = a[4 + x], r2 = a[8 + x], r3 = a[12 + x];
   return row == 0 ? r0 : (row == 1 ? r1 : (row == 2 ? r2 : r3));
@@ -546,22 +417,21 @@ __global__ __launch_bounds__(64 * kFlagWaves) void k_mlp_flag_fused(
   bf16* FS = sH1[w];  // feature staging shares the layer-1 patch (used one after the other)
   const int64_t ntiles = (n + 15) / 16;
   const int64_t stride = int64_t(gridDim.x) * kFlagWaves;
-  // The round loop is uniform over the workgroup (every wave reaches every
-  // barrier); a wave whose tile lies past the end computes on zeros and
+  // Waves run their tiles independently (every LDS patch in the loop is a
+  // wave's own); a wave whose tile lies past the end computes on zeros and
   // writes nothing.
-  for (int64_t base = int64_t(blockIdx.x) * kFlagWaves; base < ntiles; base += stride) {
-    const int64_t tile = base + w;
-    const int64_t e = tile * 16 + lr;
-    const bool live = tile < ntiles && e < n;
+  for (int64_t tile = int64_t(blockIdx.x) * kFlagWaves + w; tile < ntiles; tile += stride) {
     // layer 1 accumulates variable by variable: acc[ct] += X[:, 64v .. 64v+63] W1^T
     f32x4 acc1[8];
 #pragma unroll
     for (int ct = 0; ct < 8; ++ct) acc1[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
     for (int v = 0; v < 5; ++v) {
+      // z-slab lg of this lane's element, variable v
+      const int64_t el = tile * 16 + lr;
       double a[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) a[i] = live ? u[(int64_t(v) * 64 + lg * 16 + i) * ld + e] : 0.0;
+      for (int i = 0; i < 16; ++i) a[i] = el < n ? u[(int64_t(v) * 64 + lg * 16 + i) * ld + el] : 0.0;
 #pragma unroll
       for (int pass = 0; pass < 2; ++pass) {
         const int st = pass == 0 ? 1 : 4;
@@ -596,7 +466,7 @@ __global__ __launch_bounds__(64 * kFlagWaves) void k_mlp_flag_fused(
           for (int x = 0; x < 4; ++x) c[mz * 4 + x] += tz * val[x];
         }
       }
-      __syncthreads();  // the previous variable's fragments have been read
+      wave_lds_sync();  // the previous variable's fragments have been read
 #pragma unroll
       for (int mz = 0; mz < 4; ++mz)
 #pragma unroll
@@ -604,7 +474,7 @@ __global__ __launch_bounds__(64 * kFlagWaves) void k_mlp_flag_fused(
           const float cc = float(fabs(c[mz * 4 + x]) + 1e-14);
           FS[lr * kFS + mz * 16 + lg * 4 + x] = bf16((log10f(cc) + 7.0f) / 7.0f);
         }
-      __syncthreads();
+      wave_lds_sync();
       bf16x8 af[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) af[h] = *reinterpret_cast<const bf16x8*>(FS + lr * kFS + 32 * h + lk);
@@ -617,7 +487,7 @@ __global__ __launch_bounds__(64 * kFlagWaves) void k_mlp_flag_fused(
           acc1[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[h], bf, acc1[ct], 0, 0, 0);
         }
     }
-    __syncthreads();  // staging reads done before layer 1 writes the patch
+    wave_lds_sync();  // staging reads done before layer 1 writes the patch
 #pragma unroll
     for (int ct = 0; ct < 8; ++ct) {
       const float bias = sB[16 * ct + lr];
@@ -627,7 +497,7 @@ __global__ __launch_bounds__(64 * kFlagWaves) void k_mlp_flag_fused(
         H1[(4 * lg + q) * kH1S + 16 * ct + lr] = bf16(hv > 0.f ? hv : 0.f);
       }
     }
-    __syncthreads();
+    wave_lds_sync();
     bf16x8 h1f[4];
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) h1f[ks] = *reinterpret_cast<const bf16x8*>(H1 + lr * kH1S + 32 * ks + lk);
@@ -646,7 +516,7 @@ __global__ __launch_bounds__(64 * kFlagWaves) void k_mlp_flag_fused(
         H2[(4 * lg + q) * kH2S + 16 * ct + lr] = bf16(hv > 0.f ? hv : 0.f);
       }
     }
-    __syncthreads();
+    wave_lds_sync();
     f32x4 acc3 = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
@@ -656,9 +526,9 @@ __global__ __launch_bounds__(64 * kFlagWaves) void k_mlp_flag_fused(
     if (lr < 3)
 #pragma unroll
       for (int q = 0; q < 4; ++q) sZ[w][4 * lg + q][lr] = acc3[q] + sB[192 + lr];
-    __syncthreads();
+    wave_lds_sync();
     const int64_t eo = tile * 16 + lane;
-    if (lane < 16 && tile < ntiles && eo < n) {
+    if (lane < 16 && eo < n) {
       const float z0 = sZ[w][lane][0], z1 = sZ[w][lane][1], z2 = sZ[w][lane][2];
       const float mx = fmaxf(z0, fmaxf(z1, z2));
       const float e0 = expf(z0 - mx), e1 = expf(z1 - mx), e2 = expf(z2 - mx);
@@ -678,6 +548,7 @@ __global__ __launch_bounds__(64 * kFlagWaves) void k_mlp_flag_fused(
       if (f == -1 && d <= lo) f = 0;
       flags[eo] = int8_t(f);
     }
+    wave_lds_sync();  // sZ and the patches are rewritten by the next tile
   }
 }
 
