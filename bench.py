@@ -190,6 +190,7 @@ def chosen_cycle(lt, torch, synth, w, nodes, stream, steps, warmup, u, cap, E, t
         t.transfer(w.p, u[cur], u_new=u[1 - cur], precision=1)
         cur = 1 - cur
     torch.cuda.synchronize()
+    tuned = t.autotune_transfer(w.p, u[1 - cur], u[cur], precision=1)
     pair = [u[cur], u[1 - cur]]
     capacity = min(cap, int(t.size() * 1.25))
     cyc = lt.Cycle(t, w.p, w.nvar, capacity, pair, fa(warmup), balance_passes=2, precision=1, mlp=m,
@@ -241,6 +242,7 @@ def chosen_cycle(lt, torch, synth, w, nodes, stream, steps, warmup, u, cap, E, t
                       "disagreement": held},
         "capture": {"runs": runs, "eager_finishes": eager, "recaptures": recap,
                     "capacity": capacity, "balance_passes": 2},
+        "transfer_tuning": tuned,
         "note": "learned flags (geometric fallback below 0.9) + split-precision transfer, the "
                 "whole cycle captured in a hipGraph; host wall clock per cycle around the replay "
                 "(one synchronisation); the solution is reset to the vortex field before each "
@@ -299,6 +301,7 @@ def graph_cycle(lt, torch, synth, w, nodes, stream, steps, warmup, u, cap, E, pa
         t.transfer(w.p, u[cur], u_new=u[1 - cur])
         cur = 1 - cur
     torch.cuda.synchronize()
+    tuned = t.autotune_transfer(w.p, u[1 - cur], u[cur])
     pair = [u[cur], u[1 - cur]]
     # capacity: the leaves now plus 25% headroom (the timed cycles grow ~3%)
     capacity = min(cap, int(t.size() * 1.25))
@@ -317,6 +320,7 @@ def graph_cycle(lt, torch, synth, w, nodes, stream, steps, warmup, u, cap, E, pa
     total = sum(b for _, b in sizes)
     return {"value": total / elapsed, "unit": "octants/s", "ms_per_step": elapsed * 1e3 / steps,
             "balance_passes": passes, "runs": runs, "eager_finishes": eager, "recaptures": recap,
+            "transfer_tuning": tuned,
             "capacity": capacity,
             "note": "same cycle, captured once in a hipGraph; host wall clock around the timed "
                     "cycles (one synchronisation per cycle)"}
@@ -380,6 +384,8 @@ def main():
     cap = 4_000_000  # leaves per solution buffer (steady state ~1.7M)
     u = [torch.empty((w.nvar, npts, cap), dtype=torch.float64, device="cuda") for _ in range(2)]
 
+    tunes = {}
+
     def run(precision):
         """Warm-up cycles, then the timed cycles; returns sizes, wall time and
         the transfer's event times."""
@@ -412,6 +418,10 @@ def main():
         for c in range(args.warmup):
             n_old, n_new, _ = step(c)
             log(f"[precision {precision}] warmup cycle {c}: {n_old} -> {n_new}")
+        # launch shapes of the transfer, timed on the last warm-up mapping (untimed here)
+        tuned = t.autotune_transfer(w.p, u[1 - cur], u[cur], precision=precision)
+        log(f"[precision {precision}] autotuned transfer: {tuned}")
+        tunes[precision] = tuned
         torch.cuda.synchronize()
         events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                   for _ in range(args.steps)]
@@ -478,6 +488,7 @@ def main():
             "leaves_new_mean": total_new / args.steps,
             "cycle_hbm_frac": cyc_bytes / elapsed / (HBM_PEAK_GBS * 1e9),
             "transfer_ms_mean": sum(tr_ms) / len(tr_ms),
+            "transfer_tuning": tunes.get(0),
         },
         "roofline": {
             "bound": "hbm",

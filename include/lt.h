@@ -191,6 +191,29 @@ lt_status lt_map(lt_tree t, void* stream);
 lt_status lt_transfer(lt_tree t, int p, int nvar, const double* u_old, int64_t ld_old,
                       double* u_new, int64_t ld_new, int precision, void* stream);
 
+/* Tuning of the transfer's launch shapes (results never depend on them):
+ * elements per lane of the copy pass (1, 2 or 4; one block row covers 256
+ * times that many elements) and persistent workgroups per variable of the
+ * 3D interpolation pass.  Defaults 2 and 2048. */
+typedef struct {
+  int copy_elems_per_lane;
+  int interp_grid;
+  float ms;          /* lt_autotune_transfer: mean time of the chosen shape     */
+  float ms_default;  /*   and of the default shape (ms); -1 from lt_get_tuning  */
+} lt_tune;
+
+/* Times lt_transfer (same arguments, same result every time: u_new is
+ * written repeatedly) for every tuning candidate -- copy elements per lane
+ * {1, 2, 4} x interpolation workgroups {1024, 2048, 4096} -- with HIP events,
+ * one untimed and three timed launches each, and keeps the fastest in the
+ * tree for later transfers (and cycles captured later).  Synchronises. */
+lt_status lt_autotune_transfer(lt_tree t, int p, int nvar, const double* u_old, int64_t ld_old,
+                               double* u_new, int64_t ld_new, int precision, void* stream,
+                               lt_tune* out);
+/* Set / read the tree's tuning (LT_ERR_ARG for values outside the ranges). */
+lt_status lt_set_tuning(lt_tree t, const lt_tune* tune);
+lt_status lt_get_tuning(lt_tree t, lt_tune* tune);
+
 /* Host-side sizes (no device work): current leaves, leaves before the last
  * lt_adapt (-1 if none), rows of the hanging-face table (-1 before lt_connect).
  * Any pointer may be NULL. */

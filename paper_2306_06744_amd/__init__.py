@@ -28,7 +28,8 @@ EXPORTS = ["lt_build_uniform", "lt_build", "lt_build_batch", "lt_flag_batch", "l
            "lt_view", "lt_export", "lt_mlp_create", "lt_mlp_params", "lt_mlp_features",
            "lt_mlp_grads", "lt_mlp_train_step", "lt_mlp_infer", "lt_flag_mlp", "lt_vortex_field",
            "lt_flag_modal", "lt_mlp_destroy", "lt_cycle_create", "lt_cycle_run",
-           "lt_cycle_stats", "lt_cycle_destroy", "lt_last_error", "lt_destroy"]
+           "lt_cycle_stats", "lt_cycle_destroy", "lt_autotune_transfer", "lt_set_tuning",
+           "lt_get_tuning", "lt_last_error", "lt_destroy"]
 MLP_NPARAM = 128 * 320 + 128 + 64 * 128 + 64 + 3 * 64 + 3
 
 
@@ -49,6 +50,11 @@ class FlagParams(C.Structure):
                 ("periodic_dist", C.c_int), ("p", C.c_int),
                 ("nodes01", C.POINTER(C.c_double)), ("lo", C.c_double * 3),
                 ("len", C.c_double), ("raw", C.c_int)]
+
+
+class Tune(C.Structure):
+    _fields_ = [("copy_elems_per_lane", C.c_int), ("interp_grid", C.c_int), ("ms", C.c_float),
+                ("ms_default", C.c_float)]
 
 
 class CycleDesc(C.Structure):
@@ -97,6 +103,9 @@ def lib() -> C.CDLL:
         L.lt_cycle_create.argtypes = [P, C.POINTER(CycleDesc), P, C.POINTER(P)]
         L.lt_cycle_run.argtypes = [P, C.POINTER(FlagParams), P, C.POINTER(i32)]
         L.lt_cycle_stats.argtypes = [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+        L.lt_autotune_transfer.argtypes = [P, i32, i32, P, i64, P, i64, i32, P, C.POINTER(Tune)]
+        L.lt_set_tuning.argtypes = [P, C.POINTER(Tune)]
+        L.lt_get_tuning.argtypes = [P, C.POINTER(Tune)]
         L.lt_cycle_destroy.argtypes = [P]
         L.lt_cycle_destroy.restype = None
         L.lt_last_error.restype = C.c_char_p
@@ -308,6 +317,25 @@ class Tree:
         return u_new
 
     # ---- results
+    def autotune_transfer(self, p, u_old, u_new, precision=0):
+        """Time every transfer launch shape on the current mapping and keep the
+        fastest; returns the lt_tune record (as a dict)."""
+        tn = Tune()
+        _check(lib().lt_autotune_transfer(self._h, int(p), u_old.shape[0], _dptr(u_old), u_old.shape[2],
+                                          _dptr(u_new), u_new.shape[2], int(precision), _stream(),
+                                          C.byref(tn)))
+        return {"copy_elems_per_lane": tn.copy_elems_per_lane, "interp_grid": tn.interp_grid,
+                "ms": tn.ms, "ms_default": tn.ms_default}
+
+    def set_tuning(self, copy_elems_per_lane=2, interp_grid=2048):
+        tn = Tune(int(copy_elems_per_lane), int(interp_grid), -1.0, -1.0)
+        _check(lib().lt_set_tuning(self._h, C.byref(tn)))
+
+    def tuning(self):
+        tn = Tune()
+        _check(lib().lt_get_tuning(self._h, C.byref(tn)))
+        return {"copy_elems_per_lane": tn.copy_elems_per_lane, "interp_grid": tn.interp_grid}
+
     def export(self, what: int):
         torch = _torch()
         n, n_old, n_hang = self.sizes()

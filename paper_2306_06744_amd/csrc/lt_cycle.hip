@@ -86,7 +86,7 @@ lt_status reserve(lt_cycle c, hipStream_t s) {
   c->hang_rows = t->hang_cap / (2 + (1 << (dim - 1)));
   LT_TRY_STATUS(grow(&t->map_src, &t->map_cap, C));
   LT_TRY_STATUS(grow(&t->map_kind, &t->kind_cap, C));
-  LT_TRY_STATUS(grow(&t->copy_delta, &t->copy_delta_cap, C / 512 + 2));
+  LT_TRY_STATUS(grow(&t->copy_delta, &t->copy_delta_cap, C / 256 + 2));  // chunks at the finest tuning
   LT_TRY_STATUS(grow(&t->grp_list, &t->grp_cap, C / 64 + 2));
   LT_TRY_STATUS(grow(&t->status, &t->status_cap, std::max<int64_t>(1, (C + kTile - 1) / kTile)));
   dir_params(t->g, C, &c->dir_shift, &c->dir_nb);

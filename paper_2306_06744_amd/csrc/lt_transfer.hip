@@ -203,19 +203,21 @@ typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
 
 // Copy runs.  Between the refinement fronts the new elements are copies of
 // consecutive old elements, so src[j] - j is constant over long runs.  A
-// chunk of kCopyChunk new elements that lies inside one such run is "pure":
-// its source offset is one word, and the copy of that chunk needs no
-// per-element map reads.  cdelta[c] = src[j] - j for a pure chunk, else
-// kImpure.
-constexpr int kCopyChunk = 512;
+// chunk of 256*EPL new elements (one block row of the copy pass, EPL
+// elements per lane) that lies inside one such run is "pure": its source
+// offset is one word, and the copy of that chunk needs no per-element map
+// reads.  cdelta[c] = src[j] - j for a pure chunk, else kImpure.  EPL is a
+// tuning parameter (1, 2 or 4; lt_autotune_transfer picks it).
 constexpr int64_t kImpure = INT64_MIN;
 
+template <int EPL>
 __global__ __launch_bounds__(256) void k_copy_chunks(const int32_t* __restrict__ src,
                                                      const int8_t* __restrict__ kind, Count cn,
                                                      int64_t* __restrict__ cdelta) {
+  constexpr int64_t CH = 256 * EPL;
   const int64_t n = cn.get();
   const int64_t c = blockIdx.x;
-  const int64_t j0 = c * kCopyChunk;
+  const int64_t j0 = c * CH;
   if (j0 >= n) {  // launches sized for a capacity: chunks past the end
     if (threadIdx.x == 0) cdelta[c] = kImpure;
     return;
@@ -224,42 +226,53 @@ __global__ __launch_bounds__(256) void k_copy_chunks(const int32_t* __restrict__
   const int64_t ref = head ? int64_t(src[j0]) - j0 : 0;
   bool ok = head;
 #pragma unroll
-  for (int e = 0; e < kCopyChunk / 256; ++e) {
-    const int64_t j = j0 + int64_t(threadIdx.x) * (kCopyChunk / 256) + e;
+  for (int e = 0; e < EPL; ++e) {
+    const int64_t j = j0 + int64_t(e) * 256 + threadIdx.x;
     if (j < n) ok = ok && kind[j] == 0 && int64_t(src[j]) - j == ref;
   }
   ok = __syncthreads_and(ok);
   if (threadIdx.x == 0) cdelta[c] = ok ? ref : kImpure;
 }
 
-// Copy pass (COPY elements).  One block moves one point row (variable v, point i) of one
-// chunk: 256 lanes x two elements.  Pure chunks read one offset and move
-// 16-byte pairs like a plain copy; impure chunks read the map per element and
-// move only the copy elements.  Output stores are streaming (non-temporal).
+// Copy pass (COPY elements).  One block moves one point row (variable v,
+// point i) of one chunk: 256 lanes x EPL elements.  Pure chunks read one
+// offset and move the row like a plain copy (16-byte pairs for EPL >= 2);
+// impure chunks read the map per element and move only the copy elements.
+// Output stores are streaming (non-temporal).
+template <int EPL>
 __global__ __launch_bounds__(256) void k_copy3(const int32_t* __restrict__ src,
                                                const int8_t* __restrict__ kind, Count cn,
                                                const int64_t* __restrict__ cdelta,
                                                const double* __restrict__ uo, int64_t ldo,
                                                double* __restrict__ un, int64_t ldn) {
+  constexpr int64_t CH = 256 * EPL;
   const int64_t n = cn.get();
   const int64_t c = xcd_chunk(blockIdx.x, gridDim.x);
-  if (c * kCopyChunk >= n) return;
-  const int64_t j = c * kCopyChunk + int64_t(threadIdx.x) * 2;
+  if (c * CH >= n) return;
   const double* U = uo + int64_t(blockIdx.y) * ldo;
   double* O = un + int64_t(blockIdx.y) * ldn;
   const int64_t dl = cdelta[c];
   if (dl != kImpure) {
-    if (j + 1 < n) {
-      const d2u t = *reinterpret_cast<const d2u*>(U + j + dl);
-      __builtin_nontemporal_store(t, reinterpret_cast<d2u*>(O + j));
-    } else if (j < n) {
-      __builtin_nontemporal_store(U[j + dl], O + j);
+    if constexpr (EPL == 1) {
+      const int64_t j = c * CH + threadIdx.x;
+      if (j < n) __builtin_nontemporal_store(U[j + dl], O + j);
+    } else {
+#pragma unroll
+      for (int h = 0; h < EPL / 2; ++h) {
+        const int64_t j = c * CH + int64_t(h) * 512 + int64_t(threadIdx.x) * 2;
+        if (j + 1 < n) {
+          const d2u t = *reinterpret_cast<const d2u*>(U + j + dl);
+          __builtin_nontemporal_store(t, reinterpret_cast<d2u*>(O + j));
+        } else if (j < n) {
+          __builtin_nontemporal_store(U[j + dl], O + j);
+        }
+      }
     }
     return;
   }
 #pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    const int64_t jj = j + e;
+  for (int e = 0; e < EPL; ++e) {
+    const int64_t jj = c * CH + int64_t(e) * 256 + threadIdx.x;
     if (jj < n && kind[jj] == 0) __builtin_nontemporal_store(U[src[jj]], O + jj);
   }
 }
@@ -434,7 +447,8 @@ hipError_t launch(lt_tree_s* t, const double* ops, const int32_t* src, const int
     k_group_list<<<grid_tiles(st), kBlock, 0, s>>>(kind, n, t->grp_list, st);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 gi{unsigned(std::max<int64_t>(1, std::min<int64_t>(ngroups, 2048))), unsigned(nvar), 1u};
+    const dim3 gi{unsigned(std::max<int64_t>(1, std::min<int64_t>(ngroups, t->tune.interp_grid))),
+                  unsigned(nvar), 1u};
     k_interp3<N><<<gi, 64 * N, 0, s>>>(ops, src, kind, n, t->grp_list, st.total, uo, ldo, un, ldn);
     return hipGetLastError();
   } else {
@@ -450,11 +464,23 @@ lt_status launch_copy(lt_tree_s* t, Count n, int64_t rows, const double* uo, int
                       double* un, int64_t ldn, hipStream_t s) {
   if (n.n == 0) return LT_OK;
   if (rows < 1 || rows > 65535) return fail(LT_ERR_ARG, "copy pass: rows out of range");
-  const int64_t nchunks = (n.n + kCopyChunk - 1) / kCopyChunk;
+  const int epl = t->tune.copy_epl;
+  const int64_t CH = 256 * int64_t(epl);
+  const int64_t nchunks = (n.n + CH - 1) / CH;
   LT_TRY_STATUS(grow(&t->copy_delta, &t->copy_delta_cap, nchunks));
-  k_copy_chunks<<<unsigned(nchunks), 256, 0, s>>>(t->map_src, t->map_kind, n, t->copy_delta);
   const dim3 grid{unsigned(nchunks), unsigned(rows), 1u};
-  k_copy3<<<grid, 256, 0, s>>>(t->map_src, t->map_kind, n, t->copy_delta, uo, ldo, un, ldn);
+#define LT_COPY(E)                                                                              \
+  do {                                                                                          \
+    k_copy_chunks<E><<<unsigned(nchunks), 256, 0, s>>>(t->map_src, t->map_kind, n, t->copy_delta); \
+    k_copy3<E><<<grid, 256, 0, s>>>(t->map_src, t->map_kind, n, t->copy_delta, uo, ldo, un, ldn); \
+  } while (0)
+  if (epl == 1)
+    LT_COPY(1);
+  else if (epl == 4)
+    LT_COPY(4);
+  else
+    LT_COPY(2);
+#undef LT_COPY
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("copy pass launch: ") + hipGetErrorString(e));
   return LT_OK;
@@ -527,3 +553,76 @@ lt_status launch_transfer(lt_tree_s* t, Count n, const int64_t* ngroups_dev, int
 }
 
 }  // namespace lt
+
+// ------------------------------------------------------------------ tuning
+using namespace lt;
+
+extern "C" {
+
+lt_status lt_set_tuning(lt_tree t, const lt_tune* tune) {
+  if (!t || !tune) return fail(LT_ERR_ARG, "NULL argument");
+  const int e = tune->copy_elems_per_lane;
+  if (e != 1 && e != 2 && e != 4) return fail(LT_ERR_ARG, "copy_elems_per_lane must be 1, 2 or 4");
+  if (tune->interp_grid < 1 || tune->interp_grid > 65535) return fail(LT_ERR_ARG, "interp_grid out of range");
+  t->tune.copy_epl = e;
+  t->tune.interp_grid = tune->interp_grid;
+  return LT_OK;
+}
+
+lt_status lt_get_tuning(lt_tree t, lt_tune* tune) {
+  if (!t || !tune) return fail(LT_ERR_ARG, "NULL argument");
+  tune->copy_elems_per_lane = t->tune.copy_epl;
+  tune->interp_grid = t->tune.interp_grid;
+  tune->ms = -1.f;
+  tune->ms_default = -1.f;
+  return LT_OK;
+}
+
+lt_status lt_autotune_transfer(lt_tree t, int p, int nvar, const double* u_old, int64_t ld_old,
+                               double* u_new, int64_t ld_new, int precision, void* stream, lt_tune* out) {
+  if (!t) return fail(LT_ERR_ARG, "NULL tree");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(LT_ERR_HIP, "event create");
+  const TransferTune keep = t->tune;
+  const int epls[3] = {1, 2, 4};
+  const int grids[3] = {1024, 2048, 4096};
+  TransferTune best = keep;
+  float best_ms = 1e30f, default_ms = -1.f;
+  lt_status st = LT_OK;
+  for (int a = 0; a < 3 && st == LT_OK; ++a)
+    for (int b = 0; b < 3 && st == LT_OK; ++b) {
+      t->tune.copy_epl = epls[a];
+      t->tune.interp_grid = grids[b];
+      // one untimed launch, then three timed ones (every candidate writes the same result)
+      st = lt_transfer(t, p, nvar, u_old, ld_old, u_new, ld_new, precision, stream);
+      if (st != LT_OK) break;
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < 3 && st == LT_OK; ++r)
+        st = lt_transfer(t, p, nvar, u_old, ld_old, u_new, ld_new, precision, stream);
+      (void)hipEventRecord(e1, s);
+      if (hipEventSynchronize(e1) != hipSuccess) st = fail(LT_ERR_HIP, "event sync");
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ms /= 3.f;
+      if (epls[a] == TransferTune{}.copy_epl && grids[b] == TransferTune{}.interp_grid) default_ms = ms;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = t->tune;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  t->tune = st == LT_OK ? best : keep;
+  if (st != LT_OK) return st;
+  if (out) {
+    out->copy_elems_per_lane = best.copy_epl;
+    out->interp_grid = best.interp_grid;
+    out->ms = best_ms;
+    out->ms_default = default_ms;
+  }
+  return LT_OK;
+}
+
+}  // extern "C"

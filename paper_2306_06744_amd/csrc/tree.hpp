@@ -149,8 +149,15 @@ lt_status launch_transfer(lt_tree_s* t, Count n, const int64_t* ngroups_dev, int
 
 }  // namespace lt
 
+// Tuning parameters of the transfer (results never depend on them).
+struct TransferTune {
+  int copy_epl = 2;        // copy pass: elements per lane (1, 2, 4); chunk = 256 * copy_epl
+  int interp_grid = 2048;  // persistent interpolation workgroups per variable
+};
+
 struct lt_tree_s {
   lt::KeyGeom g{};
+  TransferTune tune;
   int device = 0;
   uint64_t* kbuf[3] = {nullptr, nullptr, nullptr};
   int64_t kcap[3] = {0, 0, 0};
