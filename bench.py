@@ -492,7 +492,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "FP64 transfer: k_copy3<64> + k_interp3<4>, event-timed together",
+            "kernel": "FP64 transfer (lt_transfer: k_copy_chunks + k_copy3 copy pass, k_group_list + "
+                      "k_interp3 interpolation), event-timed together",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
