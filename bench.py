@@ -342,17 +342,24 @@ def large_variant(lt, torch, synth, stream):
     g = torch.Generator(device="cuda")
     g.manual_seed(3000)
     u_old = torch.randn((w.nvar, 64, n_old), dtype=torch.float64, device="cuda", generator=g)
-    cen = [(c[0] + 0.05, c[1], c[2]) for c in w.centres]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    f = t.flag(cen, w.r_in, w.r_out, nodes, w.lo, w.length, dist_axes=3)
-    t.adapt(f)
-    t.balance()
-    t.connect()
-    t.map()
-    u64 = t.transfer(w.p, u_old)
-    torch.cuda.synchronize()
-    cycle_s = time.perf_counter() - t0
+    # one untimed cycle grows the library's buffers to this size, then the
+    # centres move once more and the timed cycle runs on warm buffers
+    for k, timed in ((1, False), (2, True)):
+        cen = [(c[0] + 0.05 * k, c[1], c[2]) for c in w.centres]
+        if timed:
+            n_old = t.size()
+            u_old = torch.randn((w.nvar, 64, n_old), dtype=torch.float64, device="cuda",
+                                generator=g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f = t.flag(cen, w.r_in, w.r_out, nodes, w.lo, w.length, dist_axes=3)
+        t.adapt(f)
+        t.balance()
+        t.connect()
+        t.map()
+        u64 = t.transfer(w.p, u_old)
+        torch.cuda.synchronize()
+        cycle_s = time.perf_counter() - t0
     n_new = t.size()
     E = 8 * 64 * w.nvar
     nbytes = E * n_old + (E + 5) * n_new
@@ -360,6 +367,7 @@ def large_variant(lt, torch, synth, stream):
            "leaves": [n_old, n_new], "plain_cycle_ms": cycle_s * 1e3,
            "plain_cycle_octants_per_s": n_new / cycle_s}
     usp = torch.empty_like(u64)
+    out["transfer_tuning"] = t.autotune_transfer(w.p, u_old, u64)
     for name, prec, dst in (("fp64", 0, u64), ("split", 1, usp)):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         t.transfer(w.p, u_old, u_new=dst, precision=prec)

@@ -56,6 +56,8 @@ def lib():
         L.lto_encode.argtypes = [i32, i32, i32, P]
         L.lto_decode.argtypes = [i32, i32, C.c_uint64, P, P]
         L.lto_flag.argtypes = [P, i32, P, dbl, dbl, i32, i32, P, i32, P, dbl, P]
+        L.lto_flag_keys.argtypes = [i32, i32, i32, P, i64, i32, P, dbl, dbl, i32, i32, P, i32, P,
+                                    dbl, P]
         L.lto_adapt.argtypes = [P, P]
         L.lto_balance.argtypes = [P, i32]
         L.lto_is_balanced.argtypes = [P]
@@ -110,6 +112,25 @@ def operators(dim: int, p: int):
     P = np.zeros((nc, np_, np_))
     _check(lib().lto_operators(dim, p, _ptr(I), _ptr(P)))
     return I, P
+
+
+def flag_keys(dim, d_min, d_max, keys, centres, r_in, r_out, nodes01, lo, length, dist_axes=None,
+              periodic_dist=False) -> np.ndarray:
+    """The geometric criterion (Section 5.2) for arbitrary leaf keys: what
+    Tree.flag gives each of them in any tree with depth limits d_min..d_max."""
+    k = np.ascontiguousarray(keys, dtype=np.uint64)
+    c = np.zeros((len(centres), 3))
+    for v, cc in enumerate(centres):
+        c[v, : len(cc)] = cc
+    nodes = np.ascontiguousarray(nodes01, dtype=np.float64)
+    lo3 = np.zeros(3)
+    lo3[: len(lo)] = lo
+    out = np.zeros(len(k), dtype=np.int8)
+    _check(lib().lto_flag_keys(dim, d_min, d_max, _ptr(k), len(k), len(centres), _ptr(c),
+                               float(r_in), float(r_out), int(dist_axes or dim),
+                               int(bool(periodic_dist)), _ptr(nodes), len(nodes) - 1, _ptr(lo3),
+                               float(length), _ptr(out)))
+    return out
 
 
 class Tree:

@@ -486,42 +486,68 @@ int lto_old_keys(const lto_tree* t, uint64_t* out) {
 
 // Refinement criterion of Section 5.2: count the element's solution points
 // closer than r_in and farther than r_out from the vortex axis.
+// The criterion of Section 5.2 for one leaf (depth, anchor): count the
+// solution points inside R_in and outside R_out of the nearest vortex axis.
+static int8_t leaf_flag(int dim, int dmin, int dmax, int depth, const int64_t* anchor, int nvort,
+                        const double* centre, double rin2, double rout2, int dist_axes,
+                        int periodic_dist, const double* nodes01, int n1, const double* lo,
+                        double len) {
+  const double dxmin = len / double(int64_t(1) << dmax);
+  const double s = double(int64_t(1) << (dmax - depth));
+  int np = 1;
+  for (int a = 0; a < dim; ++a) np *= n1;
+  int n_in = 0, n_out = 0;
+  for (int i = 0; i < np; ++i) {
+    int ia[3] = {i % n1, (i / n1) % n1, i / (n1 * n1)};
+    double x[3];
+    for (int a = 0; a < dim; ++a) x[a] = lo[a] + dxmin * (double(anchor[a]) + s * nodes01[ia[a]]);
+    double best = 0.0;
+    for (int v = 0; v < nvort; ++v) {
+      double r2 = 0.0;
+      for (int a = 0; a < dist_axes; ++a) {
+        double d = x[a] - centre[3 * v + a];
+        if (periodic_dist) d = d - len * std::floor(d / len + 0.5);
+        r2 = r2 + d * d;
+      }
+      if (v == 0 || r2 < best) best = r2;
+    }
+    if (best < rin2) n_in++;
+    if (best > rout2) n_out++;
+  }
+  int f = n_in > n_out ? 1 : (n_in < n_out ? -1 : 0);
+  if (f == 1 && depth >= dmax) f = 0;
+  if (f == -1 && depth <= dmin) f = 0;
+  return int8_t(f);
+}
+
 int lto_flag(const lto_tree* t, int nvort, const double* centre, double r_in,
              double r_out, int dist_axes, int periodic_dist, const double* nodes01,
              int p, const double* lo, double len, int8_t* flags) {
   if (nvort < 1 || dist_axes < 1 || dist_axes > t->dim || p < 0 || p > 7)
     return fail("bad flag parameters");
-  const int n1 = p + 1;
   const double rin2 = r_in * r_in, rout2 = r_out * r_out;
-  const double dxmin = len / double(t->width());
-  int np = 1;
-  for (int a = 0; a < t->dim; ++a) np *= n1;
   for (size_t e = 0; e < t->leaves.size(); ++e) {
     const Node* n = t->leaves[e];
-    const double s = double(t->size_at(n->depth));
-    int n_in = 0, n_out = 0;
-    for (int i = 0; i < np; ++i) {
-      int ia[3] = {i % n1, (i / n1) % n1, i / (n1 * n1)};
-      double x[3];
-      for (int a = 0; a < t->dim; ++a)
-        x[a] = lo[a] + dxmin * (double(n->anchor[a]) + s * nodes01[ia[a]]);
-      double best = 0.0;
-      for (int v = 0; v < nvort; ++v) {
-        double r2 = 0.0;
-        for (int a = 0; a < dist_axes; ++a) {
-          double d = x[a] - centre[3 * v + a];
-          if (periodic_dist) d = d - len * std::floor(d / len + 0.5);
-          r2 = r2 + d * d;
-        }
-        if (v == 0 || r2 < best) best = r2;
-      }
-      if (best < rin2) n_in++;
-      if (best > rout2) n_out++;
-    }
-    int f = n_in > n_out ? 1 : (n_in < n_out ? -1 : 0);
-    if (f == 1 && n->depth >= t->dmax) f = 0;
-    if (f == -1 && n->depth <= t->dmin) f = 0;
-    flags[e] = int8_t(f);
+    flags[e] = leaf_flag(t->dim, t->dmin, t->dmax, n->depth, n->anchor, nvort, centre, rin2, rout2,
+                         dist_axes, periodic_dist, nodes01, p + 1, lo, len);
+  }
+  return 0;
+}
+
+int lto_flag_keys(int dim, int d_min, int d_max, const uint64_t* keys, int64_t n, int nvort,
+                  const double* centre, double r_in, double r_out, int dist_axes,
+                  int periodic_dist, const double* nodes01, int p, const double* lo, double len,
+                  int8_t* flags) {
+  if (dim < 2 || dim > 3 || d_min < 0 || d_min > d_max || nvort < 1 || dist_axes < 1 ||
+      dist_axes > dim || p < 0 || p > 7)
+    return fail("bad flag parameters");
+  const double rin2 = r_in * r_in, rout2 = r_out * r_out;
+  for (int64_t e = 0; e < n; ++e) {
+    int d;
+    int64_t a[3] = {0, 0, 0};
+    if (!decode_key(dim, d_max, keys[e], &d, a)) return fail("invalid key");
+    flags[e] = leaf_flag(dim, d_min, d_max, d, a, nvort, centre, rin2, rout2, dist_axes,
+                         periodic_dist, nodes01, p + 1, lo, len);
   }
   return 0;
 }

@@ -59,6 +59,13 @@ int lto_flag(const lto_tree* t, int nvort, const double* centre,
              const double* nodes01, int p, const double* lo, double len,
              int8_t* flags);
 
+/* The same criterion for n arbitrary keys (no tree needed): flags[e] is
+ * what lto_flag gives the leaf keys[e] in any tree with these depth limits. */
+int lto_flag_keys(int dim, int d_min, int d_max, const uint64_t* keys, int64_t n, int nvort,
+                  const double* centre, double r_in, double r_out, int dist_axes,
+                  int periodic_dist, const double* nodes01, int p, const double* lo, double len,
+                  int8_t* flags);
+
 /* Refine/coarsen (one level at most); snapshots the old leaves. */
 int lto_adapt(lto_tree* t, const int8_t* flags);
 

@@ -87,7 +87,7 @@ lt_status reserve(lt_cycle c, hipStream_t s) {
   LT_TRY_STATUS(grow(&t->map_src, &t->map_cap, C));
   LT_TRY_STATUS(grow(&t->map_kind, &t->kind_cap, C));
   LT_TRY_STATUS(grow(&t->copy_delta, &t->copy_delta_cap, C / 256 + 2));  // chunks at the finest tuning
-  LT_TRY_STATUS(grow(&t->grp_list, &t->grp_cap, C / 64 + 2));
+  LT_TRY_STATUS(grow(&t->grp_list, &t->grp_cap, 2 * (C / 64 + 2)));
   LT_TRY_STATUS(grow(&t->status, &t->status_cap, std::max<int64_t>(1, (C + kTile - 1) / kTile)));
   dir_params(t->g, C, &c->dir_shift, &c->dir_nb);
   LT_TRY_STATUS(grow(&t->dir, &t->dir_cap, c->dir_nb + 1));

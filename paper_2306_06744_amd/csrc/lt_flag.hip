@@ -25,10 +25,30 @@ struct FlagArgs {
   double c[LT_MAX_VORTICES][3];
 };
 
+// Squared distance along one axis from a point coordinate to a centre
+// coordinate (minimum image when periodic), or an exact 0 for an axis the
+// criterion ignores.
+__device__ inline double axis_d2(double x, double c, bool on, bool periodic, double len) {
+  double dd = x - c;
+  if (periodic) {
+    const double q = dd / len;
+    const double f = floor(q + 0.5);
+    const double sh = len * f;
+    dd = dd - sh;
+  }
+  return on ? dd * dd : 0.0;
+}
+
 // One thread per element.  The coordinate of point index k on axis a depends
-// only on (a, k), so the (p+1) values per axis are computed once.
-// For an ensemble (tab != null) each element takes the parameters of its mesh.
-template <int N1>
+// only on (a, k), so the (p+1) values per axis are computed once, and so are
+// the squared distances per axis to a centre: r^2 = (dx^2 + dy^2) + dz^2 is
+// then two additions per point, in the same order as point by point (an axis
+// outside the criterion adds an exact 0).  With several vortices each point
+// keeps the smallest r^2 over the vortices; a z slice of points is handled at
+// a time so that this running minimum stays in registers.
+// TAB: each element takes the parameters of its mesh from tab (an ensemble);
+// otherwise every element uses A0.
+template <int N1, bool TAB>
 __global__ __launch_bounds__(256) void k_flag(FlagArgs A0, const FlagArgs* __restrict__ tab,
                                               const uint64_t* __restrict__ keys, Count cn,
                                               int8_t* __restrict__ flags) {
@@ -36,14 +56,19 @@ __global__ __launch_bounds__(256) void k_flag(FlagArgs A0, const FlagArgs* __res
   if (e >= cn.get()) return;
   const KeyGeom& g = A0.g;
   const uint64_t key = keys[e];
-  const FlagArgs& A = tab ? tab[key_mesh(g, key)] : A0;
+  const FlagArgs* Ap = &A0;
+  if constexpr (TAB) Ap = &tab[key_mesh(g, key)];
+  const FlagArgs& A = *Ap;
   const int d = key_depth(g, key);
   uint64_t x[3];
   demorton(g, key_morton(g, key), x);
   const double s = double(uint64_t(1) << (g.dmax - d));
-  double X[3][N1];
+  const int nvort = A.nvort, da = A.dist_axes;
+  const bool per = A.periodic_dist != 0;
+  const double len = A.len, rin2 = A.rin2, rout2 = A.rout2;
+  double X[2][N1];
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
       const double t = s * A.nodes[k];
@@ -53,63 +78,64 @@ __global__ __launch_bounds__(256) void k_flag(FlagArgs A0, const FlagArgs* __res
     }
   const int nz = g.dim == 3 ? N1 : 1;
   int n_in = 0, n_out = 0;
-  if (A.nvort == 1) {
-    // Squared distance per axis and point index; r^2 = (dx^2 + dy^2) + dz^2,
-    // the same sums in the same order as point by point (a missing axis adds
-    // an exact 0).
-    double D2[3][N1];
+  // the z coordinate of slice iz, by the same operations as X[a][k]
+  auto zcoord = [&](int iz) {
+    const double t = s * A.nodes[iz];
+    const double u = double(x[2]) + t;
+    const double w = A.dx * u;
+    return A.lo[2] + w;
+  };
+  if (nvort == 1) {
+    double D2[2][N1];
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int k = 0; k < N1; ++k) {
-        double dd = X[a][k] - A.c[0][a];
-        if (A.periodic_dist) {
-          const double q = dd / A.len;
-          const double f = floor(q + 0.5);
-          const double sh = A.len * f;
-          dd = dd - sh;
-        }
-        D2[a][k] = a < A.dist_axes ? dd * dd : 0.0;
-      }
-    for (int iz = 0; iz < nz; ++iz)
+      for (int k = 0; k < N1; ++k) D2[a][k] = axis_d2(X[a][k], A.c[0][a], a < da, per, len);
+    for (int iz = 0; iz < nz; ++iz) {
+      const double dz = axis_d2(zcoord(iz), A.c[0][2], 2 < da, per, len);
 #pragma unroll
       for (int iy = 0; iy < N1; ++iy)
 #pragma unroll
         for (int ix = 0; ix < N1; ++ix) {
           const double xy = D2[0][ix] + D2[1][iy];
-          const double r2 = xy + D2[2][iz];
-          n_in += r2 < A.rin2 ? 1 : 0;
-          n_out += r2 > A.rout2 ? 1 : 0;
+          const double r2 = xy + dz;
+          n_in += r2 < rin2 ? 1 : 0;
+          n_out += r2 > rout2 ? 1 : 0;
         }
+    }
   } else {
-    for (int iz = 0; iz < nz; ++iz)
+    for (int iz = 0; iz < nz; ++iz) {
+      {
+        const double z = zcoord(iz);
+        double best[N1 * N1];
 #pragma unroll
-      for (int iy = 0; iy < N1; ++iy)
+        for (int i = 0; i < N1 * N1; ++i) best[i] = INFINITY;
+        for (int v = 0; v < nvort; ++v) {
+          const double cx = A.c[v][0], cy = A.c[v][1], cz = A.c[v][2];
+          double Dx[N1], Dy[N1];
 #pragma unroll
-        for (int ix = 0; ix < N1; ++ix) {
-          const double P[3] = {X[0][ix], X[1][iy], X[2][iz]};
-          double best = 0.0;
-          for (int v = 0; v < A.nvort; ++v) {
-            double r2 = 0.0;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              if (a < A.dist_axes) {
-                double dd = P[a] - A.c[v][a];
-                if (A.periodic_dist) {
-                  const double q = dd / A.len;
-                  const double f = floor(q + 0.5);
-                  const double sh = A.len * f;
-                  dd = dd - sh;
-                }
-                const double sq = dd * dd;
-                r2 = r2 + sq;
-              }
-            }
-            if (v == 0 || r2 < best) best = r2;
+          for (int k = 0; k < N1; ++k) {
+            Dx[k] = axis_d2(X[0][k], cx, 0 < da, per, len);
+            Dy[k] = axis_d2(X[1][k], cy, 1 < da, per, len);
           }
-          n_in += best < A.rin2 ? 1 : 0;
-          n_out += best > A.rout2 ? 1 : 0;
+          const double dz = axis_d2(z, cz, 2 < da, per, len);
+#pragma unroll
+          for (int iy = 0; iy < N1; ++iy)
+#pragma unroll
+            for (int ix = 0; ix < N1; ++ix) {
+              const double xy = Dx[ix] + Dy[iy];
+              const double r2 = xy + dz;
+              double& b = best[iy * N1 + ix];
+              b = r2 < b ? r2 : b;
+            }
         }
+#pragma unroll
+        for (int i = 0; i < N1 * N1; ++i) {
+          n_in += best[i] < rin2 ? 1 : 0;
+          n_out += best[i] > rout2 ? 1 : 0;
+        }
+      }
+    }
   }
   int f = n_in > n_out ? 1 : (n_in < n_out ? -1 : 0);
   if (!A.raw) {
@@ -125,7 +151,10 @@ template <int N1>
 hipError_t launch(const FlagArgs& A, const FlagArgs* tab, const uint64_t* keys, Count n, int8_t* flags,
                   hipStream_t s) {
   const unsigned blocks = unsigned((n.n + 255) / 256);
-  k_flag<N1><<<blocks, 256, 0, s>>>(A, tab, keys, n, flags);
+  if (tab)
+    k_flag<N1, true><<<blocks, 256, 0, s>>>(A, tab, keys, n, flags);
+  else
+    k_flag<N1, false><<<blocks, 256, 0, s>>>(A, tab, keys, n, flags);
   return hipGetLastError();
 }
 

@@ -302,45 +302,119 @@ __device__ inline void xy_pass(const double* Mx, const double* My, const double*
 }
 
 // Groups of 64 consecutive new elements that hold any refined or fused
-// element, listed in order by a look-back scan (count 1 per such group).
+// element.  Groups with refined children only are listed in order by a
+// look-back scan (count 1 per such group); groups that hold a fused element
+// are appended to a second list (flist, count *nflist) in any order, since
+// every group is computed on its own.
 __global__ __launch_bounds__(kBlock) void k_group_list(const int8_t* __restrict__ kind, Count cn,
-                                                       int32_t* __restrict__ list, ScanState st) {
+                                                       int32_t* __restrict__ list, ScanState st,
+                                                       int32_t* __restrict__ flist,
+                                                       int64_t* __restrict__ nflist) {
   const int64_t tile = take_ticket(st);
   if (tile >= scan_tiles(st)) return;
   const int64_t n = cn.get();
   const int64_t ngroups = st.items.get();
   const int64_t base = tile * kTile + int64_t(threadIdx.x) * kItems;
-  bool any[kItems];
+  bool ref[kItems];
   int64_t local = 0;
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
     const int64_t gidx = base + k;
-    any[k] = false;
+    ref[k] = false;
     if (gidx >= ngroups) continue;
     const int64_t j0 = gidx * 64;
+    bool any = false, fus = false;
     if (j0 + 64 <= n) {
       const uint64_t* w8 = reinterpret_cast<const uint64_t*>(kind + j0);
       uint64_t acc = 0;
 #pragma unroll
       for (int q = 0; q < 8; ++q) acc |= w8[q];
-      any[k] = acc != 0;
+      any = acc != 0;
+      fus = (acc & 0x8080808080808080ull) != 0;  // a negative kind byte
     } else {
-      for (int64_t j = j0; j < n; ++j) any[k] = any[k] || kind[j] != 0;
+      for (int64_t j = j0; j < n; ++j) {
+        any = any || kind[j] != 0;
+        fus = fus || kind[j] < 0;
+      }
     }
-    local += any[k] ? 1 : 0;
+    if (fus) {
+      const int64_t o = int64_t(atomicAdd(reinterpret_cast<unsigned long long*>(nflist), 1ull));
+      flist[o] = int32_t(gidx);
+    }
+    ref[k] = any && !fus;
+    local += ref[k] ? 1 : 0;
   }
   int64_t blk;
   const int64_t thr = block_exclusive(local, &blk);
   int64_t o = tile_prefix(st, tile, blk) + thr;
 #pragma unroll
   for (int k = 0; k < kItems; ++k)
-    if (any[k]) list[o++] = int32_t(base + k);
+    if (ref[k]) list[o++] = int32_t(base + k);
 }
 
-// 3D, interpolation / projection pass.  A block of N waves takes listed
-// groups of 64 consecutive new elements of one variable (grid-stride over the
-// device-side list); lane = element and wave w owns z-slab w (N*N points) of
-// the input and of the output.  The x and y passes act within a slab and stay
+// 3D refinement pass over the groups that hold refined children only.  A
+// block of N waves takes listed groups of 64 consecutive new elements of one
+// variable (grid-stride over the device-side list); lane = element and wave w
+// owns z-slab w (N*N points).  The x and y passes of the parent's slab w run
+// in registers, the z pass mixes the N slabs through LDS, and each output row
+// is stored as soon as it is formed.  Keeping no accumulator across rounds
+// holds the register count near half of the general kernel's, so twice as
+// many waves hide the load and store latency.
+template <int N>
+__global__ __launch_bounds__(64 * N) void k_interp3_ref(const double* __restrict__ ops,
+                                                        const int32_t* __restrict__ src,
+                                                        const int8_t* __restrict__ kind, Count cn,
+                                                        const int32_t* __restrict__ groups,
+                                                        const int64_t* __restrict__ ngroups,
+                                                        const double* __restrict__ uo, int64_t ldo,
+                                                        double* __restrict__ un, int64_t ldn) {
+  constexpr int NN = N * N;
+  constexpr int NP = NN * N;
+  __shared__ double T[N][NN][64];
+  __shared__ double M[2][NN];  // A_0, A_1
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t n = cn.get();
+  const int64_t ng = *ngroups;
+  if (int64_t(blockIdx.x) >= ng) return;
+  for (int i = threadIdx.x; i < 2 * NN; i += blockDim.x) M[i / NN][i % NN] = ops[i];
+  const int v = blockIdx.y;
+  const double* U = uo + int64_t(v) * NP * ldo + int64_t(w) * NN * ldo;
+  double* O0 = un + int64_t(v) * NP * ldn + int64_t(w) * NN * ldn;
+  __syncthreads();
+  for (int64_t gi = blockIdx.x; gi < ng; gi += gridDim.x) {
+    const int64_t j = int64_t(groups[gi]) * 64 + lane;
+    const int kd = j < n ? int(kind[j]) : 0;
+    const int c = kd > 0 ? kd - 1 : 0;
+    if (kd > 0) {
+      const int64_t s = int64_t(src[j]);
+      double in[NN], sl[NN];
+#pragma unroll
+      for (int r = 0; r < NN; ++r) in[r] = U[int64_t(r) * ldo + s];
+      xy_pass<N>(M[c & 1], M[(c >> 1) & 1], in, sl);
+#pragma unroll
+      for (int r = 0; r < NN; ++r) T[w][r][lane] = sl[r];
+    }
+    __syncthreads();
+    if (kd > 0) {
+      const double* Mz = M[(c >> 2) & 1] + w * N;
+      double* O = O0 + j;
+#pragma unroll
+      for (int r = 0; r < NN; ++r) {
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) a += Mz[k] * T[k][r][lane];
+        O[int64_t(r) * ldn] = a;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// 3D, general interpolation / projection pass, for the groups that hold a
+// fused element (refined children in the same group are handled here too).
+// A block of N waves takes listed groups of 64 consecutive new elements of
+// one variable (grid-stride over the device-side list); lane = element and
+// wave w owns z-slab w (N*N points) of the input and of the output.  The x and y passes act within a slab and stay
 // in registers; the z pass mixes slabs through LDS.  A fused element needs two
 // z rounds (children with z bit 0, then 1), a refined one a single round.
 // Copy elements are left to the copy pass.
@@ -438,18 +512,27 @@ hipError_t launch(lt_tree_s* t, const double* ops, const int32_t* src, const int
     *st_out = launch_copy(t, n, nvar * N * N * N, uo, ldo, un, ldn, s);
     if (*st_out != LT_OK) return hipSuccess;
     hipError_t e = hipSuccess;
-    *st_out = grow(&t->grp_list, &t->grp_cap, ngroups);
+    // grp_list holds the ordered list in [0, ngroups) and the list of
+    // groups with a fused element in [ngroups, 2 ngroups)
+    *st_out = grow(&t->grp_list, &t->grp_cap, 2 * ngroups);
     if (*st_out != LT_OK) return hipSuccess;
     ScanState st;
     *st_out = prep_scan(t, ngroups, s, 0, &st);
     if (*st_out != LT_OK) return hipSuccess;
     st.items.p = ngroups_dev;
-    k_group_list<<<grid_tiles(st), kBlock, 0, s>>>(kind, n, t->grp_list, st);
+    int32_t* flist = t->grp_list + ngroups;
+    k_group_list<<<grid_tiles(st), kBlock, 0, s>>>(kind, n, t->grp_list, st, flist,
+                                                   &t->dctr->nfgroups);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 gi{unsigned(std::max<int64_t>(1, std::min<int64_t>(ngroups, t->tune.interp_grid))),
                   unsigned(nvar), 1u};
-    k_interp3<N><<<gi, 64 * N, 0, s>>>(ops, src, kind, n, t->grp_list, st.total, uo, ldo, un, ldn);
+    k_interp3_ref<N><<<gi, 64 * N, 0, s>>>(ops, src, kind, n, t->grp_list, st.total, uo, ldo, un,
+                                           ldn);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_interp3<N><<<gi, 64 * N, 0, s>>>(ops, src, kind, n, flist, &t->dctr->nfgroups, uo, ldo, un,
+                                       ldn);
     return hipGetLastError();
   } else {
     dim3 grid(unsigned((n.n + 255) / 256), unsigned(nvar));

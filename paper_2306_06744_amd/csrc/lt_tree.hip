@@ -64,6 +64,7 @@ __global__ void k_clear_scan(uint64_t* status, int64_t ntiles, DevCtr* ctr, int 
     ctr->total = 0;
     ctr->nmarked = 0;
     ctr->nfused = 0;
+    ctr->nfgroups = 0;
     if (clear_err) ctr->err = 0;
   }
 }

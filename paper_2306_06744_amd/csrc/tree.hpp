@@ -20,6 +20,7 @@ struct DevCtr {
   unsigned long long nmarked;
   unsigned long long ticket;
   unsigned long long nfused;  // fused parents listed for the first balance pass
+  int64_t nfgroups;           // transfer groups holding a fused element (second list)
 };
 
 void set_error(const std::string& msg);

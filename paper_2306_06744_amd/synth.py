@@ -26,7 +26,8 @@ import numpy as np
 
 
 def gl_nodes01(p: int) -> np.ndarray:
-    """Gauss-Legendre points of degree-p FR on [0, 1] (closed forms, p <= 3)."""
+    """Gauss-Legendre points of degree-p FR on [0, 1] (closed forms for p <= 3,
+    numpy's Golub-Welsch values above)."""
     if p == 0:
         x = [0.0]
     elif p == 1:
@@ -39,8 +40,10 @@ def gl_nodes01(p: int) -> np.ndarray:
         a = math.sqrt(3.0 / 7.0 - 2.0 / 7.0 * math.sqrt(6.0 / 5.0))
         b = math.sqrt(3.0 / 7.0 + 2.0 / 7.0 * math.sqrt(6.0 / 5.0))
         x = [-b, -a, a, b]
+    elif p <= 7:
+        x = list(np.polynomial.legendre.leggauss(p + 1)[0])
     else:
-        raise ValueError("closed forms only for p <= 3")
+        raise ValueError("p must be in 0..7")
     return np.array([(1.0 + v) / 2.0 for v in x], dtype=np.float64)
 
 

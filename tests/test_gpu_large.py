@@ -50,6 +50,7 @@ def large():
     # the last cycle moves the vortices a little so it refines and coarsens
     cen = [(c[0] + 0.05, c[1], c[2]) for c in w.centres]
     f = t.flag(cen, w.r_in, w.r_out, nodes, w.lo, w.length, dist_axes=3)
+    flags = f.cpu().numpy().copy()
     t.adapt(f)
     t.balance()
     t.connect()
@@ -59,7 +60,19 @@ def large():
     keys = t.keys().cpu().numpy().view(np.uint64).copy()
     print("leaves", len(old_keys), "->", len(keys), flush=True)
     return dict(w=w, t=t, old_keys=old_keys, keys=keys, u_old=u_old, u64=u64, u_split=u_split,
-                cen=cen)
+                cen=cen, flags=flags)
+
+
+def test_flags_every_leaf(large):
+    """The four-vortex criterion on every leaf of the large tree, bit-exact
+    against the oracle's key-list form of it."""
+    w = large["w"]
+    fo = oracle.flag_keys(3, w.d_min, w.d_max, large["old_keys"], large["cen"], w.r_in, w.r_out,
+                          synth.gl_nodes01(w.p), w.lo, w.length, dist_axes=3)
+    f = large["flags"]
+    bad = np.flatnonzero(f != fo)
+    assert bad.size == 0, f"{bad.size} flags differ, first at leaf {bad[:5]}"
+    assert (f == 1).any() and (f == -1).any() and (f == 0).any()
 
 
 def test_size_order_tiling_and_centres(large):

@@ -67,6 +67,12 @@ FLAG_CASES = [
     (2, 2, 7, 1, [(0.1, 0.2), (-3.0, 2.0), (2.5, -2.5)], 0.7, 1.1, 2, True),
     (3, 2, 5, 3, [(0.4, -0.6, 0.0)], 2.0, 2.4, 2, False),
     (3, 2, 5, 2, [(0.4, -0.6, 1.3), (-2.0, 1.0, -1.0)], 1.5, 2.0, 3, True),
+    # four vortices, 3D distances, no minimum image (the large configuration's form)
+    (3, 2, 5, 3, [(1.1, -0.4, 0.9), (-2.2, 1.7, -0.6), (0.3, 2.5, -2.1), (-1.0, -2.4, 1.8)],
+     1.2, 1.5, 3, False),
+    # degree 7 (8 points per axis) with several vortices, 2D and 3D
+    (2, 2, 6, 7, [(0.3, 0.2), (-2.0, 1.5)], 1.5, 2.0, 2, False),
+    (3, 2, 4, 7, [(0.5, 0.5, 0.5), (-1.5, 0.7, -0.4)], 1.8, 2.2, 3, True),
 ]
 
 

@@ -77,3 +77,26 @@ def test_second_far_vortex_changes_nothing():
     f1 = t.flag([(0.3, 0.1)], *args)
     f2 = t.flag([(0.3, 0.1), (1e5, -1e5)], *args)
     assert np.array_equal(f1, f2)
+
+
+def test_flag_keys_matches_tree_flag():
+    """The key-list form of the criterion gives every leaf of an adapted,
+    unbalanced tree the same flag as the tree form, with several vortices,
+    3D distances and the periodic minimum image."""
+    nodes = synth.gl_nodes01(2)
+    t = oracle.Tree(3, 2, 6)
+    cen = [(0.4, -0.6, 1.3), (-2.0, 1.0, -1.0), (4.6, 4.4, -4.8)]
+    for cyc in range(3):
+        c = [(x + 0.3 * cyc, y, z) for x, y, z in cen]
+        for per in (False, True):
+            f = t.flag(c, 1.5, 2.0, nodes, (-5.0,) * 3, 10.0, dist_axes=3, periodic_dist=per)
+            fk = oracle.flag_keys(3, 2, 6, t.keys(), c, 1.5, 2.0, nodes, (-5.0,) * 3, 10.0,
+                                  dist_axes=3, periodic_dist=per)
+            assert np.array_equal(f, fk)
+        t.adapt(f)
+    assert (f == 1).any() and (f == -1).any() and (f == 0).any()
+    # shuffled keys: one flag per key, independent of order
+    k = t.keys()
+    perm = np.random.default_rng(0).permutation(len(k))
+    fk = oracle.flag_keys(3, 2, 6, k[perm], cen, 1.5, 2.0, nodes, (-5.0,) * 3, 10.0, dist_axes=3)
+    assert np.array_equal(fk, t.flag(cen, 1.5, 2.0, nodes, (-5.0,) * 3, 10.0, dist_axes=3)[perm])
