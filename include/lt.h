@@ -20,6 +20,11 @@
  *     by the caller.  Everything else (keys, the pre-adapt snapshot, nbr, hang,
  *     map arrays, scratch) is owned by the tree and freed by lt_destroy.
  *   - A tree is not thread-safe; use one tree per host thread or serialise.
+ *     Calls on one tree run one after another in stream order, with a single
+ *     exception: lt_connect keeps scratch of its own, so it may run on a
+ *     second stream beside lt_map and lt_transfer of the same tree (issue it
+ *     after lt_balance has returned; lt_connect returns once its stream is
+ *     done).
  *
  * Morton ID layout (Section 2.2, Algorithm "Morton Encoding"): the anchor
  * (lowest corner) of an octant in integer units of the finest resolution
@@ -158,7 +163,9 @@ lt_status lt_balance(lt_tree t, void* stream);
  *                    = -2 across a non-periodic domain boundary.
  *   hang row r = [e, f, k_0 .. k_{2^(dim-1)-1}], rows sorted by (e, f); k_s is
  *   the fine leaf whose tangential child bits (lower axis first) equal s.
- * Needs a 2:1-balanced tree (LT_ERR_UNBALANCED otherwise). */
+ * Needs a 2:1-balanced tree (LT_ERR_UNBALANCED otherwise).  It reads only the
+ * current keys and uses its own look-back words and counters: it may overlap
+ * lt_map / lt_transfer issued on another stream. */
 lt_status lt_connect(lt_tree t, void* stream);
 
 /* Old->new mapping (Section 4.2, mapping algorithm): for each current leaf j,

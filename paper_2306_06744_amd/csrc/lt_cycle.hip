@@ -89,6 +89,7 @@ lt_status reserve(lt_cycle c, hipStream_t s) {
   LT_TRY_STATUS(grow(&t->copy_delta, &t->copy_delta_cap, C / 256 + 2));  // chunks at the finest tuning
   LT_TRY_STATUS(grow(&t->grp_list, &t->grp_cap, 2 * (C / 64 + 2)));
   LT_TRY_STATUS(grow(&t->status, &t->status_cap, std::max<int64_t>(1, (C + kTile - 1) / kTile)));
+  LT_TRY_STATUS(grow(&t->cstatus, &t->cstatus_cap, std::max<int64_t>(1, (C + kTile - 1) / kTile)));
   dir_params(t->g, C, &c->dir_shift, &c->dir_nb);
   LT_TRY_STATUS(grow(&t->dir, &t->dir_cap, c->dir_nb + 1));
   if (!t->flag_tab) {
@@ -118,10 +119,15 @@ void drop_graphs(lt_cycle c) {
 lt_status capture(lt_cycle c) {
   drop_graphs(c);
   lt_tree t = c->t;
-  hipStream_t cs = nullptr;
+  hipStream_t cs = nullptr, side = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
     return fail(LT_ERR_HIP, "capture stream");
   lt_status st = LT_OK;
+  if (hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess)
+    st = fail(LT_ERR_HIP, "capture side stream");
   for (int q = 0; q < 2 && st == LT_OK; ++q) {
     CycleRec r{};
     r.cap = c->d.capacity;
@@ -140,6 +146,9 @@ lt_status capture(lt_cycle c) {
     r.conf_min = c->d.conf_min;
     r.dir_shift = c->dir_shift;
     r.dir_nb = c->dir_nb;
+    r.side = side;
+    r.fork = ev[0];
+    r.join = ev[1];
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       st = fail(LT_ERR_HIP, "begin capture");
       break;
@@ -157,6 +166,9 @@ lt_status capture(lt_cycle c) {
       st = fail(LT_ERR_HIP, "graph instantiate");
   }
   (void)hipStreamDestroy(cs);
+  if (side) (void)hipStreamDestroy(side);
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
   if (st != LT_OK) drop_graphs(c);
   return st;
 }

@@ -674,20 +674,31 @@ void dir_params(const KeyGeom& g, int64_t n, int* shift, int64_t* nb) {
   *nb = int64_t(1) << L;
 }
 
-lt_status prep_scan(lt_tree t, int64_t n_items, hipStream_t stream, int flags, ScanState* st) {
+namespace {
+lt_status prep_scan_on(uint64_t** status, int64_t* status_cap, DevCtr* ctr, int64_t n_items,
+                       hipStream_t stream, int flags, ScanState* st) {
   const int64_t ntiles = std::max<int64_t>(1, ceil_div(n_items, kTile));
-  LT_TRY(grow(&t->status, &t->status_cap, ntiles));
-  k_clear_scan<<<unsigned(ceil_div(ntiles, 256)), 256, 0, stream>>>(t->status, ntiles, t->dctr,
-                                                                      flags & 1, (flags >> 1) & 1);
+  LT_TRY(grow(status, status_cap, ntiles));
+  k_clear_scan<<<unsigned(ceil_div(ntiles, 256)), 256, 0, stream>>>(*status, ntiles, ctr, flags & 1,
+                                                                      (flags >> 1) & 1);
   LT_HIP(hipGetLastError());
-  st->status = t->status;
-  st->ticket = &t->dctr->ticket;
-  st->err = &t->dctr->err;
-  st->total = &t->dctr->total;
+  st->status = *status;
+  st->ticket = &ctr->ticket;
+  st->err = &ctr->err;
+  st->total = &ctr->total;
   st->items = Count{n_items, nullptr};
   st->commit = nullptr;
   st->commit_cap = 0;
   return LT_OK;
+}
+}  // namespace
+
+lt_status prep_scan(lt_tree t, int64_t n_items, hipStream_t stream, int flags, ScanState* st) {
+  return prep_scan_on(&t->status, &t->status_cap, t->dctr, n_items, stream, flags, st);
+}
+
+lt_status prep_scan_conn(lt_tree t, int64_t n_items, hipStream_t stream, int flags, ScanState* st) {
+  return prep_scan_on(&t->cstatus, &t->cstatus_cap, t->cctr, n_items, stream, flags, st);
 }
 
 lt_status read_ctr(lt_tree t, hipStream_t stream) {
@@ -735,12 +746,16 @@ lt_status new_tree(const lt_geom* geom, lt_tree* out) {
   hipError_t e = hipGetDevice(&t->device);
   if (e == hipSuccess) e = hipMalloc(&t->dctr, sizeof(DevCtr));
   if (e == hipSuccess) e = hipHostMalloc(&t->hctr, sizeof(DevCtr), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc(&t->cctr, sizeof(DevCtr));
+  if (e == hipSuccess) e = hipHostMalloc(&t->hcctr, sizeof(DevCtr), hipHostMallocDefault);
   if (e != hipSuccess) {
     lt_destroy(t);
     return fail(LT_ERR_HIP, std::string("tree setup: ") + hipGetErrorString(e));
   }
   std::memset(t->hctr, 0, sizeof(DevCtr));
+  std::memset(t->hcctr, 0, sizeof(DevCtr));
   e = hipMemset(t->dctr, 0, sizeof(DevCtr));
+  if (e == hipSuccess) e = hipMemset(t->cctr, 0, sizeof(DevCtr));
   if (e != hipSuccess) {
     lt_destroy(t);
     return fail(LT_ERR_HIP, std::string("tree setup: ") + hipGetErrorString(e));
@@ -816,10 +831,14 @@ __global__ void k_check_marks(DevCtr* ctr) {
   if (threadIdx.x == 0 && blockIdx.x == 0 && ctr->nmarked != 0) atomicOr(&ctr->err, ERR_BALANCE_PASSES);
 }
 
+// Also folds connectivity's error word (its branch ran on a side stream)
+// into the cycle's.
 __global__ void k_copy_keys(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst, Count cn,
-                            const unsigned* err) {
+                            unsigned* err, const unsigned* cerr) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (*err != 0) return;  // keep the pre-cycle keys for the host's recovery
+  const unsigned ce = *cerr;
+  if (i == 0 && ce != 0) atomicOr(err, ce);
+  if ((*err | ce) != 0) return;  // keep the pre-cycle keys for the host's recovery
   if (i < cn.get()) dst[i] = src[i];
 }
 
@@ -879,19 +898,27 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
   k_check_marks<<<1, 64, 0, s>>>(t->dctr);
   LT_HIP(hipGetLastError());
   if (ki != 0) return fail(LT_ERR_ARG, "balance passes of a captured cycle must be even");
-  // connect (the directory of K[0] was built by the check pass)
+  // connect on the side stream (the directory of K[0] was built by the check
+  // pass); it reads the new keys only, and its scan words and counters are its
+  // own, so it runs beside the mapping and the transfer
+  hipStream_t cs = r.side;
+  LT_HIP(hipEventRecord(r.fork, s));
+  LT_HIP(hipStreamWaitEvent(cs, r.fork, 0));
   if (g.dim == 3)
-    k_connect_faces<3><<<nlanes, 256, 0, s>>>(g, K[0], Count{C, &S[0]}, D, t->nbr, t->hmask);
+    k_connect_faces<3><<<nlanes, 256, 0, cs>>>(g, K[0], Count{C, &S[0]}, D, t->nbr, t->hmask);
   else
-    k_connect_faces<2><<<nlanes, 256, 0, s>>>(g, K[0], Count{C, &S[0]}, D, t->nbr, t->hmask);
-  LT_TRY(prep_scan(t, C, s, 0, &st));
-  st.items.p = &S[0];
-  st.commit = &S[2];  // rows past the table's capacity raise ERR_CAPACITY
-  st.commit_cap = r.hang_rows;
-  k_connect_rows<<<grid_tiles(st), kBlock, 0, s>>>(t->hmask, g.dim, t->hang, r.hang_rows, st);
+    k_connect_faces<2><<<nlanes, 256, 0, cs>>>(g, K[0], Count{C, &S[0]}, D, t->nbr, t->hmask);
+  ScanState cst;
+  LT_TRY(prep_scan_conn(t, C, cs, 1, &cst));
+  cst.items.p = &S[0];
+  cst.commit = &S[2];  // rows past the table's capacity raise ERR_CAPACITY
+  cst.commit_cap = r.hang_rows;
+  k_connect_rows<<<grid_tiles(cst), kBlock, 0, cs>>>(t->hmask, g.dim, t->hang, r.hang_rows, cst);
   const int nh = 1 << (g.dim - 1);
-  k_connect_fine<<<unsigned(ceil_div(r.hang_rows * nh, 256)), 256, 0, s>>>(
-      g, K[0], Count{C, &S[0]}, D, t->hang, &t->dctr->total, r.hang_rows, err);
+  k_connect_fine<<<unsigned(ceil_div(r.hang_rows * nh, 256)), 256, 0, cs>>>(
+      g, K[0], Count{C, &S[0]}, D, t->hang, &t->cctr->total, r.hang_rows, &t->cctr->err);
+  LT_HIP(hipGetLastError());
+  LT_HIP(hipEventRecord(r.join, cs));
   // map
   k_map<<<nleaf, kBlock, 0, s>>>(g, K0, Count{C, &S[1]}, K[0], Count{C, &S[0]}, t->map_src,
                                   t->map_kind, err);
@@ -903,8 +930,9 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
     k_groups_of<<<1, 64, 0, s>>>(&S[3], &S[0]);
     LT_TRY(launch_transfer(t, Count{C, &S[0]}, &S[3], r.p, r.ops, r.nvar, r.uo, r.ld, r.un, r.ld, s));
   }
-  // the new keys become the next cycle's input
-  k_copy_keys<<<nb256, 256, 0, s>>>(K[0], K0, Count{C, &S[0]}, err);
+  // the new keys become the next cycle's input, once connectivity is done
+  LT_HIP(hipStreamWaitEvent(s, r.join, 0));
+  k_copy_keys<<<nb256, 256, 0, s>>>(K[0], K0, Count{C, &S[0]}, err, &t->cctr->err);
   LT_HIP(hipGetLastError());
   return LT_OK;
 }
@@ -1197,22 +1225,23 @@ lt_status lt_connect(lt_tree t, void* stream) {
   for (int attempt = 0; attempt < 2 && rows < 0; ++attempt) {
     const int64_t cap_rows = t->hang_cap / width;
     ScanState st;
-    LT_TRY(prep_scan(t, n, s, 1, &st));
+    LT_TRY(prep_scan_conn(t, n, s, 1, &st));
     k_connect_rows<<<grid_tiles(st), kBlock, 0, s>>>(t->hmask, t->g.dim, t->hang, cap_rows, st);
     LT_HIP(hipGetLastError());
     // fine leaves of the rows the table holds (the row count stays on the device)
     k_connect_fine<<<unsigned(ceil_div(cap_rows * nh, 256)), 256, 0, s>>>(
-        t->g, t->kbuf[t->cur], Count{n, nullptr}, D, t->hang, &t->dctr->total, cap_rows,
-        &t->dctr->err);
+        t->g, t->kbuf[t->cur], Count{n, nullptr}, D, t->hang, &t->cctr->total, cap_rows,
+        &t->cctr->err);
     LT_HIP(hipGetLastError());
-    LT_TRY(read_ctr(t, s));
-    if (t->hctr->err & ERR_UNBALANCED)
+    LT_HIP(hipMemcpyAsync(t->hcctr, t->cctr, sizeof(DevCtr), hipMemcpyDeviceToHost, s));
+    LT_HIP(hipStreamSynchronize(s));
+    if (t->hcctr->err & ERR_UNBALANCED)
       return fail(LT_ERR_UNBALANCED, "tree is not 2:1 balanced across a face");
-    if (t->hctr->err) return fail(LT_ERR_INTERNAL, "device check failed in lt_connect");
-    if (t->hctr->total <= cap_rows)
-      rows = t->hctr->total;
+    if (t->hcctr->err) return fail(LT_ERR_INTERNAL, "device check failed in lt_connect");
+    if (t->hcctr->total <= cap_rows)
+      rows = t->hcctr->total;
     else  // the hanging-face table overflowed: grow it and emit the rows again
-      LT_TRY(grow(&t->hang, &t->hang_cap, t->hctr->total * width));
+      LT_TRY(grow(&t->hang, &t->hang_cap, t->hcctr->total * width));
   }
   if (rows < 0) return fail(LT_ERR_INTERNAL, "hanging-face table overflowed twice");
   t->n_hang = rows;
@@ -1307,6 +1336,9 @@ void lt_destroy(lt_tree t) {
   if (t->mesh_offs) (void)hipFree(t->mesh_offs);
   if (t->dctr) (void)hipFree(t->dctr);
   if (t->hctr) (void)hipHostFree(t->hctr);
+  if (t->cstatus) (void)hipFree(t->cstatus);
+  if (t->cctr) (void)hipFree(t->cctr);
+  if (t->hcctr) (void)hipHostFree(t->hcctr);
   for (auto& o : t->ops) if (o) (void)hipFree(o);
   if (t->split_frags) (void)hipFree(t->split_frags);
   if (t->split_vec) (void)hipFree(t->split_vec);

@@ -72,6 +72,10 @@ struct CycleRec {
   float conf_min;
   int dir_shift;
   int64_t dir_nb;
+  // connectivity runs on `side` between the events, beside the mapping and
+  // the transfer on the main stream
+  hipStream_t side;
+  hipEvent_t fork, join;
 };
 lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s);
 
@@ -109,6 +113,10 @@ namespace lt {
 // Zero the look-back words for n_items of scan work and the counters (and
 // the error word if clear_err); fills st for a scan kernel on `stream`.
 lt_status prep_scan(lt_tree_s* t, int64_t n_items, hipStream_t stream, int clear_err, ScanState* st);
+// The same on connectivity's own look-back words and counters, so that
+// lt_connect may run beside lt_map and lt_transfer on another stream.
+lt_status prep_scan_conn(lt_tree_s* t, int64_t n_items, hipStream_t stream, int clear_err,
+                         ScanState* st);
 // Copy the device counters to the pinned mirror and wait for the stream.
 lt_status read_ctr(lt_tree_s* t, hipStream_t stream);
 // Zero the counters and the error word.
@@ -201,6 +209,10 @@ struct lt_tree_s {
   int64_t status_cap = 0;
   lt::DevCtr* dctr = nullptr;
   lt::DevCtr* hctr = nullptr;  // pinned mirror
+  uint64_t* cstatus = nullptr;  // connectivity's own look-back words and counters
+  int64_t cstatus_cap = 0;
+  lt::DevCtr* cctr = nullptr;
+  lt::DevCtr* hcctr = nullptr;  // pinned mirror
 
   double* ops[LT_MAX_DEGREE + 1] = {};  // 1D factors A_0, A_1, P_0, P_1 and weights
 

@@ -141,6 +141,38 @@ def test_cycle_connect_map_transfer(dim, dmax, periodic):
             assert err <= TOL, f"p{p} transfer rel L2 {err:.3e}"
 
 
+@pytest.mark.parametrize("dim,dmax", [(2, 8), (3, 6)])
+def test_connect_on_side_stream_beside_transfer(dim, dmax):
+    """lt_connect on a second stream while lt_transfer runs on the first (the
+    two use separate scratch): connectivity, mapping bit-exact and the
+    transfer within the bar, cycle after cycle."""
+    import torch
+    say("side stream", dim, dmax)
+    g, o = both(dim, 2, dmax)
+    side = torch.cuda.Stream()
+    p = 3 if dim == 3 else 2
+    nvar = 5 if dim == 3 else 4
+    for c in range(4):
+        adapt_both(g, o, synth.random_flags(300 + c + 10 * dim, o.size(), 0.35, 0.4))
+        g.balance()
+        o.balance()
+        assert_same_tree(g, o, f"cycle {c}")
+        g.map()
+        u_old = synth.random_solution(400 + c, nvar, (p + 1) ** dim, o.old_size())
+        ug = g.transfer(p, torch.from_numpy(u_old).cuda())
+        with torch.cuda.stream(side):  # no wait on the first stream: the two overlap
+            g.connect()
+        torch.cuda.synchronize()
+        nbr_o, hang_o = o.connect()
+        assert np.array_equal(g.nbr().cpu().numpy(), nbr_o), f"cycle {c}: nbr differs"
+        assert np.array_equal(g.hang().cpu().numpy(), hang_o), f"cycle {c}: hang differs"
+        src, kind = g.mapping()
+        src_o, kind_o = o.map()
+        assert np.array_equal(src.cpu().numpy(), src_o) and np.array_equal(kind.cpu().numpy(), kind_o)
+        err = rel_l2(ug.cpu().numpy(), o.transfer(p, u_old))
+        assert err <= TOL, f"cycle {c}: transfer rel L2 {err:.3e}"
+
+
 def test_transfer_with_padding_and_high_degree_2d():
     import torch
     say("padding")
