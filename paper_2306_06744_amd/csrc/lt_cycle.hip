@@ -88,8 +88,8 @@ lt_status reserve(lt_cycle c, hipStream_t s) {
   LT_TRY_STATUS(grow(&t->map_kind, &t->kind_cap, C));
   LT_TRY_STATUS(grow(&t->copy_delta, &t->copy_delta_cap, C / 256 + 2));  // chunks at the finest tuning
   LT_TRY_STATUS(grow(&t->grp_list, &t->grp_cap, 2 * (C / 64 + 2)));
-  LT_TRY_STATUS(grow(&t->status, &t->status_cap, std::max<int64_t>(1, (C + kTile - 1) / kTile)));
-  LT_TRY_STATUS(grow(&t->cstatus, &t->cstatus_cap, std::max<int64_t>(1, (C + kTile - 1) / kTile)));
+  LT_TRY_STATUS(grow(&t->status, &t->status_cap, std::max<int64_t>(1, (C + kTileMin - 1) / kTileMin)));
+  LT_TRY_STATUS(grow(&t->cstatus, &t->cstatus_cap, std::max<int64_t>(1, (C + kTileMin - 1) / kTileMin)));
   dir_params(t->g, C, &c->dir_shift, &c->dir_nb);
   LT_TRY_STATUS(grow(&t->dir, &t->dir_cap, c->dir_nb + 1));
   if (!t->flag_tab) {

@@ -306,7 +306,7 @@ __device__ inline void xy_pass(const double* Mx, const double* My, const double*
 // look-back scan (count 1 per such group); groups that hold a fused element
 // are appended to a second list (flist, count *nflist) in any order, since
 // every group is computed on its own.
-__global__ __launch_bounds__(kBlock) void k_group_list(const int8_t* __restrict__ kind, Count cn,
+__global__ __launch_bounds__(kScanSmall) void k_group_list(const int8_t* __restrict__ kind, Count cn,
                                                        int32_t* __restrict__ list, ScanState st,
                                                        int32_t* __restrict__ flist,
                                                        int64_t* __restrict__ nflist) {
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(kBlock) void k_group_list(const int8_t* __restrict_
   if (tile >= scan_tiles(st)) return;
   const int64_t n = cn.get();
   const int64_t ngroups = st.items.get();
-  const int64_t base = tile * kTile + int64_t(threadIdx.x) * kItems;
+  const int64_t base = tile * kTileMin + int64_t(threadIdx.x) * kItems;
   bool ref[kItems];
   int64_t local = 0;
 #pragma unroll
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(kBlock) void k_group_list(const int8_t* __restrict_
     local += ref[k] ? 1 : 0;
   }
   int64_t blk;
-  const int64_t thr = block_exclusive(local, &blk);
+  const int64_t thr = block_exclusive<kScanSmall>(local, &blk);
   int64_t o = tile_prefix(st, tile, blk) + thr;
 #pragma unroll
   for (int k = 0; k < kItems; ++k)
@@ -517,11 +517,11 @@ hipError_t launch(lt_tree_s* t, const double* ops, const int32_t* src, const int
     *st_out = grow(&t->grp_list, &t->grp_cap, 2 * ngroups);
     if (*st_out != LT_OK) return hipSuccess;
     ScanState st;
-    *st_out = prep_scan(t, ngroups, s, 0, &st);
+    *st_out = prep_scan(t, ngroups, kTileMin, s, 0, &st);
     if (*st_out != LT_OK) return hipSuccess;
     st.items.p = ngroups_dev;
     int32_t* flist = t->grp_list + ngroups;
-    k_group_list<<<grid_tiles(st), kBlock, 0, s>>>(kind, n, t->grp_list, st, flist,
+    k_group_list<<<grid_tiles(st), kScanSmall, 0, s>>>(kind, n, t->grp_list, st, flist,
                                                    &t->dctr->nfgroups);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -143,14 +143,14 @@ __global__ void k_validate(KeyGeom g, const uint64_t* __restrict__ keys, int64_t
 constexpr uint32_t kMarkExamine = 4u;
 constexpr uint32_t kMarkFused = 16u;
 
-__global__ __launch_bounds__(kBlock) void k_adapt(KeyGeom g, const uint64_t* __restrict__ in,
+__global__ __launch_bounds__(kScanBig) void k_adapt(KeyGeom g, const uint64_t* __restrict__ in,
                                                   const int8_t* __restrict__ flags,
                                                   uint64_t* __restrict__ out, int64_t cap,
                                                   ScanState st, uint32_t* __restrict__ marks) {
   const int64_t tile = take_ticket(st);
   if (tile >= scan_tiles(st)) return;
   const int64_t n = st.items.get();
-  const int64_t base = tile * kTile + int64_t(threadIdx.x) * kItems;
+  const int64_t base = tile * kTileMax + int64_t(threadIdx.x) * kItems;
   const int nc = g.nchild();
   uint64_t key[kItems];
   int act[kItems];  // 0 keep, 1 refine, 2 emit parent, 3 drop
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_adapt(KeyGeom g, const uint64_t* __r
     local += a == 1 ? nc : (a == 3 ? 0 : 1);
   }
   int64_t blk;
-  const int64_t thr = block_exclusive(local, &blk);
+  const int64_t thr = block_exclusive<kScanBig>(local, &blk);
   int64_t o = tile_prefix(st, tile, blk) + thr;
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
@@ -406,7 +406,7 @@ __global__ __launch_bounds__(256) void k_build_dir(const uint64_t* __restrict__ 
 // 2:1 balance, refinement pass: split bit-0 leaves one level, in order.  The
 // new mark array holds bit 2 for leaves to examine next pass: the children of
 // split leaves and the leaves that found a violation.
-__global__ __launch_bounds__(kBlock) void k_balance_refine(KeyGeom g, const uint64_t* __restrict__ in,
+__global__ __launch_bounds__(kScanBig) void k_balance_refine(KeyGeom g, const uint64_t* __restrict__ in,
                                                            const uint32_t* __restrict__ mark,
                                                            uint64_t* __restrict__ out,
                                                            uint32_t* __restrict__ mark_out, int64_t cap,
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(kBlock) void k_balance_refine(KeyGeom g, const uint
     const int64_t n = st.items.get();
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-      const int64_t i = int64_t(blockIdx.x) * kTile + int64_t(k) * kBlock + threadIdx.x;
+      const int64_t i = int64_t(blockIdx.x) * kTileMax + int64_t(k) * kScanBig + threadIdx.x;
       if (i < n) {
         out[i] = in[i];
         mark_out[i] = 0u;
@@ -428,7 +428,7 @@ __global__ __launch_bounds__(kBlock) void k_balance_refine(KeyGeom g, const uint
   const int64_t tile = take_ticket(st);
   if (tile >= scan_tiles(st)) return;
   const int64_t n = st.items.get();
-  const int64_t base = tile * kTile + int64_t(threadIdx.x) * kItems;
+  const int64_t base = tile * kTileMax + int64_t(threadIdx.x) * kItems;
   const int nc = g.nchild();
   uint32_t w[kItems];
   int64_t local = 0;
@@ -441,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_balance_refine(KeyGeom g, const uint
     local += (w[k] & 1u) ? nc : 1;
   }
   int64_t blk;
-  const int64_t thr = block_exclusive(local, &blk);
+  const int64_t thr = block_exclusive<kScanBig>(local, &blk);
   int64_t o = tile_prefix(st, tile, blk) + thr;
   unsigned err = 0;
 #pragma unroll
@@ -526,13 +526,13 @@ __global__ __launch_bounds__(256) void k_connect_faces(KeyGeom g, const uint64_t
 
 // Pass 2: hanging-face rows in (leaf, face) order: count from the masks,
 // decoupled look-back scan, then each row's leaf and face.
-__global__ __launch_bounds__(kBlock) void k_connect_rows(const uint8_t* __restrict__ hmask, int dim,
+__global__ __launch_bounds__(kScanSmall) void k_connect_rows(const uint8_t* __restrict__ hmask, int dim,
                                                          int32_t* __restrict__ hang, int64_t cap_rows,
                                                          ScanState st) {
   const int64_t tile = take_ticket(st);
   if (tile >= scan_tiles(st)) return;
   const int64_t n = st.items.get();
-  const int64_t base = tile * kTile + int64_t(threadIdx.x) * kItems;
+  const int64_t base = tile * kTileMin + int64_t(threadIdx.x) * kItems;
   const int nf = 2 * dim;
   const int width = 2 + (1 << (dim - 1));
   uint64_t hm8 = 0;  // kItems masks, one byte each
@@ -543,7 +543,7 @@ __global__ __launch_bounds__(kBlock) void k_connect_rows(const uint8_t* __restri
       if (base + k < n) hm8 |= uint64_t(hmask[base + k]) << (8 * k);
   }
   int64_t blk;
-  const int64_t thr = block_exclusive(__popcll(hm8), &blk);
+  const int64_t thr = block_exclusive<kScanSmall>(__popcll(hm8), &blk);
   int64_t o = tile_prefix(st, tile, blk) + thr;
   for (int k = 0; k < kItems && hm8; ++k) {
     const unsigned hm = unsigned(hm8 >> (8 * k)) & 0xffu;
@@ -676,8 +676,8 @@ void dir_params(const KeyGeom& g, int64_t n, int* shift, int64_t* nb) {
 
 namespace {
 lt_status prep_scan_on(uint64_t** status, int64_t* status_cap, DevCtr* ctr, int64_t n_items,
-                       hipStream_t stream, int flags, ScanState* st) {
-  const int64_t ntiles = std::max<int64_t>(1, ceil_div(n_items, kTile));
+                       int64_t tile, hipStream_t stream, int flags, ScanState* st) {
+  const int64_t ntiles = std::max<int64_t>(1, ceil_div(n_items, tile));
   LT_TRY(grow(status, status_cap, ntiles));
   k_clear_scan<<<unsigned(ceil_div(ntiles, 256)), 256, 0, stream>>>(*status, ntiles, ctr, flags & 1,
                                                                       (flags >> 1) & 1);
@@ -687,18 +687,20 @@ lt_status prep_scan_on(uint64_t** status, int64_t* status_cap, DevCtr* ctr, int6
   st->err = &ctr->err;
   st->total = &ctr->total;
   st->items = Count{n_items, nullptr};
+  st->tile = tile;
   st->commit = nullptr;
   st->commit_cap = 0;
   return LT_OK;
 }
 }  // namespace
 
-lt_status prep_scan(lt_tree t, int64_t n_items, hipStream_t stream, int flags, ScanState* st) {
-  return prep_scan_on(&t->status, &t->status_cap, t->dctr, n_items, stream, flags, st);
+lt_status prep_scan(lt_tree t, int64_t n_items, int64_t tile, hipStream_t stream, int flags,
+                    ScanState* st) {
+  return prep_scan_on(&t->status, &t->status_cap, t->dctr, n_items, tile, stream, flags, st);
 }
 
 lt_status prep_scan_conn(lt_tree t, int64_t n_items, hipStream_t stream, int flags, ScanState* st) {
-  return prep_scan_on(&t->cstatus, &t->cstatus_cap, t->cctr, n_items, stream, flags, st);
+  return prep_scan_on(&t->cstatus, &t->cstatus_cap, t->cctr, n_items, kTileMin, stream, flags, st);
 }
 
 lt_status read_ctr(lt_tree t, hipStream_t stream) {
@@ -865,11 +867,11 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
   k_cycle_begin<<<1, 64, 0, s>>>(S, t->dctr);
   // adapt K0 -> K[0]
   ScanState st;
-  LT_TRY(prep_scan(t, C, s, 1, &st));
+  LT_TRY(prep_scan(t, C, kTileMax, s, 1, &st));
   st.items.p = &S[1];
   st.commit = &S[0];
   st.commit_cap = C;
-  k_adapt<<<grid_tiles(st), kBlock, 0, s>>>(g, K0, F, K[0], C, st, t->mbuf[0]);
+  k_adapt<<<grid_tiles(st), kScanBig, 0, s>>>(g, K0, F, K[0], C, st, t->mbuf[0]);
   LT_HIP(hipGetLastError());
   // balance: fixed passes, then a check
   // (the tree entering the cycle is balanced, so adapt's marks restrict the
@@ -886,11 +888,11 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
       k_balance_mark<2><<<nlanes, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi], 0,
                                                   t->dctr, conv);
     if (pass == r.passes) break;
-    LT_TRY(prep_scan(t, C, s, 2, &st));  // also records convergence
+    LT_TRY(prep_scan(t, C, kTileMax, s, 2, &st));  // also records convergence
     st.items.p = &S[0];
     st.commit = &S[0];
     st.commit_cap = C;
-    k_balance_refine<<<grid_tiles(st), kBlock, 0, s>>>(g, K[ki], t->mbuf[mi], K[1 - ki],
+    k_balance_refine<<<grid_tiles(st), kScanBig, 0, s>>>(g, K[ki], t->mbuf[mi], K[1 - ki],
                                                         t->mbuf[1 - mi], C, st, conv);
     ki = 1 - ki;
     mi = 1 - mi;
@@ -913,7 +915,7 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
   cst.items.p = &S[0];
   cst.commit = &S[2];  // rows past the table's capacity raise ERR_CAPACITY
   cst.commit_cap = r.hang_rows;
-  k_connect_rows<<<grid_tiles(cst), kBlock, 0, cs>>>(t->hmask, g.dim, t->hang, r.hang_rows, cst);
+  k_connect_rows<<<grid_tiles(cst), kScanSmall, 0, cs>>>(t->hmask, g.dim, t->hang, r.hang_rows, cst);
   const int nh = 1 << (g.dim - 1);
   k_connect_fine<<<unsigned(ceil_div(r.hang_rows * nh, 256)), 256, 0, cs>>>(
       g, K[0], Count{C, &S[0]}, D, t->hang, &t->cctr->total, r.hang_rows, &t->cctr->err);
@@ -1111,8 +1113,8 @@ lt_status lt_adapt(lt_tree t, const int8_t* flags, void* stream) {
   const bool marks = t->balanced;
   if (marks) LT_TRY(grow(&t->mbuf[0], &t->mcap[0], t->kcap[t->tmp]));
   ScanState st;
-  LT_TRY(prep_scan(t, n, s, 1, &st));
-  k_adapt<<<grid_tiles(st), kBlock, 0, s>>>(t->g, t->kbuf[t->cur], flags, t->kbuf[t->tmp],
+  LT_TRY(prep_scan(t, n, kTileMax, s, 1, &st));
+  k_adapt<<<grid_tiles(st), kScanBig, 0, s>>>(t->g, t->kbuf[t->cur], flags, t->kbuf[t->tmp],
                                               t->kcap[t->tmp], st, marks ? t->mbuf[0] : nullptr);
   LT_HIP(hipGetLastError());
   LT_TRY(read_ctr(t, s));
@@ -1181,9 +1183,9 @@ lt_status lt_balance(lt_tree t, void* stream) {
     LT_TRY(grow(&t->kbuf[t->tmp], &t->kcap[t->tmp], n_new));
     LT_TRY(grow(&t->mbuf[1 - mi], &t->mcap[1 - mi], n_new));
     ScanState st;
-    LT_TRY(prep_scan(t, t->n_cur, s, 0, &st));  // also zeroes the mark count for the next pass
+    LT_TRY(prep_scan(t, t->n_cur, kTileMax, s, 0, &st));  // also zeroes the mark count for the next pass
     const int64_t cap = std::min(t->kcap[t->tmp], t->mcap[1 - mi]);
-    k_balance_refine<<<grid_tiles(st), kBlock, 0, s>>>(t->g, t->kbuf[t->cur], t->mbuf[mi],
+    k_balance_refine<<<grid_tiles(st), kScanBig, 0, s>>>(t->g, t->kbuf[t->cur], t->mbuf[mi],
                                                         t->kbuf[t->tmp], t->mbuf[1 - mi], cap, st,
                                                         nullptr);
     LT_HIP(hipGetLastError());
@@ -1226,7 +1228,7 @@ lt_status lt_connect(lt_tree t, void* stream) {
     const int64_t cap_rows = t->hang_cap / width;
     ScanState st;
     LT_TRY(prep_scan_conn(t, n, s, 1, &st));
-    k_connect_rows<<<grid_tiles(st), kBlock, 0, s>>>(t->hmask, t->g.dim, t->hang, cap_rows, st);
+    k_connect_rows<<<grid_tiles(st), kScanSmall, 0, s>>>(t->hmask, t->g.dim, t->hang, cap_rows, st);
     LT_HIP(hipGetLastError());
     // fine leaves of the rows the table holds (the row count stays on the device)
     k_connect_fine<<<unsigned(ceil_div(cap_rows * nh, 256)), 256, 0, s>>>(

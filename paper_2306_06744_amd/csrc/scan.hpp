@@ -15,10 +15,19 @@
 
 namespace lt {
 
-constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / 64;
-constexpr int kItems = 8;                              // items per thread in scan-emit kernels
-constexpr int64_t kTile = int64_t(kBlock) * kItems;    // items per look-back tile
+constexpr int kBlock = 256;   // workgroup of the plain kernels
+constexpr int kItems = 8;     // items per thread in scan-emit kernels
+// Scan-emit kernels over the leaves on the critical path (adapt, balance
+// refinement, the split transfer's lists) run 1024-thread tiles of 8192
+// items: ~1.6M leaves are 200 tiles, and the look-back of the last one crosses
+// about 4 windows of 64 predecessors (each window one round trip to
+// device-coherent memory) instead of 13.  Short scans (transfer groups) and
+// scans that run beside the copy pass (connectivity rows, which would wait for
+// a whole free CU) keep 256-thread tiles of 2048 items.
+constexpr int kScanBig = 1024;
+constexpr int kScanSmall = kBlock;
+constexpr int64_t kTileMax = int64_t(kScanBig) * kItems;
+constexpr int64_t kTileMin = int64_t(kScanSmall) * kItems;
 
 enum : unsigned {
   ERR_LOOKBACK = 1u << 0,
@@ -43,7 +52,8 @@ struct ScanState {
   unsigned long long* ticket;
   unsigned* err;
   int64_t* total;         // written by the last tile: sum of all counts
-  Count items;            // items scanned; tiles = max(1, ceil(items / kTile))
+  Count items;            // items scanned; tiles = max(1, ceil(items / tile))
+  int64_t tile;           // items per tile: the kernel's workgroup size times kItems
   int64_t* commit;        // optional (captured cycles): also receives min(total, commit_cap),
   int64_t commit_cap;     // with ERR_CAPACITY raised when the total exceeds it
 };
@@ -61,7 +71,7 @@ __device__ inline void publish_total(const ScanState& st, int64_t v) {
 // workgroups than this; the extra ones take a ticket and leave at once.
 __device__ inline int64_t scan_tiles(const ScanState& st) {
   const int64_t n = st.items.get();
-  return n > 0 ? (n + kTile - 1) / kTile : 1;
+  return n > 0 ? (n + st.tile - 1) / st.tile : 1;
 }
 
 constexpr uint64_t kStAgg = uint64_t(1) << 62;
@@ -92,8 +102,10 @@ __device__ inline int64_t wave_inclusive(int64_t v) {
   return v;
 }
 
-// Exclusive scan of v over the workgroup; *total receives the sum.
+// Exclusive scan of v over a workgroup of BLOCK threads; *total receives the sum.
+template <int BLOCK>
 __device__ inline int64_t block_exclusive(int64_t v, int64_t* total) {
+  constexpr int kWaves = BLOCK / 64;
   __shared__ int64_t wsum[kWaves];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t inc = wave_inclusive(v);
@@ -171,7 +183,7 @@ __device__ inline int64_t tile_prefix(const ScanState& st, int64_t tile, int64_t
 // Workgroups of a scan launch: one per tile of the (host) item count or capacity.
 inline unsigned grid_tiles(const ScanState& st) {
   const int64_t n = st.items.n;
-  return unsigned(n > 0 ? (n + kTile - 1) / kTile : 1);
+  return unsigned(n > 0 ? (n + st.tile - 1) / st.tile : 1);
 }
 
 __device__ inline int64_t take_ticket(const ScanState& st) {

@@ -110,9 +110,12 @@ struct lt_tree_s;
 
 namespace lt {
 
-// Zero the look-back words for n_items of scan work and the counters (and
-// the error word if clear_err); fills st for a scan kernel on `stream`.
-lt_status prep_scan(lt_tree_s* t, int64_t n_items, hipStream_t stream, int clear_err, ScanState* st);
+// Zero the look-back words for n_items of scan work in tiles of `tile`
+// items (kTileMax or kTileMin, matching the kernel's workgroup) and the
+// counters (and the error word if clear_err); fills st for a scan kernel on
+// `stream`.
+lt_status prep_scan(lt_tree_s* t, int64_t n_items, int64_t tile, hipStream_t stream, int clear_err,
+                    ScanState* st);
 // The same on connectivity's own look-back words and counters, so that
 // lt_connect may run beside lt_map and lt_transfer on another stream.
 lt_status prep_scan_conn(lt_tree_s* t, int64_t n_items, hipStream_t stream, int clear_err,
