@@ -81,6 +81,7 @@ lt_status reserve(lt_cycle c, hipStream_t s) {
   LT_TRY_STATUS(grow(&t->nbr, &t->nbr_cap, C * 2 * dim));
   LT_TRY_STATUS(grow(&t->hmask, &t->hmask_cap, C + kItems));
   LT_TRY_STATUS(grow(&t->fused, &t->fused_cap, C));
+  LT_TRY_STATUS(grow(&t->elist, &t->elist_cap, C));
   c->hang_rows = std::max<int64_t>(1024, C / 16);
   LT_TRY_STATUS(grow(&t->hang, &t->hang_cap, c->hang_rows * (2 + (1 << (dim - 1)))));
   c->hang_rows = t->hang_cap / (2 + (1 << (dim - 1)));

@@ -55,10 +55,11 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // Zero the look-back words and counters before a scan.  converge (captured
 // cycles, after a balance marking pass): no fresh marks means the fixpoint.
 __global__ void k_clear_scan(uint64_t* status, int64_t ntiles, DevCtr* ctr, int clear_err,
-                             int converge) {
+                             int converge, int clear_list) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < ntiles) status[i] = 0;
   if (i == 0) {
+    if (clear_list) ctr->nexam = 0;
     if (converge && ctr->nmarked == 0) ctr->conv = 1;
     ctr->ticket = 0;
     ctr->total = 0;
@@ -141,12 +142,16 @@ __global__ void k_validate(KeyGeom g, const uint64_t* __restrict__ keys, int64_t
 // refined leaf are to be examined, a fused parent is to be checked against
 // finer neighbours; every other leaf is balanced with its neighbours already.
 constexpr uint32_t kMarkExamine = 4u;
+// Workgroups of a marking pass over the examine list (it strides over the
+// list, whose length is on the device).
+constexpr int64_t kMarkGrid = 2048;
 constexpr uint32_t kMarkFused = 16u;
 
 __global__ __launch_bounds__(kScanBig) void k_adapt(KeyGeom g, const uint64_t* __restrict__ in,
                                                   const int8_t* __restrict__ flags,
                                                   uint64_t* __restrict__ out, int64_t cap,
-                                                  ScanState st, uint32_t* __restrict__ marks) {
+                                                  ScanState st, uint32_t* __restrict__ marks,
+                                                  int32_t* __restrict__ elist, int64_t* nexam) {
   const int64_t tile = take_ticket(st);
   if (tile >= scan_tiles(st)) return;
   const int64_t n = st.items.get();
@@ -193,6 +198,11 @@ __global__ __launch_bounds__(kScanBig) void k_adapt(KeyGeom g, const uint64_t* _
     act[k] = a;
     local += a == 1 ? nc : (a == 3 ? 0 : 1);
   }
+  // the new children go on the list of leaves the first balance pass examines
+  int64_t ex = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) ex += act[k] == 1 ? nc : 0;
+  int64_t eo = elist ? wave_append(ex, nexam) : 0;
   int64_t blk;
   const int64_t thr = block_exclusive<kScanBig>(local, &blk);
   int64_t o = tile_prefix(st, tile, blk) + thr;
@@ -203,6 +213,8 @@ __global__ __launch_bounds__(kScanBig) void k_adapt(KeyGeom g, const uint64_t* _
     const int cnt = a == 1 ? nc : 1;
     if (o + cnt > cap) {
       err |= ERR_CAPACITY;
+      if (elist && a == 1)
+        for (int c = 0; c < nc; ++c) elist[eo++] = -1;
       o += cnt;
       continue;
     }
@@ -219,6 +231,7 @@ __global__ __launch_bounds__(kScanBig) void k_adapt(KeyGeom g, const uint64_t* _
       for (int c = 0; c < nc; ++c) {
         out[o + c] = child_key(g, m, d, c);
         if (marks) marks[o + c] = kMarkExamine;
+        if (elist) elist[eo++] = int32_t(o + c);
       }
     }
     o += cnt;
@@ -237,24 +250,30 @@ template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_balance_mark(KeyGeom g, const uint64_t* __restrict__ keys,
                                                          Count cn, KeyDir D, uint32_t* mark,
                                                          int check_all, DevCtr* ctr,
-                                                         const unsigned* conv) {
+                                                         const unsigned* conv,
+                                                         const int32_t* __restrict__ elist) {
   // 2^DIM lanes per leaf, lane `sub` (1 .. 2^DIM - 1) probes one searching key;
-  // waves stride over the (leaf, sub) pairs.  `conv` (captured cycles): the
-  // fixpoint was already reached, nothing to examine.
+  // waves stride over the (leaf, sub) pairs: every leaf (check_all), or the
+  // listed leaves (elist: ctr->nexam entries, the leaves holding bit 2).
+  // `conv` (captured cycles): the fixpoint was already reached, nothing to
+  // examine.
   if (conv && *conv) return;
   constexpr int SL = 1 << DIM;
   const int64_t n = cn.get();
-  const int64_t lanes = n * SL;
+  const int64_t items = elist ? ctr->nexam : n;
+  const int64_t lanes = items * SL;
   const int lane = threadIdx.x & 63;
   const int limit = g.balance == 0 ? 1 : (g.balance == 1 ? 2 : 3);
   unsigned long long nfresh = 0;
   for (int64_t wb = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63); wb < lanes;
        wb += int64_t(gridDim.x) * blockDim.x) {
     const int64_t tid = wb + lane;
-    const int64_t i = tid / SL;
+    const int64_t it = tid / SL;
+    const int64_t i = elist ? (it < items ? int64_t(elist[it]) : -1) : it;
     const int sub = int(tid % SL);
     bool viol = false, fresh = false;
-    if (i < n && sub != 0 && __popc(unsigned(sub)) <= limit && (check_all || (mark[i] & 4u))) {
+    if (i >= 0 && i < n && sub != 0 && __popc(unsigned(sub)) <= limit &&
+        (check_all || (mark[i] & 4u))) {
       const uint64_t key = keys[i];
       const int d = key_depth(g, key);
       if (d >= 2) {
@@ -285,7 +304,8 @@ __global__ __launch_bounds__(kBlock) void k_balance_mark(KeyGeom g, const uint64
     }
     const uint64_t vb = __ballot(viol);
     const uint64_t fb = __ballot(fresh);
-    if (sub == 0 && i < n && ((vb >> lane) & ((uint64_t(1) << SL) - 1))) atomicOr(&mark[i], 2u);
+    if (sub == 0 && i >= 0 && i < n && ((vb >> lane) & ((uint64_t(1) << SL) - 1)))
+      atomicOr(&mark[i], 2u);
     nfresh += __popcll(fb);
   }
   if (lane == 0 && nfresh) atomicAdd(&ctr->nmarked, nfresh);
@@ -410,7 +430,8 @@ __global__ __launch_bounds__(kScanBig) void k_balance_refine(KeyGeom g, const ui
                                                            const uint32_t* __restrict__ mark,
                                                            uint64_t* __restrict__ out,
                                                            uint32_t* __restrict__ mark_out, int64_t cap,
-                                                           ScanState st, const unsigned* conv) {
+                                                           ScanState st, const unsigned* conv,
+                                                           int32_t* __restrict__ elist, int64_t* nexam) {
   if (conv && *conv) {
     // captured cycles past the fixpoint: the pass is the identity, a plain copy
     const int64_t n = st.items.get();
@@ -440,6 +461,13 @@ __global__ __launch_bounds__(kScanBig) void k_balance_refine(KeyGeom g, const ui
     w[k] = mark[i] | 8u;  // bit 3: valid item
     local += (w[k] & 1u) ? nc : 1;
   }
+  // leaves the next pass examines (bit 2): the children of split leaves and
+  // the leaves that found a violation, also put on the examine list
+  int64_t ex = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k)
+    if (w[k] & 8u) ex += (w[k] & 1u) ? nc : ((w[k] & 2u) ? 1 : 0);
+  int64_t eo = wave_append(ex, nexam);
   int64_t blk;
   const int64_t thr = block_exclusive<kScanBig>(local, &blk);
   int64_t o = tile_prefix(st, tile, blk) + thr;
@@ -450,8 +478,10 @@ __global__ __launch_bounds__(kScanBig) void k_balance_refine(KeyGeom g, const ui
     const int64_t i = base + k;
     const uint64_t kk = in[i];
     const int cnt = (w[k] & 1u) ? nc : 1;
+    const int nex = (w[k] & 1u) ? nc : ((w[k] & 2u) ? 1 : 0);
     if (o + cnt > cap) {
       err |= ERR_CAPACITY;
+      for (int c = 0; c < nex; ++c) elist[eo++] = -1;
       o += cnt;
       continue;
     }
@@ -461,10 +491,12 @@ __global__ __launch_bounds__(kScanBig) void k_balance_refine(KeyGeom g, const ui
       for (int c = 0; c < nc; ++c) {
         out[o + c] = child_key(g, m, d, c);
         mark_out[o + c] = 4u;
+        elist[eo++] = int32_t(o + c);
       }
     } else {
       out[o] = kk;
       mark_out[o] = (w[k] & 2u) ? 4u : 0u;
+      if (w[k] & 2u) elist[eo++] = int32_t(o);
     }
     o += cnt;
   }
@@ -680,7 +712,8 @@ lt_status prep_scan_on(uint64_t** status, int64_t* status_cap, DevCtr* ctr, int6
   const int64_t ntiles = std::max<int64_t>(1, ceil_div(n_items, tile));
   LT_TRY(grow(status, status_cap, ntiles));
   k_clear_scan<<<unsigned(ceil_div(ntiles, 256)), 256, 0, stream>>>(*status, ntiles, ctr, flags & 1,
-                                                                      (flags >> 1) & 1);
+                                                                      (flags >> 1) & 1,
+                                                                      (flags >> 2) & 1);
   LT_HIP(hipGetLastError());
   st->status = *status;
   st->ticket = &ctr->ticket;
@@ -710,7 +743,7 @@ lt_status read_ctr(lt_tree t, hipStream_t stream) {
 }
 
 lt_status clear_err(lt_tree t, hipStream_t stream) {
-  k_clear_scan<<<1, 64, 0, stream>>>(t->status, 0, t->dctr, 1, 0);
+  k_clear_scan<<<1, 64, 0, stream>>>(t->status, 0, t->dctr, 1, 0, 0);
   LT_HIP(hipGetLastError());
   return LT_OK;
 }
@@ -867,11 +900,12 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
   k_cycle_begin<<<1, 64, 0, s>>>(S, t->dctr);
   // adapt K0 -> K[0]
   ScanState st;
-  LT_TRY(prep_scan(t, C, kTileMax, s, 1, &st));
+  LT_TRY(prep_scan(t, C, kTileMax, s, 1 | 4, &st));
   st.items.p = &S[1];
   st.commit = &S[0];
   st.commit_cap = C;
-  k_adapt<<<grid_tiles(st), kScanBig, 0, s>>>(g, K0, F, K[0], C, st, t->mbuf[0]);
+  k_adapt<<<grid_tiles(st), kScanBig, 0, s>>>(g, K0, F, K[0], C, st, t->mbuf[0], t->elist,
+                                              &t->dctr->nexam);
   LT_HIP(hipGetLastError());
   // balance: fixed passes, then a check
   // (the tree entering the cycle is balanced, so adapt's marks restrict the
@@ -881,19 +915,21 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
   for (int pass = 0; pass <= r.passes; ++pass) {
     k_build_dir<<<nleaf, 256, 0, s>>>(K[ki], Count{C, &S[0]}, r.dir_shift, r.dir_nb, t->dir, conv);
     if (pass == 0) LT_HIP(launch_fused_check(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi], t->fused, t->dctr, s));
+    const unsigned mgrid = unsigned(std::min<int64_t>(nlanes, kMarkGrid));
     if (g.dim == 3)
-      k_balance_mark<3><<<nlanes, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi], 0,
-                                                  t->dctr, conv);
+      k_balance_mark<3><<<mgrid, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi], 0,
+                                                 t->dctr, conv, t->elist);
     else
-      k_balance_mark<2><<<nlanes, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi], 0,
-                                                  t->dctr, conv);
+      k_balance_mark<2><<<mgrid, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi], 0,
+                                                 t->dctr, conv, t->elist);
     if (pass == r.passes) break;
-    LT_TRY(prep_scan(t, C, kTileMax, s, 2, &st));  // also records convergence
+    LT_TRY(prep_scan(t, C, kTileMax, s, 2 | 4, &st));  // also records convergence
     st.items.p = &S[0];
     st.commit = &S[0];
     st.commit_cap = C;
     k_balance_refine<<<grid_tiles(st), kScanBig, 0, s>>>(g, K[ki], t->mbuf[mi], K[1 - ki],
-                                                        t->mbuf[1 - mi], C, st, conv);
+                                                        t->mbuf[1 - mi], C, st, conv, t->elist,
+                                                        &t->dctr->nexam);
     ki = 1 - ki;
     mi = 1 - mi;
   }
@@ -1111,11 +1147,15 @@ lt_status lt_adapt(lt_tree t, const int8_t* flags, void* stream) {
   LT_TRY(grow(&t->kbuf[t->tmp], &t->kcap[t->tmp], n * t->g.nchild()));
   // From a balanced tree, adapt also writes the first balance pass's marks.
   const bool marks = t->balanced;
-  if (marks) LT_TRY(grow(&t->mbuf[0], &t->mcap[0], t->kcap[t->tmp]));
+  if (marks) {
+    LT_TRY(grow(&t->mbuf[0], &t->mcap[0], t->kcap[t->tmp]));
+    LT_TRY(grow(&t->elist, &t->elist_cap, t->kcap[t->tmp]));
+  }
   ScanState st;
-  LT_TRY(prep_scan(t, n, kTileMax, s, 1, &st));
+  LT_TRY(prep_scan(t, n, kTileMax, s, 1 | 4, &st));
   k_adapt<<<grid_tiles(st), kScanBig, 0, s>>>(t->g, t->kbuf[t->cur], flags, t->kbuf[t->tmp],
-                                              t->kcap[t->tmp], st, marks ? t->mbuf[0] : nullptr);
+                                              t->kcap[t->tmp], st, marks ? t->mbuf[0] : nullptr,
+                                              marks ? t->elist : nullptr, &t->dctr->nexam);
   LT_HIP(hipGetLastError());
   LT_TRY(read_ctr(t, s));
   if (t->hctr->err & ERR_BAD_FLAG) return fail(LT_ERR_ARG, "flags must be -1, 0 or 1");
@@ -1158,8 +1198,12 @@ lt_status lt_balance(lt_tree t, void* stream) {
     KeyDir D;
     LT_TRY(ensure_dir(t, s, &D));
     if (t->n_cur > 0) {
-      const unsigned blocks = unsigned(ceil_div(t->n_cur * t->g.nchild(), kBlock));
       const int all = pass == 0 && !restricted ? 1 : 0;
+      // every leaf: one lane per (leaf, searching key); listed leaves: a
+      // bounded grid striding over the device-side list
+      const int64_t full = ceil_div(t->n_cur * t->g.nchild(), kBlock);
+      const unsigned blocks = unsigned(all ? full : std::min<int64_t>(full, kMarkGrid));
+      const int32_t* el = all ? nullptr : t->elist;
       const Count cn{t->n_cur, nullptr};
       if (pass == 0 && restricted) {
         LT_TRY(grow(&t->fused, &t->fused_cap, t->n_cur));
@@ -1167,10 +1211,10 @@ lt_status lt_balance(lt_tree t, void* stream) {
       }
       if (t->g.dim == 3)
         k_balance_mark<3><<<blocks, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], cn, D, t->mbuf[mi], all,
-                                                    t->dctr, nullptr);
+                                                    t->dctr, nullptr, el);
       else
         k_balance_mark<2><<<blocks, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], cn, D, t->mbuf[mi], all,
-                                                    t->dctr, nullptr);
+                                                    t->dctr, nullptr, el);
       LT_HIP(hipGetLastError());
     }
     LT_TRY(read_ctr(t, s));
@@ -1182,12 +1226,14 @@ lt_status lt_balance(lt_tree t, void* stream) {
     const int64_t n_new = t->n_cur + marked * (t->g.nchild() - 1);
     LT_TRY(grow(&t->kbuf[t->tmp], &t->kcap[t->tmp], n_new));
     LT_TRY(grow(&t->mbuf[1 - mi], &t->mcap[1 - mi], n_new));
+    LT_TRY(grow(&t->elist, &t->elist_cap, n_new));
     ScanState st;
-    LT_TRY(prep_scan(t, t->n_cur, kTileMax, s, 0, &st));  // also zeroes the mark count for the next pass
-    const int64_t cap = std::min(t->kcap[t->tmp], t->mcap[1 - mi]);
+    // also zeroes the mark count and the examine list for the next pass
+    LT_TRY(prep_scan(t, t->n_cur, kTileMax, s, 4, &st));
+    const int64_t cap = std::min(std::min(t->kcap[t->tmp], t->mcap[1 - mi]), t->elist_cap);
     k_balance_refine<<<grid_tiles(st), kScanBig, 0, s>>>(t->g, t->kbuf[t->cur], t->mbuf[mi],
                                                         t->kbuf[t->tmp], t->mbuf[1 - mi], cap, st,
-                                                        nullptr);
+                                                        nullptr, t->elist, &t->dctr->nexam);
     LT_HIP(hipGetLastError());
     expect_total = n_new;
     std::swap(t->cur, t->tmp);
@@ -1339,6 +1385,7 @@ void lt_destroy(lt_tree t) {
   if (t->dctr) (void)hipFree(t->dctr);
   if (t->hctr) (void)hipHostFree(t->hctr);
   if (t->cstatus) (void)hipFree(t->cstatus);
+  if (t->elist) (void)hipFree(t->elist);
   if (t->cctr) (void)hipFree(t->cctr);
   if (t->hcctr) (void)hipHostFree(t->hcctr);
   for (auto& o : t->ops) if (o) (void)hipFree(o);

@@ -122,6 +122,18 @@ __device__ inline int64_t block_exclusive(int64_t v, int64_t* total) {
   return before + inc - v;
 }
 
+// Appends v entries per lane to a list whose length is *count (one atomic per
+// wave); returns this lane's first position.  Every lane of the wave calls it.
+__device__ inline int64_t wave_append(int64_t v, int64_t* count) {
+  const int64_t inc = wave_inclusive(v);
+  const int64_t tot = __shfl(inc, 63, 64);
+  int64_t b = 0;
+  if ((threadIdx.x & 63) == 63 && tot > 0)
+    b = int64_t(atomicAdd(reinterpret_cast<unsigned long long*>(count), (unsigned long long)tot));
+  b = __shfl(b, 63, 64);
+  return b + inc - v;
+}
+
 // Sum of v over the 64 lanes of a wave (result in every lane).
 __device__ inline int64_t wave_sum(int64_t v) {
 #pragma unroll

@@ -21,6 +21,7 @@ struct DevCtr {
   unsigned long long ticket;
   unsigned long long nfused;  // fused parents listed for the first balance pass
   int64_t nfgroups;           // transfer groups holding a fused element (second list)
+  int64_t nexam;              // balance: leaves listed for the next marking pass
 };
 
 void set_error(const std::string& msg);
@@ -212,6 +213,8 @@ struct lt_tree_s {
   int64_t status_cap = 0;
   lt::DevCtr* dctr = nullptr;
   lt::DevCtr* hctr = nullptr;  // pinned mirror
+  int32_t* elist = nullptr;     // balance: leaves to examine in the next marking pass
+  int64_t elist_cap = 0;
   uint64_t* cstatus = nullptr;  // connectivity's own look-back words and counters
   int64_t cstatus_cap = 0;
   lt::DevCtr* cctr = nullptr;
