@@ -81,6 +81,14 @@ __global__ __launch_bounds__(256) void k_vortex_field(FieldArgs A, const uint64_
 
 typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Network input of one modal coefficient magnitude cc = |c| + 1e-14 (>= 1e-14,
+// a normal FP32 number): (log10 cc + 7) / 7, formed as the hardware base-2
+// logarithm times log10(2), then times 1/7.  Within a few FP32 ulps of the
+// exactly rounded expression, far below the BF16 rounding that follows.
+__device__ inline float feature_of(float cc) {
+  return (__builtin_amdgcn_logf(cc) * 0.30102999566398120f + 7.0f) * (1.0f / 7.0f);
+}
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Modal features of 64-point elements: T[n][i] = w_i L~_n(x_i) per axis
@@ -144,7 +152,7 @@ __global__ __launch_bounds__(256) void k_mlp_features(const double* __restrict__
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const float cc = float(fabs(c[h * 8 + t]) + 1e-14);
-      o[t] = bf16((log10f(cc) + 7.0f) / 7.0f);
+      o[t] = bf16(feature_of(cc));
     }
     out[h] = o;
   }
@@ -417,21 +425,45 @@ __global__ __launch_bounds__(64 * kFlagWaves) void k_mlp_flag_fused(
   bf16* FS = sH1[w];  // feature staging shares the layer-1 patch (used one after the other)
   const int64_t ntiles = (n + 15) / 16;
   const int64_t stride = int64_t(gridDim.x) * kFlagWaves;
+  // z-slab lg of this lane's element of tile tl, variable v: unconditional
+  // loads at a clamped index, so that no branch or select stands between a
+  // load and its use.  A lane past the end reads element 0: its row of the
+  // network is finite and never written out.
+  auto load_slab = [&](int64_t tl, int v, double* dst) {
+    const int64_t el = tl * 16 + lr;
+    const int64_t ec = (tl < ntiles && el < n) ? el : 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) dst[i] = u[(int64_t(v) * 64 + lg * 16 + i) * ld + ec];
+  };
+  // The slab of the next variable (or of the next tile's first variable) is
+  // loaded while the current one is computed, into the other of two register
+  // buffers (the variable loop is unrolled, so the buffers swap roles without
+  // copies): with two waves per SIMD (the weights fill the LDS) the loads of
+  // one variable would otherwise wait alone.
+  int64_t tile = int64_t(blockIdx.x) * kFlagWaves + w;
+  double bufA[16], bufB[16];
+  if (tile < ntiles) load_slab(tile, 0, bufA);
   // Waves run their tiles independently (every LDS patch in the loop is a
   // wave's own); a wave whose tile lies past the end computes on zeros and
   // writes nothing.
-  for (int64_t tile = int64_t(blockIdx.x) * kFlagWaves + w; tile < ntiles; tile += stride) {
+  for (; tile < ntiles; tile += stride) {
+    // this tile's keys and fallback flags, read ahead of the prefetches
+    const int64_t eo = tile * 16 + lane;
+    const bool own = lane < 16 && eo < n;
+    const int64_t eoc = own ? eo : 0;
+    const uint64_t okey = keys[eoc];
+    const int ofl = int(flags[eoc]);
     // layer 1 accumulates variable by variable: acc[ct] += X[:, 64v .. 64v+63] W1^T
     f32x4 acc1[8];
 #pragma unroll
     for (int ct = 0; ct < 8; ++ct) acc1[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-    for (int v = 0; v < 5; ++v) {
-      // z-slab lg of this lane's element, variable v
-      const int64_t el = tile * 16 + lr;
-      double a[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) a[i] = el < n ? u[(int64_t(v) * 64 + lg * 16 + i) * ld + el] : 0.0;
+    for (int v = 0; v < 5; ++v) {
+      // keep each variable's work in its own region, so that the waits for
+      // the prefetched slab fall in the next variable, not this one
+      __builtin_amdgcn_sched_barrier(0);
+      double* a = (v & 1) ? bufB : bufA;
+      load_slab(v < 4 ? tile : tile + stride, v < 4 ? v + 1 : 0, (v & 1) ? bufA : bufB);
 #pragma unroll
       for (int pass = 0; pass < 2; ++pass) {
         const int st = pass == 0 ? 1 : 4;
@@ -472,7 +504,7 @@ __global__ __launch_bounds__(64 * kFlagWaves) void k_mlp_flag_fused(
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
           const float cc = float(fabs(c[mz * 4 + x]) + 1e-14);
-          FS[lr * kFS + mz * 16 + lg * 4 + x] = bf16((log10f(cc) + 7.0f) / 7.0f);
+          FS[lr * kFS + mz * 16 + lg * 4 + x] = bf16(feature_of(cc));
         }
       wave_lds_sync();
       bf16x8 af[2];
@@ -527,8 +559,7 @@ __global__ __launch_bounds__(64 * kFlagWaves) void k_mlp_flag_fused(
 #pragma unroll
       for (int q = 0; q < 4; ++q) sZ[w][4 * lg + q][lr] = acc3[q] + sB[192 + lr];
     wave_lds_sync();
-    const int64_t eo = tile * 16 + lane;
-    if (lane < 16 && eo < n) {
+    if (own) {
       const float z0 = sZ[w][lane][0], z1 = sZ[w][lane][1], z2 = sZ[w][lane][2];
       const float mx = fmaxf(z0, fmaxf(z1, z2));
       const float e0 = expf(z0 - mx), e1 = expf(z1 - mx), e2 = expf(z2 - mx);
@@ -539,16 +570,17 @@ __global__ __launch_bounds__(64 * kFlagWaves) void k_mlp_flag_fused(
       if (e2 > pc) { cls = 2; pc = e2; }
       pc /= sum;
       if (conf) conf[eo] = pc;
-      int f = pc >= conf_min ? cls - 1 : int(flags[eo]);
-      const uint64_t key = keys[eo];
-      const int d = key_depth(g, key);
+      int f = pc >= conf_min ? cls - 1 : ofl;
+      const int d = key_depth(g, okey);
       int lo, hi;
-      depth_limits(g, key, &lo, &hi);
+      depth_limits(g, okey, &lo, &hi);
       if (f == 1 && d >= hi) f = 0;
       if (f == -1 && d <= lo) f = 0;
       flags[eo] = int8_t(f);
     }
     wave_lds_sync();  // sZ and the patches are rewritten by the next tile
+#pragma unroll
+    for (int i = 0; i < 16; ++i) bufA[i] = bufB[i];  // the next tile's first slab
   }
 }
 
