@@ -703,7 +703,15 @@ void dir_params(const KeyGeom& g, int64_t n, int* shift, int64_t* nb) {
   L = std::max(10, std::min(24, L - 1));
   L = std::min(L, kb);
   *shift = kb - L;
-  *nb = int64_t(1) << L;
+  // The buckets end with the last mesh's key range (nmesh << mesh_shift),
+  // not at the next power of two of the mesh count: otherwise the last leaf
+  // would own every bucket of the empty mesh slots.
+  const int ms = g.mesh_shift;
+  const int64_t nm = std::max(1, g.nmesh);
+  if (*shift <= ms)
+    *nb = nm << (ms - *shift);
+  else
+    *nb = (nm + (int64_t(1) << (*shift - ms)) - 1) >> (*shift - ms);
 }
 
 namespace {
