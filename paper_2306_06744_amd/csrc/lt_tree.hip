@@ -1152,27 +1152,42 @@ lt_status lt_adapt(lt_tree t, const int8_t* flags, void* stream) {
   if (!t || !flags) return fail(LT_ERR_ARG, "NULL argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t n = t->n_cur;
-  LT_TRY(grow(&t->kbuf[t->tmp], &t->kcap[t->tmp], n * t->g.nchild()));
+  // Output bound: every leaf refined.  Both the spare buffer and the one
+  // holding the previous snapshot are free here (the snapshot is superseded
+  // by this call), so the output goes to whichever already holds the bound:
+  // the buffers rotate roles from cycle to cycle, and growing a small one
+  // costs a device-wide free and allocation.
+  const int64_t need = n * t->g.nchild();
+  int out = t->tmp, spare = t->old;
+  if (t->kcap[out] < need && t->kcap[spare] >= need) std::swap(out, spare);
+  if (t->kcap[out] < need) {
+    // growing: grow the other free buffer with it, so that from now on one of
+    // the two free buffers always holds the bound (only one buffer is ever
+    // current) and steady cycles allocate nothing
+    LT_TRY(grow(&t->kbuf[out], &t->kcap[out], need));
+    LT_TRY(grow(&t->kbuf[spare], &t->kcap[spare], need));
+  }
   // From a balanced tree, adapt also writes the first balance pass's marks.
   const bool marks = t->balanced;
+  int64_t cap = t->kcap[out];
   if (marks) {
-    LT_TRY(grow(&t->mbuf[0], &t->mcap[0], t->kcap[t->tmp]));
-    LT_TRY(grow(&t->elist, &t->elist_cap, t->kcap[t->tmp]));
+    LT_TRY(grow(&t->mbuf[0], &t->mcap[0], need));
+    LT_TRY(grow(&t->elist, &t->elist_cap, need));
+    cap = std::min(cap, std::min(t->mcap[0], t->elist_cap));
   }
   ScanState st;
   LT_TRY(prep_scan(t, n, kTileMax, s, 1 | 4, &st));
-  k_adapt<<<grid_tiles(st), kScanBig, 0, s>>>(t->g, t->kbuf[t->cur], flags, t->kbuf[t->tmp],
-                                              t->kcap[t->tmp], st, marks ? t->mbuf[0] : nullptr,
+  k_adapt<<<grid_tiles(st), kScanBig, 0, s>>>(t->g, t->kbuf[t->cur], flags, t->kbuf[out], cap, st,
+                                              marks ? t->mbuf[0] : nullptr,
                                               marks ? t->elist : nullptr, &t->dctr->nexam);
   LT_HIP(hipGetLastError());
   LT_TRY(read_ctr(t, s));
   if (t->hctr->err & ERR_BAD_FLAG) return fail(LT_ERR_ARG, "flags must be -1, 0 or 1");
   if (t->hctr->err) return fail(LT_ERR_INTERNAL, "device check failed in lt_adapt");
-  // old <- cur, cur <- tmp, tmp <- previous old buffer
-  const int prev_old = t->old;
+  // old <- cur, cur <- the output, tmp <- the other free buffer
   t->old = t->cur;
-  t->cur = t->tmp;
-  t->tmp = prev_old;
+  t->cur = out;
+  t->tmp = spare;
   t->n_old = n;
   t->n_cur = t->hctr->total;
   t->has_old = true;
