@@ -944,9 +944,14 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
   k_check_marks<<<1, 64, 0, s>>>(t->dctr);
   LT_HIP(hipGetLastError());
   if (ki != 0) return fail(LT_ERR_ARG, "balance passes of a captured cycle must be even");
+  // map
+  k_map<<<nleaf, kBlock, 0, s>>>(g, K0, Count{C, &S[1]}, K[0], Count{C, &S[0]}, t->map_src,
+                                  t->map_kind, err);
+  LT_HIP(hipGetLastError());
   // connect on the side stream (the directory of K[0] was built by the check
   // pass); it reads the new keys only, and its scan words and counters are its
-  // own, so it runs beside the mapping and the transfer
+  // own, so it runs beside the transfer (forked after the mapping, which runs
+  // alone: beside connectivity's searches it took three times as long)
   hipStream_t cs = r.side;
   LT_HIP(hipEventRecord(r.fork, s));
   LT_HIP(hipStreamWaitEvent(cs, r.fork, 0));
@@ -965,10 +970,6 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
       g, K[0], Count{C, &S[0]}, D, t->hang, &t->cctr->total, r.hang_rows, &t->cctr->err);
   LT_HIP(hipGetLastError());
   LT_HIP(hipEventRecord(r.join, cs));
-  // map
-  k_map<<<nleaf, kBlock, 0, s>>>(g, K0, Count{C, &S[1]}, K[0], Count{C, &S[0]}, t->map_src,
-                                  t->map_kind, err);
-  LT_HIP(hipGetLastError());
   // transfer
   if (r.precision == 1) {
     LT_TRY(launch_split_transfer(t, Count{C, &S[0]}, r.p, r.nvar, r.uo, r.ld, r.un, r.ld, s));
