@@ -108,13 +108,13 @@ __global__ void k_build_split_vec(const double* __restrict__ ops1d, int n1, int 
 // Work lists from the mapping: R = first child of each refined family (kind
 // 1), F = each fused parent (kind -1), in new-leaf order.  One scan carries
 // both counts packed as nR + (nF << 31).
-__global__ __launch_bounds__(kScanBig) void k_split_lists(const int8_t* __restrict__ kind,
+__global__ __launch_bounds__(kScanSmall) void k_split_lists(const int8_t* __restrict__ kind,
                                                         int32_t* __restrict__ R,
                                                         int32_t* __restrict__ F, ScanState st) {
   const int64_t tile = take_ticket(st);
   if (tile >= scan_tiles(st)) return;
   const int64_t n = st.items.get();
-  const int64_t base = tile * kTileMax + int64_t(threadIdx.x) * kItems;
+  const int64_t base = tile * kTileMin + int64_t(threadIdx.x) * kItems;
   int8_t kd[kItems];
   int64_t local = 0;
 #pragma unroll
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kScanBig) void k_split_lists(const int8_t* __restri
     local += (kd[k] == 1 ? 1 : 0) + (kd[k] == -1 ? (int64_t(1) << 31) : 0);
   }
   int64_t blk;
-  const int64_t thr = block_exclusive<kScanBig>(local, &blk);
+  const int64_t thr = block_exclusive<kScanSmall>(local, &blk);
   const int64_t o = tile_prefix(st, tile, blk) + thr;
   int64_t orr = o & kLow31, of = o >> 31;
 #pragma unroll
@@ -390,9 +390,9 @@ lt_status launch_split_transfer(lt_tree_s* t, Count cn, int p, int nvar, const d
   LT_TRY_STATUS(grow(&t->split_R, &t->split_R_cap, n));
   LT_TRY_STATUS(grow(&t->split_F, &t->split_F_cap, n));
   ScanState st;
-  LT_TRY_STATUS(prep_scan(t, n, kTileMax, s, 0, &st));
+  LT_TRY_STATUS(prep_scan(t, n, kTileMin, s, 0, &st));
   st.items.p = cn.p;
-  k_split_lists<<<grid_tiles(st), kScanBig, 0, s>>>(t->map_kind, t->split_R, t->split_F, st);
+  k_split_lists<<<grid_tiles(st), kScanSmall, 0, s>>>(t->map_kind, t->split_R, t->split_F, st);
   const bf16x8* fr = static_cast<const bf16x8*>(t->split_frags);
   const bf16x8* fI = fr;
   const bf16x8* fP = fr + size_t(nc) * 3 * kMT * kKS * 64;

@@ -18,12 +18,13 @@ namespace lt {
 constexpr int kBlock = 256;   // workgroup of the plain kernels
 constexpr int kItems = 8;     // items per thread in scan-emit kernels
 // Scan-emit kernels over the leaves on the critical path (adapt, balance
-// refinement, the split transfer's lists) run 1024-thread tiles of 8192
-// items: ~1.6M leaves are 200 tiles, and the look-back of the last one crosses
-// about 4 windows of 64 predecessors (each window one round trip to
-// device-coherent memory) instead of 13.  Short scans (transfer groups) and
-// scans that run beside the copy pass (connectivity rows, which would wait for
-// a whole free CU) keep 256-thread tiles of 2048 items.
+// refinement) run 1024-thread tiles of 8192 items: ~1.6M leaves are 200
+// tiles, and the look-back of the last one crosses about 4 windows of 64
+// predecessors (each window one round trip to device-coherent memory) instead
+// of 13.  Short scans (transfer groups) and scans that may run beside another
+// stream's kernels (connectivity rows, the split transfer's lists), where a
+// 1024-thread workgroup would wait for a whole free CU, keep 256-thread tiles
+// of 2048 items.
 constexpr int kScanBig = 1024;
 constexpr int kScanSmall = kBlock;
 constexpr int64_t kTileMax = int64_t(kScanBig) * kItems;
