@@ -59,12 +59,14 @@ __global__ void k_clear_scan(uint64_t* status, int64_t ntiles, DevCtr* ctr, int 
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < ntiles) status[i] = 0;
   if (i == 0) {
-    if (clear_list) ctr->nexam = 0;
+    if (clear_list) {  // the lists adapt and balance refinement build for the next pass
+      ctr->nexam = 0;
+      ctr->nfused = 0;
+    }
     if (converge && ctr->nmarked == 0) ctr->conv = 1;
     ctr->ticket = 0;
     ctr->total = 0;
     ctr->nmarked = 0;
-    ctr->nfused = 0;
     ctr->nfgroups = 0;
     if (clear_err) ctr->err = 0;
   }
@@ -151,7 +153,8 @@ __global__ __launch_bounds__(kScanBig) void k_adapt(KeyGeom g, const uint64_t* _
                                                   const int8_t* __restrict__ flags,
                                                   uint64_t* __restrict__ out, int64_t cap,
                                                   ScanState st, uint32_t* __restrict__ marks,
-                                                  int32_t* __restrict__ elist, int64_t* nexam) {
+                                                  int32_t* __restrict__ elist, int64_t* nexam,
+                                                  int32_t* __restrict__ flist, int64_t* nflist) {
   const int64_t tile = take_ticket(st);
   if (tile >= scan_tiles(st)) return;
   const int64_t n = st.items.get();
@@ -199,10 +202,15 @@ __global__ __launch_bounds__(kScanBig) void k_adapt(KeyGeom g, const uint64_t* _
     local += a == 1 ? nc : (a == 3 ? 0 : 1);
   }
   // the new children go on the list of leaves the first balance pass examines
-  int64_t ex = 0;
+  int64_t ex = 0, fx = 0;
 #pragma unroll
-  for (int k = 0; k < kItems; ++k) ex += act[k] == 1 ? nc : 0;
+  for (int k = 0; k < kItems; ++k) {
+    ex += act[k] == 1 ? nc : 0;
+    fx += act[k] == 2 ? 1 : 0;
+  }
   int64_t eo = elist ? wave_append(ex, nexam) : 0;
+  // the fused parents go on the list the first balance pass probes around
+  int64_t fo = flist ? wave_append(fx, nflist) : 0;
   int64_t blk;
   const int64_t thr = block_exclusive<kScanBig>(local, &blk);
   int64_t o = tile_prefix(st, tile, blk) + thr;
@@ -215,6 +223,7 @@ __global__ __launch_bounds__(kScanBig) void k_adapt(KeyGeom g, const uint64_t* _
       err |= ERR_CAPACITY;
       if (elist && a == 1)
         for (int c = 0; c < nc; ++c) elist[eo++] = -1;
+      if (flist && a == 2) flist[fo++] = -1;
       o += cnt;
       continue;
     }
@@ -226,6 +235,7 @@ __global__ __launch_bounds__(kScanBig) void k_adapt(KeyGeom g, const uint64_t* _
     } else if (a == 2) {
       out[o] = make_key(g, key_m(g, kk), d - 1);
       if (marks) marks[o] = kMarkFused;
+      if (flist) flist[fo++] = int32_t(o);
     } else {
       const uint64_t m = key_m(g, kk);
       for (int c = 0; c < nc; ++c) {
@@ -314,27 +324,10 @@ __global__ __launch_bounds__(kBlock) void k_balance_mark(KeyGeom g, const uint64
 // 2:1 balance after adaptation, fused parents.  A parent P (depth D) that
 // replaced 2^dim balanced leaves can touch leaves of depth D+2 (never deeper,
 // never coarser than D-1 -- the leaves it replaced were balanced); those sit
-// in the shell of depth-(D+2) cells around P.  First the fused parents are
-// listed (any order), then one lane per (parent, shell cell) -- per the
+// in the shell of depth-(D+2) cells around P.  Adapt lists the fused parents
+// (any order, count ctr->nfused); one lane per (parent, shell cell) -- per the
 // balance kind, cells across faces only, or also edges, or also corners --
 // probes its cell and marks P for splitting on a depth-(D+2) leaf.
-__global__ __launch_bounds__(kBlock) void k_fused_list(Count cn, const uint32_t* __restrict__ mark,
-                                                       int32_t* __restrict__ list, DevCtr* ctr) {
-  const int64_t n = cn.get();
-  const int lane = threadIdx.x & 63;
-  for (int64_t wb = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63); wb < n;
-       wb += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t i = wb + lane;
-    const bool f = i < n && (mark[i] & kMarkFused);
-    const uint64_t b = __ballot(f);
-    if (!b) continue;
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(&ctr->nfused, (unsigned long long)__popcll(b));
-    base = __shfl(base, 0);
-    if (f) list[base + __popcll(b & ((uint64_t(1) << lane) - 1))] = int32_t(i);
-  }
-}
-
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_fused_probe(KeyGeom g, const uint64_t* __restrict__ keys,
                                                         Count cn, KeyDir D,
@@ -374,10 +367,8 @@ __global__ __launch_bounds__(kBlock) void k_fused_probe(KeyGeom g, const uint64_
 
 // The fused-parent check of the first balance pass after adaptation.
 hipError_t launch_fused_check(const KeyGeom& g, const uint64_t* keys, Count cn, const KeyDir& D,
-                              uint32_t* mark, int32_t* list, DevCtr* ctr, hipStream_t s) {
+                              uint32_t* mark, const int32_t* list, DevCtr* ctr, hipStream_t s) {
   constexpr int64_t kGrid = 2048;
-  const unsigned lb = unsigned(std::max<int64_t>(1, std::min<int64_t>(ceil_div(cn.n, kBlock), kGrid)));
-  k_fused_list<<<lb, kBlock, 0, s>>>(cn, mark, list, ctr);
   if (g.dim == 3)
     k_fused_probe<3><<<unsigned(kGrid), kBlock, 0, s>>>(g, keys, cn, D, list, mark, ctr);
   else
@@ -913,7 +904,7 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
   st.commit = &S[0];
   st.commit_cap = C;
   k_adapt<<<grid_tiles(st), kScanBig, 0, s>>>(g, K0, F, K[0], C, st, t->mbuf[0], t->elist,
-                                              &t->dctr->nexam);
+                                              &t->dctr->nexam, t->fused, &t->dctr->nfused);
   LT_HIP(hipGetLastError());
   // balance: fixed passes, then a check
   // (the tree entering the cycle is balanced, so adapt's marks restrict the
@@ -922,7 +913,8 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
   int ki = 0, mi = 0;
   for (int pass = 0; pass <= r.passes; ++pass) {
     k_build_dir<<<nleaf, 256, 0, s>>>(K[ki], Count{C, &S[0]}, r.dir_shift, r.dir_nb, t->dir, conv);
-    if (pass == 0) LT_HIP(launch_fused_check(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi], t->fused, t->dctr, s));
+    if (pass == 0)
+      LT_HIP(launch_fused_check(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi], t->fused, t->dctr, s));
     const unsigned mgrid = unsigned(std::min<int64_t>(nlanes, kMarkGrid));
     if (g.dim == 3)
       k_balance_mark<3><<<mgrid, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi], 0,
@@ -1174,13 +1166,15 @@ lt_status lt_adapt(lt_tree t, const int8_t* flags, void* stream) {
   if (marks) {
     LT_TRY(grow(&t->mbuf[0], &t->mcap[0], need));
     LT_TRY(grow(&t->elist, &t->elist_cap, need));
-    cap = std::min(cap, std::min(t->mcap[0], t->elist_cap));
+    LT_TRY(grow(&t->fused, &t->fused_cap, need));
+    cap = std::min(cap, std::min(t->mcap[0], std::min(t->elist_cap, t->fused_cap)));
   }
   ScanState st;
   LT_TRY(prep_scan(t, n, kTileMax, s, 1 | 4, &st));
   k_adapt<<<grid_tiles(st), kScanBig, 0, s>>>(t->g, t->kbuf[t->cur], flags, t->kbuf[out], cap, st,
                                               marks ? t->mbuf[0] : nullptr,
-                                              marks ? t->elist : nullptr, &t->dctr->nexam);
+                                              marks ? t->elist : nullptr, &t->dctr->nexam,
+                                              marks ? t->fused : nullptr, &t->dctr->nfused);
   LT_HIP(hipGetLastError());
   LT_TRY(read_ctr(t, s));
   if (t->hctr->err & ERR_BAD_FLAG) return fail(LT_ERR_ARG, "flags must be -1, 0 or 1");
@@ -1214,7 +1208,11 @@ lt_status lt_balance(lt_tree t, void* stream) {
     k_fill_u32<<<unsigned(ceil_div(t->n_cur, 256)), 256, 0, s>>>(t->mbuf[mi], t->n_cur, 0u);
     LT_HIP(hipGetLastError());
   }
-  LT_TRY(clear_err(t, s));
+  // Right after a successful adapt the error word, the mark count and the
+  // fused-parent count are already zero (adapt's scan preparation cleared
+  // them and adapt read the error word back), and the examine list must
+  // survive: only other entries need the counters cleared.
+  if (!restricted) LT_TRY(clear_err(t, s));
   const int max_pass = 4 * t->g.dmax + 16;
   int64_t expect_total = -1;
   for (int pass = 0;; ++pass) {
@@ -1229,10 +1227,8 @@ lt_status lt_balance(lt_tree t, void* stream) {
       const unsigned blocks = unsigned(all ? full : std::min<int64_t>(full, kMarkGrid));
       const int32_t* el = all ? nullptr : t->elist;
       const Count cn{t->n_cur, nullptr};
-      if (pass == 0 && restricted) {
-        LT_TRY(grow(&t->fused, &t->fused_cap, t->n_cur));
+      if (pass == 0 && restricted)  // adapt listed the fused parents (the list is sized for its output)
         LT_HIP(launch_fused_check(t->g, t->kbuf[t->cur], cn, D, t->mbuf[mi], t->fused, t->dctr, s));
-      }
       if (t->g.dim == 3)
         k_balance_mark<3><<<blocks, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], cn, D, t->mbuf[mi], all,
                                                     t->dctr, nullptr, el);

@@ -19,7 +19,7 @@ struct DevCtr {
   int64_t total;
   unsigned long long nmarked;
   unsigned long long ticket;
-  unsigned long long nfused;  // fused parents listed for the first balance pass
+  int64_t nfused;             // fused parents listed for the first balance pass
   int64_t nfgroups;           // transfer groups holding a fused element (second list)
   int64_t nexam;              // balance: leaves listed for the next marking pass
 };
