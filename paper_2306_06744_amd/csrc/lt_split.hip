@@ -288,32 +288,40 @@ __global__ __launch_bounds__(64 * NC) void k_split_fuse(
     }
     __syncthreads();
     const int32_t sp = s_src[col];
-    bf16x8 b[3][kKS];
+    const bool live = sp >= 0;
+    // Rows 8*grp + 32*ks + t of child c.  A padding column (sp < 0) reads
+    // column c instead and discards it: a tile exists only when some parent
+    // fuses, so the old mesh holds at least 2^d elements.  The per-row offsets
+    // are wave-uniform, and one lane address per tile keeps the split
+    // operator (96 registers) and the values in registers without scratch.
+    const double* Ucol = U + int64_t(8 * grp) * ldo + (live ? sp : 0) + c;
     double mpart = 0.0;
-#pragma unroll
-    for (int ks = 0; ks < kKS; ++ks)
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int k = ks * 32 + 8 * grp + t;
-        const double x = sp >= 0 ? U[int64_t(k) * ldo + sp + c] : 0.0;
-        mpart += Wn[k] * x;
-        __bf16 x0, x1, x2;
-        split3(x, x0, x1, x2);
-        b[0][ks][t] = x0;
-        b[1][ks][t] = x1;
-        b[2][ks][t] = x2;
-      }
-    mpart += __shfl_xor(mpart, 16, 64);
-    mpart += __shfl_xor(mpart, 32, 64);
-    if (grp == 0) Mc[c][col] = mpart;
     f32x4 acc[kMT];
 #pragma unroll
     for (int mt = 0; mt < kMT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < kKS; ++ks)
+    for (int ks = 0; ks < kKS; ++ks) {
+      bf16x8 b0, b1, b2;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int k = ks * 32 + 8 * grp + t;
+        const double xr = Ucol[int64_t(ks * 32 + t) * ldo];
+        const double x = live ? xr : 0.0;
+        mpart += Wn[k] * x;
+        __bf16 x0, x1, x2;
+        split3(x, x0, x1, x2);
+        b0[t] = x0;
+        b1[t] = x1;
+        b2[t] = x2;
+      }
 #pragma unroll
       for (int mt = 0; mt < kMT; ++mt)
-        acc[mt] = mma6(a[0][mt][ks], a[1][mt][ks], a[2][mt][ks], b[0][ks], b[1][ks], b[2][ks], acc[mt]);
+        acc[mt] = mma6(a[0][mt][ks], a[1][mt][ks], a[2][mt][ks], b0, b1, b2, acc[mt]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    mpart += __shfl_xor(mpart, 16, 64);
+    mpart += __shfl_xor(mpart, 32, 64);
+    if (grp == 0) Mc[c][col] = mpart;
 #pragma unroll
     for (int mt = 0; mt < kMT; ++mt)
 #pragma unroll
