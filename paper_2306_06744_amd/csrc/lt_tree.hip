@@ -149,12 +149,20 @@ constexpr uint32_t kMarkExamine = 4u;
 constexpr int64_t kMarkGrid = 2048;
 constexpr uint32_t kMarkFused = 16u;
 
+// An append to a device-side list.  A captured cycle whose output outgrows
+// its capacity keeps running (the host discards the result), so appends past
+// the list's capacity are dropped rather than written.
+__device__ inline void list_put(int32_t* __restrict__ l, int64_t i, int64_t cap, int32_t v) {
+  if (i < cap) l[i] = v;
+}
+
 __global__ __launch_bounds__(kScanBig) void k_adapt(KeyGeom g, const uint64_t* __restrict__ in,
                                                   const int8_t* __restrict__ flags,
                                                   uint64_t* __restrict__ out, int64_t cap,
                                                   ScanState st, uint32_t* __restrict__ marks,
                                                   int32_t* __restrict__ elist, int64_t* nexam,
-                                                  int32_t* __restrict__ flist, int64_t* nflist) {
+                                                  int64_t ecap, int32_t* __restrict__ flist,
+                                                  int64_t* nflist, int64_t fcap) {
   const int64_t tile = take_ticket(st);
   if (tile >= scan_tiles(st)) return;
   const int64_t n = st.items.get();
@@ -221,9 +229,15 @@ __global__ __launch_bounds__(kScanBig) void k_adapt(KeyGeom g, const uint64_t* _
     const int cnt = a == 1 ? nc : 1;
     if (o + cnt > cap) {
       err |= ERR_CAPACITY;
+      // the slots below the capacity still get a valid key: the kernels after
+      // this one in a captured cycle read them before the result is discarded
+      for (int64_t q = o; q < cap && q < o + cnt; ++q) {
+        out[q] = key[k];
+        if (marks) marks[q] = 0u;
+      }
       if (elist && a == 1)
-        for (int c = 0; c < nc; ++c) elist[eo++] = -1;
-      if (flist && a == 2) flist[fo++] = -1;
+        for (int c = 0; c < nc; ++c) list_put(elist, eo++, ecap, -1);
+      if (flist && a == 2) list_put(flist, fo++, fcap, -1);
       o += cnt;
       continue;
     }
@@ -235,13 +249,13 @@ __global__ __launch_bounds__(kScanBig) void k_adapt(KeyGeom g, const uint64_t* _
     } else if (a == 2) {
       out[o] = make_key(g, key_m(g, kk), d - 1);
       if (marks) marks[o] = kMarkFused;
-      if (flist) flist[fo++] = int32_t(o);
+      if (flist) list_put(flist, fo++, fcap, int32_t(o));
     } else {
       const uint64_t m = key_m(g, kk);
       for (int c = 0; c < nc; ++c) {
         out[o + c] = child_key(g, m, d, c);
         if (marks) marks[o + c] = kMarkExamine;
-        if (elist) elist[eo++] = int32_t(o + c);
+        if (elist) list_put(elist, eo++, ecap, int32_t(o + c));
       }
     }
     o += cnt;
@@ -261,7 +275,8 @@ __global__ __launch_bounds__(kBlock) void k_balance_mark(KeyGeom g, const uint64
                                                          Count cn, KeyDir D, uint32_t* mark,
                                                          int check_all, DevCtr* ctr,
                                                          const unsigned* conv,
-                                                         const int32_t* __restrict__ elist) {
+                                                         const int32_t* __restrict__ elist,
+                                                         int64_t ecap) {
   // 2^DIM lanes per leaf, lane `sub` (1 .. 2^DIM - 1) probes one searching key;
   // waves stride over the (leaf, sub) pairs: every leaf (check_all), or the
   // listed leaves (elist: ctr->nexam entries, the leaves holding bit 2).
@@ -270,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_balance_mark(KeyGeom g, const uint64
   if (conv && *conv) return;
   constexpr int SL = 1 << DIM;
   const int64_t n = cn.get();
-  const int64_t items = elist ? ctr->nexam : n;
+  const int64_t items = elist ? min(ctr->nexam, ecap) : n;
   const int64_t lanes = items * SL;
   const int lane = threadIdx.x & 63;
   const int limit = g.balance == 0 ? 1 : (g.balance == 1 ? 2 : 3);
@@ -422,7 +437,8 @@ __global__ __launch_bounds__(kScanBig) void k_balance_refine(KeyGeom g, const ui
                                                            uint64_t* __restrict__ out,
                                                            uint32_t* __restrict__ mark_out, int64_t cap,
                                                            ScanState st, const unsigned* conv,
-                                                           int32_t* __restrict__ elist, int64_t* nexam) {
+                                                           int32_t* __restrict__ elist, int64_t* nexam,
+                                                           int64_t ecap) {
   if (conv && *conv) {
     // captured cycles past the fixpoint: the pass is the identity, a plain copy
     const int64_t n = st.items.get();
@@ -472,7 +488,11 @@ __global__ __launch_bounds__(kScanBig) void k_balance_refine(KeyGeom g, const ui
     const int nex = (w[k] & 1u) ? nc : ((w[k] & 2u) ? 1 : 0);
     if (o + cnt > cap) {
       err |= ERR_CAPACITY;
-      for (int c = 0; c < nex; ++c) elist[eo++] = -1;
+      for (int64_t q = o; q < cap && q < o + cnt; ++q) {  // valid keys below the capacity
+        out[q] = kk;
+        mark_out[q] = 0u;
+      }
+      for (int c = 0; c < nex; ++c) list_put(elist, eo++, ecap, -1);
       o += cnt;
       continue;
     }
@@ -482,12 +502,12 @@ __global__ __launch_bounds__(kScanBig) void k_balance_refine(KeyGeom g, const ui
       for (int c = 0; c < nc; ++c) {
         out[o + c] = child_key(g, m, d, c);
         mark_out[o + c] = 4u;
-        elist[eo++] = int32_t(o + c);
+        list_put(elist, eo++, ecap, int32_t(o + c));
       }
     } else {
       out[o] = kk;
       mark_out[o] = (w[k] & 2u) ? 4u : 0u;
-      if (w[k] & 2u) elist[eo++] = int32_t(o);
+      if (w[k] & 2u) list_put(elist, eo++, ecap, int32_t(o));
     }
     o += cnt;
   }
@@ -904,7 +924,8 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
   st.commit = &S[0];
   st.commit_cap = C;
   k_adapt<<<grid_tiles(st), kScanBig, 0, s>>>(g, K0, F, K[0], C, st, t->mbuf[0], t->elist,
-                                              &t->dctr->nexam, t->fused, &t->dctr->nfused);
+                                              &t->dctr->nexam, t->elist_cap, t->fused,
+                                              &t->dctr->nfused, t->fused_cap);
   LT_HIP(hipGetLastError());
   // balance: fixed passes, then a check
   // (the tree entering the cycle is balanced, so adapt's marks restrict the
@@ -918,10 +939,10 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
     const unsigned mgrid = unsigned(std::min<int64_t>(nlanes, kMarkGrid));
     if (g.dim == 3)
       k_balance_mark<3><<<mgrid, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi], 0,
-                                                 t->dctr, conv, t->elist);
+                                                 t->dctr, conv, t->elist, t->elist_cap);
     else
       k_balance_mark<2><<<mgrid, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi], 0,
-                                                 t->dctr, conv, t->elist);
+                                                 t->dctr, conv, t->elist, t->elist_cap);
     if (pass == r.passes) break;
     LT_TRY(prep_scan(t, C, kTileMax, s, 2 | 4, &st));  // also records convergence
     st.items.p = &S[0];
@@ -929,7 +950,7 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
     st.commit_cap = C;
     k_balance_refine<<<grid_tiles(st), kScanBig, 0, s>>>(g, K[ki], t->mbuf[mi], K[1 - ki],
                                                         t->mbuf[1 - mi], C, st, conv, t->elist,
-                                                        &t->dctr->nexam);
+                                                        &t->dctr->nexam, t->elist_cap);
     ki = 1 - ki;
     mi = 1 - mi;
   }
@@ -1174,7 +1195,8 @@ lt_status lt_adapt(lt_tree t, const int8_t* flags, void* stream) {
   k_adapt<<<grid_tiles(st), kScanBig, 0, s>>>(t->g, t->kbuf[t->cur], flags, t->kbuf[out], cap, st,
                                               marks ? t->mbuf[0] : nullptr,
                                               marks ? t->elist : nullptr, &t->dctr->nexam,
-                                              marks ? t->fused : nullptr, &t->dctr->nfused);
+                                              t->elist_cap, marks ? t->fused : nullptr,
+                                              &t->dctr->nfused, t->fused_cap);
   LT_HIP(hipGetLastError());
   LT_TRY(read_ctr(t, s));
   if (t->hctr->err & ERR_BAD_FLAG) return fail(LT_ERR_ARG, "flags must be -1, 0 or 1");
@@ -1231,10 +1253,10 @@ lt_status lt_balance(lt_tree t, void* stream) {
         LT_HIP(launch_fused_check(t->g, t->kbuf[t->cur], cn, D, t->mbuf[mi], t->fused, t->dctr, s));
       if (t->g.dim == 3)
         k_balance_mark<3><<<blocks, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], cn, D, t->mbuf[mi], all,
-                                                    t->dctr, nullptr, el);
+                                                    t->dctr, nullptr, el, t->elist_cap);
       else
         k_balance_mark<2><<<blocks, kBlock, 0, s>>>(t->g, t->kbuf[t->cur], cn, D, t->mbuf[mi], all,
-                                                    t->dctr, nullptr, el);
+                                                    t->dctr, nullptr, el, t->elist_cap);
       LT_HIP(hipGetLastError());
     }
     LT_TRY(read_ctr(t, s));
@@ -1253,7 +1275,8 @@ lt_status lt_balance(lt_tree t, void* stream) {
     const int64_t cap = std::min(std::min(t->kcap[t->tmp], t->mcap[1 - mi]), t->elist_cap);
     k_balance_refine<<<grid_tiles(st), kScanBig, 0, s>>>(t->g, t->kbuf[t->cur], t->mbuf[mi],
                                                         t->kbuf[t->tmp], t->mbuf[1 - mi], cap, st,
-                                                        nullptr, t->elist, &t->dctr->nexam);
+                                                        nullptr, t->elist, &t->dctr->nexam,
+                                                        t->elist_cap);
     LT_HIP(hipGetLastError());
     expect_total = n_new;
     std::swap(t->cur, t->tmp);

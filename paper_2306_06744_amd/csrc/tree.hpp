@@ -113,13 +113,14 @@ namespace lt {
 
 // Zero the look-back words for n_items of scan work in tiles of `tile`
 // items (kTileMax or kTileMin, matching the kernel's workgroup) and the
-// counters (and the error word if clear_err); fills st for a scan kernel on
-// `stream`.
-lt_status prep_scan(lt_tree_s* t, int64_t n_items, int64_t tile, hipStream_t stream, int clear_err,
+// counters; fills st for a scan kernel on `stream`.  flags: 1 = also clear
+// the error word, 2 = record the balance fixpoint (no marks since the last
+// clear; captured cycles), 4 = also clear the lists.
+lt_status prep_scan(lt_tree_s* t, int64_t n_items, int64_t tile, hipStream_t stream, int flags,
                     ScanState* st);
 // The same on connectivity's own look-back words and counters, so that
 // lt_connect may run beside lt_map and lt_transfer on another stream.
-lt_status prep_scan_conn(lt_tree_s* t, int64_t n_items, hipStream_t stream, int clear_err,
+lt_status prep_scan_conn(lt_tree_s* t, int64_t n_items, hipStream_t stream, int flags,
                          ScanState* st);
 // Copy the device counters to the pinned mirror and wait for the stream.
 lt_status read_ctr(lt_tree_s* t, hipStream_t stream);

@@ -94,6 +94,42 @@ def test_captured_cycle_capacity_error_leaves_tree_unchanged():
     del cyc
 
 
+def test_captured_cycle_balance_overflow_leaves_tree_unchanged():
+    # capacity above adapt's output but below the balanced tree: the overflow
+    # comes from a balance refinement pass, whose list appends and partial
+    # output must stay within the reserved buffers; the tree stays usable
+    import torch
+    import paper_2306_06744_amd as lt
+    w = synth.workload_3d_extruded(2007)
+    nodes = synth.gl_nodes01(w.p)
+    E = lt.Tree.uniform(3, w.d_min, w.d_max)
+    G = lt.Tree.uniform(3, w.d_min, w.d_max)
+    for t in (E, G):
+        t.adapt(t.flag(**flag_args(w, 0, nodes)))
+        t.balance()
+    n0 = G.size()
+    keys0 = G.keys().cpu().numpy().copy()
+    fa = flag_args(w, 1, nodes)
+    E.adapt(E.flag(**fa))
+    n_adapt = E.size()
+    E.balance()
+    n_bal = E.size()
+    assert n_bal > n_adapt > n0, (n0, n_adapt, n_bal)
+    cap = (n_adapt + n_bal) // 2
+    print("balance overflow case: n0", n0, "adapt", n_adapt, "balanced", n_bal, "cap", cap, flush=True)
+    u = [torch.zeros((w.nvar, 64, cap), dtype=torch.float64, device="cuda") for _ in range(2)]
+    cyc = lt.Cycle(G, w.p, w.nvar, cap, u, fa)
+    with pytest.raises(lt.LtError) as ei:
+        cyc.run(fa)
+    assert ei.value.status == 9
+    del cyc
+    assert G.size() == n0
+    assert np.array_equal(G.keys().cpu().numpy(), keys0)
+    G.adapt(G.flag(**fa))
+    G.balance()
+    assert np.array_equal(G.keys().cpu().numpy(), E.keys().cpu().numpy())
+
+
 def test_captured_ensemble_cycle_matches_eager():
     import torch
     import paper_2306_06744_amd as lt
