@@ -30,6 +30,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# Workgroups of the face-connectivity search where it runs on a second stream
+# beside the transfer (one per compute unit): the search is latency-bound and
+# still ends first, and the transfer keeps the other wave slots.
+CONN_GRID = 256
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -174,6 +179,7 @@ def chosen_cycle(lt, torch, synth, w, nodes, stream, steps, warmup, u, cap, E, t
     # warm-up cycles eagerly (learned flags, split transfer), then the whole
     # cycle captured once in a hipGraph for the timed cycles
     t = lt.Tree.uniform(w.dim, w.d_min, w.d_max)
+    t.set_connect_grid(CONN_GRID)
     cur = 0
 
     def fa(c):
@@ -286,6 +292,7 @@ def graph_cycle(lt, torch, synth, w, nodes, stream, steps, warmup, u, cap, E, pa
     cycles eagerly, then the graph is created at the current tree and replayed
     for the timed cycles (one host synchronisation per cycle)."""
     t = lt.Tree.uniform(w.dim, w.d_min, w.d_max)
+    t.set_connect_grid(CONN_GRID)
     g = torch.Generator(device="cuda")
     g.manual_seed(2000)
     cur = 0
@@ -460,6 +467,7 @@ def main():
         """Warm-up cycles, then the timed cycles; returns sizes, wall time and
         the transfer's event times."""
         t = lt.Tree.uniform(w.dim, w.d_min, w.d_max)
+        t.set_connect_grid(CONN_GRID)
         g = torch.Generator(device="cuda")
         g.manual_seed(args.seed)
         u[0][:, :, : t.size()].normal_(generator=g)

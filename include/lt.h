@@ -168,6 +168,16 @@ lt_status lt_balance(lt_tree t, void* stream);
  * lt_map / lt_transfer issued on another stream. */
 lt_status lt_connect(lt_tree t, void* stream);
 
+/* Caps the workgroups (256 lanes each) of lt_connect's face search, which
+ * strides over its lanes: 0, the default, launches one lane per face.  The
+ * search is bound by the latency of its key lookups.  Issued on a second
+ * stream beside lt_map and lt_transfer, a small grid (256 workgroups on
+ * MI355X, one per compute unit) leaves the other wave slots to the
+ * bandwidth-bound transfer, which then runs faster while the search still ends
+ * first; alone, the search takes longer with a cap.  Applies to later
+ * lt_connect calls and to cycles captured later.  LT_ERR_ARG if negative. */
+lt_status lt_set_connect_grid(lt_tree t, int blocks);
+
 /* Old->new mapping (Section 4.2, mapping algorithm): for each current leaf j,
  *   map_kind[j] = 0      map_src[j] = old index of the same octant (copy),
  *   map_kind[j] = 1 + c  map_src[j] = old index of its parent (refined, child c),

@@ -24,7 +24,8 @@ STATUS = {0: "LT_OK", 1: "LT_ERR_ARG", 2: "LT_ERR_OOM", 3: "LT_ERR_HIP", 4: "LT_
 
 # Every symbol include/lt.h declares.
 EXPORTS = ["lt_build_uniform", "lt_build", "lt_build_batch", "lt_flag_batch", "lt_mesh_offsets",
-           "lt_flag", "lt_adapt", "lt_balance", "lt_connect", "lt_map", "lt_transfer", "lt_size",
+           "lt_flag", "lt_adapt", "lt_balance", "lt_connect", "lt_set_connect_grid", "lt_map",
+           "lt_transfer", "lt_size",
            "lt_view", "lt_export", "lt_mlp_create", "lt_mlp_params", "lt_mlp_features",
            "lt_mlp_grads", "lt_mlp_train_step", "lt_mlp_infer", "lt_flag_mlp", "lt_vortex_field",
            "lt_flag_modal", "lt_mlp_destroy", "lt_cycle_create", "lt_cycle_run",
@@ -84,6 +85,7 @@ def lib() -> C.CDLL:
         L.lt_adapt.argtypes = [P, P, P]
         L.lt_balance.argtypes = [P, P]
         L.lt_connect.argtypes = [P, P]
+        L.lt_set_connect_grid.argtypes = [P, i32]
         L.lt_map.argtypes = [P, P]
         L.lt_transfer.argtypes = [P, i32, i32, P, i64, P, i64, i32, P]
         L.lt_size.argtypes = [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
@@ -298,6 +300,10 @@ class Tree:
 
     def connect(self):
         _check(lib().lt_connect(self._h, _stream()))
+
+    def set_connect_grid(self, blocks):
+        """Cap the face search's workgroups (0: one lane per face); see lt.h."""
+        _check(lib().lt_set_connect_grid(self._h, int(blocks)))
 
     def map(self):
         _check(lib().lt_map(self._h, _stream()))

@@ -968,10 +968,11 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
   hipStream_t cs = r.side;
   LT_HIP(hipEventRecord(r.fork, s));
   LT_HIP(hipStreamWaitEvent(cs, r.fork, 0));
+  const unsigned cgrid = t->conn_grid > 0 ? std::min<unsigned>(nlanes, unsigned(t->conn_grid)) : nlanes;
   if (g.dim == 3)
-    k_connect_faces<3><<<nlanes, 256, 0, cs>>>(g, K[0], Count{C, &S[0]}, D, t->nbr, t->hmask);
+    k_connect_faces<3><<<cgrid, 256, 0, cs>>>(g, K[0], Count{C, &S[0]}, D, t->nbr, t->hmask);
   else
-    k_connect_faces<2><<<nlanes, 256, 0, cs>>>(g, K[0], Count{C, &S[0]}, D, t->nbr, t->hmask);
+    k_connect_faces<2><<<cgrid, 256, 0, cs>>>(g, K[0], Count{C, &S[0]}, D, t->nbr, t->hmask);
   ScanState cst;
   LT_TRY(prep_scan_conn(t, C, cs, 1, &cst));
   cst.items.p = &S[0];
@@ -1302,7 +1303,8 @@ lt_status lt_connect(lt_tree t, void* stream) {
   KeyDir D;
   LT_TRY(ensure_dir(t, s, &D));
   if (n > 0) {
-    const unsigned blocks = unsigned(ceil_div(n * t->g.nchild(), 256));
+    const int64_t lanes = ceil_div(n * t->g.nchild(), 256);
+    const unsigned blocks = unsigned(t->conn_grid > 0 ? std::min<int64_t>(lanes, t->conn_grid) : lanes);
     if (t->g.dim == 3)
       k_connect_faces<3><<<blocks, 256, 0, s>>>(t->g, t->kbuf[t->cur], Count{n, nullptr}, D, t->nbr,
                                                 t->hmask);
@@ -1337,6 +1339,13 @@ lt_status lt_connect(lt_tree t, void* stream) {
   if (rows < 0) return fail(LT_ERR_INTERNAL, "hanging-face table overflowed twice");
   t->n_hang = rows;
   t->conn_valid = true;
+  return LT_OK;
+}
+
+lt_status lt_set_connect_grid(lt_tree t, int blocks) {
+  if (!t) return fail(LT_ERR_ARG, "NULL tree");
+  if (blocks < 0) return fail(LT_ERR_ARG, "the connectivity grid cap must be >= 0");
+  t->conn_grid = blocks;
   return LT_OK;
 }
 

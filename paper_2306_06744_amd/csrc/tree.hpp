@@ -180,6 +180,7 @@ struct lt_tree_s {
   bool has_old = false;
   bool balanced = false;     // the current leaves are known to be 2:1 balanced
   bool adapt_marks = false;  // mbuf[0] holds adapt's marks for the first balance pass
+  int conn_grid = 0;         // cap on the face search's workgroups (0: one lane per face)
 
   uint32_t* mbuf[2] = {nullptr, nullptr};  // balance marks, ping-pong
   int64_t mcap[2] = {0, 0};

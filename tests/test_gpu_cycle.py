@@ -49,6 +49,8 @@ def test_captured_cycle_matches_eager(case, passes):
     npts = (w.p + 1) ** w.dim
     E = lt.Tree.uniform(w.dim, w.d_min, w.d_max)
     G = lt.Tree.uniform(w.dim, w.d_min, w.d_max)
+    if passes == 2:
+        G.set_connect_grid(256)  # the captured face search with a capped grid
     for c in range(warm):
         for t in (E, G):
             t.adapt(t.flag(**flag_args(w, c, nodes)))

@@ -145,10 +145,15 @@ def test_cycle_connect_map_transfer(dim, dmax, periodic):
 def test_connect_on_side_stream_beside_transfer(dim, dmax):
     """lt_connect on a second stream while lt_transfer runs on the first (the
     two use separate scratch): connectivity, mapping bit-exact and the
-    transfer within the bar, cycle after cycle."""
+    transfer within the bar, cycle after cycle, each cycle with another cap
+    on the face search's grid (the search strides over its lanes)."""
     import torch
+    import paper_2306_06744_amd as lt
     say("side stream", dim, dmax)
     g, o = both(dim, 2, dmax)
+    with pytest.raises(lt.LtError) as ei:
+        g.set_connect_grid(-1)
+    assert ei.value.status == 1
     side = torch.cuda.Stream()
     p = 3 if dim == 3 else 2
     nvar = 5 if dim == 3 else 4
@@ -160,6 +165,7 @@ def test_connect_on_side_stream_beside_transfer(dim, dmax):
         g.map()
         u_old = synth.random_solution(400 + c, nvar, (p + 1) ** dim, o.old_size())
         ug = g.transfer(p, torch.from_numpy(u_old).cuda())
+        g.set_connect_grid((0, 256, 7, 1)[c])
         with torch.cuda.stream(side):  # no wait on the first stream: the two overlap
             g.connect()
         torch.cuda.synchronize()
