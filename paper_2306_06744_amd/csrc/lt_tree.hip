@@ -1297,9 +1297,10 @@ lt_status lt_connect(lt_tree t, void* stream) {
   const int width = 2 + (1 << (t->g.dim - 1));
   LT_TRY(grow(&t->nbr, &t->nbr_cap, n * nf));
   LT_TRY(grow(&t->hmask, &t->hmask_cap, n + kItems));
-  // initial table: one row per 64 leaves (the hanging faces sit on the
-  // refinement fronts, a small fraction of all faces)
-  LT_TRY(grow(&t->hang, &t->hang_cap, std::max<int64_t>(1024, n / 64) * width));
+  // initial table: one row per 16 leaves, as a captured cycle reserves (the
+  // hanging faces sit on the refinement fronts: one per 90 leaves in the
+  // 1.7M-leaf workload, more than one per 64 at 9M leaves)
+  LT_TRY(grow(&t->hang, &t->hang_cap, std::max<int64_t>(1024, n / 16) * width));
   KeyDir D;
   LT_TRY(ensure_dir(t, s, &D));
   if (n > 0) {
@@ -1333,8 +1334,10 @@ lt_status lt_connect(lt_tree t, void* stream) {
     if (t->hcctr->err) return fail(LT_ERR_INTERNAL, "device check failed in lt_connect");
     if (t->hcctr->total <= cap_rows)
       rows = t->hcctr->total;
-    else  // the hanging-face table overflowed: grow it and emit the rows again
-      LT_TRY(grow(&t->hang, &t->hang_cap, t->hcctr->total * width));
+    else  // the hanging-face table overflowed: grow it (with room for the next
+          // cycles: a regrowth frees memory, which waits for the whole device)
+          // and emit the rows again
+      LT_TRY(grow(&t->hang, &t->hang_cap, 2 * t->hcctr->total * width));
   }
   if (rows < 0) return fail(LT_ERR_INTERNAL, "hanging-face table overflowed twice");
   t->n_hang = rows;
