@@ -15,10 +15,15 @@
  *     (lt_build, lt_adapt, lt_balance, lt_connect, lt_map) synchronise the
  *     stream before returning; lt_flag and lt_transfer do not.
  *   - Every call returns an lt_status; no exception crosses the ABI.  The text
- *     of the last error of the calling thread is lt_last_error().
+ *     of the last error of the calling thread is lt_last_error().  On an
+ *     error the tree's leaves, its old tree and its connectivity and mapping
+ *     results are as before the call (strong guarantee), except where a
+ *     declaration below says otherwise.
  *   - Caller-owned buffers (flags, solution arrays, export targets) stay owned
  *     by the caller.  Everything else (keys, the pre-adapt snapshot, nbr, hang,
- *     map arrays, scratch) is owned by the tree and freed by lt_destroy.
+ *     map arrays, scratch) is owned by the tree and freed by lt_destroy; its
+ *     device memory comes from the allocator registered with lt_set_allocator
+ *     when the tree was created (hipMalloc / hipFree if none was).
  *   - A tree is not thread-safe; use one tree per host thread or serialise.
  *     Calls on one tree run one after another in stream order, with a single
  *     exception: lt_connect keeps scratch of its own, so it may run on a
@@ -35,6 +40,7 @@
  */
 #ifndef LT_H
 #define LT_H
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -100,6 +106,18 @@ typedef struct {
   int raw;                /* 1: skip the d_min / d_max clamps (training labels)      */
 } lt_flag_params;
 
+/* Device allocator for the trees, captured cycles and models created after
+ * this call (each keeps the allocator it was created with until it is
+ * destroyed).  alloc(bytes, stream, ctx) returns device memory of the
+ * current device or NULL (the call needing it then fails with LT_ERR_OOM and
+ * leaves its tree as before); free_(ptr, stream, ctx) releases it.  The
+ * library passes stream = NULL and synchronises the device before every
+ * free, so a stream-ordered caching allocator may hand the memory out again
+ * at once.  Both NULL restores hipMalloc / hipFree; one NULL is LT_ERR_ARG.
+ * Process-wide; ctx is passed through untouched. */
+lt_status lt_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ctx),
+                           void (*free_)(void* ptr, void* stream, void* ctx), void* ctx);
+
 /* Uniform tree of all 2^(dim*depth) octants at `depth` (d_min <= depth <= d_max
  * is not required: depth may be below d_min or above it up to d_max).
  * Ownership of *out passes to the caller (release with lt_destroy). */
@@ -110,6 +128,23 @@ lt_status lt_build_uniform(const lt_geom* geom, int depth, void* stream, lt_tree
  * LT_ERR_INVALID_TREE.  Balance is not checked here. */
 lt_status lt_build(const lt_geom* geom, const uint64_t* keys, int64_t n, void* stream,
                    lt_tree* out);
+
+/* Tree built bottom-up from n scattered points (Section 3.1, tree
+ * construction and linearization; Section 5.1: a coarse background at d_min
+ * with the points encoded at d_max).  pts: device FP64 [n][dim], point-major,
+ * in the physical cube [lo, lo+len)^dim (lo: host, dim values).  A point's
+ * finest cell is i_a = floor((x_a - lo[a]) / dx) with dx = len / 2^d_max,
+ * evaluated in FP64 in that order; every cell must lie in [0, 2^d_max)
+ * (LT_ERR_ARG otherwise, also for a NaN coordinate).  The result is the
+ * coarsest complete linear tree whose leaves all have depth >= d_min and in
+ * which every point's finest cell is a leaf (duplicates allowed; n = 0 gives
+ * the uniform tree at d_min).  It is not 2:1 balanced: call lt_balance.
+ * 0 <= n < 2^31 and fewer than 2^31 leaves.  Synchronises the stream; the
+ * temporaries (two sort buffers of n keys, offsets) come from the registered
+ * allocator and are freed before returning.  Ownership of *out passes to the
+ * caller. */
+lt_status lt_build_points(const lt_geom* geom, const double* pts, int64_t n, const double* lo,
+                          double len, void* stream, lt_tree* out);
 
 /* Ensemble of `nmesh` independent trees in one key array, each starting
  * uniform at depth[m] (form 2 of the cycle: every later call -- adapt,
@@ -145,13 +180,16 @@ lt_status lt_flag(lt_tree t, const lt_flag_params* fp, int8_t* flags, void* stre
  * -1 (depth > d_min) is replaced by its parent; every other -1 acts as 0.  No
  * octant changes more than once.  flags: device int8 [n_cur], values -1, 0, 1
  * (others: LT_ERR_ARG detected on the device, tree unchanged).  The keys
- * before the call are kept as the old tree for lt_map / lt_transfer. */
+ * before the call are kept as the old tree for lt_map / lt_transfer (on an
+ * error the previous old tree is kept instead). */
 lt_status lt_adapt(lt_tree t, const int8_t* flags, void* stream);
 
 /* Strong 2:1 balance (Section 3.2): replace the tree by its coarsest
  * refinement in which any two leaves touching across a face (or edge /
  * corner, per geom.balance; periodic axes wrap) differ by at most one level.
- * On error the tree is a valid, possibly partially balanced refinement. */
+ * Every pass writes into a spare key buffer, so on any error (LT_ERR_OOM when
+ * a buffer cannot grow, LT_ERR_HIP, LT_ERR_INTERNAL) the tree is exactly as
+ * before the call. */
 lt_status lt_balance(lt_tree t, void* stream);
 
 /* Face connectivity (Section 3.3).  Face f = 2*axis + side (side 0 = low
@@ -355,11 +393,14 @@ lt_status lt_cycle_create(lt_tree t, const lt_cycle_desc* d, void* stream, lt_cy
  * solution (the other one held it before).  Synchronises once.
  * If the fixed balance passes did not reach the 2:1 fixpoint, the cycle is
  * finished by the eager calls (same result) and the graphs are recaptured
- * when buffers had to grow.  If a size passed the capacity, the tree is
- * restored to its state before the call and LT_ERR_CAPACITY is returned
- * (create a new cycle with a larger capacity); if that happens while
- * finishing eagerly, the tree holds the new leaves but u was not
- * transferred.  Other device check failures give LT_ERR_INTERNAL. */
+ * when buffers had to grow.  If a size passed the capacity inside the graph,
+ * the tree is restored to its state before the call and LT_ERR_CAPACITY is
+ * returned (create a new cycle with a larger capacity).  If finishing
+ * eagerly fails (LT_ERR_CAPACITY when the balanced tree outgrew the
+ * capacity: the tree then holds the new balanced leaves but u was not
+ * transferred; or any error of the eager calls), the cycle drops its graphs
+ * and every later lt_cycle_run returns LT_ERR_STATE without launching
+ * anything; destroy it.  Other device check failures give LT_ERR_INTERNAL. */
 lt_status lt_cycle_run(lt_cycle c, const lt_flag_params* fp, void* stream, int* u_index);
 
 /* Host counters of a cycle: runs, runs whose balance was finished by the

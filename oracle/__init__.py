@@ -45,6 +45,9 @@ def lib():
         L.lto_create.argtypes = [i32, i32, i32, u32, i32, P, i64]
         L.lto_create_uniform.restype = P
         L.lto_create_uniform.argtypes = [i32, i32, i32, u32, i32, i32]
+        L.lto_create_points.restype = P
+        L.lto_create_points.argtypes = [i32, i32, i32, u32, i32, P, i64, P, dbl]
+        L.lto_point_cells.argtypes = [i32, i32, P, i64, P, dbl, P]
         L.lto_destroy.argtypes = [P]
         L.lto_size.restype = i64
         L.lto_size.argtypes = [P]
@@ -133,15 +136,32 @@ def flag_keys(dim, d_min, d_max, keys, centres, r_in, r_out, nodes01, lo, length
     return out
 
 
+def point_cells(dim, d_max, pts, lo, length) -> np.ndarray:
+    """Finest cells (n, dim) of points (n, dim) in [lo, lo+length)^dim."""
+    p = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, dim)
+    lo3 = np.zeros(3)
+    lo3[:dim] = lo
+    out = np.zeros(p.shape, dtype=np.int64)
+    _check(lib().lto_point_cells(dim, d_max, _ptr(p), len(p), _ptr(lo3), float(length), _ptr(out)))
+    return out
+
+
 class Tree:
     """Pointer-tree oracle of one linear tree (host memory)."""
 
     def __init__(self, dim, d_min, d_max, periodic_mask=None, balance=2, keys=None,
-                 start_depth=None):
+                 start_depth=None, points=None, lo=None, length=None):
         if periodic_mask is None:
             periodic_mask = (1 << dim) - 1
         self.dim, self.d_min, self.d_max = dim, d_min, d_max
-        if keys is None:
+        if points is not None:
+            pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, dim)
+            lo3 = np.zeros(3)
+            lo3[:dim] = lo
+            h = lib().lto_create_points(dim, d_min, d_max, periodic_mask, balance,
+                                        _ptr(pts) if len(pts) else None, len(pts), _ptr(lo3),
+                                        float(length))
+        elif keys is None:
             sd = d_min if start_depth is None else start_depth
             h = lib().lto_create_uniform(dim, d_min, d_max, periodic_mask, balance, sd)
         else:

@@ -467,6 +467,52 @@ lto_tree* lto_create_uniform(int dim, int d_min, int d_max, unsigned periodic_ma
   return t;
 }
 
+int lto_point_cells(int dim, int d_max, const double* pts, int64_t n, const double* lo, double len,
+                    int64_t* anchors) {
+  if (dim < 2 || dim > 3 || d_max < 1 || d_max > 21) return fail("bad dim / d_max");
+  if (!(len > 0.0)) return fail("domain length must be positive");
+  const int64_t W = int64_t(1) << d_max;
+  const double dx = len / double(W);
+  for (int64_t j = 0; j < n; ++j)
+    for (int a = 0; a < dim; ++a) {
+      const double f = std::floor((pts[dim * j + a] - lo[a]) / dx);
+      if (!(f >= 0.0 && f < double(W))) return fail("a point lies outside the domain");
+      anchors[dim * j + a] = int64_t(f);
+    }
+  return 0;
+}
+
+// Section 3.1: the points' finest cells are the seeds of the tree; every
+// octant that strictly contains a seed is split, and so is every octant
+// shallower than d_min (the coarse background).  Splitting exactly those
+// octants gives the coarsest complete tree with the seeds as leaves: each
+// split is forced, and no leaf can merge with its siblings without either
+// swallowing a seed or rising above d_min.
+lto_tree* lto_create_points(int dim, int d_min, int d_max, unsigned periodic_mask,
+                            int balance_kind, const double* pts, int64_t n, const double* lo,
+                            double len) {
+  if (n < 0 || (n > 0 && !pts)) { fail("bad point array"); return nullptr; }
+  std::vector<int64_t> anc(size_t(n) * dim);
+  if (n > 0 && lto_point_cells(dim, d_max, pts, n, lo, len, anc.data())) return nullptr;
+  lto_tree* t = lto_create_uniform(dim, d_min, d_max, periodic_mask, balance_kind, d_min);
+  if (!t) return nullptr;
+  for (int64_t j = 0; j < n; ++j) {
+    int64_t p[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) p[a] = anc[size_t(j) * dim + a];
+    Node* nd = t->locate(p);  // the leaf holding the seed
+    while (nd->depth < d_max) {
+      t->split(nd);
+      const int64_t half = t->size_at(nd->depth + 1);
+      int c = 0;
+      for (int a = 0; a < dim; ++a)
+        if (p[a] >= nd->anchor[a] + half) c |= 1 << a;
+      nd = nd->child[c];
+    }
+  }
+  t->relist();
+  return t;
+}
+
 void lto_destroy(lto_tree* t) { delete t; }
 
 int64_t lto_size(const lto_tree* t) { return int64_t(t->leaves.size()); }

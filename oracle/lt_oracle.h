@@ -36,6 +36,22 @@ typedef struct lto_tree_s lto_tree;
  * 1 edge, 2 corner.  Returns NULL on error. */
 lto_tree* lto_create(int dim, int d_min, int d_max, unsigned periodic_mask,
                      int balance_kind, const uint64_t* keys, int64_t n);
+/* Tree built bottom-up from n scattered points (Section 3.1, tree
+ * construction and linearization; Section 5.1: a d_min background with the
+ * points encoded at d_max).  pts[dim*j + a] is coordinate a of point j in the
+ * physical cube [lo, lo+len)^dim; its finest cell is
+ *   i_a = floor((pts[dim*j + a] - lo[a]) / dx),  dx = len / 2^d_max
+ * (FP64, in that order), which must lie in [0, 2^d_max) (else NULL).  The
+ * result is the coarsest complete linear tree whose leaves all have depth
+ * >= d_min and in which every point's finest cell is a leaf.  Not balanced. */
+lto_tree* lto_create_points(int dim, int d_min, int d_max, unsigned periodic_mask,
+                            int balance_kind, const double* pts, int64_t n, const double* lo,
+                            double len);
+/* The same point -> finest cell conversion: anchors[dim*j + a] = i_a, or
+ * non-zero with an error when a point lies outside the domain. */
+int lto_point_cells(int dim, int d_max, const double* pts, int64_t n, const double* lo, double len,
+                    int64_t* anchors);
+
 /* Uniform tree at start_depth (d_min stays the coarsening floor). */
 lto_tree* lto_create_uniform(int dim, int d_min, int d_max, unsigned periodic_mask,
                              int balance_kind, int start_depth);

@@ -23,7 +23,7 @@ STATUS = {0: "LT_OK", 1: "LT_ERR_ARG", 2: "LT_ERR_OOM", 3: "LT_ERR_HIP", 4: "LT_
           8: "LT_ERR_INTERNAL", 9: "LT_ERR_CAPACITY"}
 
 # Every symbol include/lt.h declares.
-EXPORTS = ["lt_build_uniform", "lt_build", "lt_build_batch", "lt_flag_batch", "lt_mesh_offsets",
+EXPORTS = ["lt_set_allocator", "lt_build_uniform", "lt_build", "lt_build_points", "lt_build_batch", "lt_flag_batch", "lt_mesh_offsets",
            "lt_flag", "lt_adapt", "lt_balance", "lt_connect", "lt_set_connect_grid", "lt_map",
            "lt_transfer", "lt_size",
            "lt_view", "lt_export", "lt_mlp_create", "lt_mlp_params", "lt_mlp_features",
@@ -65,6 +65,9 @@ class CycleDesc(C.Structure):
                 ("mlp", C.c_void_p), ("conf_min", C.c_float)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
 _lib = None
 
 
@@ -76,8 +79,10 @@ def lib() -> C.CDLL:
             raise LtError(3, f"{SO_PATH} is missing: run __graft_entry__.build() first")
         L = C.CDLL(SO_PATH)
         P, i64, i32 = C.c_void_p, C.c_int64, C.c_int
+        L.lt_set_allocator.argtypes = [ALLOC_FN, FREE_FN, P]
         L.lt_build_uniform.argtypes = [C.POINTER(Geom), i32, P, C.POINTER(P)]
         L.lt_build.argtypes = [C.POINTER(Geom), P, i64, P, C.POINTER(P)]
+        L.lt_build_points.argtypes = [C.POINTER(Geom), P, i64, P, C.c_double, P, C.POINTER(P)]
         L.lt_build_batch.argtypes = [C.POINTER(Geom), i32, P, P, P, P, C.POINTER(P)]
         L.lt_flag_batch.argtypes = [P, P, i32, P, P]
         L.lt_mesh_offsets.argtypes = [P, P, P]
@@ -137,6 +142,54 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+class TorchAllocator:
+    """torch's caching allocator behind lt_set_allocator, so that trees,
+    cycles and models draw device memory from the same pool as tensors.
+    ``limit`` (bytes, optional) caps what the library holds at once: a
+    request beyond it is refused and the call needing it fails with
+    LT_ERR_OOM.  ``held`` is what the library holds now."""
+
+    def __init__(self, limit=None):
+        import torch
+        self.limit = limit
+        self.held = 0
+        self._live = {}
+
+        def _alloc(nbytes, stream, ctx):
+            if self.limit is not None and self.held + nbytes > self.limit:
+                return None
+            try:
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), stream=0)
+            except RuntimeError:
+                return None
+            self._live[ptr] = int(nbytes)
+            self.held += int(nbytes)
+            return ptr
+
+        def _free(ptr, stream, ctx):
+            self.held -= self._live.pop(ptr, 0)
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._a = ALLOC_FN(_alloc)
+        self._f = FREE_FN(_free)
+
+
+# Every allocator ever registered stays referenced: the objects created while
+# it was registered call it until they are destroyed.
+_ALLOCATORS = []
+
+
+def set_allocator(a=None):
+    """Register ``a`` (a TorchAllocator) for the trees, cycles and models
+    created from now on; None restores hipMalloc / hipFree."""
+    _torch()
+    if a is None:
+        _check(lib().lt_set_allocator(ALLOC_FN(), FREE_FN(), None))
+    else:
+        _ALLOCATORS.append(a)
+        _check(lib().lt_set_allocator(a._a, a._f, None))
+
+
 def _dptr(t) -> C.c_void_p:
     assert t.is_cuda and t.is_contiguous()
     return C.c_void_p(t.data_ptr())
@@ -185,6 +238,22 @@ class Tree:
                  balance)
         h = C.c_void_p()
         _check(lib().lt_build(C.byref(g), _dptr(k), k.numel(), _stream(), C.byref(h)))
+        return cls(h, g)
+
+    @classmethod
+    def from_points(cls, points, dim, d_min, d_max, lo, length, periodic_mask=None,
+                    balance=2) -> "Tree":
+        """Bottom-up construction (lt_build_points): points is an (n, dim)
+        float64 tensor (moved to the device); the tree is not balanced."""
+        torch = _torch()
+        pts = points.to(device="cuda", dtype=torch.float64).contiguous()
+        g = Geom(dim, d_min, d_max, (1 << dim) - 1 if periodic_mask is None else periodic_mask,
+                 balance)
+        lo3 = (C.c_double * 3)(*([float(x) for x in lo] + [0.0] * (3 - len(lo))))
+        h = C.c_void_p()
+        _check(lib().lt_build_points(C.byref(g), _dptr(pts) if pts.numel() else None,
+                                     pts.shape[0] if pts.numel() else 0, lo3, float(length),
+                                     _stream(), C.byref(h)))
         return cls(h, g)
 
     @classmethod

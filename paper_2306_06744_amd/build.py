@@ -2,7 +2,8 @@
 
 Every translation unit is compiled by hipcc with packed-FP32 instructions
 disabled; the flag kernel's unit is also compiled without floating-point
-contraction so its FP64 decisions follow the documented operation order.
+contraction so its FP64 decisions follow the documented operation order, and
+so is the construction unit (point -> finest cell).
 """
 from __future__ import annotations
 
@@ -15,8 +16,9 @@ CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "liblt.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["lt_tree.hip", "lt_flag.hip", "lt_transfer.hip", "lt_split.hip", "lt_mlp.hip", "lt_cycle.hip"]
-NO_CONTRACT = {"lt_flag.hip"}
+SOURCES = ["lt_tree.hip", "lt_flag.hip", "lt_transfer.hip", "lt_split.hip", "lt_mlp.hip", "lt_cycle.hip",
+           "lt_build.hip"]
+NO_CONTRACT = {"lt_flag.hip", "lt_build.hip"}
 HEADERS = ["keys.hpp", "scan.hpp", "tree.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

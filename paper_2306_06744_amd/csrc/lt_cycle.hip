@@ -33,6 +33,10 @@ struct lt_cycle_s {
   int64_t runs = 0, eager_finishes = 0, recaptures = 0;
   int dir_shift = 0;
   int64_t dir_nb = 0;
+  // Set when finishing a cycle eagerly failed: the graphs were dropped (the
+  // eager calls may have moved buffers the graphs point at) and every later
+  // run returns LT_ERR_STATE without launching anything.
+  bool dead = false;
 };
 
 namespace {
@@ -40,14 +44,16 @@ namespace {
 // Grow a key buffer to `need` keeping its first `keep` keys.
 lt_status grow_keys(lt_tree t, int i, int64_t need, int64_t keep, hipStream_t s) {
   if (t->kcap[i] >= need && t->kbuf[i]) return LT_OK;
-  uint64_t* q = nullptr;
+  void* q = nullptr;
   const int64_t cap = need + need / 4;
-  if (hipMalloc(&q, size_t(cap) * 8) != hipSuccess) return fail(LT_ERR_OOM, "key buffer for the cycle");
-  if (keep > 0 && hipMemcpyAsync(q, t->kbuf[i], size_t(keep) * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+  if (dev_malloc(t->A, &q, size_t(cap) * 8) != hipSuccess) return fail(LT_ERR_OOM, "key buffer for the cycle");
+  if (keep > 0 && hipMemcpyAsync(q, t->kbuf[i], size_t(keep) * 8, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+    (void)dev_free(t->A, q);
     return fail(LT_ERR_HIP, "key copy");
+  }
   if (hipStreamSynchronize(s) != hipSuccess) return fail(LT_ERR_HIP, "sync");
-  if (t->kbuf[i]) (void)hipFree(t->kbuf[i]);
-  t->kbuf[i] = q;
+  (void)dev_free(t->A, t->kbuf[i]);
+  t->kbuf[i] = static_cast<uint64_t*>(q);
   t->kcap[i] = cap;
   return LT_OK;
 }
@@ -68,6 +74,7 @@ lt_status reserve(lt_cycle c, hipStream_t s) {
   t->cur = 0;
   t->tmp = 1;
   t->old = 2;
+  t->aux = 3;
   t->has_old = false;
   t->n_old = -1;
   t->map_valid = false;
@@ -76,32 +83,32 @@ lt_status reserve(lt_cycle c, hipStream_t s) {
   t->n_hang = -1;
   LT_TRY_STATUS(grow_keys(t, 1, C, 0, s));
   LT_TRY_STATUS(grow_keys(t, 2, C, 0, s));
-  LT_TRY_STATUS(grow(&t->mbuf[0], &t->mcap[0], C));
-  LT_TRY_STATUS(grow(&t->mbuf[1], &t->mcap[1], C));
-  LT_TRY_STATUS(grow(&t->nbr, &t->nbr_cap, C * 2 * dim));
-  LT_TRY_STATUS(grow(&t->hmask, &t->hmask_cap, C + kItems));
-  LT_TRY_STATUS(grow(&t->fused, &t->fused_cap, C));
-  LT_TRY_STATUS(grow(&t->elist, &t->elist_cap, C));
+  LT_TRY_STATUS(grow(t->A, &t->mbuf[0], &t->mcap[0], C));
+  LT_TRY_STATUS(grow(t->A, &t->mbuf[1], &t->mcap[1], C));
+  LT_TRY_STATUS(grow(t->A, &t->nbr, &t->nbr_cap, C * 2 * dim));
+  LT_TRY_STATUS(grow(t->A, &t->hmask, &t->hmask_cap, C + kItems));
+  LT_TRY_STATUS(grow(t->A, &t->fused, &t->fused_cap, C));
+  LT_TRY_STATUS(grow(t->A, &t->elist, &t->elist_cap, C));
   c->hang_rows = std::max<int64_t>(1024, C / 16);
-  LT_TRY_STATUS(grow(&t->hang, &t->hang_cap, c->hang_rows * (2 + (1 << (dim - 1)))));
+  LT_TRY_STATUS(grow(t->A, &t->hang, &t->hang_cap, c->hang_rows * (2 + (1 << (dim - 1)))));
   c->hang_rows = t->hang_cap / (2 + (1 << (dim - 1)));
-  LT_TRY_STATUS(grow(&t->map_src, &t->map_cap, C));
-  LT_TRY_STATUS(grow(&t->map_kind, &t->kind_cap, C));
-  LT_TRY_STATUS(grow(&t->copy_delta, &t->copy_delta_cap, C / 256 + 2));  // chunks at the finest tuning
-  LT_TRY_STATUS(grow(&t->grp_list, &t->grp_cap, 2 * (C / 64 + 2)));
-  LT_TRY_STATUS(grow(&t->status, &t->status_cap, std::max<int64_t>(1, (C + kTileMin - 1) / kTileMin)));
-  LT_TRY_STATUS(grow(&t->cstatus, &t->cstatus_cap, std::max<int64_t>(1, (C + kTileMin - 1) / kTileMin)));
+  LT_TRY_STATUS(grow(t->A, &t->map_src, &t->map_cap, C));
+  LT_TRY_STATUS(grow(t->A, &t->map_kind, &t->kind_cap, C));
+  LT_TRY_STATUS(grow(t->A, &t->copy_delta, &t->copy_delta_cap, C / 256 + 2));  // chunks at the finest tuning
+  LT_TRY_STATUS(grow(t->A, &t->grp_list, &t->grp_cap, 2 * (C / 64 + 2)));
+  LT_TRY_STATUS(grow(t->A, &t->status, &t->status_cap, std::max<int64_t>(1, (C + kTileMin - 1) / kTileMin)));
+  LT_TRY_STATUS(grow(t->A, &t->cstatus, &t->cstatus_cap, std::max<int64_t>(1, (C + kTileMin - 1) / kTileMin)));
   dir_params(t->g, C, &c->dir_shift, &c->dir_nb);
-  LT_TRY_STATUS(grow(&t->dir, &t->dir_cap, c->dir_nb + 1));
+  LT_TRY_STATUS(grow(t->A, &t->dir, &t->dir_cap, c->dir_nb + 1));
   if (!t->flag_tab) {
-    if (hipMalloc(&t->flag_tab, flag_args_size() * size_t(c->nmesh)) != hipSuccess)
+    if (dev_malloc(t->A, &t->flag_tab, flag_args_size() * size_t(c->nmesh)) != hipSuccess)
       return fail(LT_ERR_OOM, "flag table");
   }
-  LT_TRY_STATUS(build_transfer_ops(c->d.p, &t->ops[c->d.p], s));
+  LT_TRY_STATUS(build_transfer_ops(t->A, c->d.p, &t->ops[c->d.p], s));
   if (c->d.precision == 1) {
     LT_TRY_STATUS(prepare_split(t, c->d.p, s));
-    LT_TRY_STATUS(grow(&t->split_R, &t->split_R_cap, C));
-    LT_TRY_STATUS(grow(&t->split_F, &t->split_F_cap, C));
+    LT_TRY_STATUS(grow(t->A, &t->split_R, &t->split_R_cap, C));
+    LT_TRY_STATUS(grow(t->A, &t->split_F, &t->split_F_cap, C));
   }
   if (c->d.mlp) LT_TRY_STATUS(mlp_reserve(c->d.mlp, C));
   if (hipStreamSynchronize(s) != hipSuccess) return fail(LT_ERR_HIP, "sync");
@@ -182,6 +189,60 @@ lt_status upload_count(lt_cycle c, hipStream_t s) {
   return LT_OK;
 }
 
+// Finishes a cycle whose fixed balance passes stopped short of the fixpoint
+// with the eager calls (same result), then recaptures the graphs when
+// buffers moved.  On error the caller drops the graphs.
+lt_status finish_eagerly(lt_cycle c, int q, void* stream, int* u_index) {
+  lt_tree t = c->t;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto buffers = [t]() {
+    return std::vector<const void*>{t->kbuf[0], t->kbuf[1], t->kbuf[2], t->mbuf[0], t->mbuf[1],
+                                    t->nbr, t->hmask, t->hang, t->map_src, t->map_kind, t->dir,
+                                    t->status, t->cstatus, t->elist, t->copy_delta, t->grp_list,
+                                    t->fused, t->split_R, t->split_F};
+  };
+  const std::vector<const void*> before = buffers();
+  t->old = 0;
+  t->cur = 1;
+  t->tmp = 2;
+  t->aux = 3;
+  t->n_old = c->hsz[1];
+  t->n_cur = c->hsz[0];
+  t->has_old = true;
+  t->dir_valid = t->conn_valid = t->map_valid = false;
+  t->n_hang = -1;
+  LT_TRY_STATUS(lt_balance(t, stream));
+  if (t->n_cur > c->d.capacity)
+    return fail(LT_ERR_CAPACITY,
+                "the cycle outgrew its capacity while finishing eagerly; u not transferred");
+  LT_TRY_STATUS(lt_connect(t, stream));
+  LT_TRY_STATUS(lt_map(t, stream));
+  LT_TRY_STATUS(lt_transfer(t, c->d.p, c->d.nvar, c->d.u[q], c->d.ld, c->d.u[1 - q], c->d.ld,
+                            c->d.precision, stream));
+  if (t->cur != 0) {
+    if (hipMemcpyAsync(t->kbuf[0], t->kbuf[t->cur], size_t(t->n_cur) * 8, hipMemcpyDeviceToDevice, s) !=
+        hipSuccess)
+      return fail(LT_ERR_HIP, "key copy");
+    t->cur = 0;
+    t->tmp = 1;
+    t->old = 2;
+    t->aux = 3;
+  }
+  t->has_old = false;
+  t->dir_valid = false;
+  c->parity = 1 - q;
+  if (u_index) *u_index = c->parity;
+  LT_TRY_STATUS(upload_count(c, s));
+  if (buffers() != before) {
+    // buffers moved: size everything for the capacity again and recapture
+    c->recaptures++;
+    LT_TRY_STATUS(reserve(c, s));
+    LT_TRY_STATUS(upload_count(c, s));
+    LT_TRY_STATUS(capture(c));
+  }
+  return LT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -222,7 +283,7 @@ lt_status lt_cycle_create(lt_tree t, const lt_cycle_desc* d, void* stream, lt_cy
   c->tmpl[0].centre = c->tmpl_centres.data();
   c->d.flag_template = nullptr;
   lt_status st = LT_OK;
-  if (hipMalloc(&c->dsz, 4 * sizeof(int64_t)) != hipSuccess ||
+  if (dev_malloc(t->A, reinterpret_cast<void**>(&c->dsz), 4 * sizeof(int64_t)) != hipSuccess ||
       hipHostMalloc(&c->hsz, 4 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(&c->flag_host, flag_args_size() * size_t(c->nmesh), hipHostMallocDefault) != hipSuccess)
     st = fail(LT_ERR_OOM, "cycle state");
@@ -241,6 +302,8 @@ lt_status lt_cycle_create(lt_tree t, const lt_cycle_desc* d, void* stream, lt_cy
 
 lt_status lt_cycle_run(lt_cycle c, const lt_flag_params* fp, void* stream, int* u_index) {
   if (!c || !fp) return fail(LT_ERR_ARG, "NULL argument");
+  if (c->dead)
+    return fail(LT_ERR_STATE, "an earlier run of this cycle failed while finishing eagerly; create a new cycle");
   lt_tree t = c->t;
   hipStream_t s = static_cast<hipStream_t>(stream);
   for (int m = 0; m < c->nmesh; ++m)
@@ -265,6 +328,7 @@ lt_status lt_cycle_run(lt_cycle c, const lt_flag_params* fp, void* stream, int* 
     t->cur = 0;
     t->tmp = 1;
     t->old = 2;
+    t->aux = 3;
     t->has_old = false;  // the pre-cycle keys were overwritten by the new ones
     t->balanced = true;
     t->adapt_marks = false;
@@ -291,48 +355,14 @@ lt_status lt_cycle_run(lt_cycle c, const lt_flag_params* fp, void* stream, int* 
   // The fixed balance passes stopped short of the fixpoint: finish eagerly
   // from the partly balanced keys in kbuf[1].
   c->eager_finishes++;
-  void* before[] = {t->kbuf[0], t->kbuf[1], t->kbuf[2], t->mbuf[0], t->mbuf[1], t->nbr, t->hmask,
-                    t->hang, t->map_src, t->map_kind, t->dir, t->status, t->copy_delta, t->grp_list,
-                    t->fused};
-  t->old = 0;
-  t->cur = 1;
-  t->tmp = 2;
-  t->n_old = c->hsz[1];
-  t->n_cur = c->hsz[0];
-  t->has_old = true;
-  t->dir_valid = t->conn_valid = t->map_valid = false;
-  t->n_hang = -1;
-  LT_TRY_STATUS(lt_balance(t, stream));
-  LT_TRY_STATUS(lt_connect(t, stream));
-  LT_TRY_STATUS(lt_map(t, stream));
-  if (t->n_cur > c->d.capacity)
-    return fail(LT_ERR_CAPACITY, "the cycle outgrew its capacity while finishing eagerly; u not transferred");
-  LT_TRY_STATUS(lt_transfer(t, c->d.p, c->d.nvar, c->d.u[q], c->d.ld, c->d.u[1 - q], c->d.ld,
-                            c->d.precision, stream));
-  if (t->cur != 0) {
-    if (hipMemcpyAsync(t->kbuf[0], t->kbuf[t->cur], size_t(t->n_cur) * 8, hipMemcpyDeviceToDevice, s) !=
-        hipSuccess)
-      return fail(LT_ERR_HIP, "key copy");
-    t->cur = 0;
-    t->tmp = 1;
-    t->old = 2;
+  const lt_status st = finish_eagerly(c, q, stream, u_index);
+  if (st != LT_OK) {
+    // The eager calls may have moved or regrown buffers the graphs point at:
+    // the graphs are dropped and the cycle refuses later runs.
+    drop_graphs(c);
+    c->dead = true;
   }
-  t->has_old = false;
-  t->dir_valid = false;
-  c->parity = 1 - q;
-  if (u_index) *u_index = c->parity;
-  LT_TRY_STATUS(upload_count(c, s));
-  void* after[] = {t->kbuf[0], t->kbuf[1], t->kbuf[2], t->mbuf[0], t->mbuf[1], t->nbr, t->hmask,
-                   t->hang, t->map_src, t->map_kind, t->dir, t->status, t->copy_delta, t->grp_list,
-                   t->fused};
-  if (std::memcmp(before, after, sizeof(before)) != 0) {
-    // buffers moved: size everything for the capacity again and recapture
-    c->recaptures++;
-    LT_TRY_STATUS(reserve(c, s));
-    LT_TRY_STATUS(upload_count(c, s));
-    LT_TRY_STATUS(capture(c));
-  }
-  return LT_OK;
+  return st;
 }
 
 lt_status lt_cycle_stats(lt_cycle c, int64_t* runs, int64_t* eager_finishes, int64_t* recaptures) {
@@ -347,7 +377,7 @@ void lt_cycle_destroy(lt_cycle c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
   drop_graphs(c);
-  if (c->dsz) (void)hipFree(c->dsz);
+  (void)dev_free(c->t->A, c->dsz);
   if (c->hsz) (void)hipHostFree(c->hsz);
   if (c->flag_host) (void)hipHostFree(c->flag_host);
   delete c;

@@ -624,6 +624,7 @@ bool modal_matrix(int p, double* T) {
 struct lt_mlp_s {
   static constexpr int kIn = 320, kH1 = 128, kH2 = 64, kOut = 3;
   int device = 0;
+  lt::Alloc A;  // device allocator of every buffer below
   // FP32 master parameters, BF16 copies (row-major [out][in]) and transposes
   float* P = nullptr;   // W1 b1 W2 b2 W3 b3 (FP32, contiguous)
   float* G = nullptr;   // gradients, same layout
@@ -652,12 +653,12 @@ namespace {
 
 lt_status mlp_scratch(lt_mlp_s* m, int64_t B) {
   if (B <= m->cap) return LT_OK;
-  auto fr = [](void* p) { if (p) (void)hipFree(p); };
+  auto fr = [m](void* p) { (void)dev_free(m->A, p); };
   fr(m->H1); fr(m->H2); fr(m->XT); fr(m->H1T); fr(m->H2T); fr(m->D1T); fr(m->D2T); fr(m->D3T);
   fr(m->D2b); fr(m->D3b); fr(m->Z3); fr(m->D1); fr(m->D2); fr(m->D3); fr(m->loss);
   const int64_t c = B + B / 4 + 64;
   hipError_t e = hipSuccess;
-  auto al = [&](void** p, size_t bytes) { if (e == hipSuccess) e = hipMalloc(p, bytes); };
+  auto al = [&](void** p, size_t bytes) { if (e == hipSuccess) e = dev_malloc(m->A, p, bytes); };
   al((void**)&m->H1, c * 128 * 2); al((void**)&m->H2, c * 64 * 2); al((void**)&m->XT, c * 320 * 2);
   al((void**)&m->H1T, c * 128 * 2); al((void**)&m->H2T, c * 64 * 2); al((void**)&m->D1T, c * 128 * 2);
   al((void**)&m->D2T, c * 64 * 2); al((void**)&m->D3T, c * 3 * 2); al((void**)&m->D2b, c * 64 * 2);
@@ -752,10 +753,11 @@ namespace lt {
 
 lt_status mlp_reserve(lt_mlp m, int64_t n) {
   if (m->xcap >= n) return LT_OK;
-  if (m->X) (void)hipFree(m->X);
+  (void)dev_free(m->A, m->X);
   m->X = nullptr;
   m->xcap = 0;
-  if (hipMalloc(&m->X, size_t(n) * 320 * 2) != hipSuccess) return fail(LT_ERR_OOM, "MLP features");
+  if (dev_malloc(m->A, reinterpret_cast<void**>(&m->X), size_t(n) * 320 * 2) != hipSuccess)
+    return fail(LT_ERR_OOM, "MLP features");
   m->xcap = n;
   return LT_OK;
 }
@@ -782,9 +784,10 @@ extern "C" {
 lt_status lt_mlp_create(const float* params, lt_mlp* out) {
   if (!params || !out) return fail(LT_ERR_ARG, "NULL argument");
   lt_mlp m = new lt_mlp_s;
+  m->A = registered_alloc();
   hipError_t e = hipGetDevice(&m->device);
   const size_t np = size_t(lt_mlp_s::nparam);
-  auto al = [&](void** p, size_t bytes) { if (e == hipSuccess) e = hipMalloc(p, bytes); };
+  auto al = [&](void** p, size_t bytes) { if (e == hipSuccess) e = dev_malloc(m->A, p, bytes); };
   al((void**)&m->P, np * 4); al((void**)&m->G, np * 4); al((void**)&m->M1, np * 4); al((void**)&m->M2, np * 4);
   al((void**)&m->W1, 128 * 320 * 2); al((void**)&m->W2, 64 * 128 * 2); al((void**)&m->W3, 3 * 64 * 2);
   al((void**)&m->W1T, 128 * 320 * 2); al((void**)&m->W2T, 64 * 128 * 2); al((void**)&m->W3T, 3 * 64 * 2);
@@ -799,7 +802,8 @@ lt_status lt_mlp_create(const float* params, lt_mlp* out) {
   }
   if (e != hipSuccess) {
     lt_mlp_destroy(m);
-    return fail(LT_ERR_HIP, std::string("MLP create: ") + hipGetErrorString(e));
+    return fail(e == hipErrorOutOfMemory ? LT_ERR_OOM : LT_ERR_HIP,
+                std::string("MLP create: ") + hipGetErrorString(e));
   }
   lt_status st = mlp_refresh(m, nullptr);
   if (st == LT_OK && hipDeviceSynchronize() != hipSuccess) st = fail(LT_ERR_HIP, "MLP create sync");
@@ -939,8 +943,7 @@ void lt_mlp_destroy(lt_mlp m) {
   void* ptrs[] = {m->P, m->G, m->M1, m->M2, m->W1, m->W2, m->W3, m->W1T, m->W2T, m->W3T, m->T4,
                   m->H1, m->H2, m->XT, m->H1T, m->H2T, m->D1T, m->D2T, m->D3T, m->D2b, m->D3b,
                   m->Z3, m->D1, m->D2, m->D3, m->loss, m->X};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+  for (void* p : ptrs) (void)dev_free(m->A, p);
   delete m;
 }
 

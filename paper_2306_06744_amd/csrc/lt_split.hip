@@ -358,22 +358,22 @@ lt_status prepare_split(lt_tree_s* t, int p, hipStream_t s) {
   if (!((dim == 3 && p == 3) || (dim == 2 && p == 7)))
     return fail(LT_ERR_ARG, "split precision needs 64 points per element (3D p=3 or 2D p=7)");
   const int nc = 1 << dim, n1 = p + 1;
-  LT_TRY_STATUS(build_transfer_ops(p, &t->ops[p], s));
+  LT_TRY_STATUS(build_transfer_ops(t->A, p, &t->ops[p], s));
   if (!t->split_frags) {
     const size_t nfr = size_t(2) * nc * 3 * kMT * kKS * 64;
     void* q = nullptr;
-    if (hipMalloc(&q, nfr * sizeof(bf16x8)) != hipSuccess) return fail(LT_ERR_OOM, "split operators");
+    if (dev_malloc(t->A, &q, nfr * sizeof(bf16x8)) != hipSuccess) return fail(LT_ERR_OOM, "split operators");
     void* qv = nullptr;
-    if (hipMalloc(&qv, sizeof(double) * (kNP + nc * kNP)) != hipSuccess) {
-      (void)hipFree(q);
+    if (dev_malloc(t->A, &qv, sizeof(double) * (kNP + nc * kNP)) != hipSuccess) {
+      (void)dev_free(t->A, q);
       return fail(LT_ERR_OOM, "split operators");
     }
     k_build_split<<<unsigned((nfr / 3 + 255) / 256), 256, 0, s>>>(t->ops[p], n1, dim, nc,
                                                                   static_cast<bf16x8*>(q));
     k_build_split_vec<<<1, 256, 0, s>>>(t->ops[p], n1, dim, nc, static_cast<double*>(qv));
     if (hipGetLastError() != hipSuccess) {
-      (void)hipFree(q);
-      (void)hipFree(qv);
+      (void)dev_free(t->A, q);
+      (void)dev_free(t->A, qv);
       return fail(LT_ERR_HIP, "split operator build failed to launch");
     }
     t->split_frags = q;
@@ -395,8 +395,8 @@ lt_status launch_split_transfer(lt_tree_s* t, Count cn, int p, int nvar, const d
   const int nc = 1 << dim;
   const int64_t n = cn.n;  // leaves, or the capacity of a launch whose count lives on the device
   if (n == 0) return LT_OK;
-  LT_TRY_STATUS(grow(&t->split_R, &t->split_R_cap, n));
-  LT_TRY_STATUS(grow(&t->split_F, &t->split_F_cap, n));
+  LT_TRY_STATUS(grow(t->A, &t->split_R, &t->split_R_cap, n));
+  LT_TRY_STATUS(grow(t->A, &t->split_F, &t->split_F_cap, n));
   ScanState st;
   LT_TRY_STATUS(prep_scan(t, n, kTileMin, s, 0, &st));
   st.items.p = cn.p;

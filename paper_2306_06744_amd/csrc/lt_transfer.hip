@@ -505,36 +505,52 @@ __global__ __launch_bounds__(64 * N) void k_interp3(const double* __restrict__ o
   }
 }
 
+// Scratch of one FP64 transfer, sized for n new leaves: per copy chunk the
+// source offset of a pure copy run (ceil(n / 256) entries at the finest
+// tuning), the interpolation-group lists (the ordered list of groups with a
+// refined element, then the groups holding a fused one: 2 ceil(n / 64)),
+// look-back words and counters.  From the tree's buffers (lt_transfer) or
+// from storage of a fixed size that the caller provides.
+struct XferScratch {
+  int64_t* copy_delta;
+  int32_t* grp_list;
+  uint64_t* status;
+  int64_t status_cap;
+  DevCtr* ctr;
+};
+
+lt_status copy_pass(const TransferTune& tune, const int32_t* src, const int8_t* kind, Count n,
+                    int64_t rows, const double* uo, int64_t ldo, double* un, int64_t ldn,
+                    int64_t* copy_delta, hipStream_t s);
+
 template <int DIM, int N>
-hipError_t launch(lt_tree_s* t, const double* ops, const int32_t* src, const int8_t* kind, Count n,
-                  const int64_t* ngroups_dev, int nvar, const double* uo, int64_t ldo, double* un,
-                  int64_t ldn, hipStream_t s, lt_status* st_out) {
+hipError_t launch(const TransferTune& tune, const double* ops, const int32_t* src, const int8_t* kind,
+                  Count n, const int64_t* ngroups_dev, int nvar, const double* uo, int64_t ldo,
+                  double* un, int64_t ldn, const XferScratch& X, hipStream_t s, lt_status* st_out) {
   *st_out = LT_OK;
   if constexpr (DIM == 3) {
     const int64_t ngroups = (n.n + 63) / 64;
-    *st_out = launch_copy(t, n, nvar * N * N * N, uo, ldo, un, ldn, s);
+    *st_out = copy_pass(tune, src, kind, n, nvar * N * N * N, uo, ldo, un, ldn, X.copy_delta, s);
     if (*st_out != LT_OK) return hipSuccess;
     hipError_t e = hipSuccess;
     // grp_list holds the ordered list in [0, ngroups) and the list of
     // groups with a fused element in [ngroups, 2 ngroups)
-    *st_out = grow(&t->grp_list, &t->grp_cap, 2 * ngroups);
-    if (*st_out != LT_OK) return hipSuccess;
     ScanState st;
-    *st_out = prep_scan(t, ngroups, kTileMin, s, 0, &st);
+    *st_out = prep_scan_fixed(X.status, X.status_cap, X.ctr, ngroups, kTileMin, s, 0, &st);
     if (*st_out != LT_OK) return hipSuccess;
     st.items.p = ngroups_dev;
-    int32_t* flist = t->grp_list + ngroups;
-    k_group_list<<<grid_tiles(st), kScanSmall, 0, s>>>(kind, n, t->grp_list, st, flist,
-                                                   &t->dctr->nfgroups);
+    int32_t* flist = X.grp_list + ngroups;
+    k_group_list<<<grid_tiles(st), kScanSmall, 0, s>>>(kind, n, X.grp_list, st, flist,
+                                                   &X.ctr->nfgroups);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 gi{unsigned(std::max<int64_t>(1, std::min<int64_t>(ngroups, t->tune.interp_grid))),
+    const dim3 gi{unsigned(std::max<int64_t>(1, std::min<int64_t>(ngroups, tune.interp_grid))),
                   unsigned(nvar), 1u};
-    k_interp3_ref<N><<<gi, 64 * N, 0, s>>>(ops, src, kind, n, t->grp_list, st.total, uo, ldo, un,
+    k_interp3_ref<N><<<gi, 64 * N, 0, s>>>(ops, src, kind, n, X.grp_list, st.total, uo, ldo, un,
                                            ldn);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_interp3<N><<<gi, 64 * N, 0, s>>>(ops, src, kind, n, flist, &t->dctr->nfgroups, uo, ldo, un,
+    k_interp3<N><<<gi, 64 * N, 0, s>>>(ops, src, kind, n, flist, &X.ctr->nfgroups, uo, ldo, un,
                                        ldn);
     return hipGetLastError();
   } else {
@@ -546,19 +562,20 @@ hipError_t launch(lt_tree_s* t, const double* ops, const int32_t* src, const int
 
 }  // namespace
 
-lt_status launch_copy(lt_tree_s* t, Count n, int64_t rows, const double* uo, int64_t ldo,
-                      double* un, int64_t ldn, hipStream_t s) {
+namespace {
+lt_status copy_pass(const TransferTune& tune, const int32_t* src, const int8_t* kind, Count n,
+                    int64_t rows, const double* uo, int64_t ldo, double* un, int64_t ldn,
+                    int64_t* copy_delta, hipStream_t s) {
   if (n.n == 0) return LT_OK;
   if (rows < 1 || rows > 65535) return fail(LT_ERR_ARG, "copy pass: rows out of range");
-  const int epl = t->tune.copy_epl;
+  const int epl = tune.copy_epl;
   const int64_t CH = 256 * int64_t(epl);
   const int64_t nchunks = (n.n + CH - 1) / CH;
-  LT_TRY_STATUS(grow(&t->copy_delta, &t->copy_delta_cap, nchunks));
   const dim3 grid{unsigned(nchunks), unsigned(rows), 1u};
 #define LT_COPY(E)                                                                              \
   do {                                                                                          \
-    k_copy_chunks<E><<<unsigned(nchunks), 256, 0, s>>>(t->map_src, t->map_kind, n, t->copy_delta); \
-    k_copy3<E><<<grid, 256, 0, s>>>(t->map_src, t->map_kind, n, t->copy_delta, uo, ldo, un, ldn); \
+    k_copy_chunks<E><<<unsigned(nchunks), 256, 0, s>>>(src, kind, n, copy_delta);               \
+    k_copy3<E><<<grid, 256, 0, s>>>(src, kind, n, copy_delta, uo, ldo, un, ldn);                \
   } while (0)
   if (epl == 1)
     LT_COPY(1);
@@ -571,17 +588,26 @@ lt_status launch_copy(lt_tree_s* t, Count n, int64_t rows, const double* uo, int
   if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("copy pass launch: ") + hipGetErrorString(e));
   return LT_OK;
 }
+}  // namespace
 
-lt_status build_transfer_ops(int p, double** ops, hipStream_t stream) {
+lt_status launch_copy(lt_tree_s* t, Count n, int64_t rows, const double* uo, int64_t ldo,
+                      double* un, int64_t ldn, hipStream_t s) {
+  if (n.n == 0) return LT_OK;
+  const int64_t CH = 256 * int64_t(t->tune.copy_epl);
+  LT_TRY_STATUS(grow(t->A, &t->copy_delta, &t->copy_delta_cap, (n.n + CH - 1) / CH));
+  return copy_pass(t->tune, t->map_src, t->map_kind, n, rows, uo, ldo, un, ldn, t->copy_delta, s);
+}
+
+lt_status build_transfer_ops(const Alloc& A, int p, double** ops, hipStream_t stream) {
   if (*ops) return LT_OK;
   const int n = p + 1;
   void* q = nullptr;
-  hipError_t e = hipMalloc(&q, sizeof(double) * (4 * n * n + n));
+  hipError_t e = dev_malloc(A, &q, sizeof(double) * (4 * n * n + n));
   if (e != hipSuccess) return fail(LT_ERR_OOM, "transfer operator allocation failed");
   k_build_ops<<<1, 64, 0, stream>>>(n, static_cast<double*>(q));
   e = hipGetLastError();
   if (e != hipSuccess) {
-    (void)hipFree(q);
+    (void)dev_free(A, q);
     return fail(LT_ERR_HIP, std::string("operator build: ") + hipGetErrorString(e));
   }
   *ops = static_cast<double*>(q);
@@ -599,12 +625,13 @@ lt_status launch_transfer(lt_tree_s* t, int p, const double* ops, int nvar, cons
                          ld_new, s);
 }
 
-lt_status launch_transfer(lt_tree_s* t, Count n, const int64_t* ngroups_dev, int p,
-                          const double* ops, int nvar, const double* u_old, int64_t ld_old,
-                          double* u_new, int64_t ld_new, hipStream_t s) {
-  const int dim = t->g.dim;
-  const int32_t* src = t->map_src;
-  const int8_t* kind = t->map_kind;
+namespace {
+// The FP64 transfer over n new leaves of a mapping (src, kind) with the given
+// scratch; no allocation.
+lt_status transfer_with(int dim, const TransferTune& tune, const int32_t* src, const int8_t* kind,
+                        Count n, const int64_t* ngroups_dev, int p, const double* ops, int nvar,
+                        const double* u_old, int64_t ld_old, double* u_new, int64_t ld_new,
+                        const XferScratch& X, hipStream_t s) {
   if (n.n == 0) return LT_OK;
   int64_t npts = 1;
   for (int a = 0; a < dim; ++a) npts *= p + 1;
@@ -612,7 +639,7 @@ lt_status launch_transfer(lt_tree_s* t, Count n, const int64_t* ngroups_dev, int
     return fail(LT_ERR_ARG, "nvar * (p+1)^dim must be in [1, 65535]");
   hipError_t e = hipErrorInvalidValue;
   lt_status st = LT_OK;
-#define LT_L(D, NN) e = launch<D, NN>(t, ops, src, kind, n, ngroups_dev, nvar, u_old, ld_old, u_new, ld_new, s, &st)
+#define LT_L(D, NN) e = launch<D, NN>(tune, ops, src, kind, n, ngroups_dev, nvar, u_old, ld_old, u_new, ld_new, X, s, &st)
   if (dim == 3) {
     switch (p) {
       case 1: LT_L(3, 2); break;
@@ -636,6 +663,25 @@ lt_status launch_transfer(lt_tree_s* t, Count n, const int64_t* ngroups_dev, int
   if (st != LT_OK) return st;
   if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("transfer launch: ") + hipGetErrorString(e));
   return LT_OK;
+}
+}  // namespace
+
+lt_status launch_transfer(lt_tree_s* t, Count n, const int64_t* ngroups_dev, int p,
+                          const double* ops, int nvar, const double* u_old, int64_t ld_old,
+                          double* u_new, int64_t ld_new, hipStream_t s) {
+  if (n.n == 0) return LT_OK;
+  XferScratch X{};
+  if (t->g.dim == 3) {
+    const int64_t ngroups = (n.n + 63) / 64;
+    const int64_t CH = 256 * int64_t(t->tune.copy_epl);
+    LT_TRY_STATUS(grow(t->A, &t->copy_delta, &t->copy_delta_cap, (n.n + CH - 1) / CH));
+    LT_TRY_STATUS(grow(t->A, &t->grp_list, &t->grp_cap, 2 * ngroups));
+    LT_TRY_STATUS(grow(t->A, &t->status, &t->status_cap,
+                       std::max<int64_t>(1, (ngroups + kTileMin - 1) / kTileMin)));
+    X = XferScratch{t->copy_delta, t->grp_list, t->status, t->status_cap, t->dctr};
+  }
+  return transfer_with(t->g.dim, t->tune, t->map_src, t->map_kind, n, ngroups_dev, p, ops, nvar,
+                       u_old, ld_old, u_new, ld_new, X, s);
 }
 
 }  // namespace lt

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -28,6 +29,36 @@ void set_error(const std::string& msg) { g_err = msg; }
 lt_status fail(lt_status s, const std::string& msg) {
   g_err = msg;
   return s;
+}
+
+namespace {
+std::mutex g_alloc_mu;
+Alloc g_alloc;  // registered by lt_set_allocator; empty: hipMalloc / hipFree
+}  // namespace
+
+Alloc registered_alloc() {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  return g_alloc;
+}
+
+void register_alloc(const Alloc& A) {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc = A;
+}
+
+hipError_t dev_malloc(const Alloc& A, void** p, size_t bytes) {
+  *p = nullptr;
+  if (!A.alloc) return hipMalloc(p, bytes);
+  *p = A.alloc(bytes, nullptr, A.ctx);
+  return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+hipError_t dev_free(const Alloc& A, void* p) {
+  if (!p) return hipSuccess;
+  if (!A.free_) return hipFree(p);
+  const hipError_t e = hipDeviceSynchronize();
+  A.free_(p, nullptr, A.ctx);
+  return e;
 }
 
 }  // namespace lt
@@ -725,16 +756,15 @@ void dir_params(const KeyGeom& g, int64_t n, int* shift, int64_t* nb) {
     *nb = (nm + (int64_t(1) << (*shift - ms)) - 1) >> (*shift - ms);
 }
 
-namespace {
-lt_status prep_scan_on(uint64_t** status, int64_t* status_cap, DevCtr* ctr, int64_t n_items,
-                       int64_t tile, hipStream_t stream, int flags, ScanState* st) {
+lt_status prep_scan_fixed(uint64_t* status, int64_t status_cap, DevCtr* ctr, int64_t n_items,
+                          int64_t tile, hipStream_t stream, int flags, ScanState* st) {
   const int64_t ntiles = std::max<int64_t>(1, ceil_div(n_items, tile));
-  LT_TRY(grow(status, status_cap, ntiles));
-  k_clear_scan<<<unsigned(ceil_div(ntiles, 256)), 256, 0, stream>>>(*status, ntiles, ctr, flags & 1,
+  if (ntiles > status_cap) return fail(LT_ERR_ARG, "scan needs more look-back words than provided");
+  k_clear_scan<<<unsigned(ceil_div(ntiles, 256)), 256, 0, stream>>>(status, ntiles, ctr, flags & 1,
                                                                       (flags >> 1) & 1,
                                                                       (flags >> 2) & 1);
   LT_HIP(hipGetLastError());
-  st->status = *status;
+  st->status = status;
   st->ticket = &ctr->ticket;
   st->err = &ctr->err;
   st->total = &ctr->total;
@@ -744,15 +774,24 @@ lt_status prep_scan_on(uint64_t** status, int64_t* status_cap, DevCtr* ctr, int6
   st->commit_cap = 0;
   return LT_OK;
 }
+
+namespace {
+lt_status prep_scan_on(const Alloc& A, uint64_t** status, int64_t* status_cap, DevCtr* ctr,
+                       int64_t n_items, int64_t tile, hipStream_t stream, int flags, ScanState* st) {
+  const int64_t ntiles = std::max<int64_t>(1, ceil_div(n_items, tile));
+  LT_TRY(grow(A, status, status_cap, ntiles));
+  return prep_scan_fixed(*status, *status_cap, ctr, n_items, tile, stream, flags, st);
+}
 }  // namespace
 
 lt_status prep_scan(lt_tree t, int64_t n_items, int64_t tile, hipStream_t stream, int flags,
                     ScanState* st) {
-  return prep_scan_on(&t->status, &t->status_cap, t->dctr, n_items, tile, stream, flags, st);
+  return prep_scan_on(t->A, &t->status, &t->status_cap, t->dctr, n_items, tile, stream, flags, st);
 }
 
 lt_status prep_scan_conn(lt_tree t, int64_t n_items, hipStream_t stream, int flags, ScanState* st) {
-  return prep_scan_on(&t->cstatus, &t->cstatus_cap, t->cctr, n_items, kTileMin, stream, flags, st);
+  return prep_scan_on(t->A, &t->cstatus, &t->cstatus_cap, t->cctr, n_items, kTileMin, stream, flags,
+                      st);
 }
 
 lt_status read_ctr(lt_tree t, hipStream_t stream) {
@@ -797,14 +836,16 @@ lt_status new_tree(const lt_geom* geom, lt_tree* out) {
   t->g.mesh_shift = mb + geom->dim * geom->d_max;
   t->g.nmesh = 1;
   t->g.lim = nullptr;
+  t->A = registered_alloc();
   hipError_t e = hipGetDevice(&t->device);
-  if (e == hipSuccess) e = hipMalloc(&t->dctr, sizeof(DevCtr));
+  if (e == hipSuccess) e = dev_malloc(t->A, reinterpret_cast<void**>(&t->dctr), sizeof(DevCtr));
   if (e == hipSuccess) e = hipHostMalloc(&t->hctr, sizeof(DevCtr), hipHostMallocDefault);
-  if (e == hipSuccess) e = hipMalloc(&t->cctr, sizeof(DevCtr));
+  if (e == hipSuccess) e = dev_malloc(t->A, reinterpret_cast<void**>(&t->cctr), sizeof(DevCtr));
   if (e == hipSuccess) e = hipHostMalloc(&t->hcctr, sizeof(DevCtr), hipHostMallocDefault);
   if (e != hipSuccess) {
     lt_destroy(t);
-    return fail(LT_ERR_HIP, std::string("tree setup: ") + hipGetErrorString(e));
+    return fail(e == hipErrorOutOfMemory ? LT_ERR_OOM : LT_ERR_HIP,
+                std::string("tree setup: ") + hipGetErrorString(e));
   }
   std::memset(t->hctr, 0, sizeof(DevCtr));
   std::memset(t->hcctr, 0, sizeof(DevCtr));
@@ -831,7 +872,7 @@ lt_status ensure_dir(lt_tree t, hipStream_t s, KeyDir* D) {
   const int64_t n = t->n_cur;
   if (!t->dir_valid) {
     dir_params(t->g, n, &t->dir_shift, &t->dir_nb);
-    LT_TRY(grow(&t->dir, &t->dir_cap, t->dir_nb + 1));
+    LT_TRY(grow(t->A, &t->dir, &t->dir_cap, t->dir_nb + 1));
     if (n > 0) {
       k_build_dir<<<unsigned(ceil_div(n, 256)), 256, 0, s>>>(t->kbuf[t->cur], Count{n, nullptr},
                                                              t->dir_shift, t->dir_nb, t->dir, nullptr);
@@ -847,8 +888,8 @@ lt_status ensure_dir(lt_tree t, hipStream_t s, KeyDir* D) {
 
 lt_status do_map(lt_tree t, hipStream_t stream) {
   if (!t->has_old) return fail(LT_ERR_STATE, "lt_map needs a prior lt_adapt");
-  LT_TRY(grow(&t->map_src, &t->map_cap, t->n_cur));
-  LT_TRY(grow(&t->map_kind, &t->kind_cap, t->n_cur));
+  LT_TRY(grow(t->A, &t->map_src, &t->map_cap, t->n_cur));
+  LT_TRY(grow(t->A, &t->map_kind, &t->kind_cap, t->n_cur));
   LT_TRY(clear_err(t, stream));
   if (t->n_cur > 0)
     k_map<<<unsigned(ceil_div(t->n_cur, kBlock)), kBlock, 0, stream>>>(
@@ -1001,6 +1042,10 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
 namespace {
 
 }  // namespace
+// A new tree with no leaves yet (geometry checked, allocator and counters set
+// up), for the translation units that build trees of their own.
+lt_status create_tree(const lt_geom* geom, lt_tree* out) { return new_tree(geom, out); }
+
 }  // namespace lt
 
 using namespace lt;
@@ -1009,6 +1054,18 @@ using namespace lt;
 extern "C" {
 
 const char* lt_last_error(void) { return lt::g_err.c_str(); }
+
+lt_status lt_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ctx),
+                           void (*free_)(void* ptr, void* stream, void* ctx), void* ctx) {
+  if ((alloc == nullptr) != (free_ == nullptr))
+    return fail(LT_ERR_ARG, "alloc and free must both be set or both be NULL");
+  Alloc A;
+  A.alloc = alloc;
+  A.free_ = free_;
+  A.ctx = alloc ? ctx : nullptr;
+  register_alloc(A);
+  return LT_OK;
+}
 
 lt_status lt_build_uniform(const lt_geom* geom, int depth, void* stream, lt_tree* out) {
   lt_tree t = nullptr;
@@ -1023,7 +1080,7 @@ lt_status lt_build_uniform(const lt_geom* geom, int depth, void* stream, lt_tree
   }
   const int64_t n = int64_t(1) << (geom->dim * depth);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  lt_status st = grow(&t->kbuf[t->cur], &t->kcap[t->cur], n);
+  lt_status st = grow(t->A, &t->kbuf[t->cur], &t->kcap[t->cur], n);
   if (st != LT_OK) {
     lt_destroy(t);
     return st;
@@ -1046,7 +1103,7 @@ lt_status lt_build(const lt_geom* geom, const uint64_t* keys, int64_t n, void* s
   lt_tree t = nullptr;
   LT_TRY(new_tree(geom, &t));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  lt_status st = grow(&t->kbuf[t->cur], &t->kcap[t->cur], n);
+  lt_status st = grow(t->A, &t->kbuf[t->cur], &t->kcap[t->cur], n);
   if (st != LT_OK) {
     lt_destroy(t);
     return st;
@@ -1102,13 +1159,14 @@ lt_status lt_build_batch(const lt_geom* geom, int nmesh, const int* d_min, const
   LT_TRY(new_tree(&g0, &t));
   hipStream_t s = static_cast<hipStream_t>(stream);
   int8_t* dep_dev = nullptr;
-  lt_status st = grow(&t->kbuf[t->cur], &t->kcap[t->cur], n);
+  lt_status st = grow(t->A, &t->kbuf[t->cur], &t->kcap[t->cur], n);
   hipError_t e = hipSuccess;
   if (st == LT_OK) {
-    e = hipMalloc(&t->lim, lim.size());
-    if (e == hipSuccess) e = hipMalloc(&t->mesh_offs, sizeof(int64_t) * (nmesh + 1));
-    if (e == hipSuccess) e = hipMalloc(&dep_dev, dep.size());
-    if (e == hipSuccess) e = hipMalloc(&t->flag_tab, flag_args_size() * nmesh);
+    e = dev_malloc(t->A, reinterpret_cast<void**>(&t->lim), lim.size());
+    if (e == hipSuccess)
+      e = dev_malloc(t->A, reinterpret_cast<void**>(&t->mesh_offs), sizeof(int64_t) * (nmesh + 1));
+    if (e == hipSuccess) e = dev_malloc(t->A, reinterpret_cast<void**>(&dep_dev), dep.size());
+    if (e == hipSuccess) e = dev_malloc(t->A, &t->flag_tab, flag_args_size() * nmesh);
     if (e == hipSuccess)
       e = hipMemcpy(t->lim, lim.data(), lim.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dep_dev, dep.data(), dep.size(), hipMemcpyHostToDevice);
@@ -1122,9 +1180,11 @@ lt_status lt_build_batch(const lt_geom* geom, int nmesh, const int* d_min, const
       e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) st = fail(LT_ERR_HIP, std::string("batch build: ") + hipGetErrorString(e));
+    if (e != hipSuccess)
+      st = fail(e == hipErrorOutOfMemory ? LT_ERR_OOM : LT_ERR_HIP,
+                std::string("batch build: ") + hipGetErrorString(e));
   }
-  if (dep_dev) (void)hipFree(dep_dev);
+  (void)dev_free(t->A, dep_dev);
   if (st != LT_OK) {
     lt_destroy(t);
     return st;
@@ -1148,7 +1208,9 @@ lt_status lt_mesh_offsets(lt_tree t, int64_t* offsets, void* stream) {
   if (!t || !offsets) return fail(LT_ERR_ARG, "NULL argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nm = t->g.nmesh;
-  if (!t->mesh_offs) LT_HIP(hipMalloc(&t->mesh_offs, sizeof(int64_t) * (nm + 1)));
+  if (!t->mesh_offs)
+    if (dev_malloc(t->A, reinterpret_cast<void**>(&t->mesh_offs), sizeof(int64_t) * (nm + 1)) != hipSuccess)
+      return fail(LT_ERR_OOM, "mesh offsets");
   k_mesh_offsets<<<unsigned(ceil_div(nm + 1, 64)), 64, 0, s>>>(t->g, t->kbuf[t->cur], t->n_cur, nm,
                                                                  t->mesh_offs);
   LT_HIP(hipGetLastError());
@@ -1167,28 +1229,26 @@ lt_status lt_adapt(lt_tree t, const int8_t* flags, void* stream) {
   if (!t || !flags) return fail(LT_ERR_ARG, "NULL argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t n = t->n_cur;
-  // Output bound: every leaf refined.  Both the spare buffer and the one
-  // holding the previous snapshot are free here (the snapshot is superseded
-  // by this call), so the output goes to whichever already holds the bound:
-  // the buffers rotate roles from cycle to cycle, and growing a small one
-  // costs a device-wide free and allocation.
+  // Output bound: every leaf refined.  The output goes to whichever of the
+  // two free key buffers already holds the bound: the buffers rotate roles
+  // from cycle to cycle, and growing a small one costs a device-wide free and
+  // allocation.  The old snapshot is left alone until the call has succeeded.
   const int64_t need = n * t->g.nchild();
-  int out = t->tmp, spare = t->old;
+  int out = t->tmp, spare = t->aux;
   if (t->kcap[out] < need && t->kcap[spare] >= need) std::swap(out, spare);
   if (t->kcap[out] < need) {
     // growing: grow the other free buffer with it, so that from now on one of
-    // the two free buffers always holds the bound (only one buffer is ever
-    // current) and steady cycles allocate nothing
-    LT_TRY(grow(&t->kbuf[out], &t->kcap[out], need));
-    LT_TRY(grow(&t->kbuf[spare], &t->kcap[spare], need));
+    // the free buffers holds the bound and steady cycles allocate nothing
+    LT_TRY(grow(t->A, &t->kbuf[out], &t->kcap[out], need));
+    LT_TRY(grow(t->A, &t->kbuf[spare], &t->kcap[spare], need));
   }
   // From a balanced tree, adapt also writes the first balance pass's marks.
   const bool marks = t->balanced;
   int64_t cap = t->kcap[out];
   if (marks) {
-    LT_TRY(grow(&t->mbuf[0], &t->mcap[0], need));
-    LT_TRY(grow(&t->elist, &t->elist_cap, need));
-    LT_TRY(grow(&t->fused, &t->fused_cap, need));
+    LT_TRY(grow(t->A, &t->mbuf[0], &t->mcap[0], need));
+    LT_TRY(grow(t->A, &t->elist, &t->elist_cap, need));
+    LT_TRY(grow(t->A, &t->fused, &t->fused_cap, need));
     cap = std::min(cap, std::min(t->mcap[0], std::min(t->elist_cap, t->fused_cap)));
   }
   ScanState st;
@@ -1202,10 +1262,13 @@ lt_status lt_adapt(lt_tree t, const int8_t* flags, void* stream) {
   LT_TRY(read_ctr(t, s));
   if (t->hctr->err & ERR_BAD_FLAG) return fail(LT_ERR_ARG, "flags must be -1, 0 or 1");
   if (t->hctr->err) return fail(LT_ERR_INTERNAL, "device check failed in lt_adapt");
-  // old <- cur, cur <- the output, tmp <- the other free buffer
+  // old <- cur, cur <- the output, the other free buffer and the superseded
+  // snapshot become the free ones
+  const int prev_old = t->old;
   t->old = t->cur;
   t->cur = out;
   t->tmp = spare;
+  t->aux = prev_old;
   t->n_old = n;
   t->n_cur = t->hctr->total;
   t->has_old = true;
@@ -1215,9 +1278,14 @@ lt_status lt_adapt(lt_tree t, const int8_t* flags, void* stream) {
   return LT_OK;
 }
 
-lt_status lt_balance(lt_tree t, void* stream) {
-  if (!t) return fail(LT_ERR_ARG, "NULL tree");
-  hipStream_t s = static_cast<hipStream_t>(stream);
+}  // extern "C"
+
+namespace {
+// The balance fixpoint from the leaves in kbuf[t->cur].  Each refinement pass
+// reads the current buffer and writes into one of the two free ones (tmp and
+// aux in turn), then makes its output current; the buffer that held the
+// leaves on entry is never written, so the caller can restore it.
+lt_status balance_passes(lt_tree t, hipStream_t s) {
   // One host readback per pass (the number of leaves to split).  The refine
   // pass's own consistency checks land in the error word and are read with
   // the next pass's count.
@@ -1227,7 +1295,7 @@ lt_status lt_balance(lt_tree t, void* stream) {
   const bool restricted = t->adapt_marks && t->mcap[0] >= t->n_cur;
   t->adapt_marks = false;
   if (!restricted) {
-    LT_TRY(grow(&t->mbuf[mi], &t->mcap[mi], t->n_cur));
+    LT_TRY(grow(t->A, &t->mbuf[mi], &t->mcap[mi], t->n_cur));
     k_fill_u32<<<unsigned(ceil_div(t->n_cur, 256)), 256, 0, s>>>(t->mbuf[mi], t->n_cur, 0u);
     LT_HIP(hipGetLastError());
   }
@@ -1267,27 +1335,61 @@ lt_status lt_balance(lt_tree t, void* stream) {
     const int64_t marked = int64_t(t->hctr->nmarked);
     if (marked == 0) break;
     const int64_t n_new = t->n_cur + marked * (t->g.nchild() - 1);
-    LT_TRY(grow(&t->kbuf[t->tmp], &t->kcap[t->tmp], n_new));
-    LT_TRY(grow(&t->mbuf[1 - mi], &t->mcap[1 - mi], n_new));
-    LT_TRY(grow(&t->elist, &t->elist_cap, n_new));
+    const int out = t->cur == t->tmp ? t->aux : t->tmp;
+    LT_TRY(grow(t->A, &t->kbuf[out], &t->kcap[out], n_new));
+    LT_TRY(grow(t->A, &t->mbuf[1 - mi], &t->mcap[1 - mi], n_new));
+    LT_TRY(grow(t->A, &t->elist, &t->elist_cap, n_new));
     ScanState st;
     // also zeroes the mark count and the examine list for the next pass
     LT_TRY(prep_scan(t, t->n_cur, kTileMax, s, 4, &st));
-    const int64_t cap = std::min(std::min(t->kcap[t->tmp], t->mcap[1 - mi]), t->elist_cap);
+    const int64_t cap = std::min(std::min(t->kcap[out], t->mcap[1 - mi]), t->elist_cap);
     k_balance_refine<<<grid_tiles(st), kScanBig, 0, s>>>(t->g, t->kbuf[t->cur], t->mbuf[mi],
-                                                        t->kbuf[t->tmp], t->mbuf[1 - mi], cap, st,
+                                                        t->kbuf[out], t->mbuf[1 - mi], cap, st,
                                                         nullptr, t->elist, &t->dctr->nexam,
                                                         t->elist_cap);
     LT_HIP(hipGetLastError());
     expect_total = n_new;
-    std::swap(t->cur, t->tmp);
+    t->cur = out;
     t->n_cur = n_new;
     mi = 1 - mi;
     invalidate(t);
   }
+  return LT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+lt_status lt_balance(lt_tree t, void* stream) {
+  if (!t) return fail(LT_ERR_ARG, "NULL tree");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int cur0 = t->cur;
+  const int64_t n0 = t->n_cur;
+  const bool conn0 = t->conn_valid, map0 = t->map_valid;
+  const int64_t hang0 = t->n_hang;
+  const lt_status st = balance_passes(t, s);
+  if (st != LT_OK) {
+    // strong guarantee: the leaves before the call are still in kbuf[cur0];
+    // connectivity and mapping arrays were not touched by the passes
+    t->cur = cur0;
+    t->n_cur = n0;
+    t->conn_valid = conn0;
+    t->map_valid = map0;
+    t->n_hang = hang0;
+    t->dir_valid = false;     // the directory may describe intermediate leaves
+    t->adapt_marks = false;   // the first pass's marks were consumed
+    return st;
+  }
+  if (t->cur != cur0) {  // cur0 and the free buffer the passes did not end in are free
+    if (t->cur == t->tmp)
+      t->tmp = cur0;
+    else
+      t->aux = cur0;
+  }
   t->balanced = true;
   return LT_OK;
 }
+
 
 lt_status lt_connect(lt_tree t, void* stream) {
   if (!t) return fail(LT_ERR_ARG, "NULL tree");
@@ -1295,12 +1397,12 @@ lt_status lt_connect(lt_tree t, void* stream) {
   const int64_t n = t->n_cur;
   const int nf = 2 * t->g.dim;
   const int width = 2 + (1 << (t->g.dim - 1));
-  LT_TRY(grow(&t->nbr, &t->nbr_cap, n * nf));
-  LT_TRY(grow(&t->hmask, &t->hmask_cap, n + kItems));
+  LT_TRY(grow(t->A, &t->nbr, &t->nbr_cap, n * nf));
+  LT_TRY(grow(t->A, &t->hmask, &t->hmask_cap, n + kItems));
   // initial table: one row per 16 leaves, as a captured cycle reserves (the
   // hanging faces sit on the refinement fronts: one per 90 leaves in the
   // 1.7M-leaf workload, more than one per 64 at 9M leaves)
-  LT_TRY(grow(&t->hang, &t->hang_cap, std::max<int64_t>(1024, n / 16) * width));
+  LT_TRY(grow(t->A, &t->hang, &t->hang_cap, std::max<int64_t>(1024, n / 16) * width));
   KeyDir D;
   LT_TRY(ensure_dir(t, s, &D));
   if (n > 0) {
@@ -1337,7 +1439,7 @@ lt_status lt_connect(lt_tree t, void* stream) {
     else  // the hanging-face table overflowed: grow it (with room for the next
           // cycles: a regrowth frees memory, which waits for the whole device)
           // and emit the rows again
-      LT_TRY(grow(&t->hang, &t->hang_cap, 2 * t->hcctr->total * width));
+      LT_TRY(grow(t->A, &t->hang, &t->hang_cap, 2 * t->hcctr->total * width));
   }
   if (rows < 0) return fail(LT_ERR_INTERNAL, "hanging-face table overflowed twice");
   t->n_hang = rows;
@@ -1369,7 +1471,7 @@ lt_status lt_transfer(lt_tree t, int p, int nvar, const double* u_old, int64_t l
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (!t->map_valid) LT_TRY(lt_map(t, stream));
   if (precision == 1) return launch_split_transfer(t, p, nvar, u_old, ld_old, u_new, ld_new, s);
-  LT_TRY(build_transfer_ops(p, &t->ops[p], s));
+  LT_TRY(build_transfer_ops(t->A, p, &t->ops[p], s));
   return launch_transfer(t, p, t->ops[p], nvar, u_old, ld_old, u_new, ld_new, s);
 }
 
@@ -1424,32 +1526,19 @@ lt_status lt_export(lt_tree t, lt_field what, void* dst, int64_t capacity, void*
 void lt_destroy(lt_tree t) {
   if (!t) return;
   (void)hipDeviceSynchronize();
-  for (auto& b : t->kbuf) if (b) (void)hipFree(b);
-  for (auto& b : t->mbuf) if (b) (void)hipFree(b);
-  if (t->nbr) (void)hipFree(t->nbr);
-  if (t->hmask) (void)hipFree(t->hmask);
-  if (t->fused) (void)hipFree(t->fused);
-  if (t->dir) (void)hipFree(t->dir);
-  if (t->hang) (void)hipFree(t->hang);
-  if (t->map_src) (void)hipFree(t->map_src);
-  if (t->map_kind) (void)hipFree(t->map_kind);
-  if (t->status) (void)hipFree(t->status);
-  if (t->lim) (void)hipFree(t->lim);
-  if (t->flag_tab) (void)hipFree(t->flag_tab);
-  if (t->mesh_offs) (void)hipFree(t->mesh_offs);
-  if (t->dctr) (void)hipFree(t->dctr);
+  const Alloc A = t->A;
+  auto fr = [&](void* p) { (void)dev_free(A, p); };
+  for (auto& b : t->kbuf) fr(b);
+  for (auto& b : t->mbuf) fr(b);
+  for (void* b : {(void*)t->nbr, (void*)t->hmask, (void*)t->fused, (void*)t->dir, (void*)t->hang,
+                  (void*)t->map_src, (void*)t->map_kind, (void*)t->status, (void*)t->lim,
+                  (void*)t->flag_tab, (void*)t->mesh_offs, (void*)t->dctr, (void*)t->cstatus,
+                  (void*)t->elist, (void*)t->cctr, t->split_frags, (void*)t->split_vec,
+                  (void*)t->split_R, (void*)t->split_F, (void*)t->copy_delta, (void*)t->grp_list})
+    fr(b);
+  for (auto& o : t->ops) fr(o);
   if (t->hctr) (void)hipHostFree(t->hctr);
-  if (t->cstatus) (void)hipFree(t->cstatus);
-  if (t->elist) (void)hipFree(t->elist);
-  if (t->cctr) (void)hipFree(t->cctr);
   if (t->hcctr) (void)hipHostFree(t->hcctr);
-  for (auto& o : t->ops) if (o) (void)hipFree(o);
-  if (t->split_frags) (void)hipFree(t->split_frags);
-  if (t->split_vec) (void)hipFree(t->split_vec);
-  if (t->split_R) (void)hipFree(t->split_R);
-  if (t->split_F) (void)hipFree(t->split_F);
-  if (t->copy_delta) (void)hipFree(t->copy_delta);
-  if (t->grp_list) (void)hipFree(t->grp_list);
   delete t;
 }
 

@@ -81,21 +81,41 @@ struct CycleRec {
 lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s);
 
 // Builds (once per degree) the FP64 1D transfer operators into ops.
-lt_status build_transfer_ops(int p, double** ops, hipStream_t stream);
+struct Alloc;
+lt_status build_transfer_ops(const Alloc& A, int p, double** ops, hipStream_t stream);
+
+// Device allocator of a tree (with its cycles) or a model: the one registered
+// with lt_set_allocator when the object was created, or hipMalloc / hipFree
+// when none was.  Every device buffer an object owns goes through it.
+struct Alloc {
+  void* (*alloc)(size_t bytes, void* stream, void* ctx) = nullptr;
+  void (*free_)(void* ptr, void* stream, void* ctx) = nullptr;
+  void* ctx = nullptr;
+};
+// The allocator registered now (copied into each new object), and its
+// replacement (lt_set_allocator).
+Alloc registered_alloc();
+void register_alloc(const Alloc& A);
+// hipMalloc semantics: hipSuccess and *p set, or an error and *p = NULL.
+hipError_t dev_malloc(const Alloc& A, void** p, size_t bytes);
+// Frees p (NULL is ignored).  The device is synchronised first, as hipFree
+// does, so no kernel still in flight can touch the memory a caching
+// allocator hands out again.
+hipError_t dev_free(const Alloc& A, void* p);
 
 // Grow a device buffer to hold `need` elements (contents are not kept).
 template <class T>
-inline lt_status grow(T** p, int64_t* cap, int64_t need) {
+inline lt_status grow(const Alloc& A, T** p, int64_t* cap, int64_t need) {
   if (need <= *cap && *p) return LT_OK;
   int64_t ncap = std::max<int64_t>(need + need / 4, 1024);
   if (*p) {
-    hipError_t e = hipFree(*p);
+    hipError_t e = dev_free(A, *p);
     *p = nullptr;
     *cap = 0;
-    if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("hipFree: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("device free: ") + hipGetErrorString(e));
   }
   void* q = nullptr;
-  hipError_t e = hipMalloc(&q, size_t(ncap) * sizeof(T));
+  hipError_t e = dev_malloc(A, &q, size_t(ncap) * sizeof(T));
   if (e != hipSuccess || !q)
     return fail(LT_ERR_OOM, "device allocation of " + std::to_string(size_t(ncap) * sizeof(T)) +
                                 " bytes failed");
@@ -118,10 +138,16 @@ namespace lt {
 // clear; captured cycles), 4 = also clear the lists.
 lt_status prep_scan(lt_tree_s* t, int64_t n_items, int64_t tile, hipStream_t stream, int flags,
                     ScanState* st);
+// The same over caller-provided look-back words (status_cap of them) and
+// counters, allocating nothing (LT_ERR_ARG when the words do not suffice).
+lt_status prep_scan_fixed(uint64_t* status, int64_t status_cap, DevCtr* ctr, int64_t n_items,
+                          int64_t tile, hipStream_t stream, int flags, ScanState* st);
 // The same on connectivity's own look-back words and counters, so that
 // lt_connect may run beside lt_map and lt_transfer on another stream.
 lt_status prep_scan_conn(lt_tree_s* t, int64_t n_items, hipStream_t stream, int flags,
                          ScanState* st);
+// A new tree with no leaves yet (geometry checked, counters allocated).
+lt_status create_tree(const lt_geom* geom, lt_tree_s** out);
 // Copy the device counters to the pinned mirror and wait for the stream.
 lt_status read_ctr(lt_tree_s* t, hipStream_t stream);
 // Zero the counters and the error word.
@@ -171,11 +197,16 @@ struct TransferTune {
 
 struct lt_tree_s {
   lt::KeyGeom g{};
+  lt::Alloc A;  // device allocator of every buffer below (and of the tree's cycles)
   TransferTune tune;
   int device = 0;
-  uint64_t* kbuf[3] = {nullptr, nullptr, nullptr};
-  int64_t kcap[3] = {0, 0, 0};
-  int cur = 0, tmp = 1, old = 2;  // roles of the three key buffers
+  // Four key buffers in four roles: the current leaves, the leaves before the
+  // last adapt (the old tree of lt_map / lt_transfer), and two free ones that
+  // adapt and balance write into.  A call swaps roles only once it has
+  // succeeded, so on any error the current and old leaves are as before.
+  uint64_t* kbuf[4] = {nullptr, nullptr, nullptr, nullptr};
+  int64_t kcap[4] = {0, 0, 0, 0};
+  int cur = 0, tmp = 1, old = 2, aux = 3;  // roles of the four key buffers
   int64_t n_cur = 0, n_old = -1, n_hang = -1;
   bool has_old = false;
   bool balanced = false;     // the current leaves are known to be 2:1 balanced

@@ -153,6 +153,33 @@ def workload_ensemble(seed: int = 4000, nmesh: int = 64) -> list:
     return out
 
 
+def surface_points(dim: int, n: int, seed: int, kind: str = "sphere") -> np.ndarray:
+    """(n, dim) points sampled uniformly on a closed surface inside [-5,5]^dim,
+    a stand-in for the surface geometry the paper builds initial trees from
+    (Section 5.1): a circle (2D) or sphere (3D) of radius 3, or (3D, kind
+    "torus") a torus of radii 3 and 1 about the z axis, centred off the
+    origin so that the cloud does not align with the tree."""
+    g = rng(seed)
+    c = np.array([0.137, -0.211, 0.073][:dim])
+    if dim == 2:
+        th = g.uniform(0.0, 2.0 * math.pi, n)
+        return c + 3.0 * np.stack([np.cos(th), np.sin(th)], axis=1)
+    if kind == "torus":
+        # area-uniform: accept the tube angle with probability (R + r cos v) / (R + r)
+        out = np.zeros((0, 3))
+        while len(out) < n:
+            u = g.uniform(0.0, 2.0 * math.pi, 2 * n)
+            v = g.uniform(0.0, 2.0 * math.pi, 2 * n)
+            keep = g.random(2 * n) < (3.0 + np.cos(v)) / 4.0
+            u, v = u[keep], v[keep]
+            p = np.stack([(3.0 + np.cos(v)) * np.cos(u), (3.0 + np.cos(v)) * np.sin(u), np.sin(v)],
+                         axis=1)
+            out = np.concatenate([out, p])
+        return c + out[:n]
+    x = g.standard_normal((n, 3))
+    return c + 3.0 * x / np.linalg.norm(x, axis=1, keepdims=True)
+
+
 def mlp_init(seed: int) -> np.ndarray:
     """He-normal initial parameters of the 320 -> 128 -> 64 -> 3 indicator
     network, flat FP32: W1[128][320], b1[128], W2[64][128], b2[64], W3[3][64], b3[3]."""

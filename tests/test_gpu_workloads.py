@@ -6,8 +6,10 @@ up to ~1.7M leaves) run through the C ABI in the launch configuration the
 benchmark times.  Flags, keys, connectivity and the mapping are checked bit
 for bit against SHA-256 hashes of the oracle's arrays (tests/golden, written
 by make_workload_golden.py from the oracle only).  The transfer is checked on
-a seeded sample of new elements against the oracle's dense operators applied
-to the same synthetic input; the small 2D workload is checked in full."""
+every refined and fused element and a seeded 1% of the copies against the
+oracle's dense operators applied to the same synthetic input, per class
+(copies bit-exact; refined and fused within 1e-13); the small 2D workload is
+checked in full against the oracle's tree transfer."""
 import hashlib
 import json
 import os
@@ -18,7 +20,7 @@ import pytest
 import oracle
 from paper_2306_06744_amd import synth
 
-from gpu_util import rel_l2
+from gpu_util import assert_transfer, changed_and_sampled, dense_expected
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -31,30 +33,6 @@ def sha(a):
 def golden(name):
     with open(os.path.join(HERE, "golden", f"workload_{name}.json")) as fh:
         return json.load(fh)["cycles"]
-
-
-def sampled_transfer_check(dim, p, u_old, u_new, src, kind, rng, nsample=3000):
-    I, P = oracle.operators(dim, p)
-    n = u_new.shape[2]
-    js = rng.choice(n, size=min(nsample, n), replace=False)
-    # always include some of each kind
-    for k in (0, -1):
-        idx = np.flatnonzero(kind == k)
-        if len(idx):
-            js = np.concatenate([js, rng.choice(idx, size=min(200, len(idx)), replace=False)])
-    idx = np.flatnonzero(kind > 0)
-    if len(idx):
-        js = np.concatenate([js, rng.choice(idx, size=min(200, len(idx)), replace=False)])
-    exp = np.zeros((u_old.shape[0], u_old.shape[1], len(js)))
-    for t, j in enumerate(js):
-        s, k = int(src[j]), int(kind[j])
-        if k == 0:
-            exp[:, :, t] = u_old[:, :, s]
-        elif k > 0:
-            exp[:, :, t] = u_old[:, :, s] @ I[k - 1].T
-        else:
-            exp[:, :, t] = sum(u_old[:, :, s + c] @ P[c].T for c in range(1 << dim))
-    return rel_l2(u_new[:, :, js], exp)
 
 
 @pytest.mark.parametrize("name,maker,seed", [("2d_small", synth.workload_2d_small, 1000),
@@ -89,8 +67,9 @@ def test_workload_cycles_bit_exact(name, maker, seed):
         assert sha(src) == rec["map_src"] and sha(kind) == rec["map_kind"], "mapping"
         u_old = torch.from_numpy(synth.random_solution(seed + cyc, w.nvar, npts, rec["n_old"])).cuda()
         u_new = t.transfer(w.p, u_old).cpu().numpy()
-        err = sampled_transfer_check(w.dim, w.p, u_old.cpu().numpy(), u_new, src, kind, rng)
-        assert err <= 1e-13, f"transfer sample rel L2 {err:.3e}"
+        js = changed_and_sampled(kind, rng)
+        exp = dense_expected(w.dim, w.p, u_old.cpu().numpy(), src, kind, js)
+        assert_transfer(u_new[:, :, js], exp, kind[js], 1e-13, f"{name} cycle {cyc}")
         del u_old, u_new
         torch.cuda.empty_cache()
 
@@ -109,4 +88,5 @@ def test_small_workload_transfer_full():
     t.balance()
     o.balance()
     u = synth.random_solution(1000, w.nvar, (w.p + 1) ** w.dim, o.old_size())
-    assert rel_l2(t.transfer(w.p, torch.from_numpy(u).cuda()).cpu().numpy(), o.transfer(w.p, u)) <= 1e-13
+    assert_transfer(t.transfer(w.p, torch.from_numpy(u).cuda()).cpu().numpy(), o.transfer(w.p, u),
+                    o.map()[1], 1e-13, "2d workload")
