@@ -269,6 +269,46 @@ lt_status lt_autotune_transfer(lt_tree t, int p, int nvar, const double* u_old, 
 lt_status lt_set_tuning(lt_tree t, const lt_tune* tune);
 lt_status lt_get_tuning(lt_tree t, lt_tune* tune);
 
+/* ------------------------------------------------------------------------
+ * Flux reconstruction on the current (2:1-balanced, connected, periodic)
+ * tree for the Euler equations: 2D (rho, rho u, rho v, E), 3D (rho, rho u,
+ * rho v, rho w, E); p = (p+1)^dim Gauss-Legendre solution points per element,
+ * u[(v * n_p + i) * ld + e] as lt_transfer; gamma > 1; the tree's cube has
+ * physical edge `length`.  All three need lt_connect on the current leaves
+ * (LT_ERR_STATE otherwise), a tree periodic on every axis and a single mesh
+ * (LT_ERR_ARG), p 1..3 in 3D and 1..7 in 2D.  Asynchronous; the tree keeps a
+ * face buffer of 2 dim (dim+2) (p+1)^(dim-1) doubles per leaf.
+ * ------------------------------------------------------------------------ */
+
+/* Common normal fluxes at every element face (Section 4.3, Algorithm
+ * "Procedure of common flux calculations"): the solution's traces at the
+ * face points; a conforming face takes the Rusanov flux of its two traces; at
+ * a hanging face the coarse trace is L2-projected onto each of the 2^(dim-1)
+ * mortars (eq. interpolation_operator), the fine traces are copied onto them,
+ * the Rusanov flux is taken on each mortar, each fine face receives its
+ * mortar's flux and the coarse face the L2 projection of the mortar fluxes
+ * (eq. projection_operator).  Each face slot has one writer: deterministic,
+ * no atomics.  fhat: device FP64, fhat[((f * (dim+2) + v) * nfp + q) * ld_f + e]
+ * with face f = 2 axis + side, face point q over the tangential axes in
+ * increasing order (the lower fastest), nfp = (p+1)^(dim-1); the value is the
+ * flux component along the face's axis (not multiplied by an outward sign). */
+lt_status lt_fr_face_flux(lt_tree t, int p, const double* u, int64_t ld, double gamma, double* fhat,
+                          int64_t ld_f, void* stream);
+
+/* FR residual R = -sum_a d f_a / d x_a (Section 2.1): along every line of
+ * solution points the flux polynomial's derivative plus the Radau
+ * corrections g_L'(f^(-1) - f(-1)) + g_R'(f^(1) - f(1)) with the common fluxes
+ * above, scaled by 2/h.  R: device FP64, layout as u with ld_r >= n_cur, not
+ * aliasing u. */
+lt_status lt_fr_residual(lt_tree t, int p, const double* u, int64_t ld, double gamma, double length,
+                         double* R, int64_t ld_r, void* stream);
+
+/* `steps` steps of the three-stage Runge-Kutta scheme (eq. rk3) in place on
+ * u, with time step dt; work: device FP64 of u's shape and ld, not aliasing u
+ * (holds the intermediate stages). */
+lt_status lt_fr_rk3(lt_tree t, int p, double* u, int64_t ld, double* work, double dt, double gamma,
+                    double length, int steps, void* stream);
+
 /* Host-side sizes (no device work): current leaves, leaves before the last
  * lt_adapt (-1 if none), rows of the hanging-face table (-1 before lt_connect).
  * Any pointer may be NULL. */

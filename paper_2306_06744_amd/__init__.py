@@ -30,7 +30,8 @@ EXPORTS = ["lt_set_allocator", "lt_build_uniform", "lt_build", "lt_build_points"
            "lt_mlp_grads", "lt_mlp_train_step", "lt_mlp_infer", "lt_flag_mlp", "lt_vortex_field",
            "lt_flag_modal", "lt_mlp_destroy", "lt_cycle_create", "lt_cycle_run",
            "lt_cycle_stats", "lt_cycle_destroy", "lt_autotune_transfer", "lt_set_tuning",
-           "lt_get_tuning", "lt_last_error", "lt_destroy"]
+           "lt_get_tuning", "lt_fr_face_flux", "lt_fr_residual", "lt_fr_rk3", "lt_last_error",
+           "lt_destroy"]
 MLP_NPARAM = 128 * 320 + 128 + 64 * 128 + 64 + 3 * 64 + 3
 
 
@@ -113,6 +114,9 @@ def lib() -> C.CDLL:
         L.lt_autotune_transfer.argtypes = [P, i32, i32, P, i64, P, i64, i32, P, C.POINTER(Tune)]
         L.lt_set_tuning.argtypes = [P, C.POINTER(Tune)]
         L.lt_get_tuning.argtypes = [P, C.POINTER(Tune)]
+        L.lt_fr_face_flux.argtypes = [P, i32, P, i64, C.c_double, P, i64, P]
+        L.lt_fr_residual.argtypes = [P, i32, P, i64, C.c_double, C.c_double, P, i64, P]
+        L.lt_fr_rk3.argtypes = [P, i32, P, i64, P, C.c_double, C.c_double, C.c_double, i32, P]
         L.lt_cycle_destroy.argtypes = [P]
         L.lt_cycle_destroy.restype = None
         L.lt_last_error.restype = C.c_char_p
@@ -390,6 +394,33 @@ class Tree:
         _check(lib().lt_transfer(self._h, p, nvar, _dptr(u_old), ld_old, _dptr(u_new),
                                  u_new.shape[2], precision, _stream()))
         return u_new
+
+    # ---- flux reconstruction (Euler, periodic)
+    def fr_face_flux(self, p, u, gamma=1.4):
+        """Common normal fluxes at every face: (2 dim, dim+2, (p+1)^(dim-1), n)."""
+        torch = _torch()
+        n = self.size()
+        nfp = (p + 1) ** (self.dim - 1)
+        out = torch.empty((2 * self.dim, self.dim + 2, nfp, n), dtype=torch.float64, device="cuda")
+        _check(lib().lt_fr_face_flux(self._h, int(p), _dptr(u), u.shape[2], float(gamma), _dptr(out),
+                                     n, _stream()))
+        return out
+
+    def fr_residual(self, p, u, length, gamma=1.4, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty((u.shape[0], u.shape[1], self.size()), dtype=torch.float64,
+                              device="cuda")
+        _check(lib().lt_fr_residual(self._h, int(p), _dptr(u), u.shape[2], float(gamma),
+                                    float(length), _dptr(out), out.shape[2], _stream()))
+        return out
+
+    def fr_rk3(self, p, u, work, dt, length, gamma=1.4, steps=1):
+        """steps RK3 steps in place on u (work: same shape)."""
+        assert work.shape == u.shape
+        _check(lib().lt_fr_rk3(self._h, int(p), _dptr(u), u.shape[2], _dptr(work), float(dt),
+                               float(gamma), float(length), int(steps), _stream()))
+        return u
 
     # ---- results
     def autotune_transfer(self, p, u_old, u_new, precision=0):

@@ -17,7 +17,7 @@ SO = os.path.join(HERE, "liblt.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["lt_tree.hip", "lt_flag.hip", "lt_transfer.hip", "lt_split.hip", "lt_mlp.hip", "lt_cycle.hip",
-           "lt_build.hip"]
+           "lt_build.hip", "lt_fr.hip"]
 NO_CONTRACT = {"lt_flag.hip", "lt_build.hip"}
 HEADERS = ["keys.hpp", "scan.hpp", "tree.hpp"]
 

@@ -1537,6 +1537,8 @@ void lt_destroy(lt_tree t) {
                   (void*)t->split_R, (void*)t->split_F, (void*)t->copy_delta, (void*)t->grp_list})
     fr(b);
   for (auto& o : t->ops) fr(o);
+  for (auto& o : t->fr_tab) fr(o);
+  fr(t->fr_fb);
   if (t->hctr) (void)hipHostFree(t->hctr);
   if (t->hcctr) (void)hipHostFree(t->hcctr);
   delete t;

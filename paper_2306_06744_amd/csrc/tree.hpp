@@ -261,6 +261,9 @@ struct lt_tree_s {
   int64_t split_R_cap = 0;
   int32_t* split_F = nullptr;   // fused parents
   int64_t split_F_cap = 0;
+  double* fr_tab[LT_MAX_DEGREE + 1] = {};  // flux reconstruction: 1D tables per degree
+  double* fr_fb = nullptr;                  // flux reconstruction: face traces / common fluxes
+  int64_t fr_fb_cap = 0;
   int32_t* grp_list = nullptr;  // 64-element groups holding refined/fused elements
   int64_t grp_cap = 0;
   int64_t* copy_delta = nullptr;  // per copy chunk: source offset of a pure run, or a flag

@@ -247,6 +247,8 @@ def test_split_transfer_error_bound(large):
     kind_t = torch.from_numpy(large["kind"]).cuda()
     for name, sel in (("refined", kind_t > 0), ("fused", kind_t < 0), ("copy", kind_t == 0)):
         idx = torch.nonzero(sel).flatten()
+        if idx.numel() == 0:
+            continue
         x, y = a.index_select(2, idx), b.index_select(2, idx)
         l2 = float(torch.linalg.vector_norm(x - y) / torch.linalg.vector_norm(y))
         mx = float((x - y).abs().max() / y.abs().max())
