@@ -246,6 +246,22 @@ lt_status lt_map(lt_tree t, void* stream);
 lt_status lt_transfer(lt_tree t, int p, int nvar, const double* u_old, int64_t ld_old,
                       double* u_new, int64_t ld_new, int precision, void* stream);
 
+/* lt_transfer at precision 0 for callers that cannot allocate device memory
+ * (code under hipGraph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same results bit for bit, but the
+ * transfer's scratch -- copy-run source offsets, interpolation-group lists,
+ * look-back words, counters, the FP64 1D operators -- lives in a static
+ * device array of the library (about 5.3 MiB, one copy per GPU, kept until
+ * the process ends) instead of buffers the tree grows.  The call allocates
+ * nothing: it needs the mapping of the last adaptation already computed
+ * (lt_map, or an earlier lt_transfer; LT_ERR_STATE otherwise), at most 2^25
+ * current leaves (LT_ERR_ARG otherwise), and the tree's device current.
+ * Every call on one GPU shares that array, so calls that overlap on one GPU
+ * (on different streams, or from several threads) race; serialise them.
+ * Arguments, layout and supported degrees as lt_transfer.  Asynchronous. */
+lt_status lt_transfer_noalloc(lt_tree t, int p, int nvar, const double* u_old, int64_t ld_old,
+                              double* u_new, int64_t ld_new, void* stream);
+
 /* Tuning of the transfer's launch shapes (results never depend on them):
  * elements per lane of the copy pass (1, 2 or 4; one block row covers 256
  * times that many elements) and persistent workgroups per variable of the

@@ -25,7 +25,7 @@ STATUS = {0: "LT_OK", 1: "LT_ERR_ARG", 2: "LT_ERR_OOM", 3: "LT_ERR_HIP", 4: "LT_
 # Every symbol include/lt.h declares.
 EXPORTS = ["lt_set_allocator", "lt_build_uniform", "lt_build", "lt_build_points", "lt_build_batch", "lt_flag_batch", "lt_mesh_offsets",
            "lt_flag", "lt_adapt", "lt_balance", "lt_connect", "lt_set_connect_grid", "lt_map",
-           "lt_transfer", "lt_size",
+           "lt_transfer", "lt_transfer_noalloc", "lt_size",
            "lt_view", "lt_export", "lt_mlp_create", "lt_mlp_params", "lt_mlp_features",
            "lt_mlp_grads", "lt_mlp_train_step", "lt_mlp_infer", "lt_flag_mlp", "lt_vortex_field",
            "lt_flag_modal", "lt_mlp_destroy", "lt_cycle_create", "lt_cycle_run",
@@ -94,6 +94,7 @@ def lib() -> C.CDLL:
         L.lt_set_connect_grid.argtypes = [P, i32]
         L.lt_map.argtypes = [P, P]
         L.lt_transfer.argtypes = [P, i32, i32, P, i64, P, i64, i32, P]
+        L.lt_transfer_noalloc.argtypes = [P, i32, i32, P, i64, P, i64, P]
         L.lt_size.argtypes = [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
         L.lt_view.argtypes = [P, i32, C.POINTER(P), C.POINTER(i64)]
         L.lt_export.argtypes = [P, i32, P, i64, P]
@@ -393,6 +394,15 @@ class Tree:
             u_new = torch.empty((nvar, npts, n), dtype=torch.float64, device="cuda")
         _check(lib().lt_transfer(self._h, p, nvar, _dptr(u_old), ld_old, _dptr(u_new),
                                  u_new.shape[2], precision, _stream()))
+        return u_new
+
+    def transfer_noalloc(self, p, u_old, u_new):
+        """lt_transfer_noalloc: the FP64 transfer into the caller's u_new
+        (nvar, n_p, ld_new) with no device allocation; needs map() first."""
+        torch = _torch()
+        assert u_old.dtype == torch.float64 and u_new.dtype == torch.float64
+        _check(lib().lt_transfer_noalloc(self._h, int(p), u_old.shape[0], _dptr(u_old), u_old.shape[2],
+                                         _dptr(u_new), u_new.shape[2], _stream()))
         return u_new
 
     # ---- flux reconstruction (Euler, periodic)

@@ -16,6 +16,8 @@
 // rather than by FP64 throughput.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <algorithm>
 #include <string>
 
@@ -510,7 +512,7 @@ __global__ __launch_bounds__(64 * N) void k_interp3(const double* __restrict__ o
 // tuning), the interpolation-group lists (the ordered list of groups with a
 // refined element, then the groups holding a fused one: 2 ceil(n / 64)),
 // look-back words and counters.  From the tree's buffers (lt_transfer) or
-// from storage of a fixed size that the caller provides.
+// from the library's static array (lt_transfer_noalloc).
 struct XferScratch {
   int64_t* copy_delta;
   int32_t* grp_list;
@@ -686,10 +688,86 @@ lt_status launch_transfer(lt_tree_s* t, Count n, const int64_t* ngroups_dev, int
 
 }  // namespace lt
 
+// ------------------------------------------------------- allocation-free form
+namespace lt {
+namespace {
+
+// Static scratch of lt_transfer_noalloc, one copy per GPU (the device keeps
+// it until the process ends), laid out for up to kNoallocLeaves new leaves:
+//   [0, 4 KiB)       FP64 1D operators (4 (p+1)^2 + (p+1) doubles, p <= 7)
+//   [4 KiB, 8 KiB)   counters (DevCtr)
+//   [8 KiB, 16 KiB)  look-back words of the group scan
+//   then             copy-chunk source offsets, interpolation-group lists.
+constexpr int64_t kNoallocLeaves = int64_t(1) << 25;
+constexpr size_t kOffOps = 0, kOffCtr = 4096, kOffStatus = 8192, kOffDelta = 16384;
+constexpr int64_t kStatusWords = (kOffDelta - kOffStatus) / 8;
+constexpr int64_t kDeltaWords = kNoallocLeaves / 256 + 2;
+constexpr size_t kOffGroups = kOffDelta + size_t(kDeltaWords) * 8;
+constexpr int64_t kGroupWords = 2 * (kNoallocLeaves / 64 + 2);
+constexpr size_t kScratchBytes = (kOffGroups + size_t(kGroupWords) * 4 + 255) / 256 * 256;
+static_assert(sizeof(double) * (4 * 8 * 8 + 8) <= kOffCtr - kOffOps, "operators fit");
+static_assert(sizeof(DevCtr) <= kOffStatus - kOffCtr, "counters fit");
+static_assert((kNoallocLeaves / 64 + kTileMin - 1) / kTileMin <= kStatusWords, "look-back words fit");
+
+// In host code this name is only a stand-in for the symbol: the device
+// address comes from hipGetSymbolAddress, per device.
+static __device__ __align__(256) uint64_t scratch[kScratchBytes / 8];
+
+std::mutex g_scratch_mu;
+void* g_scratch_dev[64] = {};
+
+// The device address of `scratch` on the current device, looked up on the
+// first call there.
+lt_status scratch_address(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= 64) return fail(LT_ERR_ARG, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(LT_ERR_HIP, std::string("static scratch address: ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = p;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_dev[dev]);
+  return LT_OK;
+}
+
+}  // namespace
+}  // namespace lt
+
 // ------------------------------------------------------------------ tuning
 using namespace lt;
 
 extern "C" {
+
+lt_status lt_transfer_noalloc(lt_tree t, int p, int nvar, const double* u_old, int64_t ld_old,
+                              double* u_new, int64_t ld_new, void* stream) {
+  if (!t || !u_old || !u_new) return fail(LT_ERR_ARG, "NULL argument");
+  if (nvar < 1) return fail(LT_ERR_ARG, "nvar must be positive");
+  if (p < 1 || p > (t->g.dim == 3 ? 3 : LT_MAX_DEGREE))
+    return fail(LT_ERR_ARG, "unsupported polynomial degree for this dimension");
+  if (t->n_cur > kNoallocLeaves)
+    return fail(LT_ERR_ARG, "lt_transfer_noalloc takes at most 2^25 leaves (" +
+                                std::to_string(t->n_cur) + " given)");
+  if (!t->has_old || !t->map_valid)
+    return fail(LT_ERR_STATE, "lt_transfer_noalloc needs the mapping of an adaptation (lt_map)");
+  if (ld_old < t->n_old || ld_new < t->n_cur) return fail(LT_ERR_ARG, "leading dimension too small");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(LT_ERR_HIP, "hipGetDevice");
+  if (dev != t->device) return fail(LT_ERR_ARG, "the tree lives on another device than the current one");
+  unsigned char* base = nullptr;
+  LT_TRY_STATUS(scratch_address(dev, &base));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* ops = reinterpret_cast<double*>(base + kOffOps);
+  k_build_ops<<<1, 64, 0, s>>>(p + 1, ops);
+  if (hipGetLastError() != hipSuccess) return fail(LT_ERR_HIP, "operator build launch");
+  const XferScratch X{reinterpret_cast<int64_t*>(base + kOffDelta),
+                      reinterpret_cast<int32_t*>(base + kOffGroups),
+                      reinterpret_cast<uint64_t*>(base + kOffStatus), kStatusWords,
+                      reinterpret_cast<DevCtr*>(base + kOffCtr)};
+  return transfer_with(t->g.dim, t->tune, t->map_src, t->map_kind, Count{t->n_cur, nullptr}, nullptr,
+                       p, ops, nvar, u_old, ld_old, u_new, ld_new, X, s);
+}
 
 lt_status lt_set_tuning(lt_tree t, const lt_tune* tune) {
   if (!t || !tune) return fail(LT_ERR_ARG, "NULL argument");
