@@ -166,6 +166,21 @@ lt_status lt_build_batch(const lt_geom* geom, int nmesh, const int* d_min, const
 lt_status lt_flag_batch(lt_tree t, const lt_flag_params* per_mesh, int nmesh, int8_t* flags,
                         void* stream);
 
+/* Per-mesh degrees of a 3D ensemble for lt_transfer_mixed and for captured
+ * cycles with p = -1 (host array of nmesh values, each 1..3; form 2 of the
+ * cycle with meshes of different order).  Synchronises. */
+lt_status lt_set_mesh_degree(lt_tree t, const int* p, void* stream);
+
+/* FP64 solution transfer (Section 4.2) of an ensemble whose meshes have
+ * their own degree (lt_set_mesh_degree), every kernel one launch for all
+ * meshes and degrees.  Layout u[(v * NPM + i) * ld + e] with NPM the largest
+ * (p+1)^3 over the meshes; an element of a mesh of degree p uses the rows
+ * i < (p+1)^3 of each variable block, and its other rows are neither read nor
+ * written.  Otherwise as lt_transfer at precision 0 (LT_ERR_STATE without
+ * degrees or a prior lt_adapt).  Asynchronous unless the mapping was stale. */
+lt_status lt_transfer_mixed(lt_tree t, int nvar, const double* u_old, int64_t ld_old, double* u_new,
+                            int64_t ld_new, void* stream);
+
 /* offsets[m] = index of the first leaf of mesh m, offsets[nmesh] = n_cur
  * (host array of nmesh + 1; a single tree has nmesh = 1).  Synchronises. */
 lt_status lt_mesh_offsets(lt_tree t, int64_t* offsets, void* stream);
@@ -414,16 +429,18 @@ lt_status lt_flag_modal(lt_tree t, int p, const double* u, int64_t ld, double ta
  * lt_transfer with a leading dimension ld >= capacity) hold the solution
  * alternately.  Balance runs
  * `balance_passes` one-level passes (even, >= 2) and a check pass.
- * flag_template (host, nmesh entries, nmesh = the tree's mesh count) fixes the
- * degree p of the flag points, the geometry and the criterion's form; each run
- * passes the cycle's own parameters (e.g. advected centres) with the same p.
+ * flag_template (host, nmesh entries, nmesh = the tree's mesh count) fixes
+ * each mesh's degree p of the flag points (meshes may differ), the geometry
+ * and the criterion's form; each run passes the cycle's own parameters (e.g.
+ * advected centres) with the same degrees.
  * The transfer may be FP64 (3D p 1..3, 2D p 1..7) or split precision
  * (64 points per element), and the flags geometric or learned (lt_flag_mlp:
  * the network over the geometric fallback below conf_min; the network's
  * weights are read at each replay, so training between runs takes effect). */
 typedef struct lt_cycle_s* lt_cycle;
 typedef struct {
-  int p;                  /* transfer degree                                        */
+  int p;                  /* transfer degree, or -1: each mesh's own degree          */
+                          /*   (lt_set_mesh_degree; lt_transfer_mixed layout, FP64)  */
   int nvar;               /* variables; nvar * (p+1)^dim <= 65535                   */
   int64_t capacity;       /* leaves the graph's buffers hold (>= current leaves)     */
   int64_t ld;             /* leading dimension of u[0], u[1] (>= capacity)          */

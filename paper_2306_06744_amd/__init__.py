@@ -23,7 +23,8 @@ STATUS = {0: "LT_OK", 1: "LT_ERR_ARG", 2: "LT_ERR_OOM", 3: "LT_ERR_HIP", 4: "LT_
           8: "LT_ERR_INTERNAL", 9: "LT_ERR_CAPACITY"}
 
 # Every symbol include/lt.h declares.
-EXPORTS = ["lt_set_allocator", "lt_build_uniform", "lt_build", "lt_build_points", "lt_build_batch", "lt_flag_batch", "lt_mesh_offsets",
+EXPORTS = ["lt_set_allocator", "lt_build_uniform", "lt_build", "lt_build_points", "lt_build_batch",
+           "lt_flag_batch", "lt_mesh_offsets", "lt_set_mesh_degree", "lt_transfer_mixed",
            "lt_flag", "lt_adapt", "lt_balance", "lt_connect", "lt_set_connect_grid", "lt_map",
            "lt_transfer", "lt_transfer_noalloc", "lt_size",
            "lt_view", "lt_export", "lt_mlp_create", "lt_mlp_params", "lt_mlp_features",
@@ -87,6 +88,8 @@ def lib() -> C.CDLL:
         L.lt_build_batch.argtypes = [C.POINTER(Geom), i32, P, P, P, P, C.POINTER(P)]
         L.lt_flag_batch.argtypes = [P, P, i32, P, P]
         L.lt_mesh_offsets.argtypes = [P, P, P]
+        L.lt_set_mesh_degree.argtypes = [P, P, P]
+        L.lt_transfer_mixed.argtypes = [P, i32, P, i64, P, i64, P]
         L.lt_flag.argtypes = [P, C.POINTER(FlagParams), P, P]
         L.lt_adapt.argtypes = [P, P, P]
         L.lt_balance.argtypes = [P, P]
@@ -317,6 +320,22 @@ class Tree:
         _check(lib().lt_flag_batch(self._h, C.cast(fps, C.c_void_p), len(per_mesh), _dptr(out),
                                    _stream()))
         return out
+
+    def set_mesh_degree(self, degrees):
+        """Per-mesh degrees (lt_set_mesh_degree) for transfer_mixed / mixed cycles."""
+        arr = (C.c_int * len(degrees))(*[int(x) for x in degrees])
+        _check(lib().lt_set_mesh_degree(self._h, arr, _stream()))
+        self.degrees = [int(x) for x in degrees]
+
+    def transfer_mixed(self, u_old, u_new=None):
+        """u_old: (nvar, NPM, ld_old) with NPM the largest (p+1)^3 -> (nvar, NPM, n_cur)."""
+        torch = _torch()
+        nvar, npm, ld_old = u_old.shape
+        if u_new is None:
+            u_new = torch.empty((nvar, npm, self.size()), dtype=torch.float64, device="cuda")
+        _check(lib().lt_transfer_mixed(self._h, nvar, _dptr(u_old), ld_old, _dptr(u_new),
+                                       u_new.shape[2], _stream()))
+        return u_new
 
     def mesh_offsets(self):
         nm = getattr(self, "nmesh", 1)

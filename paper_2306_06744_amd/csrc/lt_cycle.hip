@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -104,7 +105,14 @@ lt_status reserve(lt_cycle c, hipStream_t s) {
     if (dev_malloc(t->A, &t->flag_tab, flag_args_size() * size_t(c->nmesh)) != hipSuccess)
       return fail(LT_ERR_OOM, "flag table");
   }
-  LT_TRY_STATUS(build_transfer_ops(t->A, c->d.p, &t->ops[c->d.p], s));
+  if (c->d.p > 0) {
+    LT_TRY_STATUS(build_transfer_ops(t->A, c->d.p, &t->ops[c->d.p], s));
+  } else {  // per-mesh degrees: every degree's operators, the chunk table and room for the entries
+    for (int p = 1; p <= 3; ++p)
+      if (t->mesh_degs & (1u << p)) LT_TRY_STATUS(build_transfer_ops(t->A, p, &t->ops[p], s));
+    LT_TRY_STATUS(grow(t->A, &t->chunk_np, &t->chunk_np_cap, C / 256 + 2));
+    LT_TRY_STATUS(grow(t->A, &t->grp_list, &t->grp_cap, 6 * (C / 64 + 2)));
+  }
   if (c->d.precision == 1) {
     LT_TRY_STATUS(prepare_split(t, c->d.p, s));
     LT_TRY_STATUS(grow(t->A, &t->split_R, &t->split_R_cap, C));
@@ -147,8 +155,10 @@ lt_status capture(lt_cycle c) {
     r.un = c->d.u[1 - q];
     r.ld = c->d.ld;
     r.fp0 = c->tmpl[0];
+    r.tmpl = c->tmpl.data();
+    r.nmesh = c->nmesh;
     r.dsz = c->dsz;
-    r.ops = t->ops[c->d.p];
+    r.ops = c->d.p > 0 ? t->ops[c->d.p] : nullptr;
     r.precision = c->d.precision;
     r.mlp = c->d.mlp;
     r.conf_min = c->d.conf_min;
@@ -199,7 +209,7 @@ lt_status finish_eagerly(lt_cycle c, int q, void* stream, int* u_index) {
     return std::vector<const void*>{t->kbuf[0], t->kbuf[1], t->kbuf[2], t->mbuf[0], t->mbuf[1],
                                     t->nbr, t->hmask, t->hang, t->map_src, t->map_kind, t->dir,
                                     t->status, t->cstatus, t->elist, t->copy_delta, t->grp_list,
-                                    t->fused, t->split_R, t->split_F};
+                                    t->fused, t->split_R, t->split_F, t->chunk_np};
   };
   const std::vector<const void*> before = buffers();
   t->old = 0;
@@ -217,8 +227,11 @@ lt_status finish_eagerly(lt_cycle c, int q, void* stream, int* u_index) {
                 "the cycle outgrew its capacity while finishing eagerly; u not transferred");
   LT_TRY_STATUS(lt_connect(t, stream));
   LT_TRY_STATUS(lt_map(t, stream));
-  LT_TRY_STATUS(lt_transfer(t, c->d.p, c->d.nvar, c->d.u[q], c->d.ld, c->d.u[1 - q], c->d.ld,
-                            c->d.precision, stream));
+  if (c->d.p > 0)
+    LT_TRY_STATUS(lt_transfer(t, c->d.p, c->d.nvar, c->d.u[q], c->d.ld, c->d.u[1 - q], c->d.ld,
+                              c->d.precision, stream));
+  else
+    LT_TRY_STATUS(lt_transfer_mixed(t, c->d.nvar, c->d.u[q], c->d.ld, c->d.u[1 - q], c->d.ld, stream));
   if (t->cur != 0) {
     if (hipMemcpyAsync(t->kbuf[0], t->kbuf[t->cur], size_t(t->n_cur) * 8, hipMemcpyDeviceToDevice, s) !=
         hipSuccess)
@@ -254,16 +267,20 @@ lt_status lt_cycle_create(lt_tree t, const lt_cycle_desc* d, void* stream, lt_cy
   if (d->nmesh != t->g.nmesh) return fail(LT_ERR_ARG, "nmesh must equal the tree's mesh count");
   if (d->balance_passes < 2 || d->balance_passes > 64 || (d->balance_passes & 1))
     return fail(LT_ERR_ARG, "balance_passes must be even, 2..64");
-  if ((dim == 3 && (d->p < 1 || d->p > 3)) || (dim == 2 && (d->p < 1 || d->p > LT_MAX_DEGREE)))
+  const bool mixed = d->p == -1;
+  if (mixed && (!t->mesh_np || d->precision != 0 || d->mlp))
+    return fail(LT_ERR_ARG, "p = -1 needs lt_set_mesh_degree, precision 0 and no learned flags");
+  if (!mixed && ((dim == 3 && (d->p < 1 || d->p > 3)) || (dim == 2 && (d->p < 1 || d->p > LT_MAX_DEGREE))))
     return fail(LT_ERR_ARG, "transfer degree out of range");
   int64_t npts = 1;
-  for (int a = 0; a < dim; ++a) npts *= d->p + 1;
+  if (mixed)
+    npts = t->mesh_npm;
+  else
+    for (int a = 0; a < dim; ++a) npts *= d->p + 1;
   if (d->nvar < 1 || int64_t(d->nvar) * npts > 65535) return fail(LT_ERR_ARG, "nvar out of range");
   if (d->capacity < std::max<int64_t>(t->n_cur, 1) || d->capacity > (int64_t(1) << 31) - 1)
     return fail(LT_ERR_ARG, "capacity must hold the current leaves and stay below 2^31");
   if (d->ld < d->capacity) return fail(LT_ERR_ARG, "ld must be at least the capacity");
-  for (int m = 0; m < d->nmesh; ++m)
-    if (d->flag_template[m].p != d->flag_template[0].p) return fail(LT_ERR_ARG, "flag templates need one p");
   if (d->precision != 0 && d->precision != 1) return fail(LT_ERR_ARG, "precision must be 0 or 1");
   if (d->precision == 1 && !((dim == 3 && d->p == 3) || (dim == 2 && d->p == 7)))
     return fail(LT_ERR_ARG, "split precision needs 64 points per element");
@@ -307,7 +324,7 @@ lt_status lt_cycle_run(lt_cycle c, const lt_flag_params* fp, void* stream, int* 
   lt_tree t = c->t;
   hipStream_t s = static_cast<hipStream_t>(stream);
   for (int m = 0; m < c->nmesh; ++m)
-    if (fp[m].p != c->tmpl[0].p) return fail(LT_ERR_ARG, "flag parameters need the template's p");
+    if (fp[m].p != c->tmpl[m].p) return fail(LT_ERR_ARG, "flag parameters need each mesh's template p");
   LT_TRY_STATUS(fill_flag_table(t->g, fp, c->nmesh, c->flag_host));
   const int q = c->parity;
   if (hipMemcpyAsync(t->flag_tab, c->flag_host, flag_args_size() * size_t(c->nmesh), hipMemcpyHostToDevice,
@@ -350,7 +367,9 @@ lt_status lt_cycle_run(lt_cycle c, const lt_flag_params* fp, void* stream, int* 
   if (err & ~ERR_BALANCE_PASSES) {
     t->n_cur = c->hsz[1];
     t->dir_valid = t->conn_valid = t->map_valid = false;
-    return fail(LT_ERR_INTERNAL, "device check failed in a captured cycle");
+    char msg[96];
+    snprintf(msg, sizeof msg, "device check failed in a captured cycle (error bits 0x%x)", err);
+    return fail(LT_ERR_INTERNAL, msg);
   }
   // The fixed balance passes stopped short of the fixpoint: finish eagerly
   // from the partly balanced keys in kbuf[1].

@@ -48,17 +48,8 @@ __device__ inline double axis_d2(double x, double c, bool on, bool periodic, dou
 // a time so that this running minimum stays in registers.
 // TAB: each element takes the parameters of its mesh from tab (an ensemble);
 // otherwise every element uses A0.
-template <int N1, bool TAB>
-__global__ __launch_bounds__(256) void k_flag(FlagArgs A0, const FlagArgs* __restrict__ tab,
-                                              const uint64_t* __restrict__ keys, Count cn,
-                                              int8_t* __restrict__ flags) {
-  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= cn.get()) return;
-  const KeyGeom& g = A0.g;
-  const uint64_t key = keys[e];
-  const FlagArgs* Ap = &A0;
-  if constexpr (TAB) Ap = &tab[key_mesh(g, key)];
-  const FlagArgs& A = *Ap;
+template <int N1>
+__device__ inline int8_t flag_of(const FlagArgs& A, const KeyGeom& g, uint64_t key) {
   const int d = key_depth(g, key);
   uint64_t x[3];
   demorton(g, key_morton(g, key), x);
@@ -144,7 +135,44 @@ __global__ __launch_bounds__(256) void k_flag(FlagArgs A0, const FlagArgs* __res
     if (f == 1 && d >= hi) f = 0;
     if (f == -1 && d <= lo) f = 0;
   }
-  flags[e] = int8_t(f);
+  return int8_t(f);
+}
+
+template <int N1, bool TAB>
+__global__ __launch_bounds__(256) void k_flag(FlagArgs A0, const FlagArgs* __restrict__ tab,
+                                              const uint64_t* __restrict__ keys, Count cn,
+                                              int8_t* __restrict__ flags) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= cn.get()) return;
+  const KeyGeom& g = A0.g;
+  const uint64_t key = keys[e];
+  const FlagArgs* Ap = &A0;
+  if constexpr (TAB) Ap = &tab[key_mesh(g, key)];
+  flags[e] = flag_of<N1>(*Ap, g, key);
+}
+
+// An ensemble whose meshes have different degrees, in one launch: each
+// element takes its mesh's parameters and branches on that mesh's point
+// count (the branch is uniform across a wave except at mesh boundaries).
+__global__ __launch_bounds__(256) void k_flag_mixed(KeyGeom g, const FlagArgs* __restrict__ tab,
+                                                    const uint64_t* __restrict__ keys, Count cn,
+                                                    int8_t* __restrict__ flags) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= cn.get()) return;
+  const uint64_t key = keys[e];
+  const FlagArgs& A = tab[key_mesh(g, key)];
+  int8_t f = 0;
+  switch (A.p + 1) {
+    case 1: f = flag_of<1>(A, g, key); break;
+    case 2: f = flag_of<2>(A, g, key); break;
+    case 3: f = flag_of<3>(A, g, key); break;
+    case 4: f = flag_of<4>(A, g, key); break;
+    case 5: f = flag_of<5>(A, g, key); break;
+    case 6: f = flag_of<6>(A, g, key); break;
+    case 7: f = flag_of<7>(A, g, key); break;
+    default: f = flag_of<8>(A, g, key); break;
+  }
+  flags[e] = f;
 }
 
 template <int N1>
@@ -214,18 +242,29 @@ size_t flag_args_size() { return sizeof(FlagArgs); }
 
 // Copies the per-mesh table from pageable host memory (staged by the runtime
 // before the call returns, so the host copy may go out of scope at once).
+bool mixed_degrees(const lt_flag_params* fps, int nmesh) {
+  for (int m = 1; m < nmesh; ++m)
+    if (fps[m].p != fps[0].p) return true;
+  return false;
+}
+
+hipError_t dispatch_table(const KeyGeom& g, const lt_flag_params* fps, int nmesh, const FlagArgs& A0,
+                          const FlagArgs* tab, const uint64_t* keys, Count n, int8_t* flags,
+                          hipStream_t stream) {
+  if (!mixed_degrees(fps, nmesh)) return dispatch(fps[0].p + 1, A0, tab, keys, n, flags, stream);
+  k_flag_mixed<<<unsigned((n.n + 255) / 256), 256, 0, stream>>>(g, tab, keys, n, flags);
+  return hipGetLastError();
+}
+
 lt_status launch_flag_batch(const KeyGeom& g, const lt_flag_params* fps, int nmesh, void* dev_table,
                             const uint64_t* keys, int64_t n, int8_t* flags, hipStream_t stream) {
   std::vector<FlagArgs> H(static_cast<size_t>(nmesh));
-  for (int m = 0; m < nmesh; ++m) {
-    LT_TRY_STATUS(fill_args(g, &fps[m], &H[m]));
-    if (fps[m].p != fps[0].p) return fail(LT_ERR_ARG, "every mesh of an ensemble flag call needs the same p");
-  }
+  for (int m = 0; m < nmesh; ++m) LT_TRY_STATUS(fill_args(g, &fps[m], &H[m]));
   hipError_t e = hipMemcpyAsync(dev_table, H.data(), sizeof(FlagArgs) * nmesh, hipMemcpyHostToDevice,
                                 stream);
   if (e == hipSuccess && n > 0)
-    e = dispatch(fps[0].p + 1, H[0], static_cast<const FlagArgs*>(dev_table), keys, Count{n, nullptr},
-                 flags, stream);
+    e = dispatch_table(g, fps, nmesh, H[0], static_cast<const FlagArgs*>(dev_table), keys,
+                       Count{n, nullptr}, flags, stream);
   if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("flag launch: ") + hipGetErrorString(e));
   return LT_OK;
 }
@@ -233,22 +272,21 @@ lt_status launch_flag_batch(const KeyGeom& g, const lt_flag_params* fps, int nme
 // Host table of per-mesh parameters (validated) for a later upload.
 lt_status fill_flag_table(const KeyGeom& g, const lt_flag_params* fps, int nmesh, void* host_table) {
   FlagArgs* H = static_cast<FlagArgs*>(host_table);
-  for (int m = 0; m < nmesh; ++m) {
-    LT_TRY_STATUS(fill_args(g, &fps[m], &H[m]));
-    if (fps[m].p != fps[0].p) return fail(LT_ERR_ARG, "every mesh of an ensemble flag call needs the same p");
-  }
+  for (int m = 0; m < nmesh; ++m) LT_TRY_STATUS(fill_args(g, &fps[m], &H[m]));
   return LT_OK;
 }
 
 // Flags from the parameters in dev_table (one entry per mesh), over a count
-// that may live on the device; fp0 fixes the degree and the geometry.
-lt_status launch_flag_table(const KeyGeom& g, const lt_flag_params* fp0, const void* dev_table,
+// that may live on the device; fps (host, nmesh entries) fix each mesh's
+// degree (one kernel for one degree, the branching kernel for several) and
+// the geometry.
+lt_status launch_flag_table(const KeyGeom& g, const lt_flag_params* fps, int nmesh, const void* dev_table,
                             const uint64_t* keys, Count n, int8_t* flags, hipStream_t stream) {
   FlagArgs A;
-  LT_TRY_STATUS(fill_args(g, fp0, &A));
+  LT_TRY_STATUS(fill_args(g, fps, &A));
   if (n.n == 0) return LT_OK;
-  const hipError_t e = dispatch(fp0->p + 1, A, static_cast<const FlagArgs*>(dev_table), keys, n, flags,
-                                stream);
+  const hipError_t e = dispatch_table(g, fps, nmesh, A, static_cast<const FlagArgs*>(dev_table), keys, n,
+                                      flags, stream);
   if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("flag launch: ") + hipGetErrorString(e));
   return LT_OK;
 }

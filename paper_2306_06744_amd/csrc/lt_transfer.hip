@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <string>
+#include <vector>
 
 #include "tree.hpp"
 
@@ -507,6 +508,267 @@ __global__ __launch_bounds__(64 * N) void k_interp3(const double* __restrict__ o
   }
 }
 
+// ----------------------------------------------------------- mixed degrees
+// An ensemble whose meshes carry their own degree (3D, p 1..3) in one
+// solution layout u[(v * NPM + i) * ld + e], NPM = the largest point count;
+// an element of a mesh with N = p+1 points per axis uses rows i < N^3 of each
+// variable block.  np_of_mesh[m] = N^3 of mesh m.  Every kernel below handles
+// all degrees in one launch.
+
+__device__ inline int elem_np(const KeyGeom& g, const uint8_t* __restrict__ np_of_mesh, uint64_t key) {
+  return np_of_mesh[key_mesh(g, key)];
+}
+
+// Pure copy runs as k_copy_chunks, plus the largest point count of the
+// chunk's elements (rows beyond it are skipped by the copy pass).
+template <int EPL>
+__global__ __launch_bounds__(256) void k_copy_chunks_mixed(KeyGeom g, const uint64_t* __restrict__ keys,
+                                                           const uint8_t* __restrict__ np_of_mesh,
+                                                           const int32_t* __restrict__ src,
+                                                           const int8_t* __restrict__ kind, Count cn,
+                                                           int64_t* __restrict__ cdelta,
+                                                           int32_t* __restrict__ cnp) {
+  constexpr int64_t CH = 256 * EPL;
+  __shared__ int s_np;
+  const int64_t n = cn.get();
+  const int64_t c = blockIdx.x;
+  const int64_t j0 = c * CH;
+  if (j0 >= n) {
+    if (threadIdx.x == 0) {
+      cdelta[c] = kImpure;
+      cnp[c] = 0;
+    }
+    return;
+  }
+  if (threadIdx.x == 0) s_np = 0;
+  __syncthreads();
+  const bool head = kind[j0] == 0;
+  const int64_t ref = head ? int64_t(src[j0]) - j0 : 0;
+  bool ok = head;
+  int mx = 0;
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) {
+    const int64_t j = j0 + int64_t(e) * 256 + threadIdx.x;
+    if (j < n) {
+      ok = ok && kind[j] == 0 && int64_t(src[j]) - j == ref;
+      mx = max(mx, elem_np(g, np_of_mesh, keys[j]));
+    }
+  }
+  atomicMax(&s_np, mx);
+  ok = __syncthreads_and(ok);
+  if (threadIdx.x == 0) {
+    cdelta[c] = ok ? ref : kImpure;
+    cnp[c] = s_np;
+  }
+}
+
+// The copy pass with rows r = v * NPM + i skipped where i >= the chunk's
+// largest point count.
+template <int EPL>
+__global__ __launch_bounds__(256) void k_copy3_mixed(const int32_t* __restrict__ src,
+                                                     const int8_t* __restrict__ kind, Count cn,
+                                                     const int64_t* __restrict__ cdelta,
+                                                     const int32_t* __restrict__ cnp, int npm,
+                                                     const double* __restrict__ uo, int64_t ldo,
+                                                     double* __restrict__ un, int64_t ldn) {
+  constexpr int64_t CH = 256 * EPL;
+  const int64_t n = cn.get();
+  const int64_t c = xcd_chunk(blockIdx.x, gridDim.x);
+  if (c * CH >= n) return;
+  if (int(blockIdx.y % npm) >= cnp[c]) return;
+  const double* U = uo + int64_t(blockIdx.y) * ldo;
+  double* O = un + int64_t(blockIdx.y) * ldn;
+  const int64_t dl = cdelta[c];
+  if (dl != kImpure) {
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const int64_t j = c * CH + int64_t(e) * 256 + threadIdx.x;
+      if (j < n) __builtin_nontemporal_store(__builtin_nontemporal_load(U + j + dl), O + j);
+    }
+    return;
+  }
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) {
+    const int64_t jj = c * CH + int64_t(e) * 256 + threadIdx.x;
+    if (jj < n && kind[jj] == 0)
+      __builtin_nontemporal_store(__builtin_nontemporal_load(U + src[jj]), O + jj);
+  }
+}
+
+// Work entries of the interpolation passes: (group << 2) | (N - 1) for every
+// degree N present among a group's refined / fused elements.  Groups whose
+// elements of degree N are refined only go to the ordered list (look-back
+// scan, one entry per such (group, degree)); the others to flist (any order).
+__global__ __launch_bounds__(kScanSmall) void k_group_list_mixed(KeyGeom g, const uint64_t* __restrict__ keys,
+                                                                 const uint8_t* __restrict__ np_of_mesh,
+                                                                 const int8_t* __restrict__ kind, Count cn,
+                                                                 int32_t* __restrict__ list, ScanState st,
+                                                                 int32_t* __restrict__ flist,
+                                                                 int64_t* __restrict__ nflist) {
+  const int64_t tile = take_ticket(st);
+  if (tile >= scan_tiles(st)) return;
+  const int64_t n = cn.get();
+  const int64_t ngroups = st.items.get();
+  const int64_t base = tile * kTileMin + int64_t(threadIdx.x) * kItems;
+  unsigned refmask[kItems];  // bit N-1: a degree-N refined-only entry
+  int64_t local = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t gidx = base + k;
+    refmask[k] = 0;
+    if (gidx >= ngroups) continue;
+    unsigned any = 0, fus = 0;  // bit N-1 per degree
+    const int64_t j0 = gidx * 64;
+    for (int64_t j = j0; j < j0 + 64 && j < n; ++j) {
+      const int kd = kind[j];
+      if (kd == 0) continue;
+      const int np = elem_np(g, np_of_mesh, keys[j]);
+      const int N = np == 8 ? 2 : (np == 27 ? 3 : 4);
+      any |= 1u << (N - 1);
+      if (kd < 0) fus |= 1u << (N - 1);
+    }
+    for (int N = 2; N <= 4; ++N)
+      if (fus & (1u << (N - 1))) {
+        const int64_t o = int64_t(atomicAdd(reinterpret_cast<unsigned long long*>(nflist), 1ull));
+        flist[o] = int32_t(gidx * 4 + (N - 1));
+      }
+    refmask[k] = any & ~fus;
+    local += __popc(refmask[k]);
+  }
+  int64_t blk;
+  const int64_t thr = block_exclusive<kScanSmall>(local, &blk);
+  int64_t o = tile_prefix(st, tile, blk) + thr;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k)
+    for (int N = 2; N <= 4; ++N)
+      if (refmask[k] & (1u << (N - 1))) list[o++] = int32_t((base + k) * 4 + (N - 1));
+}
+
+// One entry of degree N in a block of 4 waves (wave w owns z-slab w; waves
+// w >= N only join the barriers).  Lanes whose element has another degree,
+// or is a copy, do nothing.  M: A_0, A_1, P_0, P_1 of degree N (N*N each).
+template <int N>
+__device__ inline void mixed_entry(const KeyGeom& g, const uint64_t* __restrict__ keys,
+                                   const uint8_t* __restrict__ np_of_mesh,
+                                   const int32_t* __restrict__ src, const int8_t* __restrict__ kind,
+                                   int64_t n, int64_t gidx, const double (*M)[16], int npm, int v,
+                                   const double* __restrict__ uo, int64_t ldo, double* __restrict__ un,
+                                   int64_t ldn, double (*T)[16][64]) {
+  constexpr int NN = N * N;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t j = gidx * 64 + lane;
+  int kd = j < n ? int(kind[j]) : 0;
+  if (kd != 0 && elem_np(g, np_of_mesh, keys[j]) != NN * N) kd = 0;
+  if (w >= N) kd = 0;
+  const int rounds = __ballot(kd < 0) != 0 ? 2 : 1;
+  const int64_t s = kd != 0 ? int64_t(src[j]) : 0;
+  const int c = kd > 0 ? kd - 1 : 0;
+  const double* U = uo + (int64_t(v) * npm + int64_t(w) * NN) * ldo;
+  double acc[NN];
+#pragma unroll
+  for (int r = 0; r < NN; ++r) acc[r] = 0.0;
+  // the block's rounds must agree: a fused element anywhere needs two
+  __shared__ int s_rounds;
+  if (threadIdx.x == 0) s_rounds = 1;
+  __syncthreads();
+  if (lane == 0 && rounds == 2) s_rounds = 2;
+  __syncthreads();
+  const int R = s_rounds;
+  for (int rz = 0; rz < R; ++rz) {
+    double sl[NN];
+#pragma unroll
+    for (int r = 0; r < NN; ++r) sl[r] = 0.0;
+    if (kd > 0) {
+      if (rz == 0) {
+        double in[NN];
+#pragma unroll
+        for (int r = 0; r < NN; ++r) in[r] = U[int64_t(r) * ldo + s];
+        xy_pass<N>(M[c & 1], M[(c >> 1) & 1], in, sl);
+      }
+    } else if (kd < 0) {
+#pragma unroll 1
+      for (int cc = 0; cc < 4; ++cc) {
+        const int child = cc + 4 * rz;
+        double in[NN], t[NN];
+#pragma unroll
+        for (int r = 0; r < NN; ++r) in[r] = U[int64_t(r) * ldo + s + child];
+        xy_pass<N>(M[2 + (cc & 1)], M[2 + (cc >> 1)], in, t);
+#pragma unroll
+        for (int r = 0; r < NN; ++r) sl[r] += t[r];
+      }
+    }
+    if (w < N) {
+#pragma unroll
+      for (int r = 0; r < NN; ++r) T[w][r][lane] = sl[r];
+    }
+    __syncthreads();
+    if (kd > 0 && rz == 0) {
+      const double* Mz = M[(c >> 2) & 1] + w * N;
+#pragma unroll
+      for (int r = 0; r < NN; ++r) {
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) a += Mz[k] * T[k][r][lane];
+        acc[r] = a;
+      }
+    } else if (kd < 0) {
+      const double* Mz = M[2 + rz] + w * N;
+#pragma unroll
+      for (int r = 0; r < NN; ++r) {
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) a += Mz[k] * T[k][r][lane];
+        acc[r] += a;
+      }
+    }
+    __syncthreads();
+  }
+  if (kd != 0) {
+    double* O = un + (int64_t(v) * npm + int64_t(w) * NN) * ldn + j;
+#pragma unroll
+    for (int r = 0; r < NN; ++r) O[int64_t(r) * ldn] = acc[r];
+  }
+}
+
+// Interpolation / projection over work entries of any degree: blocks of 4
+// waves take entries grid-stride (blockIdx.y = variable).  ops1d[N] holds the
+// degree-N factors A_0, A_1, P_0, P_1 (or null when no mesh has degree N).
+__global__ __launch_bounds__(256) void k_interp3_mixed(KeyGeom g, const uint64_t* __restrict__ keys,
+                                                       const uint8_t* __restrict__ np_of_mesh,
+                                                       const double* ops2, const double* ops3,
+                                                       const double* ops4,
+                                                       const int32_t* __restrict__ src,
+                                                       const int8_t* __restrict__ kind, Count cn,
+                                                       const int32_t* __restrict__ entries,
+                                                       const int64_t* __restrict__ nentries, int npm,
+                                                       const double* __restrict__ uo, int64_t ldo,
+                                                       double* __restrict__ un, int64_t ldn) {
+  __shared__ double T[4][16][64];
+  __shared__ double M[3][4][16];  // degree 2, 3, 4: A_0, A_1, P_0, P_1
+  const int64_t n = cn.get();
+  const int64_t ne = *nentries;
+  if (int64_t(blockIdx.x) >= ne) return;
+  const double* ops[3] = {ops2, ops3, ops4};
+  for (int d = 0; d < 3; ++d) {
+    const int N = d + 2;
+    if (!ops[d]) continue;
+    for (int i = threadIdx.x; i < 4 * N * N; i += blockDim.x) M[d][i / (N * N)][i % (N * N)] = ops[d][i];
+  }
+  __syncthreads();
+  const int v = blockIdx.y;
+  for (int64_t ei = blockIdx.x; ei < ne; ei += gridDim.x) {
+    const int32_t ent = entries[ei];
+    const int64_t gidx = ent >> 2;
+    const int N = (ent & 3) + 1;
+    if (N == 2)
+      mixed_entry<2>(g, keys, np_of_mesh, src, kind, n, gidx, M[0], npm, v, uo, ldo, un, ldn, T);
+    else if (N == 3)
+      mixed_entry<3>(g, keys, np_of_mesh, src, kind, n, gidx, M[1], npm, v, uo, ldo, un, ldn, T);
+    else
+      mixed_entry<4>(g, keys, np_of_mesh, src, kind, n, gidx, M[2], npm, v, uo, ldo, un, ldn, T);
+  }
+}
+
 // Scratch of one FP64 transfer, sized for n new leaves: per copy chunk the
 // source offset of a pure copy run (ceil(n / 256) entries at the finest
 // tuning), the interpolation-group lists (the ordered list of groups with a
@@ -668,6 +930,59 @@ lt_status transfer_with(int dim, const TransferTune& tune, const int32_t* src, c
 }
 }  // namespace
 
+lt_status launch_transfer_mixed(lt_tree_s* t, const uint64_t* keys, Count n, const int64_t* ngroups_dev,
+                                int nvar, const double* uo, int64_t ldo, double* un, int64_t ldn,
+                                hipStream_t s) {
+  if (n.n == 0) return LT_OK;
+  if (!t->mesh_np || t->g.dim != 3) return fail(LT_ERR_STATE, "per-mesh degrees are not set");
+  const int npm = t->mesh_npm;
+  if (nvar < 1 || int64_t(nvar) * npm > 65535) return fail(LT_ERR_ARG, "nvar * points out of range");
+  const double* ops[3] = {nullptr, nullptr, nullptr};
+  for (int p = 1; p <= 3; ++p)
+    if (t->mesh_degs & (1u << p)) {
+      LT_TRY_STATUS(build_transfer_ops(t->A, p, &t->ops[p], s));
+      ops[p - 1] = t->ops[p];
+    }
+  const int epl = t->tune.copy_epl;
+  const int64_t CH = 256 * int64_t(epl);
+  const int64_t nchunks = (n.n + CH - 1) / CH;
+  const int64_t ngroups = (n.n + 63) / 64;
+  LT_TRY_STATUS(grow(t->A, &t->copy_delta, &t->copy_delta_cap, nchunks));
+  LT_TRY_STATUS(grow(t->A, &t->chunk_np, &t->chunk_np_cap, nchunks));
+  LT_TRY_STATUS(grow(t->A, &t->grp_list, &t->grp_cap, 6 * ngroups));
+  const dim3 grid{unsigned(nchunks), unsigned(nvar * npm), 1u};
+#define LT_CM(E)                                                                                    \
+  do {                                                                                              \
+    k_copy_chunks_mixed<E><<<unsigned(nchunks), 256, 0, s>>>(t->g, keys, t->mesh_np, t->map_src,     \
+                                                            t->map_kind, n, t->copy_delta,          \
+                                                            t->chunk_np);                           \
+    k_copy3_mixed<E><<<grid, 256, 0, s>>>(t->map_src, t->map_kind, n, t->copy_delta, t->chunk_np,   \
+                                          npm, uo, ldo, un, ldn);                                   \
+  } while (0)
+  if (epl == 1)
+    LT_CM(1);
+  else if (epl == 4)
+    LT_CM(4);
+  else
+    LT_CM(2);
+#undef LT_CM
+  ScanState st;
+  LT_TRY_STATUS(prep_scan(t, ngroups, kTileMin, s, 0, &st));
+  st.items.p = ngroups_dev;
+  int32_t* flist = t->grp_list + 3 * ngroups;
+  k_group_list_mixed<<<grid_tiles(st), kScanSmall, 0, s>>>(t->g, keys, t->mesh_np, t->map_kind, n,
+                                                           t->grp_list, st, flist, &t->dctr->nfgroups);
+  const dim3 gi{unsigned(std::max<int64_t>(1, std::min<int64_t>(3 * ngroups, t->tune.interp_grid))),
+                unsigned(nvar), 1u};
+  k_interp3_mixed<<<gi, 256, 0, s>>>(t->g, keys, t->mesh_np, ops[0], ops[1], ops[2], t->map_src,
+                                     t->map_kind, n, t->grp_list, st.total, npm, uo, ldo, un, ldn);
+  k_interp3_mixed<<<gi, 256, 0, s>>>(t->g, keys, t->mesh_np, ops[0], ops[1], ops[2], t->map_src,
+                                     t->map_kind, n, flist, &t->dctr->nfgroups, npm, uo, ldo, un, ldn);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("mixed transfer launch: ") + hipGetErrorString(e));
+  return LT_OK;
+}
+
 lt_status launch_transfer(lt_tree_s* t, Count n, const int64_t* ngroups_dev, int p,
                           const double* ops, int nvar, const double* u_old, int64_t ld_old,
                           double* u_new, int64_t ld_new, hipStream_t s) {
@@ -767,6 +1082,42 @@ lt_status lt_transfer_noalloc(lt_tree t, int p, int nvar, const double* u_old, i
                       reinterpret_cast<DevCtr*>(base + kOffCtr)};
   return transfer_with(t->g.dim, t->tune, t->map_src, t->map_kind, Count{t->n_cur, nullptr}, nullptr,
                        p, ops, nvar, u_old, ld_old, u_new, ld_new, X, s);
+}
+
+lt_status lt_set_mesh_degree(lt_tree t, const int* p, void* stream) {
+  if (!t || !p) return fail(LT_ERR_ARG, "NULL argument");
+  if (t->g.dim != 3) return fail(LT_ERR_ARG, "per-mesh degrees are for 3D ensembles");
+  const int nm = t->g.nmesh;
+  std::vector<uint8_t> np(static_cast<size_t>(nm));
+  unsigned degs = 0;
+  int npm = 0;
+  for (int m = 0; m < nm; ++m) {
+    if (p[m] < 1 || p[m] > 3) return fail(LT_ERR_ARG, "mesh degrees must be 1..3");
+    np[m] = uint8_t((p[m] + 1) * (p[m] + 1) * (p[m] + 1));
+    degs |= 1u << p[m];
+    npm = std::max(npm, int(np[m]));
+  }
+  if (!t->mesh_np &&
+      dev_malloc(t->A, reinterpret_cast<void**>(&t->mesh_np), std::max<size_t>(nm, 256)) != hipSuccess)
+    return fail(LT_ERR_OOM, "mesh degree table");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (hipMemcpyAsync(t->mesh_np, np.data(), np.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(LT_ERR_HIP, "mesh degree upload");
+  t->mesh_degs = degs;
+  t->mesh_npm = npm;
+  return LT_OK;
+}
+
+lt_status lt_transfer_mixed(lt_tree t, int nvar, const double* u_old, int64_t ld_old, double* u_new,
+                            int64_t ld_new, void* stream) {
+  if (!t || !u_old || !u_new) return fail(LT_ERR_ARG, "NULL argument");
+  if (!t->mesh_np) return fail(LT_ERR_STATE, "lt_transfer_mixed needs lt_set_mesh_degree");
+  if (!t->has_old) return fail(LT_ERR_STATE, "lt_transfer_mixed needs a prior lt_adapt");
+  if (ld_old < t->n_old || ld_new < t->n_cur) return fail(LT_ERR_ARG, "leading dimension too small");
+  if (!t->map_valid) LT_TRY_STATUS(lt_map(t, stream));
+  return launch_transfer_mixed(t, t->kbuf[t->cur], Count{t->n_cur, nullptr}, nullptr, nvar, u_old, ld_old,
+                               u_new, ld_new, static_cast<hipStream_t>(stream));
 }
 
 lt_status lt_set_tuning(lt_tree t, const lt_tune* tune) {

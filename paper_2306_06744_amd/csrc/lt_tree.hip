@@ -954,7 +954,7 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
   unsigned* err = &t->dctr->err;
   int8_t* F = t->map_kind;  // the flags live in the kind array until the mapping overwrites it
   // flags (parameters from the device table)
-  LT_TRY(launch_flag_table(g, &r.fp0, t->flag_tab, K0, Count{C, &S[0]}, F, s));
+  LT_TRY(launch_flag_table(g, r.tmpl, r.nmesh, t->flag_tab, K0, Count{C, &S[0]}, F, s));
   if (r.mlp)  // learned flags, the geometric ones as the fallback below conf_min
     LT_TRY(launch_mlp_flag(t, r.mlp, Count{C, &S[0]}, r.uo, r.ld, r.conf_min, F, nullptr, s));
   k_cycle_begin<<<1, 64, 0, s>>>(S, t->dctr);
@@ -1028,6 +1028,9 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
   // transfer
   if (r.precision == 1) {
     LT_TRY(launch_split_transfer(t, Count{C, &S[0]}, r.p, r.nvar, r.uo, r.ld, r.un, r.ld, s));
+  } else if (r.p < 0) {  // per-mesh degrees
+    k_groups_of<<<1, 64, 0, s>>>(&S[3], &S[0]);
+    LT_TRY(launch_transfer_mixed(t, K[0], Count{C, &S[0]}, &S[3], r.nvar, r.uo, r.ld, r.un, r.ld, s));
   } else {
     k_groups_of<<<1, 64, 0, s>>>(&S[3], &S[0]);
     LT_TRY(launch_transfer(t, Count{C, &S[0]}, &S[3], r.p, r.ops, r.nvar, r.uo, r.ld, r.un, r.ld, s));
@@ -1538,6 +1541,8 @@ void lt_destroy(lt_tree t) {
     fr(b);
   for (auto& o : t->ops) fr(o);
   for (auto& o : t->fr_tab) fr(o);
+  fr(t->mesh_np);
+  fr(t->chunk_np);
   fr(t->fr_fb);
   if (t->hctr) (void)hipHostFree(t->hctr);
   if (t->hcctr) (void)hipHostFree(t->hcctr);

@@ -47,7 +47,7 @@ lt_status launch_flag_batch(const KeyGeom& g, const lt_flag_params* fps, int nme
 // bytes per mesh), and flags from a device copy of such a table over a count
 // that may live on the device (captured cycles).
 lt_status fill_flag_table(const KeyGeom& g, const lt_flag_params* fps, int nmesh, void* host_table);
-lt_status launch_flag_table(const KeyGeom& g, const lt_flag_params* fp0, const void* dev_table,
+lt_status launch_flag_table(const KeyGeom& g, const lt_flag_params* fps, int nmesh, const void* dev_table,
                             const uint64_t* keys, Count n, int8_t* flags, hipStream_t stream);
 
 // One whole cycle recorded on a stream with every count kept on the device
@@ -66,6 +66,8 @@ struct CycleRec {
   double* un;
   int64_t ld;          // leading dimension of uo and un
   lt_flag_params fp0;  // degree and geometry of the flags (the centres come from the table)
+  const lt_flag_params* tmpl;  // every mesh's template (only the degrees are read here)
+  int nmesh;
   int64_t* dsz;
   const double* ops;
   int precision;       // transfer: 0 FP64, 1 split
@@ -172,6 +174,13 @@ lt_status launch_mlp_flag(lt_tree_s* t, lt_mlp m, Count n, const double* u, int6
 
 lt_status launch_transfer(lt_tree_s* t, int p, const double* ops, int nvar, const double* u_old,
                           int64_t ld_old, double* u_new, int64_t ld_new, hipStream_t s);
+// FP64 transfer of an ensemble with per-mesh degrees (lt_set_mesh_degree), over
+// a count that may live on the device; asynchronous.  keys: the new leaves'
+// keys (each element's mesh, hence its degree, comes from its key), which a
+// captured cycle holds in another buffer than the tree's current one.
+lt_status launch_transfer_mixed(lt_tree_s* t, const uint64_t* keys, Count n, const int64_t* ngroups_dev,
+                                int nvar, const double* uo, int64_t ldo, double* un, int64_t ldn,
+                                hipStream_t s);
 
 // COPY elements of the current mapping, all `rows` point rows (nvar * n_p);
 // asynchronous.
@@ -264,6 +273,11 @@ struct lt_tree_s {
   double* fr_tab[LT_MAX_DEGREE + 1] = {};  // flux reconstruction: 1D tables per degree
   double* fr_fb = nullptr;                  // flux reconstruction: face traces / common fluxes
   int64_t fr_fb_cap = 0;
+  uint8_t* mesh_np = nullptr;   // ensemble with per-mesh degrees: points per element of each mesh
+  int mesh_npm = 0;             //   the largest of them (the solution layout's point stride)
+  unsigned mesh_degs = 0;       //   bit p set: some mesh has degree p
+  int32_t* chunk_np = nullptr;  // mixed-degree copy pass: largest point count per chunk
+  int64_t chunk_np_cap = 0;
   int32_t* grp_list = nullptr;  // 64-element groups holding refined/fused elements
   int64_t grp_cap = 0;
   int64_t* copy_delta = nullptr;  // per copy chunk: source offset of a pure run, or a flag

@@ -116,3 +116,66 @@ def test_ensemble_64_bit_exact_per_mesh():
         del t
         torch.cuda.empty_cache()
     assert checked == len(meshes)
+
+
+def test_ensemble_64_one_tree_mixed_degrees():
+    """All 64 meshes in one tree with per-mesh degrees (lt_set_mesh_degree,
+    one solution array of 64 rows per variable), as the benchmark's one-tree
+    runs: the same per-mesh hashes, and the last cycle's lt_transfer_mixed on
+    every refined and fused element and a seeded 1% of the copies against the
+    oracle's dense operators at each mesh's own degree."""
+    import torch
+    import paper_2306_06744_amd as lt
+    with open(os.path.join(HERE, "golden", "workload_ensemble_64.json")) as fh:
+        gold = json.load(fh)
+    meshes = synth.workload_ensemble(4000)
+    degs = [m.p for m in meshes]
+
+    def margs(m, cyc):
+        return dict(centres=m.centres_at(cyc), r_in=m.r_in, r_out=m.r_out,
+                    nodes01=synth.gl_nodes01(m.p), lo=(-5.0,) * 3, length=10.0, dist_axes=3,
+                    periodic_dist=False)
+
+    t = lt.Tree.batch(3, D_FINE, [m.d_min for m in meshes], [m.d_max for m in meshes],
+                      [m.d_min for m in meshes])
+    t.set_mesh_degree(degs)
+    for cyc in range(gold["cycles"]):
+        offs_old = t.mesh_offsets()
+        f = t.flag_batch([margs(m, cyc) for m in meshes])
+        t.adapt(f)
+        t.balance()
+    flags = f.cpu().numpy()
+    t.map()
+    src_all, kind_all = (a.cpu().numpy() for a in t.mapping())
+    offs = t.mesh_offsets()
+    print(f"one tree: {offs[-1]} leaves", flush=True)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4064)
+    u_old = torch.randn((5, 64, offs_old[-1]), dtype=torch.float64, device="cuda", generator=gen)
+    u_new = t.transfer_mixed(u_old)
+    js_all = changed_and_sampled(kind_all, np.random.default_rng(64))
+    mesh_of = np.searchsorted(np.array(offs), js_all, side="right") - 1
+    deg_of = np.array(degs)[mesh_of]
+    for p in (2, 3):
+        n_p = (p + 1) ** 3
+        js = js_all[deg_of == p]
+        k_js, s_js = kind_all[js].astype(np.int64), src_all[js].astype(np.int64)
+        cols = np.unique(np.concatenate([s_js[k_js >= 0]] + [s_js[k_js < 0] + c for c in range(8)]))
+        sub = u_old[:, :n_p].index_select(2, torch.from_numpy(cols).cuda()).cpu().numpy()
+        src_sub = np.zeros(len(src_all), dtype=np.int64)
+        src_sub[js] = np.searchsorted(cols, s_js)
+        exp = dense_expected(3, p, sub, src_sub, kind_all, js)
+        got = u_new[:, :n_p].index_select(2, torch.from_numpy(js).cuda()).cpu().numpy()
+        errs = assert_transfer(got, exp, kind_all[js], 1e-13, f"one tree, p{p} meshes")
+        assert "refined" in errs and ("fused" in errs or p == 2)
+    del u_old, u_new
+    keys = t.keys().cpu().numpy().view(np.uint64)
+    src, kind = src_all, kind_all
+    for i, m in enumerate(meshes):
+        g = gold["meshes"][i]
+        a, b = offs[i], offs[i + 1]
+        assert g["counts"][-1] == b - a, f"mesh {i}: leaf count"
+        assert sha(flags[offs_old[i]:offs_old[i + 1]]) == g["flags"], f"mesh {i}: flags"
+        assert sha(mesh_keys(keys[a:b], 3, D_FINE, m.d_max)) == g["keys"], f"mesh {i}: keys"
+        assert sha(src[a:b] - np.int32(offs_old[i])) == g["map_src"], f"mesh {i}: map_src"
+        assert sha(kind[a:b]) == g["map_kind"], f"mesh {i}: map_kind"
