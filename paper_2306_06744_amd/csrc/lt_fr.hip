@@ -21,12 +21,12 @@
 // Every slot is read and written by exactly one owner: no atomics, and the
 // result is the same on every run (the paper accumulates the coarse side with
 // atomic additions).
-//   k_fr_volume  one workgroup per 64 elements (lane = element, so every load
-//                of a point row is one contiguous run), one wave per slab of
-//                points along the last axis; derivatives along the in-slab
-//                axes in registers, along the last axis through LDS, the
-//                Radau corrections from the face buffer, and the stage
-//                combination out = c0 u0 + c1 u + c2 dt R fused in.
+//   k_fr_volume  a lane holds one x-line of points of one element (lanes
+//                of a wave part = consecutive elements, so every load of a
+//                point row is one contiguous run); the x derivative in
+//                registers, the y and z derivatives through LDS, the Radau
+//                corrections from the face buffer, and the stage combination
+//                out = c0 u0 + c1 u + c2 dt R fused in.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -57,59 +57,86 @@ struct FrTab {
   __host__ __device__ static constexpr int size(int n) { return 5 * n * n + 4 * n; }
 };
 
-// Host: Gauss-Legendre nodes / weights by Newton on P_n (Bonnet recurrence).
-void gl_host(int n, std::vector<double>& z, std::vector<double>& w) {
-  z.assign(n, 0.0);
-  w.assign(n, 0.0);
-  for (int i = 0; i < n; ++i) {
-    double x = -std::cos(M_PI * (i + 0.75) / (n + 0.5));
-    for (int it = 0; it < 100; ++it) {
-      double p0 = 1.0, p1 = x;
-      for (int k = 2; k <= n; ++k) {
-        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
-        p0 = p1;
-        p1 = p2;
-      }
-      if (n == 1) p1 = x, p0 = 1.0;
-      const double dp = n * (x * p1 - p0) / (x * x - 1.0);
-      const double dx = p1 / dp;
-      x -= dx;
-      if (std::fabs(dx) < 1e-16) break;
-    }
-    double p0 = 1.0, p1 = x;
-    for (int k = 2; k <= n; ++k) {
-      const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
-      p0 = p1;
-      p1 = p2;
-    }
-    const double dp = n * (x * p1 - p0) / (x * x - 1.0);
-    z[i] = x;
-    w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+// The 1D operators are built by constexpr functions, so that the volume
+// kernel takes them as literal constants (no loads, no registers held across
+// its loop) and the device tables of the other kernels hold the same values.
+
+// cos by its Taylor series (|x| <= pi; a starting guess only).
+constexpr double cx_cos(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 30; ++k) {
+    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
   }
+  return sum;
 }
 
-double lag(const std::vector<double>& z, int k, double x) {
+constexpr double cx_abs(double x) { return x < 0.0 ? -x : x; }
+
+// P_n(x) and P_{n-1}(x) by the three-term (Bonnet) recurrence.
+constexpr void legendre_pair(int n, double x, double* pn, double* pm) {
+  double p0 = 1.0, p1 = x;
+  for (int k = 2; k <= n; ++k) {
+    const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  *pn = n == 0 ? 1.0 : p1;
+  *pm = n == 0 ? 0.0 : p0;
+}
+
+template <int Q>
+struct GaussLegendre {
+  double z[Q] = {};
+  double w[Q] = {};
+};
+
+// Gauss-Legendre nodes (ascending) and weights: Newton on P_Q from the usual
+// cosine guess, w = 2 / ((1 - z^2) P_Q'(z)^2).
+template <int Q>
+constexpr GaussLegendre<Q> gauss_legendre() {
+  GaussLegendre<Q> r;
+  for (int i = 0; i < Q; ++i) {
+    double x = -cx_cos(M_PI * (i + 0.75) / (Q + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double pn = 0.0, pm = 0.0;
+      legendre_pair(Q, x, &pn, &pm);
+      const double dp = Q * (x * pn - pm) / (x * x - 1.0);
+      const double dx = pn / dp;
+      x -= dx;
+      if (cx_abs(dx) < 1e-16) break;
+    }
+    double pn = 0.0, pm = 0.0;
+    legendre_pair(Q, x, &pn, &pm);
+    const double dp = Q * (x * pn - pm) / (x * x - 1.0);
+    r.z[i] = x;
+    r.w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+  return r;
+}
+
+// Lagrange basis l_k on the nodes z (n of them) and its derivative.
+constexpr double lag(const double* z, int n, int k, double x) {
   double v = 1.0;
-  for (size_t m = 0; m < z.size(); ++m)
-    if (int(m) != k) v *= (x - z[m]) / (z[k] - z[m]);
+  for (int m = 0; m < n; ++m)
+    if (m != k) v *= (x - z[m]) / (z[k] - z[m]);
   return v;
 }
 
-double lag_d(const std::vector<double>& z, int k, double x) {
+constexpr double lag_d(const double* z, int n, int k, double x) {
   double s = 0.0;
-  for (size_t r = 0; r < z.size(); ++r) {
-    if (int(r) == k) continue;
+  for (int r = 0; r < n; ++r) {
+    if (r == k) continue;
     double t = 1.0 / (z[k] - z[r]);
-    for (size_t m = 0; m < z.size(); ++m)
-      if (int(m) != k && m != r) t *= (x - z[m]) / (z[k] - z[m]);
+    for (int m = 0; m < n; ++m)
+      if (m != k && m != r) t *= (x - z[m]) / (z[k] - z[m]);
     s += t;
   }
   return s;
 }
 
-// Legendre P_n'(x) from the recurrence P_{k+1} = ((2k+1) x P_k - k P_{k-1})/(k+1)
-// and P_{k+1}' = P_{k-1}' + (2k+1) P_k.
-double leg_d(int n, double x) {
+// P_n'(x) from P_{k+1}' = P_{k-1}' + (2k+1) P_k.
+constexpr double leg_d(int n, double x) {
   if (n == 0) return 0.0;
   double pm = 1.0, pc = x, dm = 0.0, dc = 1.0;
   for (int k = 1; k < n; ++k) {
@@ -123,36 +150,63 @@ double leg_d(int n, double x) {
   return dc;
 }
 
-std::vector<double> fr_tables(int p) {
-  const int n = p + 1;
-  std::vector<double> z, w, zq, wq;
-  gl_host(n, z, w);
-  gl_host(n + 1, zq, wq);
-  std::vector<double> T(FrTab::size(n), 0.0);
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) T[FrTab::kD + i * n + j] = lag_d(z, j, z[i]);
-  for (int j = 0; j < n; ++j) {
-    T[FrTab::lL(n) + j] = lag(z, j, -1.0);
-    T[FrTab::lR(n) + j] = lag(z, j, 1.0);
+// The operators of degree N - 1 on N Gauss-Legendre points, laid out as the
+// device table (FrTab).
+template <int N>
+struct Ops1D {
+  double t[5 * N * N + 4 * N] = {};
+};
+
+template <int N>
+constexpr Ops1D<N> ops_1d() {
+  constexpr int p = N - 1;
+  const GaussLegendre<N> gl = gauss_legendre<N>();
+  const GaussLegendre<N + 1> gq = gauss_legendre<N + 1>();
+  Ops1D<N> o;
+  double* T = o.t;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) T[FrTab::kD + i * N + j] = lag_d(gl.z, N, j, gl.z[i]);
+  for (int j = 0; j < N; ++j) {
+    T[FrTab::lL(N) + j] = lag(gl.z, N, j, -1.0);
+    T[FrTab::lR(N) + j] = lag(gl.z, N, j, 1.0);
   }
   // g_L = (-1)^(p+1)/2 (P_{p+1} - P_p), g_R = (P_{p+1} + P_p)/2
   const double sL = (p + 1) % 2 ? -0.5 : 0.5;
-  for (int i = 0; i < n; ++i) {
-    T[FrTab::dgL(n) + i] = sL * (leg_d(p + 1, z[i]) - leg_d(p, z[i]));
-    T[FrTab::dgR(n) + i] = 0.5 * (leg_d(p + 1, z[i]) + leg_d(p, z[i]));
+  for (int i = 0; i < N; ++i) {
+    T[FrTab::dgL(N) + i] = sL * (leg_d(p + 1, gl.z[i]) - leg_d(p, gl.z[i]));
+    T[FrTab::dgR(N) + i] = 0.5 * (leg_d(p + 1, gl.z[i]) + leg_d(p, gl.z[i]));
   }
   for (int b = 0; b < 2; ++b) {
-    for (int i = 0; i < n; ++i)
-      for (int k = 0; k < n; ++k) T[FrTab::A(n, b) + i * n + k] = lag(z, k, (z[i] + 2.0 * b - 1.0) / 2.0);
+    for (int i = 0; i < N; ++i)
+      for (int k = 0; k < N; ++k) T[FrTab::A(N, b) + i * N + k] = lag(gl.z, N, k, (gl.z[i] + 2.0 * b - 1.0) / 2.0);
     // P_b = M^-1 S_b, M = diag(w) (exact for GL), S_b[j][i] = int_{half b} l_j l^_i
-    for (int j = 0; j < n; ++j)
-      for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < N; ++j)
+      for (int i = 0; i < N; ++i) {
         double s = 0.0;
-        for (int q = 0; q < n + 1; ++q) s += wq[q] / 2.0 * lag(z, j, (zq[q] + 2.0 * b - 1.0) / 2.0) * lag(z, i, zq[q]);
-        T[FrTab::P(n, b) + j * n + i] = s / w[j];
+        for (int q = 0; q < N + 1; ++q)
+          s += gq.w[q] / 2.0 * lag(gl.z, N, j, (gq.z[q] + 2.0 * b - 1.0) / 2.0) * lag(gl.z, N, i, gq.z[q]);
+        T[FrTab::P(N, b) + j * N + i] = s / gl.w[j];
       }
   }
-  return T;
+  return o;
+}
+
+template <int N>
+std::vector<double> tables_of() {
+  constexpr Ops1D<N> o = ops_1d<N>();
+  return std::vector<double>(o.t, o.t + FrTab::size(N));
+}
+
+std::vector<double> fr_tables(int p) {
+  switch (p + 1) {
+    case 2: return tables_of<2>();
+    case 3: return tables_of<3>();
+    case 4: return tables_of<4>();
+    case 5: return tables_of<5>();
+    case 6: return tables_of<6>();
+    case 7: return tables_of<7>();
+    default: return tables_of<8>();
+  }
 }
 
 // ------------------------------------------------------------------ physics
@@ -404,118 +458,180 @@ __global__ __launch_bounds__(256) void k_fr_mortar(const int32_t* __restrict__ h
   }
 }
 
-// Volume part and stage combination.  Workgroup: N waves (slab z = wave for
-// 3D, y = wave for 2D), 64 elements (lane = element).
-template <int DIM, int N>
-__global__ __launch_bounds__(64 * N) void k_fr_volume(KeyGeom g, const uint64_t* __restrict__ keys,
-                                                      int64_t n, const double* __restrict__ tab,
-                                                      double length, double gamma,
-                                                      const double* __restrict__ uin, int64_t ld,
-                                                      const double* __restrict__ fb, int64_t ldf,
-                                                      const double* __restrict__ u0, double c0,
-                                                      double c1, double c2,
-                                                      double* __restrict__ out, int64_t ldo) {
-  constexpr int SP = DIM == 3 ? N * N : N;  // points of a slab
-  constexpr int NP = SP * N;
+// Entry r of N compile-time values, r uniform across the wave, as
+// sum_k [k == r] row[k] (exact: the other terms are zeros), so that no array
+// is indexed at run time (which would place it in scratch memory).
+template <int N>
+__device__ inline double row_at(const double* row, int r) {
+  double x = 0.0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) x += (r == k ? 1.0 : 0.0) * row[k];
+  return x;
+}
+
+// Volume part and stage combination.  A lane holds one x-line of N points
+// of one element; a workgroup holds every line of EB = 64 / H elements
+// (lane = element within each of the H parts of a wave, so that every load
+// of a point row is one contiguous run).  Wave w holds lines w + (NL / H) h,
+// h = 0..H-1 (NL = N^2 lines in 3D, N in 2D); NL / H is a multiple of N so
+// that the line's y is uniform across the wave.  Each point's inverse density
+// and pressure are formed once per pass; the variables are taken one at a
+// time (a loop that is not unrolled, to bound the code and the registers),
+// with component v of the flux along axis a written as
+//   F_a[v] = (U[v] + [v is energy] p) m_a / rho + [v is momentum a] p
+// (the mass flux m_a for v = 0).  U[v] is formed as sum_k [k == v] U[k]
+// (exact: the other terms are zeros), so that no register array is indexed
+// by the loop variable (that would move it to scratch memory).  The x
+// derivative stays in registers; the y and z fluxes go through LDS for the
+// derivatives across lines.  The 1D operators are literal constants.
+template <int DIM, int N, int H>
+__global__ __launch_bounds__(64 * (DIM == 3 ? N * N : N) / H) void k_fr_volume(
+    KeyGeom g, const uint64_t* __restrict__ keys, int64_t n, double length, double gamma,
+    const double* __restrict__ uin, int64_t ld, const double* __restrict__ fb, int64_t ldf,
+    const double* __restrict__ u0, double c0, double c1, double c2, double* __restrict__ out,
+    int64_t ldo) {
+  constexpr int NL = DIM == 3 ? N * N : N;  // x-lines
+  constexpr int NP = NL * N;
   constexpr int NV = DIM + 2;
-  constexpr int NFP = SP;
-  constexpr int LA = DIM - 1;  // the slab axis
-  __shared__ double H[N][SP][64];
-  __shared__ double tb[5 * N * N + 4 * N];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int i = threadIdx.x; i < FrTab::size(N); i += blockDim.x) tb[i] = tab[i];
-  const int64_t e = int64_t(blockIdx.x) * 64 + lane;
-  const bool live = e < n;
+  constexpr int NFP = NL;  // points of a face
+  constexpr int EB = 64 / H;  // elements of a workgroup
+  static_assert(NL % H == 0 && (NL / H) % N == 0, "the parts of a wave must share y");
+  constexpr Ops1D<N> O = ops_1d<N>();
+  const double* D = O.t + FrTab::kD;
+  const double* lL = O.t + FrTab::lL(N);
+  const double* lR = O.t + FrTab::lR(N);
+  const double* dgL = O.t + FrTab::dgL(N);
+  const double* dgR = O.t + FrTab::dgR(N);
+  __shared__ double Hy[NP][EB];
+  __shared__ double Hz[DIM == 3 ? NP : 1][EB];
+  const int lane = threadIdx.x & 63;
+  const int el = lane % EB;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int l = w + (NL / H) * (lane / EB);  // the lane's line
+  const int y = w % N;                       // uniform
+  const int z = l / N;                       // uniform when H = 1
+  const int64_t e0 = int64_t(blockIdx.x) * EB;
+  const bool live = e0 + el < n;
+  // lanes past the last element read the last element's values and store nothing
+  const int64_t e = live ? e0 + el : n - 1;
   const double gm1 = gamma - 1.0;
-  double U[NV][SP];
+  auto row = [&](auto* p, int64_t r, int64_t stride) { return p + (r * stride + e); };
+  double U[NV][N];
 #pragma unroll
   for (int v = 0; v < NV; ++v)
 #pragma unroll
-    for (int sp = 0; sp < SP; ++sp)
-      U[v][sp] = live ? uin[(int64_t(v) * NP + w * SP + sp) * ld + e] : (v == 0 ? 1.0 : 0.0);
-  const double h = live ? ldexp(length, -key_depth(g, keys[e])) : 1.0;
+    for (int i = 0; i < N; ++i) U[v][i] = *row(uin, int64_t(v) * NP + l * N + i, ld);
+  const double h = ldexp(length, -key_depth(g, keys[e]));
   const double scale = -2.0 / h;
-  __syncthreads();
-  const double* D = tb + FrTab::kD;
-  const double* lL = tb + FrTab::lL(N);
-  const double* lR = tb + FrTab::lR(N);
-  const double* dgL = tb + FrTab::dgL(N);
-  const double* dgR = tb + FrTab::dgR(N);
+  // the operators' rows at the line's y and z
+  double Dy[N], Dz[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    double c[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) c[r] = D[r * N + k];
+    Dy[k] = row_at<N>(c, y);
+    Dz[k] = row_at<N>(c, z);
+  }
+  const double gLy = row_at<N>(dgL, y), gRy = row_at<N>(dgR, y);
+  const double gLz = row_at<N>(dgL, z), gRz = row_at<N>(dgR, z);
 #pragma unroll 1
   for (int v = 0; v < NV; ++v) {
-    double R[SP];
+    // values derived from the state are not kept across passes
 #pragma unroll
-    for (int sp = 0; sp < SP; ++sp) R[sp] = 0.0;
-    // in-slab axes
+    for (int k = 0; k < NV; ++k)
 #pragma unroll
-    for (int a = 0; a < DIM - 1; ++a) {
-      const int stride = a == 0 ? 1 : N;
+      for (int i = 0; i < N; ++i) asm volatile("" : "+v"(U[k][i]));
+    double ir[N], pr[N];
 #pragma unroll
-      for (int l = 0; l < SP / N; ++l) {
-        // line l: the other in-slab index (3D) or none (2D)
-        const int base = a == 0 ? l * N : l;
-        double Fv[N];
+    for (int i = 0; i < N; ++i) {
+      ir[i] = 1.0 / U[0][i];
+      double kin = 0.0;
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-          double Up[NV];
+      for (int b = 0; b < DIM; ++b) kin += U[1 + b][i] * U[1 + b][i];
+      pr[i] = gm1 * (U[NV - 1][i] - 0.5 * kin * ir[i]);
+    }
+    const double HxL = *row(fb, fb_index<DIM>(0, v, l, NFP, 1, 0), ldf);
+    const double HxR = *row(fb, fb_index<DIM>(1, v, l, NFP, 1, 0), ldf);
+    const bool is_e = v == NV - 1;
+    double cur[N];
 #pragma unroll
-          for (int vv = 0; vv < NV; ++vv) Up[vv] = U[vv][base + j * stride];
-          Fv[j] = flux_comp<DIM>(Up, a, v, gm1);
-        }
-        double FL = 0.0, FR = 0.0;
+    for (int i = 0; i < N; ++i) {
+      double x = 0.0;
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-          FL += lL[j] * Fv[j];
-          FR += lR[j] * Fv[j];
-        }
-        int idx[3] = {0, 0, 0};
-        idx[LA] = w;
-        if (DIM == 3) idx[a == 0 ? 1 : 0] = l;  // the in-slab index across the line
-        const int q = face_point<DIM, N>(idx, a);
-        const double HL = live ? fb[fb_index<DIM>(2 * a, v, q, NFP, ldf, e)] : 0.0;
-        const double HR = live ? fb[fb_index<DIM>(2 * a + 1, v, q, NFP, ldf, e)] : 0.0;
+      for (int k = 0; k < NV; ++k) x += (v == k ? 1.0 : 0.0) * U[k][i];
+      cur[i] = x;
+    }
+    auto flux = [&](int a, int i) {
+      const double x = cur[i] + (is_e ? pr[i] : 0.0);
+      return x * (U[1 + a][i] * ir[i]) + (v == 1 + a ? pr[i] : 0.0);
+    };
+    // fluxes across lines to LDS first, so that the x work below hides the barrier's wait
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-          double d = 0.0;
+    for (int i = 0; i < N; ++i) {
+      Hy[l * N + i][el] = flux(1, i);
+      if constexpr (DIM == 3) Hz[l * N + i][el] = flux(2, i);
+    }
+    double R[N];
+    {  // x: the lane's own line
+      double F[N];
 #pragma unroll
-          for (int j = 0; j < N; ++j) d += D[i * N + j] * Fv[j];
-          R[base + i * stride] += d + dgL[i] * (HL - FL) + dgR[i] * (HR - FR);
-        }
+      for (int k = 0; k < N; ++k) F[k] = flux(0, k);
+      double FL = 0.0, FR = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        FL += lL[k] * F[k];
+        FR += lR[k] * F[k];
+      }
+      const double jL = HxL - FL, jR = HxR - FR;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        double d = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) d += D[i * N + k] * F[k];
+        R[i] = d + dgL[i] * jL + dgR[i] * jR;
       }
     }
-    // the slab axis through LDS
-#pragma unroll
-    for (int sp = 0; sp < SP; ++sp) {
-      double Up[NV];
-#pragma unroll
-      for (int vv = 0; vv < NV; ++vv) Up[vv] = U[vv][sp];
-      H[w][sp][lane] = flux_comp<DIM>(Up, LA, v, gm1);
-    }
     __syncthreads();
+    // y: point (i, y, z) on the line of points (i, k, z)
 #pragma unroll
-    for (int sp = 0; sp < SP; ++sp) {
+    for (int i = 0; i < N; ++i) {
       double d = 0.0, FL = 0.0, FR = 0.0;
 #pragma unroll
       for (int k = 0; k < N; ++k) {
-        const double x = H[k][sp][lane];
-        d += D[w * N + k] * x;
+        const double x = Hy[i + N * k + N * N * z][el];
+        d += Dy[k] * x;
         FL += lL[k] * x;
         FR += lR[k] * x;
       }
-      const double HL = live ? fb[fb_index<DIM>(2 * LA, v, sp, NFP, ldf, e)] : 0.0;
-      const double HR = live ? fb[fb_index<DIM>(2 * LA + 1, v, sp, NFP, ldf, e)] : 0.0;
-      R[sp] += d + dgL[w] * (HL - FL) + dgR[w] * (HR - FR);
+      R[i] += d + gLy * (*row(fb, fb_index<DIM>(2, v, i + N * z, NFP, 1, 0), ldf) - FL) +
+              gRy * (*row(fb, fb_index<DIM>(3, v, i + N * z, NFP, 1, 0), ldf) - FR);
     }
-    __syncthreads();
-    if (live) {
+    if constexpr (DIM == 3) {  // z: the line of points (i, y, k)
 #pragma unroll
-      for (int sp = 0; sp < SP; ++sp) {
-        const int64_t o = (int64_t(v) * NP + w * SP + sp);
-        double r = c1 * U[v][sp] + c2 * (scale * R[sp]);
-        if (c0 != 0.0) r += c0 * u0[o * ld + e];
-        out[o * ldo + e] = r;
+      for (int i = 0; i < N; ++i) {
+        double d = 0.0, FL = 0.0, FR = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          const double x = Hz[i + N * y + N * N * k][el];
+          d += Dz[k] * x;
+          FL += lL[k] * x;
+          FR += lR[k] * x;
+        }
+        R[i] += d + gLz * (*row(fb, fb_index<DIM>(4, v, i + N * y, NFP, 1, 0), ldf) - FL) +
+                gRz * (*row(fb, fb_index<DIM>(5, v, i + N * y, NFP, 1, 0), ldf) - FR);
       }
     }
+    if (live) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int64_t o = int64_t(v) * NP + l * N + i;
+        double r = c1 * cur[i] + c2 * (scale * R[i]);
+        if (c0 != 0.0) r += c0 * *row(u0, o, ld);
+        *row(out, o, ldo) = r;
+      }
+    }
+    __syncthreads();  // before the next variable overwrites Hy, Hz
   }
 }
 
@@ -538,9 +654,14 @@ lt_status fr_volume(lt_tree_s* t, const double* tab, double length, double gamma
                     int64_t ld, const double* fb, int64_t ldf, const double* u0, double c0, double c1,
                     double c2, double* out, int64_t ldo, hipStream_t s) {
   const int64_t n = t->n_cur;
-  k_fr_volume<DIM, N><<<unsigned((n + 63) / 64), 64 * N, 0, s>>>(t->g, t->kbuf[t->cur], n, tab, length,
-                                                                 gamma, uin, ld, fb, ldf, u0, c0, c1,
-                                                                 c2, out, ldo);
+  // p = 3 in 3D: four parts of 16 elements per wave, 4 waves (16 lines of
+  // 16 elements): no spills at 224 VGPRs and two workgroups per CU; else one
+  // part of 64 elements, one wave per line
+  constexpr int H = (DIM == 3 && N == 4) ? 4 : 1;
+  constexpr int waves = (DIM == 3 ? N * N : N) / H;
+  constexpr int EB = 64 / H;
+  k_fr_volume<DIM, N, H><<<unsigned((n + EB - 1) / EB), 64 * waves, 0, s>>>(
+      t->g, t->kbuf[t->cur], n, length, gamma, uin, ld, fb, ldf, u0, c0, c1, c2, out, ldo);
   if (hipGetLastError() != hipSuccess) return fail(LT_ERR_HIP, "FR volume kernel launch");
   return LT_OK;
 }
