@@ -27,7 +27,7 @@ struct lt_cycle_s {
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   int parity = 0;                  // u[parity] holds the solution
-  int64_t* dsz = nullptr;          // device: leaves, leaves before, hanging rows, groups
+  int64_t* dsz = nullptr;          // device: leaves, leaves before, hanging rows, groups, a balance pass's input
   int64_t* hsz = nullptr;          // pinned mirror
   void* flag_host = nullptr;       // pinned flag-parameter table
   int64_t hang_rows = 0;
@@ -300,7 +300,7 @@ lt_status lt_cycle_create(lt_tree t, const lt_cycle_desc* d, void* stream, lt_cy
   c->tmpl[0].centre = c->tmpl_centres.data();
   c->d.flag_template = nullptr;
   lt_status st = LT_OK;
-  if (dev_malloc(t->A, reinterpret_cast<void**>(&c->dsz), 4 * sizeof(int64_t)) != hipSuccess ||
+  if (dev_malloc(t->A, reinterpret_cast<void**>(&c->dsz), 5 * sizeof(int64_t)) != hipSuccess ||
       hipHostMalloc(&c->hsz, 4 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(&c->flag_host, flag_args_size() * size_t(c->nmesh), hipHostMallocDefault) != hipSuccess)
     st = fail(LT_ERR_OOM, "cycle state");

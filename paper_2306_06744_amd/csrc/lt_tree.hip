@@ -918,6 +918,10 @@ __global__ void k_cycle_begin(int64_t* S, DevCtr* ctr) {
 }
 
 
+__global__ void k_pass_count(int64_t* dst, const int64_t* n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *n;
+}
+
 __global__ void k_groups_of(int64_t* dst, const int64_t* n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *dst = (*n + 63) / 64;
 }
@@ -986,7 +990,11 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
                                                  t->dctr, conv, t->elist, t->elist_cap);
     if (pass == r.passes) break;
     LT_TRY(prep_scan(t, C, kTileMax, s, 2 | 4, &st));  // also records convergence
-    st.items.p = &S[0];
+    // the pass reads its input count from S[4]: the last tile commits the
+    // new count to S[0] while workgroups of the capacity-sized grid may still
+    // be taking tickets, and each must see the count the scan started from
+    k_pass_count<<<1, 64, 0, s>>>(&S[4], &S[0]);
+    st.items.p = &S[4];
     st.commit = &S[0];
     st.commit_cap = C;
     k_balance_refine<<<grid_tiles(st), kScanBig, 0, s>>>(g, K[ki], t->mbuf[mi], K[1 - ki],

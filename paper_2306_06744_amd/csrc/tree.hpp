@@ -56,7 +56,7 @@ lt_status launch_flag_table(const KeyGeom& g, const lt_flag_params* fps, int nme
 // check pass, connect, map, transfer uo -> un, then the new keys copied back
 // to kbuf[0] (skipped when an error bit is set).  dsz[0] = leaves,
 // dsz[1] = leaves before the cycle, dsz[2] = hanging rows, dsz[3] = groups of
-// 64 leaves.  Every buffer must already hold `cap` leaves (no allocation).
+// 64 leaves, dsz[4] = a balance pass's input count.  Every buffer must already hold `cap` leaves (no allocation).
 struct CycleRec {
   int64_t cap;        // leaves
   int64_t hang_rows;  // rows of the hanging-face table

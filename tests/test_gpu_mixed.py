@@ -140,3 +140,52 @@ def test_mixed_degree_arguments_are_checked():
     t2 = lt.Tree.uniform(2, 1, 5)
     with pytest.raises(lt.LtError):
         t2.set_mesh_degree([2])
+
+
+def test_captured_mixed_cycle_64_meshes_matches_eager():
+    """The 64-mesh ensemble (p 2 and 3 mixed, finest levels 6..9) captured for
+    five cycles, the fourth of which quadruples the leaves (575k -> 2.3M): a
+    balance pass whose refinements grow the count across many scan tiles,
+    with a capacity-sized grid, against the eager calls bit for bit."""
+    import torch
+    import paper_2306_06744_amd as lt
+    meshes = synth.workload_ensemble(4000)
+    degs = [m.p for m in meshes]
+
+    def margs(m, cyc):
+        return dict(centres=m.centres_at(cyc), r_in=m.r_in, r_out=m.r_out,
+                    nodes01=synth.gl_nodes01(m.p), lo=(-5.0,) * 3, length=10.0, dist_axes=3,
+                    periodic_dist=False)
+
+    trees = []
+    for _ in range(2):
+        t = lt.Tree.batch(3, 9, [m.d_min for m in meshes], [m.d_max for m in meshes],
+                          [m.d_min for m in meshes])
+        t.set_mesh_degree(degs)
+        trees.append(t)
+    E, G = trees
+    nvar, cap = 1, 6_000_000
+    u = [torch.zeros((nvar, 64, cap), dtype=torch.float64, device="cuda") for _ in range(2)]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(64)
+    u[0][:, :, :G.size()] = torch.randn((nvar, 64, G.size()), dtype=torch.float64, device="cuda",
+                                        generator=gen)
+    uE = u[0][:, :, :E.size()].clone()
+    cyc = lt.Cycle(G, -1, nvar, cap, u, [margs(m, 0) for m in meshes])
+    for c in range(5):
+        fa = [margs(m, c) for m in meshes]
+        ui = cyc.run(fa)
+        E.adapt(E.flag_batch(fa))
+        E.balance()
+        E.map()
+        uE = E.transfer_mixed(uE)
+        torch.cuda.synchronize()
+        print("64-mesh captured cycle", c, G.size(), cyc.stats(), flush=True)
+        assert np.array_equal(G.keys().cpu().numpy(), E.keys().cpu().numpy())
+        for a, b in zip(G.mapping(), E.mapping()):
+            assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+        offs = E.mesh_offsets()
+        for m, (x, y) in enumerate(zip(owned(u[ui], offs, degs), owned(uE, offs, degs))):
+            assert bool((x == y).all()), f"mesh {m} cycle {c}"
+    assert G.size() > 2_000_000
+    del cyc
