@@ -71,18 +71,30 @@ def cpu_baseline(w, nodes):
         if cyc == 1:
             t_all = time.perf_counter() - t0
             timed_new = o.size()
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": timed_new / t_all, "unit": "octants/s", "cores": 1, "kind": "oracle",
+            "host_nproc": os.cpu_count(), "host_cpu": model,
             "sample": f"cycle 1 of the same workload ({n_old} -> {timed_new} leaves, full "
                       f"flag/adapt/balance/connect/map/transfer, {t_all:.1f} s, pointer-tree "
                       f"oracle, one thread)"}
 
 
-def ensemble_variant(lt, torch, synth, seed, nvar=5, warm=8):
-    """64 independent 3D meshes (levels up to 6..9, p in {2,3}): one timed
-    cycle (after `warm` cycles, centres advected +0.1 x per cycle) of the
-    batched path -- one ensemble tree per p, every phase one launch for all of
-    its meshes -- against a loop over 64 separate trees."""
+def ensemble_variant(lt, torch, synth, seed, nvar=5, warm=8, timed=5):
+    """64 independent 3D meshes (levels up to 6..9, p in {2,3}): `timed`
+    cycles (after `warm` cycles, centres advected +0.1 x per cycle), each
+    timed on its own, of four ways to run them: one tree holding all 64 meshes
+    with per-mesh degrees (every phase one launch for all meshes, one solution
+    array of 64 rows per variable), eagerly and as the captured cycle; one
+    ensemble tree per degree; and a loop over 64 separate trees."""
     meshes = synth.workload_ensemble(seed)
+    degs = [m.p for m in meshes]
 
     def margs(m, cyc):
         return dict(centres=m.centres_at(cyc), r_in=m.r_in, r_out=m.r_out,
@@ -91,36 +103,88 @@ def ensemble_variant(lt, torch, synth, seed, nvar=5, warm=8):
 
     side = torch.cuda.Stream()
 
-    def cycle_tree(t, p, u_old, cyc, flag_fn):
+    def new_state(t, rows):
+        return {"u": [torch.zeros((nvar, rows, t.size()), dtype=torch.float64, device="cuda"), None],
+                "cur": 0, "rows": rows}
+
+    def reserve(st, n, factor=1.3):
+        # room for the timed cycles' growth, so that they allocate nothing
+        for i in range(2):
+            x = st["u"][i]
+            if x is None or x.shape[2] < factor * n:
+                y = torch.empty((nvar, st["rows"], int(factor * n) + 1), dtype=torch.float64, device="cuda")
+                if x is not None and i == st["cur"]:
+                    y[:, :, :x.shape[2]].copy_(x)
+                st["u"][i] = y
+
+    def cycle_tree(t, p, st, cyc, flag_fn):
         # the same order as the plain cycle: connectivity on a second stream
-        # beside the transfer, its face search on a capped grid
+        # beside the transfer, its face search on a capped grid.  The
+        # solution arrays are a pair of buffers of some capacity (ld), grown
+        # only when the leaves outgrow them.
         f = flag_fn(cyc)
         t.adapt(f)
         t.balance()
         t.map()
         n = t.size()
-        u_new = torch.empty((nvar, (p + 1) ** 3, n), dtype=torch.float64, device="cuda")
-        t.transfer(p, u_old, u_new=u_new)
+        u_old = st["u"][st["cur"]]
+        u_new = st["u"][1 - st["cur"]]
+        if u_new is None or u_new.shape[2] < n:
+            u_new = torch.empty((nvar, st["rows"], int(1.3 * n) + 1), dtype=torch.float64, device="cuda")
+            st["u"][1 - st["cur"]] = u_new
+        if p < 0:
+            t.transfer_mixed(u_old, u_new=u_new)
+        else:
+            t.transfer(p, u_old, u_new=u_new)
+        st["cur"] = 1 - st["cur"]
         with torch.cuda.stream(side):
             t.connect()
-        return u_new, n
+        return n
 
-    def batched():
+    def all_meshes():
+        t = lt.Tree.batch(3, 9, [m.d_min for m in meshes], [m.d_max for m in meshes],
+                          [m.d_min for m in meshes])
+        t.set_connect_grid(CONN_GRID_LARGE)
+        t.set_mesh_degree(degs)
+        return t
+
+    def mixed():
+        t = all_meshes()
+        st = new_state(t, 64)
+
+        def one(cyc):
+            return cycle_tree(t, -1, st, cyc, lambda c: t.flag_batch([margs(m, c) for m in meshes]))
+        one.reserve = lambda: reserve(st, t.size())
+        return one
+
+    def mixed_captured():
+        t = all_meshes()
+        cap = 14_000_000
+        u = [torch.zeros((nvar, 64, cap), dtype=torch.float64, device="cuda") for _ in range(2)]
+        holder = {}
+
+        def one(cyc):
+            fa = [margs(m, cyc) for m in meshes]
+            if "cyc" not in holder:  # the graph is recorded on the first cycle
+                holder["cyc"] = lt.Cycle(t, -1, nvar, cap, u, fa, balance_passes=8)
+            holder["cyc"].run(fa)
+            return t.size()
+        one.stats = lambda: holder["cyc"].stats()
+        return one
+
+    def per_degree():
         trees = []
         for p in (2, 3):
             grp = [m for m in meshes if m.p == p]
             t = lt.Tree.batch(3, 9, [m.d_min for m in grp], [m.d_max for m in grp],
                               [m.d_min for m in grp])
             t.set_connect_grid(CONN_GRID_LARGE)
-            u = torch.zeros((nvar, (p + 1) ** 3, t.size()), dtype=torch.float64, device="cuda")
-            trees.append((t, p, grp, u))
+            trees.append((t, p, grp, new_state(t, (p + 1) ** 3)))
+
         def one(cyc):
-            total = 0
-            for i, (t, p, grp, u) in enumerate(trees):
-                u, n = cycle_tree(t, p, u, cyc, lambda c: t.flag_batch([margs(m, c) for m in grp]))
-                trees[i] = (t, p, grp, u)
-                total += n
-            return total
+            return sum(cycle_tree(t, p, st, cyc, lambda c: t.flag_batch([margs(m, c) for m in grp]))
+                       for t, p, grp, st in trees)
+        one.reserve = lambda: [reserve(st, t.size()) for t, _, _, st in trees]
         return one
 
     def looped():
@@ -128,37 +192,44 @@ def ensemble_variant(lt, torch, synth, seed, nvar=5, warm=8):
         for m in meshes:
             t = lt.Tree.uniform(3, m.d_min, m.d_max)
             t.set_connect_grid(CONN_GRID)
-            u = torch.zeros((nvar, (m.p + 1) ** 3, t.size()), dtype=torch.float64, device="cuda")
-            trees.append([t, m, u])
+            trees.append((t, m, new_state(t, (m.p + 1) ** 3)))
+
         def one(cyc):
-            total = 0
-            for rec in trees:
-                t, m, u = rec
-                a = margs(m, cyc)
-                rec[2], n = cycle_tree(t, m.p, u, cyc, lambda c: t.flag(**margs(m, c)))
-                total += n
-            return total
+            return sum(cycle_tree(t, m.p, st, cyc, lambda c: t.flag(**margs(m, c)))
+                       for t, m, st in trees)
+        one.reserve = lambda: [reserve(st, t.size()) for t, _, st in trees]
         return one
 
     out = {}
-    for name, make in (("batched", batched), ("per_mesh_loop", looped)):
+    for name, make in (("mixed_one_tree", mixed), ("mixed_one_tree_captured", mixed_captured),
+                       ("per_degree_trees", per_degree), ("per_mesh_loop", looped)):
         one = make()
         for c in range(warm):
             n = one(c)
+        if hasattr(one, "reserve"):
+            one.reserve()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        n = one(warm)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        out[name] = {"ms": dt * 1e3, "octants_per_s": n / dt}
-        out["leaves"] = n
-        log(f"ensemble {name}: {n} leaves, {dt * 1e3:.2f} ms")
+        ms, leaves = [], []
+        for c in range(warm, warm + timed):
+            t0 = time.perf_counter()
+            n = one(c)
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - t0) * 1e3)
+            leaves.append(n)
+        med = sorted(ms)[len(ms) // 2]
+        out[name] = {"ms_median": med, "ms": ms, "leaves": leaves,
+                     "octants_per_s": leaves[ms.index(med)] / (med * 1e-3)}
+        if hasattr(one, "stats"):
+            out[name]["runs_eager_recaptures"] = list(one.stats())
+        log(f"ensemble {name}: {leaves} leaves, {['%.2f' % x for x in ms]} ms")
         del one
         torch.cuda.empty_cache()
-    out["speedup"] = out["per_mesh_loop"]["ms"] / out["batched"]["ms"]
+    base = out["per_mesh_loop"]["ms_median"]
+    out["speedup_vs_loop"] = {k: base / out[k]["ms_median"] for k in
+                              ("mixed_one_tree", "mixed_one_tree_captured", "per_degree_trees")}
     out["workload"] = ("64 independent 3D meshes [-5,5]^3, 1-4 vortices (3D distance), finest "
-                       "level U{6..9}, p U{2,3}, 5 FP64 variables, uniform start at level 3, one "
-                       f"timed cycle after {warm}")
+                       "level U{6..9}, p U{2,3}, 5 FP64 variables, uniform start at level 3, "
+                       f"{timed} timed cycles after {warm} (median reported)")
     return out
 
 
@@ -266,6 +337,120 @@ def chosen_cycle(lt, torch, synth, w, nodes, stream, steps, warmup, u, cap, E, t
                 "(one synchronisation); the solution is reset to the vortex field before each "
                 "cycle (untimed); transfer_ms_mean is one event-timed eager split transfer",
     }
+
+
+def construct_variant(lt, torch, synth, reps=5):
+    """Bottom-up construction from surface points (lt_build_points), then 2:1
+    balance: a sampled torus at levels 4..9 and 4..10 (the paper's bunny runs
+    use d_min 4 with d_max 9 and 10).  Median of `reps` runs each."""
+    out = {}
+    for n_pts, d_max in ((1 << 20, 9), (1 << 22, 10)):
+        pts = torch.from_numpy(synth.surface_points(3, n_pts, 5, "torus")).cuda()
+        tb, tc = [], []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t = lt.Tree.from_points(pts, 3, 4, d_max, (-5.0,) * 3, 10.0)
+            t1 = time.perf_counter()
+            n_built = t.size()
+            t.balance()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            tb.append((t1 - t0) * 1e3)
+            tc.append((t2 - t1) * 1e3)
+            n_bal = t.size()
+            del t
+        tb.sort()
+        tc.sort()
+        out[f"torus_{n_pts}_l4-{d_max}"] = {
+            "points": n_pts, "leaves_built": n_built, "leaves_balanced": n_bal,
+            "construct_ms_median": tb[reps // 2], "balance_ms_median": tc[reps // 2],
+            "points_per_s": n_pts / (tb[reps // 2] * 1e-3),
+            "balanced_leaves_per_s": n_bal / ((tb[reps // 2] + tc[reps // 2]) * 1e-3)}
+        log(f"construct {n_pts} points l4-{d_max}: {n_built} -> {n_bal} leaves, "
+            f"{tb[reps // 2]:.2f} + {tc[reps // 2]:.2f} ms")
+        del pts
+    out["paper_context"] = ("Stanford bunny on an RTX 2060: balance 0.0569 s at d_max 9 (~0.4M "
+                            "octants), 0.2282 s at d_max 10 (~0.9M, two passes); the bunny is not "
+                            "available, a sampled torus stands in")
+    return out
+
+
+def solver_variant(lt, torch, synth, blocks=6, steps_per_adapt=10):
+    """The adaptation share of wall time (Section 5.2's measure): the 3D
+    workload's mesh (levels 4..7, p=3) carrying the isentropic vortex, advanced
+    by the three-stage Runge-Kutta FR solver, with the whole adaptation cycle
+    (flag at the advected centre, adapt, balance, connectivity, mapping, FP64
+    transfer) every `steps_per_adapt` steps.  Adaptation and solver are timed
+    separately with host clocks around synchronised phases."""
+    import numpy as np
+    w = synth.workload_3d_extruded(2000)
+    nodes = synth.gl_nodes01(w.p)
+    npts = (w.p + 1) ** 3
+    t = lt.Tree.uniform(3, w.d_min, w.d_max)
+    t.set_connect_grid(CONN_GRID)
+    for c in range(4):  # the mesh around the vortex at t = 0
+        t.adapt(t.flag(w.centres_at(0), w.r_in, w.r_out, nodes, w.lo, w.length, dist_axes=2))
+        t.balance()
+    cap = int(t.size() * 1.3)
+    u = [torch.empty((w.nvar, npts, cap), dtype=torch.float64, device="cuda") for _ in range(2)]
+    work = torch.empty_like(u[0])
+    t.vortex_field(w.centres_at(0), w.strengths, nodes, w.lo, w.length, out=u[0])
+    t.connect()
+    h_min = w.length / 2 ** w.d_max
+    dt = 0.4 * h_min / (2.5 * (2 * w.p + 1))   # CFL 0.4 of h / ((|v|+c) (2p+1)), |v|+c < 2.5
+    wq = torch.from_numpy(np.kron(np.kron(*(2 * [synth.gl_weights(w.p)])), synth.gl_weights(w.p))).cuda()
+
+    def mass(uu, n):
+        keys = t.keys()
+        depth = (keys & ((1 << w.d_max.bit_length()) - 1)).to(torch.float64)
+        vol = (w.length * torch.pow(2.0, -depth) / 2) ** 3
+        return float(((uu[0, :, :n] * wq[:, None]).sum(0) * vol).sum())
+
+    cur = 0
+    m0 = mass(u[0], t.size())
+    adapt_s = solve_s = 0.0
+    tm = 0.0
+    sizes = []
+    for b in range(blocks):
+        # adaptation at the centre carried by the free stream (u = 1, v = 0)
+        cen = [(c[0] + tm, c[1], c[2]) for c in w.centres]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n_old = t.size()
+        t.adapt(t.flag(cen, w.r_in, w.r_out, nodes, w.lo, w.length, dist_axes=2))
+        t.balance()
+        t.map()
+        if t.size() > cap:
+            raise RuntimeError("solver variant: solution buffer too small")
+        t.transfer(w.p, u[cur], u_new=u[1 - cur])
+        t.connect()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cur = 1 - cur
+        t.fr_rk3(w.p, u[cur], work, dt, w.length, steps=steps_per_adapt)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        tm += steps_per_adapt * dt
+        if b > 0:  # the first block grows buffers
+            adapt_s += t1 - t0
+            solve_s += t2 - t1
+        sizes.append((n_old, t.size()))
+        log(f"solver block {b}: {n_old} -> {t.size()} leaves, adapt {(t1 - t0) * 1e3:.2f} ms, "
+            f"{steps_per_adapt} RK3 steps {(t2 - t1) * 1e3:.1f} ms")
+    m1 = mass(u[cur], t.size())
+    rho_min = float(u[cur][0, :, : t.size()].min())
+    del t, u, work
+    return {"workload": "3D [-5,5]^3 levels 4..7, p=3, 5 FP64 variables, isentropic vortex "
+                        "(free stream u=1), geometric indicator at the advected centre",
+            "leaves": sizes, "dt": dt, "steps_per_adaptation": steps_per_adapt,
+            "timed_blocks": blocks - 1,
+            "adaptation_s": adapt_s, "solver_s": solve_s,
+            "adaptation_share": adapt_s / (adapt_s + solve_s),
+            "rk3_step_ms": solve_s * 1e3 / ((blocks - 1) * steps_per_adapt),
+            "mass_relative_drift": abs(m1 - m0) / abs(m0), "rho_min": rho_min,
+            "paper_context": "adaptation / total wall time 2.82% (3D p3, d_max 7) and 1.94% (3D p2, "
+                             "d_max 8) on an RTX 2060, adapting every 10 RK3 steps"}
 
 
 TRAFFIC_SUMMARY = os.path.join("profiles", "transfer_3d_p3_l4-7_traffic.md")
@@ -451,9 +636,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-only", action="store_true",
                     help="time only the plain FP64 cycle (skip the split-precision variant)")
-    ap.add_argument("--variants", default="graph,ensemble,large,split,chosen",
+    ap.add_argument("--variants", default="graph,ensemble,large,split,chosen,construct,solver",
                     help="comma-separated variants to run after the plain cycle "
-                         "(graph, ensemble, large, split, chosen; empty for none)")
+                         "(graph, ensemble, large, split, chosen, construct, solver; empty for "
+                         "none)")
     ap.add_argument("--train-seeds", type=int, default=2000,
                     help="training fields of the learned indicator (chosen variant)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -481,6 +667,7 @@ def main():
     u = [torch.empty((w.nvar, npts, cap), dtype=torch.float64, device="cuda") for _ in range(2)]
 
     tunes = {}
+    copy_runs = {}
 
     side = torch.cuda.Stream()
 
@@ -539,6 +726,21 @@ def main():
         for k, (sz, ms) in enumerate(zip(sizes, tr_ms)):
             log(f"[precision {precision}] cycle {args.warmup + k}: {sz[0]} -> {sz[1]} leaves, "
                 f"{sz[2]} hanging faces, transfer {ms:.3f} ms")
+        if precision == 0:
+            # the transfer over an all-copy mapping (flags 0: the tree is unchanged), i.e. the
+            # library's copy pass alone on this size: the ceiling the transfer runs against
+            t.adapt(torch.zeros(t.size(), dtype=torch.int8, device="cuda"))
+            t.map()
+            n = t.size()
+            ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            t.transfer(w.p, u[cur], u_new=u[1 - cur])
+            ev[0].record(stream)
+            for _ in range(5):
+                t.transfer(w.p, u[cur], u_new=u[1 - cur])
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            copy_runs["GBs"] = 2 * E * n / (ev[0].elapsed_time(ev[1]) / 5 * 1e-3) / 1e9
+            copy_runs["leaves"] = n
         del t
         return sizes, elapsed, tr_ms
 
@@ -562,6 +764,10 @@ def main():
         variants["chosen_learned_split"] = chosen_cycle(lt, torch, synth, w, nodes, stream,
                                                         args.steps, args.warmup, u, cap, E,
                                                         args.train_seeds)
+    if "construct" in which:
+        variants["construct_torus"] = construct_variant(lt, torch, synth)
+    if "solver" in which:
+        variants["solver_adaptation_share"] = solver_variant(lt, torch, synth)
     if "split" in which:
         s1, e1, t1 = run(1)
         n1 = sum(s[1] for s in s1)
@@ -594,6 +800,10 @@ def main():
             "cycle_hbm_frac": cyc_bytes / elapsed / (HBM_PEAK_GBS * 1e9),
             "transfer_ms_mean": sum(tr_ms) / len(tr_ms),
             "transfer_tuning": tunes.get(0),
+            "cycles": [{"cycle": args.warmup + k, "n_old": a, "n_new": b, "n_hang": h,
+                        "transfer_ms": ms,
+                        "transfer_hbm_frac": (E * a + (E + 5) * b) / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
+                       for k, ((a, b, h), ms) in enumerate(zip(sizes, tr_ms))],
         },
         "roofline": {
             "bound": "hbm",
@@ -608,6 +818,8 @@ def main():
                                         traffic["algorithmic_bytes_per_launch"]) if traffic else None,
             "traffic_source": traffic["source"] if traffic else None,
             "plain_copy_GBs": copy_ceiling,
+            "copy_pass_all_copies_GBs": copy_runs.get("GBs"),
+            "frac_of_copy_pass": achieved / copy_runs["GBs"] if copy_runs.get("GBs") else None,
         },
         "variants": variants,
         "paper_context": {

@@ -562,8 +562,9 @@ __global__ __launch_bounds__(256) void k_copy_chunks_mixed(KeyGeom g, const uint
   }
 }
 
-// The copy pass with rows r = v * NPM + i skipped where i >= the chunk's
-// largest point count.
+// The copy pass over the rows the chunk's elements own: a workgroup per
+// (chunk, variable) walks rows i < the chunk's largest point count (so that
+// no workgroup is launched for rows no element of the chunk owns).
 template <int EPL>
 __global__ __launch_bounds__(256) void k_copy3_mixed(const int32_t* __restrict__ src,
                                                      const int8_t* __restrict__ kind, Count cn,
@@ -575,23 +576,37 @@ __global__ __launch_bounds__(256) void k_copy3_mixed(const int32_t* __restrict__
   const int64_t n = cn.get();
   const int64_t c = xcd_chunk(blockIdx.x, gridDim.x);
   if (c * CH >= n) return;
-  if (int(blockIdx.y % npm) >= cnp[c]) return;
-  const double* U = uo + int64_t(blockIdx.y) * ldo;
-  double* O = un + int64_t(blockIdx.y) * ldn;
+  const int rows = cnp[c];
+  const int64_t r0 = int64_t(blockIdx.y) * npm;
   const int64_t dl = cdelta[c];
   if (dl != kImpure) {
+#pragma unroll 4
+    for (int i = 0; i < rows; ++i) {
+      const double* U = uo + (r0 + i) * ldo;
+      double* O = un + (r0 + i) * ldn;
 #pragma unroll
-    for (int e = 0; e < EPL; ++e) {
-      const int64_t j = c * CH + int64_t(e) * 256 + threadIdx.x;
-      if (j < n) __builtin_nontemporal_store(__builtin_nontemporal_load(U + j + dl), O + j);
+      for (int e = 0; e < EPL; ++e) {
+        const int64_t j = c * CH + int64_t(e) * 256 + threadIdx.x;
+        if (j < n) __builtin_nontemporal_store(__builtin_nontemporal_load(U + j + dl), O + j);
+      }
     }
     return;
   }
+  int64_t sj[EPL];
 #pragma unroll
   for (int e = 0; e < EPL; ++e) {
     const int64_t jj = c * CH + int64_t(e) * 256 + threadIdx.x;
-    if (jj < n && kind[jj] == 0)
-      __builtin_nontemporal_store(__builtin_nontemporal_load(U + src[jj]), O + jj);
+    sj[e] = jj < n && kind[jj] == 0 ? int64_t(src[jj]) : -1;
+  }
+#pragma unroll 4
+  for (int i = 0; i < rows; ++i) {
+    const double* U = uo + (r0 + i) * ldo;
+    double* O = un + (r0 + i) * ldn;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e)
+      if (sj[e] >= 0)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(U + sj[e]),
+                                    O + c * CH + int64_t(e) * 256 + threadIdx.x);
   }
 }
 
@@ -950,7 +965,7 @@ lt_status launch_transfer_mixed(lt_tree_s* t, const uint64_t* keys, Count n, con
   LT_TRY_STATUS(grow(t->A, &t->copy_delta, &t->copy_delta_cap, nchunks));
   LT_TRY_STATUS(grow(t->A, &t->chunk_np, &t->chunk_np_cap, nchunks));
   LT_TRY_STATUS(grow(t->A, &t->grp_list, &t->grp_cap, 6 * ngroups));
-  const dim3 grid{unsigned(nchunks), unsigned(nvar * npm), 1u};
+  const dim3 grid{unsigned(nchunks), unsigned(nvar), 1u};
 #define LT_CM(E)                                                                                    \
   do {                                                                                              \
     k_copy_chunks_mixed<E><<<unsigned(nchunks), 256, 0, s>>>(t->g, keys, t->mesh_np, t->map_src,     \

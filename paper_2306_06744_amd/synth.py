@@ -47,6 +47,11 @@ def gl_nodes01(p: int) -> np.ndarray:
     return np.array([(1.0 + v) / 2.0 for v in x], dtype=np.float64)
 
 
+def gl_weights(p: int) -> np.ndarray:
+    """Gauss-Legendre weights of the p+1 points on [-1, 1] (summing to 2)."""
+    return np.polynomial.legendre.leggauss(p + 1)[1]
+
+
 def rng(seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(seed))
 
