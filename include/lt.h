@@ -290,7 +290,7 @@ typedef struct {
 
 /* Times lt_transfer (same arguments, same result every time: u_new is
  * written repeatedly) for every tuning candidate -- copy elements per lane
- * {1, 2, 4} x interpolation workgroups {1024, 2048, 4096} -- with HIP events,
+ * {1, 2, 4} x interpolation workgroups {1024, 2048, 4096, 16384, 65535} -- with HIP events,
  * one untimed and three timed launches each, and keeps the fastest in the
  * tree for later transfers (and cycles captured later).  Synchronises. */
 lt_status lt_autotune_transfer(lt_tree t, int p, int nvar, const double* u_old, int64_t ld_old,

@@ -241,10 +241,14 @@ __global__ __launch_bounds__(256) void k_copy_chunks(const int32_t* __restrict__
 // point i) of one chunk: 256 lanes x EPL elements.  Pure chunks read one
 // offset and move the row like a plain copy (16-byte pairs for EPL >= 2);
 // impure chunks read the map per element and move only the copy elements.
+// SKIP: a wave leaves out its 64 elements (one interpolation group) when any
+// of them is refined or fused -- the interpolation passes then write the
+// group's copies too, so that every row segment of a group is written whole
+// by one kernel (pieces written by two kernels reach HBM as partial lines).
 // Source loads and output stores are streaming (non-temporal): every copied
 // value is touched once, and keeping it out of the caches was measured ~2.5%
 // faster for the whole transfer.
-template <int EPL>
+template <int EPL, bool SKIP>
 __global__ __launch_bounds__(256) void k_copy3(const int32_t* __restrict__ src,
                                                const int8_t* __restrict__ kind, Count cn,
                                                const int64_t* __restrict__ cdelta,
@@ -278,8 +282,9 @@ __global__ __launch_bounds__(256) void k_copy3(const int32_t* __restrict__ src,
 #pragma unroll
   for (int e = 0; e < EPL; ++e) {
     const int64_t jj = c * CH + int64_t(e) * 256 + threadIdx.x;
-    if (jj < n && kind[jj] == 0)
-      __builtin_nontemporal_store(__builtin_nontemporal_load(U + src[jj]), O + jj);
+    const int kd = jj < n ? int(kind[jj]) : 0;
+    if (SKIP && __ballot(kd != 0) != 0) continue;  // an interpolation group
+    if (jj < n && kd == 0) __builtin_nontemporal_store(__builtin_nontemporal_load(U + src[jj]), O + jj);
   }
 }
 
@@ -365,7 +370,9 @@ __global__ __launch_bounds__(kScanSmall) void k_group_list(const int8_t* __restr
 // in registers, the z pass mixes the N slabs through LDS, and each output row
 // is stored as soon as it is formed.  Keeping no accumulator across rounds
 // holds the register count near half of the general kernel's, so twice as
-// many waves hide the load and store latency.
+// many waves hide the load and store latency.  The group's copies are moved
+// here as well (the copy pass leaves listed groups out), so that each row
+// segment of a group is written whole by this kernel.
 template <int N>
 __global__ __launch_bounds__(64 * N) void k_interp3_ref(const double* __restrict__ ops,
                                                         const int32_t* __restrict__ src,
@@ -387,15 +394,38 @@ __global__ __launch_bounds__(64 * N) void k_interp3_ref(const double* __restrict
   const double* U = uo + int64_t(v) * NP * ldo + int64_t(w) * NN * ldo;
   double* O0 = un + int64_t(v) * NP * ldn + int64_t(w) * NN * ldn;
   __syncthreads();
-  for (int64_t gi = blockIdx.x; gi < ng; gi += gridDim.x) {
-    const int64_t j = int64_t(groups[gi]) * 64 + lane;
-    const int kd = j < n ? int(kind[j]) : 0;
+  // the map of the block's next group is loaded while the current one is
+  // worked on
+  int64_t gi = blockIdx.x;
+  int64_t j = int64_t(groups[gi]) * 64 + lane;
+  int kd = j < n ? int(kind[j]) : 0;
+  int64_t s = j < n ? int64_t(src[j]) : 0;
+  for (; gi < ng; gi += gridDim.x) {
+    const int64_t gn = gi + gridDim.x;
+    int64_t jn = 0, sn = 0;
+    int kdn = 0;
+    if (gn < ng) {
+      jn = int64_t(groups[gn]) * 64 + lane;
+      if (jn < n) {
+        kdn = int(kind[jn]);
+        sn = int64_t(src[jn]);
+      }
+    }
+    // a copy loads its own source, a refined child its parent: the same rows
+    const bool live = j < n;
+    double in[NN];
+    if (live) {
+#pragma unroll
+      for (int r = 0; r < NN; ++r) in[r] = __builtin_nontemporal_load(U + int64_t(r) * ldo + s);
+    }
+    double* O = O0 + j;
+    if (live && kd == 0) {  // a copy of the group (the copy pass left the group out)
+#pragma unroll
+      for (int r = 0; r < NN; ++r) __builtin_nontemporal_store(in[r], O + int64_t(r) * ldn);
+    }
     const int c = kd > 0 ? kd - 1 : 0;
     if (kd > 0) {
-      const int64_t s = int64_t(src[j]);
-      double in[NN], sl[NN];
-#pragma unroll
-      for (int r = 0; r < NN; ++r) in[r] = U[int64_t(r) * ldo + s];
+      double sl[NN];
       xy_pass<N>(M[c & 1], M[(c >> 1) & 1], in, sl);
 #pragma unroll
       for (int r = 0; r < NN; ++r) T[w][r][lane] = sl[r];
@@ -403,16 +433,18 @@ __global__ __launch_bounds__(64 * N) void k_interp3_ref(const double* __restrict
     __syncthreads();
     if (kd > 0) {
       const double* Mz = M[(c >> 2) & 1] + w * N;
-      double* O = O0 + j;
 #pragma unroll
       for (int r = 0; r < NN; ++r) {
         double a = 0.0;
 #pragma unroll
         for (int k = 0; k < N; ++k) a += Mz[k] * T[k][r][lane];
-        O[int64_t(r) * ldn] = a;
+        __builtin_nontemporal_store(a, O + int64_t(r) * ldn);
       }
     }
     __syncthreads();
+    j = jn;
+    kd = kdn;
+    s = sn;
   }
 }
 
@@ -420,10 +452,11 @@ __global__ __launch_bounds__(64 * N) void k_interp3_ref(const double* __restrict
 // fused element (refined children in the same group are handled here too).
 // A block of N waves takes listed groups of 64 consecutive new elements of
 // one variable (grid-stride over the device-side list); lane = element and
-// wave w owns z-slab w (N*N points) of the input and of the output.  The x and y passes act within a slab and stay
-// in registers; the z pass mixes slabs through LDS.  A fused element needs two
-// z rounds (children with z bit 0, then 1), a refined one a single round.
-// Copy elements are left to the copy pass.
+// wave w owns z-slab w (N*N points) of the input and of the output.  The x
+// and y passes act within a slab and stay in registers; the z pass mixes
+// slabs through LDS.  A fused element needs two z rounds (children with z
+// bit 0, then 1), a refined one a single round.  The group's copies are moved
+// here as well (the copy pass leaves listed groups out).
 template <int N>
 __global__ __launch_bounds__(64 * N) void k_interp3(const double* __restrict__ ops,
                                                     const int32_t* __restrict__ src,
@@ -448,7 +481,7 @@ __global__ __launch_bounds__(64 * N) void k_interp3(const double* __restrict__ o
     const int64_t j = int64_t(groups[gi]) * 64 + lane;
     const int kd = j < n ? int(kind[j]) : 0;
     const int rounds = __ballot(kd < 0) != 0 ? 2 : 1;
-    const int64_t s = kd != 0 ? int64_t(src[j]) : 0;
+    const int64_t s = j < n ? int64_t(src[j]) : 0;
     const int c = kd > 0 ? kd - 1 : 0;
     double acc[NN];
 #pragma unroll
@@ -500,10 +533,14 @@ __global__ __launch_bounds__(64 * N) void k_interp3(const double* __restrict__ o
       }
       __syncthreads();
     }
+    double* O = un + int64_t(v) * NP * ldn + int64_t(w) * NN * ldn + j;
     if (kd != 0) {
-      double* O = un + int64_t(v) * NP * ldn + int64_t(w) * NN * ldn + j;
 #pragma unroll
-      for (int r = 0; r < NN; ++r) O[int64_t(r) * ldn] = acc[r];
+      for (int r = 0; r < NN; ++r) __builtin_nontemporal_store(acc[r], O + int64_t(r) * ldn);
+    } else if (j < n) {  // a copy of the group (the copy pass left the group out)
+#pragma unroll
+      for (int r = 0; r < NN; ++r)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(U + int64_t(r) * ldo + s), O + int64_t(r) * ldn);
     }
   }
 }
@@ -800,7 +837,7 @@ struct XferScratch {
 
 lt_status copy_pass(const TransferTune& tune, const int32_t* src, const int8_t* kind, Count n,
                     int64_t rows, const double* uo, int64_t ldo, double* un, int64_t ldn,
-                    int64_t* copy_delta, hipStream_t s);
+                    int64_t* copy_delta, bool skip_groups, hipStream_t s);
 
 template <int DIM, int N>
 hipError_t launch(const TransferTune& tune, const double* ops, const int32_t* src, const int8_t* kind,
@@ -809,7 +846,8 @@ hipError_t launch(const TransferTune& tune, const double* ops, const int32_t* sr
   *st_out = LT_OK;
   if constexpr (DIM == 3) {
     const int64_t ngroups = (n.n + 63) / 64;
-    *st_out = copy_pass(tune, src, kind, n, nvar * N * N * N, uo, ldo, un, ldn, X.copy_delta, s);
+    // the copies of interpolation groups are left to the interpolation passes
+    *st_out = copy_pass(tune, src, kind, n, nvar * N * N * N, uo, ldo, un, ldn, X.copy_delta, true, s);
     if (*st_out != LT_OK) return hipSuccess;
     hipError_t e = hipSuccess;
     // grp_list holds the ordered list in [0, ngroups) and the list of
@@ -844,7 +882,7 @@ hipError_t launch(const TransferTune& tune, const double* ops, const int32_t* sr
 namespace {
 lt_status copy_pass(const TransferTune& tune, const int32_t* src, const int8_t* kind, Count n,
                     int64_t rows, const double* uo, int64_t ldo, double* un, int64_t ldn,
-                    int64_t* copy_delta, hipStream_t s) {
+                    int64_t* copy_delta, bool skip_groups, hipStream_t s) {
   if (n.n == 0) return LT_OK;
   if (rows < 1 || rows > 65535) return fail(LT_ERR_ARG, "copy pass: rows out of range");
   const int epl = tune.copy_epl;
@@ -854,7 +892,10 @@ lt_status copy_pass(const TransferTune& tune, const int32_t* src, const int8_t* 
 #define LT_COPY(E)                                                                              \
   do {                                                                                          \
     k_copy_chunks<E><<<unsigned(nchunks), 256, 0, s>>>(src, kind, n, copy_delta);               \
-    k_copy3<E><<<grid, 256, 0, s>>>(src, kind, n, copy_delta, uo, ldo, un, ldn);                \
+    if (skip_groups)                                                                            \
+      k_copy3<E, true><<<grid, 256, 0, s>>>(src, kind, n, copy_delta, uo, ldo, un, ldn);        \
+    else                                                                                        \
+      k_copy3<E, false><<<grid, 256, 0, s>>>(src, kind, n, copy_delta, uo, ldo, un, ldn);       \
   } while (0)
   if (epl == 1)
     LT_COPY(1);
@@ -874,7 +915,7 @@ lt_status launch_copy(lt_tree_s* t, Count n, int64_t rows, const double* uo, int
   if (n.n == 0) return LT_OK;
   const int64_t CH = 256 * int64_t(t->tune.copy_epl);
   LT_TRY_STATUS(grow(t->A, &t->copy_delta, &t->copy_delta_cap, (n.n + CH - 1) / CH));
-  return copy_pass(t->tune, t->map_src, t->map_kind, n, rows, uo, ldo, un, ldn, t->copy_delta, s);
+  return copy_pass(t->tune, t->map_src, t->map_kind, n, rows, uo, ldo, un, ldn, t->copy_delta, false, s);
 }
 
 lt_status build_transfer_ops(const Alloc& A, int p, double** ops, hipStream_t stream) {
@@ -1163,12 +1204,12 @@ lt_status lt_autotune_transfer(lt_tree t, int p, int nvar, const double* u_old, 
     return fail(LT_ERR_HIP, "event create");
   const TransferTune keep = t->tune;
   const int epls[3] = {1, 2, 4};
-  const int grids[3] = {1024, 2048, 4096};
+  const int grids[5] = {1024, 2048, 4096, 16384, 65535};
   TransferTune best = keep;
   float best_ms = 1e30f, default_ms = -1.f;
   lt_status st = LT_OK;
   for (int a = 0; a < 3 && st == LT_OK; ++a)
-    for (int b = 0; b < 3 && st == LT_OK; ++b) {
+    for (int b = 0; b < 5 && st == LT_OK; ++b) {
       t->tune.copy_epl = epls[a];
       t->tune.interp_grid = grids[b];
       // one untimed launch, then three timed ones (every candidate writes the same result)
