@@ -363,6 +363,19 @@ __global__ __launch_bounds__(kScanSmall) void k_group_list(const int8_t* __restr
     if (ref[k]) list[o++] = int32_t(base + k);
 }
 
+// Ensembles with a degree per mesh (lt_set_mesh_degree): the interpolation
+// kernels below also run over (group, degree) entries, entry = group * 4 +
+// N - 1, one launch per degree present.  A lane then works only if its
+// element's mesh has degree N (the key's mesh bits index the point-count
+// table); copies are left to the copy pass, and a variable's rows are npm
+// apart (the largest point count of the ensemble).
+struct MixedArgs {
+  KeyGeom g;
+  const uint64_t* keys = nullptr;
+  const uint8_t* np_of_mesh = nullptr;
+  int npm = 0;
+};
+
 // 3D refinement pass over the groups that hold refined children only.  A
 // block of N waves takes listed groups of 64 consecutive new elements of one
 // variable (grid-stride over the device-side list); lane = element and wave w
@@ -372,15 +385,16 @@ __global__ __launch_bounds__(kScanSmall) void k_group_list(const int8_t* __restr
 // holds the register count near half of the general kernel's, so twice as
 // many waves hide the load and store latency.  The group's copies are moved
 // here as well (the copy pass leaves listed groups out), so that each row
-// segment of a group is written whole by this kernel.
-template <int N>
+// segment of a group is written whole by this kernel.  MIXED: see MixedArgs.
+template <int N, bool MIXED>
 __global__ __launch_bounds__(64 * N) void k_interp3_ref(const double* __restrict__ ops,
                                                         const int32_t* __restrict__ src,
                                                         const int8_t* __restrict__ kind, Count cn,
                                                         const int32_t* __restrict__ groups,
                                                         const int64_t* __restrict__ ngroups,
                                                         const double* __restrict__ uo, int64_t ldo,
-                                                        double* __restrict__ un, int64_t ldn) {
+                                                        double* __restrict__ un, int64_t ldn,
+                                                        MixedArgs mx) {
   constexpr int NN = N * N;
   constexpr int NP = NN * N;
   __shared__ double T[N][NN][64];
@@ -391,35 +405,30 @@ __global__ __launch_bounds__(64 * N) void k_interp3_ref(const double* __restrict
   if (int64_t(blockIdx.x) >= ng) return;
   for (int i = threadIdx.x; i < 2 * NN; i += blockDim.x) M[i / NN][i % NN] = ops[i];
   const int v = blockIdx.y;
-  const double* U = uo + int64_t(v) * NP * ldo + int64_t(w) * NN * ldo;
-  double* O0 = un + int64_t(v) * NP * ldn + int64_t(w) * NN * ldn;
+  const int64_t vstride = MIXED ? mx.npm : NP;
+  const double* U = uo + int64_t(v) * vstride * ldo + int64_t(w) * NN * ldo;
+  double* O0 = un + int64_t(v) * vstride * ldn + int64_t(w) * NN * ldn;
   __syncthreads();
-  // the map of the block's next group is loaded while the current one is
-  // worked on
-  int64_t gi = blockIdx.x;
-  int64_t j = int64_t(groups[gi]) * 64 + lane;
-  int kd = j < n ? int(kind[j]) : 0;
-  int64_t s = j < n ? int64_t(src[j]) : 0;
-  for (; gi < ng; gi += gridDim.x) {
-    const int64_t gn = gi + gridDim.x;
-    int64_t jn = 0, sn = 0;
-    int kdn = 0;
-    if (gn < ng) {
-      jn = int64_t(groups[gn]) * 64 + lane;
-      if (jn < n) {
-        kdn = int(kind[jn]);
-        sn = int64_t(src[jn]);
-      }
+  for (int64_t gi = blockIdx.x; gi < ng; gi += gridDim.x) {
+    int64_t grp = groups[gi];
+    if constexpr (MIXED) {
+      if ((grp & 3) != N - 1) continue;  // another degree's entry (uniform over the block)
+      grp >>= 2;
     }
+    const int64_t j = grp * 64 + lane;
+    bool live = j < n;
+    if constexpr (MIXED) live = live && int(mx.np_of_mesh[key_mesh(mx.g, mx.keys[j])]) == NP;
+    const int kd = live ? int(kind[j]) : 0;
     // a copy loads its own source, a refined child its parent: the same rows
-    const bool live = j < n;
     double in[NN];
-    if (live) {
+    const bool work = live && (!MIXED || kd > 0);
+    if (work) {
+      const int64_t s = int64_t(src[j]);
 #pragma unroll
       for (int r = 0; r < NN; ++r) in[r] = __builtin_nontemporal_load(U + int64_t(r) * ldo + s);
     }
     double* O = O0 + j;
-    if (live && kd == 0) {  // a copy of the group (the copy pass left the group out)
+    if (!MIXED && live && kd == 0) {  // a copy of the group (the copy pass left the group out)
 #pragma unroll
       for (int r = 0; r < NN; ++r) __builtin_nontemporal_store(in[r], O + int64_t(r) * ldn);
     }
@@ -442,9 +451,6 @@ __global__ __launch_bounds__(64 * N) void k_interp3_ref(const double* __restrict
       }
     }
     __syncthreads();
-    j = jn;
-    kd = kdn;
-    s = sn;
   }
 }
 
@@ -456,15 +462,17 @@ __global__ __launch_bounds__(64 * N) void k_interp3_ref(const double* __restrict
 // and y passes act within a slab and stay in registers; the z pass mixes
 // slabs through LDS.  A fused element needs two z rounds (children with z
 // bit 0, then 1), a refined one a single round.  The group's copies are moved
-// here as well (the copy pass leaves listed groups out).
-template <int N>
+// here as well (the copy pass leaves listed groups out).  MIXED: see
+// MixedArgs.
+template <int N, bool MIXED>
 __global__ __launch_bounds__(64 * N) void k_interp3(const double* __restrict__ ops,
                                                     const int32_t* __restrict__ src,
                                                     const int8_t* __restrict__ kind, Count cn,
                                                     const int32_t* __restrict__ groups,
                                                     const int64_t* __restrict__ ngroups,
                                                     const double* __restrict__ uo, int64_t ldo,
-                                                    double* __restrict__ un, int64_t ldn) {
+                                                    double* __restrict__ un, int64_t ldn,
+                                                    MixedArgs mx) {
   constexpr int NN = N * N;
   constexpr int NP = NN * N;
   __shared__ double T[N][NN][64];
@@ -475,13 +483,22 @@ __global__ __launch_bounds__(64 * N) void k_interp3(const double* __restrict__ o
   if (int64_t(blockIdx.x) >= ng) return;
   for (int i = threadIdx.x; i < 4 * NN; i += blockDim.x) M[i / NN][i % NN] = ops[i];
   const int v = blockIdx.y;
-  const double* U = uo + int64_t(v) * NP * ldo + int64_t(w) * NN * ldo;
+  const int64_t vstride = MIXED ? mx.npm : NP;
+  const double* U = uo + int64_t(v) * vstride * ldo + int64_t(w) * NN * ldo;
   __syncthreads();
   for (int64_t gi = blockIdx.x; gi < ng; gi += gridDim.x) {
-    const int64_t j = int64_t(groups[gi]) * 64 + lane;
-    const int kd = j < n ? int(kind[j]) : 0;
+    int64_t grp = groups[gi];
+    if constexpr (MIXED) {
+      if ((grp & 3) != N - 1) continue;  // another degree's entry (uniform over the block)
+      grp >>= 2;
+    }
+    const int64_t j = grp * 64 + lane;
+    bool live = j < n;
+    if constexpr (MIXED) live = live && int(mx.np_of_mesh[key_mesh(mx.g, mx.keys[j])]) == NP;
+    const int kd = live ? int(kind[j]) : 0;
+    // every wave sees the same 64 elements, so the rounds agree across the block
     const int rounds = __ballot(kd < 0) != 0 ? 2 : 1;
-    const int64_t s = j < n ? int64_t(src[j]) : 0;
+    const int64_t s = live ? int64_t(src[j]) : 0;
     const int c = kd > 0 ? kd - 1 : 0;
     double acc[NN];
 #pragma unroll
@@ -533,11 +550,11 @@ __global__ __launch_bounds__(64 * N) void k_interp3(const double* __restrict__ o
       }
       __syncthreads();
     }
-    double* O = un + int64_t(v) * NP * ldn + int64_t(w) * NN * ldn + j;
+    double* O = un + int64_t(v) * vstride * ldn + int64_t(w) * NN * ldn + j;
     if (kd != 0) {
 #pragma unroll
       for (int r = 0; r < NN; ++r) __builtin_nontemporal_store(acc[r], O + int64_t(r) * ldn);
-    } else if (j < n) {  // a copy of the group (the copy pass left the group out)
+    } else if (!MIXED && live) {  // a copy of the group (the copy pass left the group out)
 #pragma unroll
       for (int r = 0; r < NN; ++r)
         __builtin_nontemporal_store(__builtin_nontemporal_load(U + int64_t(r) * ldo + s), O + int64_t(r) * ldn);
@@ -549,8 +566,10 @@ __global__ __launch_bounds__(64 * N) void k_interp3(const double* __restrict__ o
 // An ensemble whose meshes carry their own degree (3D, p 1..3) in one
 // solution layout u[(v * NPM + i) * ld + e], NPM = the largest point count;
 // an element of a mesh with N = p+1 points per axis uses rows i < N^3 of each
-// variable block.  np_of_mesh[m] = N^3 of mesh m.  Every kernel below handles
-// all degrees in one launch.
+// variable block.  np_of_mesh[m] = N^3 of mesh m.  The copy pass and the
+// group lists below handle all degrees in one launch; the interpolation runs
+// the uniform kernels once per degree present over the (group, degree)
+// entries (their MIXED form).
 
 __device__ inline int elem_np(const KeyGeom& g, const uint8_t* __restrict__ np_of_mesh, uint64_t key) {
   return np_of_mesh[key_mesh(g, key)];
@@ -696,131 +715,6 @@ __global__ __launch_bounds__(kScanSmall) void k_group_list_mixed(KeyGeom g, cons
       if (refmask[k] & (1u << (N - 1))) list[o++] = int32_t((base + k) * 4 + (N - 1));
 }
 
-// One entry of degree N in a block of 4 waves (wave w owns z-slab w; waves
-// w >= N only join the barriers).  Lanes whose element has another degree,
-// or is a copy, do nothing.  M: A_0, A_1, P_0, P_1 of degree N (N*N each).
-template <int N>
-__device__ inline void mixed_entry(const KeyGeom& g, const uint64_t* __restrict__ keys,
-                                   const uint8_t* __restrict__ np_of_mesh,
-                                   const int32_t* __restrict__ src, const int8_t* __restrict__ kind,
-                                   int64_t n, int64_t gidx, const double (*M)[16], int npm, int v,
-                                   const double* __restrict__ uo, int64_t ldo, double* __restrict__ un,
-                                   int64_t ldn, double (*T)[16][64]) {
-  constexpr int NN = N * N;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t j = gidx * 64 + lane;
-  int kd = j < n ? int(kind[j]) : 0;
-  if (kd != 0 && elem_np(g, np_of_mesh, keys[j]) != NN * N) kd = 0;
-  if (w >= N) kd = 0;
-  const int rounds = __ballot(kd < 0) != 0 ? 2 : 1;
-  const int64_t s = kd != 0 ? int64_t(src[j]) : 0;
-  const int c = kd > 0 ? kd - 1 : 0;
-  const double* U = uo + (int64_t(v) * npm + int64_t(w) * NN) * ldo;
-  double acc[NN];
-#pragma unroll
-  for (int r = 0; r < NN; ++r) acc[r] = 0.0;
-  // the block's rounds must agree: a fused element anywhere needs two
-  __shared__ int s_rounds;
-  if (threadIdx.x == 0) s_rounds = 1;
-  __syncthreads();
-  if (lane == 0 && rounds == 2) s_rounds = 2;
-  __syncthreads();
-  const int R = s_rounds;
-  for (int rz = 0; rz < R; ++rz) {
-    double sl[NN];
-#pragma unroll
-    for (int r = 0; r < NN; ++r) sl[r] = 0.0;
-    if (kd > 0) {
-      if (rz == 0) {
-        double in[NN];
-#pragma unroll
-        for (int r = 0; r < NN; ++r) in[r] = U[int64_t(r) * ldo + s];
-        xy_pass<N>(M[c & 1], M[(c >> 1) & 1], in, sl);
-      }
-    } else if (kd < 0) {
-#pragma unroll 1
-      for (int cc = 0; cc < 4; ++cc) {
-        const int child = cc + 4 * rz;
-        double in[NN], t[NN];
-#pragma unroll
-        for (int r = 0; r < NN; ++r) in[r] = U[int64_t(r) * ldo + s + child];
-        xy_pass<N>(M[2 + (cc & 1)], M[2 + (cc >> 1)], in, t);
-#pragma unroll
-        for (int r = 0; r < NN; ++r) sl[r] += t[r];
-      }
-    }
-    if (w < N) {
-#pragma unroll
-      for (int r = 0; r < NN; ++r) T[w][r][lane] = sl[r];
-    }
-    __syncthreads();
-    if (kd > 0 && rz == 0) {
-      const double* Mz = M[(c >> 2) & 1] + w * N;
-#pragma unroll
-      for (int r = 0; r < NN; ++r) {
-        double a = 0.0;
-#pragma unroll
-        for (int k = 0; k < N; ++k) a += Mz[k] * T[k][r][lane];
-        acc[r] = a;
-      }
-    } else if (kd < 0) {
-      const double* Mz = M[2 + rz] + w * N;
-#pragma unroll
-      for (int r = 0; r < NN; ++r) {
-        double a = 0.0;
-#pragma unroll
-        for (int k = 0; k < N; ++k) a += Mz[k] * T[k][r][lane];
-        acc[r] += a;
-      }
-    }
-    __syncthreads();
-  }
-  if (kd != 0) {
-    double* O = un + (int64_t(v) * npm + int64_t(w) * NN) * ldn + j;
-#pragma unroll
-    for (int r = 0; r < NN; ++r) O[int64_t(r) * ldn] = acc[r];
-  }
-}
-
-// Interpolation / projection over work entries of any degree: blocks of 4
-// waves take entries grid-stride (blockIdx.y = variable).  ops1d[N] holds the
-// degree-N factors A_0, A_1, P_0, P_1 (or null when no mesh has degree N).
-__global__ __launch_bounds__(256) void k_interp3_mixed(KeyGeom g, const uint64_t* __restrict__ keys,
-                                                       const uint8_t* __restrict__ np_of_mesh,
-                                                       const double* ops2, const double* ops3,
-                                                       const double* ops4,
-                                                       const int32_t* __restrict__ src,
-                                                       const int8_t* __restrict__ kind, Count cn,
-                                                       const int32_t* __restrict__ entries,
-                                                       const int64_t* __restrict__ nentries, int npm,
-                                                       const double* __restrict__ uo, int64_t ldo,
-                                                       double* __restrict__ un, int64_t ldn) {
-  __shared__ double T[4][16][64];
-  __shared__ double M[3][4][16];  // degree 2, 3, 4: A_0, A_1, P_0, P_1
-  const int64_t n = cn.get();
-  const int64_t ne = *nentries;
-  if (int64_t(blockIdx.x) >= ne) return;
-  const double* ops[3] = {ops2, ops3, ops4};
-  for (int d = 0; d < 3; ++d) {
-    const int N = d + 2;
-    if (!ops[d]) continue;
-    for (int i = threadIdx.x; i < 4 * N * N; i += blockDim.x) M[d][i / (N * N)][i % (N * N)] = ops[d][i];
-  }
-  __syncthreads();
-  const int v = blockIdx.y;
-  for (int64_t ei = blockIdx.x; ei < ne; ei += gridDim.x) {
-    const int32_t ent = entries[ei];
-    const int64_t gidx = ent >> 2;
-    const int N = (ent & 3) + 1;
-    if (N == 2)
-      mixed_entry<2>(g, keys, np_of_mesh, src, kind, n, gidx, M[0], npm, v, uo, ldo, un, ldn, T);
-    else if (N == 3)
-      mixed_entry<3>(g, keys, np_of_mesh, src, kind, n, gidx, M[1], npm, v, uo, ldo, un, ldn, T);
-    else
-      mixed_entry<4>(g, keys, np_of_mesh, src, kind, n, gidx, M[2], npm, v, uo, ldo, un, ldn, T);
-  }
-}
-
 // Scratch of one FP64 transfer, sized for n new leaves: per copy chunk the
 // source offset of a pure copy run (ceil(n / 256) entries at the finest
 // tuning), the interpolation-group lists (the ordered list of groups with a
@@ -863,12 +757,12 @@ hipError_t launch(const TransferTune& tune, const double* ops, const int32_t* sr
     if (e != hipSuccess) return e;
     const dim3 gi{unsigned(std::max<int64_t>(1, std::min<int64_t>(ngroups, tune.interp_grid))),
                   unsigned(nvar), 1u};
-    k_interp3_ref<N><<<gi, 64 * N, 0, s>>>(ops, src, kind, n, X.grp_list, st.total, uo, ldo, un,
-                                           ldn);
+    k_interp3_ref<N, false><<<gi, 64 * N, 0, s>>>(ops, src, kind, n, X.grp_list, st.total, uo, ldo, un,
+                                                  ldn, MixedArgs{});
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_interp3<N><<<gi, 64 * N, 0, s>>>(ops, src, kind, n, flist, &X.ctr->nfgroups, uo, ldo, un,
-                                       ldn);
+    k_interp3<N, false><<<gi, 64 * N, 0, s>>>(ops, src, kind, n, flist, &X.ctr->nfgroups, uo, ldo, un,
+                                              ldn, MixedArgs{});
     return hipGetLastError();
   } else {
     dim3 grid(unsigned((n.n + 255) / 256), unsigned(nvar));
@@ -1028,12 +922,22 @@ lt_status launch_transfer_mixed(lt_tree_s* t, const uint64_t* keys, Count n, con
   int32_t* flist = t->grp_list + 3 * ngroups;
   k_group_list_mixed<<<grid_tiles(st), kScanSmall, 0, s>>>(t->g, keys, t->mesh_np, t->map_kind, n,
                                                            t->grp_list, st, flist, &t->dctr->nfgroups);
+  // one launch of each interpolation kernel per degree present; the blocks of a
+  // launch skip the other degrees' entries
   const dim3 gi{unsigned(std::max<int64_t>(1, std::min<int64_t>(3 * ngroups, t->tune.interp_grid))),
                 unsigned(nvar), 1u};
-  k_interp3_mixed<<<gi, 256, 0, s>>>(t->g, keys, t->mesh_np, ops[0], ops[1], ops[2], t->map_src,
-                                     t->map_kind, n, t->grp_list, st.total, npm, uo, ldo, un, ldn);
-  k_interp3_mixed<<<gi, 256, 0, s>>>(t->g, keys, t->mesh_np, ops[0], ops[1], ops[2], t->map_src,
-                                     t->map_kind, n, flist, &t->dctr->nfgroups, npm, uo, ldo, un, ldn);
+  const MixedArgs mx{t->g, keys, t->mesh_np, npm};
+#define LT_MX(NN, OPS)                                                                                   \
+  do {                                                                                                   \
+    k_interp3_ref<NN, true><<<gi, 64 * NN, 0, s>>>(OPS, t->map_src, t->map_kind, n, t->grp_list, st.total, \
+                                                   uo, ldo, un, ldn, mx);                               \
+    k_interp3<NN, true><<<gi, 64 * NN, 0, s>>>(OPS, t->map_src, t->map_kind, n, flist,                   \
+                                               &t->dctr->nfgroups, uo, ldo, un, ldn, mx);               \
+  } while (0)
+  if (ops[0]) LT_MX(2, ops[0]);
+  if (ops[1]) LT_MX(3, ops[1]);
+  if (ops[2]) LT_MX(4, ops[2]);
+#undef LT_MX
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("mixed transfer launch: ") + hipGetErrorString(e));
   return LT_OK;
