@@ -344,6 +344,9 @@ def construct_variant(lt, torch, synth, reps=5):
     balance: a sampled torus at levels 4..9 and 4..10 (the paper's bunny runs
     use d_min 4 with d_max 9 and 10).  Median of `reps` runs each."""
     out = {}
+    # a fresh tree and its construction temporaries per run: through torch's
+    # caching allocator, as a PyTorch caller would register it
+    lt.set_allocator(lt.TorchAllocator())
     for n_pts, d_max in ((1 << 20, 9), (1 << 22, 10)):
         pts = torch.from_numpy(synth.surface_points(3, n_pts, 5, "torus")).cuda()
         tb, tc = [], []
@@ -370,6 +373,8 @@ def construct_variant(lt, torch, synth, reps=5):
         log(f"construct {n_pts} points l4-{d_max}: {n_built} -> {n_bal} leaves, "
             f"{tb[reps // 2]:.2f} + {tc[reps // 2]:.2f} ms")
         del pts
+    lt.set_allocator(None)
+    out["allocator"] = "torch caching allocator (lt_set_allocator)"
     out["paper_context"] = ("Stanford bunny on an RTX 2060: balance 0.0569 s at d_max 9 (~0.4M "
                             "octants), 0.2282 s at d_max 10 (~0.9M, two passes); the bunny is not "
                             "available, a sampled torus stands in")

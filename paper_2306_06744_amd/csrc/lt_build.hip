@@ -15,9 +15,8 @@
 //      scatter ranked in LDS with wave ballots);
 //   3. unique: count -> look-back scan -> emit of the distinct indices;
 //   4. completion: per gap, the number of octants of its greedy tiling,
-//      scanned into output offsets; then one wave per gap writes them, the
-//      single lane the short ascending and descending runs, all lanes the run
-//      of background-size octants in between.
+//      scanned into output offsets; then one lane per gap writes them
+//      (nearly every gap holds a few leaves).
 //
 // Where the paper appends the octants between consecutive points through
 // shared-memory and atomic counters, sorts and linearizes, the count -> scan
@@ -274,41 +273,35 @@ __global__ __launch_bounds__(kScanSmall) void k_gap_count(const uint64_t* __rest
   }
 }
 
-// One wave per gap writes its leaves at goff[g]: lane 0 the ascending and
-// descending runs and the closing point cell, every lane a share of the
-// full-size run.
+// One lane per gap writes its leaves at goff[g]: the ascending run, the
+// full-size run, the descending run and the closing point cell.  Nearly
+// every gap holds a few leaves; the long full-size runs (at most the
+// background's 2^(d d_min) octants, in the gaps far from every point) are
+// rare, and a lane walks them alone.
 __global__ __launch_bounds__(256) void k_gap_emit(const uint64_t* __restrict__ S, int64_t m,
                                                   uint64_t end, KeyGeom g, int K,
                                                   const int64_t* __restrict__ goff,
                                                   uint64_t* __restrict__ keys) {
-  const int lane = threadIdx.x & 63;
-  const int64_t gi = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t gi = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (gi > m) return;
   const int dim = g.dim;
   const Gap q = gap_of(S, m, gi, end);
   const Runs r = gap_runs(q.lo, q.hi, dim, K);
   int64_t o = goff[gi];
-  if (lane == 0) {
-    uint64_t x = q.lo;
-    for (int64_t i = 0; i < r.n_up; ++i) {
-      const int k = greedy_exp(x, q.hi, dim, K);
-      keys[o + i] = make_key(g, x, g.dmax - k);
-      x += uint64_t(1) << (dim * k);
-    }
+  uint64_t x = q.lo;
+  for (int64_t i = 0; i < r.n_up; ++i) {
+    const int k = greedy_exp(x, q.hi, dim, K);
+    keys[o++] = make_key(g, x, g.dmax - k);
+    x += uint64_t(1) << (dim * k);
   }
-  o += r.n_up;
-  for (uint64_t i = lane; i < r.mid_n; i += 64)
-    keys[o + int64_t(i)] = make_key(g, r.mid_lo + (i << (dim * K)), g.dmax - K);
-  o += int64_t(r.mid_n);
-  if (lane == 0) {
-    uint64_t x = r.mid_lo + (r.mid_n << (dim * K));
-    for (int64_t i = 0; i < r.n_down; ++i) {
-      const int k = greedy_exp(x, q.hi, dim, K);
-      keys[o + i] = make_key(g, x, g.dmax - k);
-      x += uint64_t(1) << (dim * k);
-    }
-    if (gi < m) keys[o + r.n_down] = make_key(g, S[gi], g.dmax);
+  for (uint64_t i = 0; i < r.mid_n; ++i) keys[o++] = make_key(g, r.mid_lo + (i << (dim * K)), g.dmax - K);
+  x = r.mid_lo + (r.mid_n << (dim * K));
+  for (int64_t i = 0; i < r.n_down; ++i) {
+    const int k = greedy_exp(x, q.hi, dim, K);
+    keys[o++] = make_key(g, x, g.dmax - k);
+    x += uint64_t(1) << (dim * k);
   }
+  if (gi < m) keys[o] = make_key(g, S[gi], g.dmax);
 }
 
 // Device temporaries of one construction, freed on every exit path.
@@ -390,7 +383,7 @@ lt_status build_points(lt_tree t, const double* pts, int64_t n, const double* lo
   const int64_t total = t->hctr->total;
   if (total > (int64_t(1) << 31) - 1) return fail(LT_ERR_ARG, "the tree would hold 2^31 leaves or more");
   LT_TRY_STATUS(grow(t->A, &t->kbuf[t->cur], &t->kcap[t->cur], total));
-  const int64_t threads = (m + 1) * 64;
+  const int64_t threads = m + 1;  // one lane per gap
   k_gap_emit<<<unsigned((threads + 255) / 256), 256, 0, s>>>(S, m, end, g, K, goff,
                                                              t->kbuf[t->cur]);
   if (hipGetLastError() != hipSuccess) return fail(LT_ERR_HIP, "gap emit launch");
