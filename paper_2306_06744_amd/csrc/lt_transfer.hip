@@ -256,35 +256,37 @@ __global__ __launch_bounds__(256) void k_copy3(const int32_t* __restrict__ src,
                                                double* __restrict__ un, int64_t ldn) {
   constexpr int64_t CH = 256 * EPL;
   const int64_t n = cn.get();
-  const int64_t c = xcd_chunk(blockIdx.x, gridDim.x);
-  if (c * CH >= n) return;
   const double* U = uo + int64_t(blockIdx.y) * ldo;
   double* O = un + int64_t(blockIdx.y) * ldn;
-  const int64_t dl = cdelta[c];
-  if (dl != kImpure) {
-    if constexpr (EPL == 1) {
-      const int64_t j = c * CH + threadIdx.x;
-      if (j < n) __builtin_nontemporal_store(__builtin_nontemporal_load(U + j + dl), O + j);
-    } else {
+  // one chunk per block, unless the grid was sized below the count (a
+  // captured cycle's launch sized for the count at capture): then stride
+  for (int64_t c = xcd_chunk(blockIdx.x, gridDim.x); c * CH < n; c += gridDim.x) {
+    const int64_t dl = cdelta[c];
+    if (dl != kImpure) {
+      if constexpr (EPL == 1) {
+        const int64_t j = c * CH + threadIdx.x;
+        if (j < n) __builtin_nontemporal_store(__builtin_nontemporal_load(U + j + dl), O + j);
+      } else {
 #pragma unroll
-      for (int h = 0; h < EPL / 2; ++h) {
-        const int64_t j = c * CH + int64_t(h) * 512 + int64_t(threadIdx.x) * 2;
-        if (j + 1 < n) {
-          const d2u t = __builtin_nontemporal_load(reinterpret_cast<const d2u*>(U + j + dl));
-          __builtin_nontemporal_store(t, reinterpret_cast<d2u*>(O + j));
-        } else if (j < n) {
-          __builtin_nontemporal_store(__builtin_nontemporal_load(U + j + dl), O + j);
+        for (int h = 0; h < EPL / 2; ++h) {
+          const int64_t j = c * CH + int64_t(h) * 512 + int64_t(threadIdx.x) * 2;
+          if (j + 1 < n) {
+            const d2u t = __builtin_nontemporal_load(reinterpret_cast<const d2u*>(U + j + dl));
+            __builtin_nontemporal_store(t, reinterpret_cast<d2u*>(O + j));
+          } else if (j < n) {
+            __builtin_nontemporal_store(__builtin_nontemporal_load(U + j + dl), O + j);
+          }
         }
       }
+      continue;
     }
-    return;
-  }
 #pragma unroll
-  for (int e = 0; e < EPL; ++e) {
-    const int64_t jj = c * CH + int64_t(e) * 256 + threadIdx.x;
-    const int kd = jj < n ? int(kind[jj]) : 0;
-    if (SKIP && __ballot(kd != 0) != 0) continue;  // an interpolation group
-    if (jj < n && kd == 0) __builtin_nontemporal_store(__builtin_nontemporal_load(U + src[jj]), O + jj);
+    for (int e = 0; e < EPL; ++e) {
+      const int64_t jj = c * CH + int64_t(e) * 256 + threadIdx.x;
+      const int kd = jj < n ? int(kind[jj]) : 0;
+      if (SKIP && __ballot(kd != 0) != 0) continue;  // an interpolation group
+      if (jj < n && kd == 0) __builtin_nontemporal_store(__builtin_nontemporal_load(U + src[jj]), O + jj);
+    }
   }
 }
 
@@ -782,7 +784,11 @@ lt_status copy_pass(const TransferTune& tune, const int32_t* src, const int8_t* 
   const int epl = tune.copy_epl;
   const int64_t CH = 256 * int64_t(epl);
   const int64_t nchunks = (n.n + CH - 1) / CH;
-  const dim3 grid{unsigned(nchunks), unsigned(rows), 1u};
+  // a capacity-sized launch with a hint: workgroups for the hinted count and
+  // an eighth more, striding over whatever lies beyond
+  const int64_t nlaunch =
+      n.hint > 0 ? std::max<int64_t>(1, std::min(nchunks, (n.hint + n.hint / 8 + CH - 1) / CH)) : nchunks;
+  const dim3 grid{unsigned(nlaunch), unsigned(rows), 1u};
 #define LT_COPY(E)                                                                              \
   do {                                                                                          \
     k_copy_chunks<E><<<unsigned(nchunks), 256, 0, s>>>(src, kind, n, copy_delta);               \

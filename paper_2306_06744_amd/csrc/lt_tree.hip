@@ -85,8 +85,12 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // ------------------------------------------------------------------ kernels
 // Zero the look-back words and counters before a scan.  converge (captured
 // cycles, after a balance marking pass): no fresh marks means the fixpoint.
+// Captured cycles also fold their count bookkeeping in here (one launch fewer
+// each): *cnt_dst = *cnt_src when both are set, and reset_conv clears the
+// fixpoint flag at the start of a cycle.
 __global__ void k_clear_scan(uint64_t* status, int64_t ntiles, DevCtr* ctr, int clear_err,
-                             int converge, int clear_list) {
+                             int converge, int clear_list, int reset_conv, int64_t* cnt_dst,
+                             const int64_t* cnt_src) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < ntiles) status[i] = 0;
   if (i == 0) {
@@ -95,6 +99,8 @@ __global__ void k_clear_scan(uint64_t* status, int64_t ntiles, DevCtr* ctr, int 
       ctr->nfused = 0;
     }
     if (converge && ctr->nmarked == 0) ctr->conv = 1;
+    if (reset_conv) ctr->conv = 0;
+    if (cnt_dst && cnt_src) *cnt_dst = *cnt_src;
     ctr->ticket = 0;
     ctr->total = 0;
     ctr->nmarked = 0;
@@ -757,12 +763,13 @@ void dir_params(const KeyGeom& g, int64_t n, int* shift, int64_t* nb) {
 }
 
 lt_status prep_scan_fixed(uint64_t* status, int64_t status_cap, DevCtr* ctr, int64_t n_items,
-                          int64_t tile, hipStream_t stream, int flags, ScanState* st) {
+                          int64_t tile, hipStream_t stream, int flags, ScanState* st, int64_t* cnt_dst,
+                          const int64_t* cnt_src) {
   const int64_t ntiles = std::max<int64_t>(1, ceil_div(n_items, tile));
   if (ntiles > status_cap) return fail(LT_ERR_ARG, "scan needs more look-back words than provided");
-  k_clear_scan<<<unsigned(ceil_div(ntiles, 256)), 256, 0, stream>>>(status, ntiles, ctr, flags & 1,
-                                                                      (flags >> 1) & 1,
-                                                                      (flags >> 2) & 1);
+  k_clear_scan<<<unsigned(ceil_div(ntiles, 256)), 256, 0, stream>>>(
+      status, ntiles, ctr, flags & 1, (flags >> 1) & 1, (flags >> 2) & 1, (flags >> 3) & 1, cnt_dst,
+      cnt_src);
   LT_HIP(hipGetLastError());
   st->status = status;
   st->ticket = &ctr->ticket;
@@ -777,16 +784,18 @@ lt_status prep_scan_fixed(uint64_t* status, int64_t status_cap, DevCtr* ctr, int
 
 namespace {
 lt_status prep_scan_on(const Alloc& A, uint64_t** status, int64_t* status_cap, DevCtr* ctr,
-                       int64_t n_items, int64_t tile, hipStream_t stream, int flags, ScanState* st) {
+                       int64_t n_items, int64_t tile, hipStream_t stream, int flags, ScanState* st,
+                       int64_t* cnt_dst = nullptr, const int64_t* cnt_src = nullptr) {
   const int64_t ntiles = std::max<int64_t>(1, ceil_div(n_items, tile));
   LT_TRY(grow(A, status, status_cap, ntiles));
-  return prep_scan_fixed(*status, *status_cap, ctr, n_items, tile, stream, flags, st);
+  return prep_scan_fixed(*status, *status_cap, ctr, n_items, tile, stream, flags, st, cnt_dst, cnt_src);
 }
 }  // namespace
 
 lt_status prep_scan(lt_tree t, int64_t n_items, int64_t tile, hipStream_t stream, int flags,
-                    ScanState* st) {
-  return prep_scan_on(t->A, &t->status, &t->status_cap, t->dctr, n_items, tile, stream, flags, st);
+                    ScanState* st, int64_t* cnt_dst, const int64_t* cnt_src) {
+  return prep_scan_on(t->A, &t->status, &t->status_cap, t->dctr, n_items, tile, stream, flags, st,
+                      cnt_dst, cnt_src);
 }
 
 lt_status prep_scan_conn(lt_tree t, int64_t n_items, hipStream_t stream, int flags, ScanState* st) {
@@ -801,7 +810,7 @@ lt_status read_ctr(lt_tree t, hipStream_t stream) {
 }
 
 lt_status clear_err(lt_tree t, hipStream_t stream) {
-  k_clear_scan<<<1, 64, 0, stream>>>(t->status, 0, t->dctr, 1, 0, 0);
+  k_clear_scan<<<1, 64, 0, stream>>>(t->status, 0, t->dctr, 1, 0, 0, 0, nullptr, nullptr);
   LT_HIP(hipGetLastError());
   return LT_OK;
 }
@@ -908,26 +917,14 @@ lt_status do_map(lt_tree t, hipStream_t stream) {
 // ---------------------------------------------------------- captured cycles
 // Single-thread bookkeeping kernels of a cycle whose counts stay on the device.
 
-// Start of a captured cycle: leaves before the cycle <- current leaves; the
-// balance fixpoint not yet reached.
-__global__ void k_cycle_begin(int64_t* S, DevCtr* ctr) {
+// After the balance passes: marks left mean the fixed passes did not reach
+// the fixpoint; and the transfer's groups of 64 leaves, ceil(S[0] / 64), the
+// count being final here.
+__global__ void k_check_marks(DevCtr* ctr, int64_t* groups, const int64_t* n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    S[1] = S[0];
-    ctr->conv = 0;
+    if (ctr->nmarked != 0) atomicOr(&ctr->err, ERR_BALANCE_PASSES);
+    *groups = (*n + 63) / 64;
   }
-}
-
-
-__global__ void k_pass_count(int64_t* dst, const int64_t* n) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *n;
-}
-
-__global__ void k_groups_of(int64_t* dst, const int64_t* n) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = (*n + 63) / 64;
-}
-
-__global__ void k_check_marks(DevCtr* ctr) {
-  if (threadIdx.x == 0 && blockIdx.x == 0 && ctr->nmarked != 0) atomicOr(&ctr->err, ERR_BALANCE_PASSES);
 }
 
 // Also folds connectivity's error word (its branch ran on a side stream)
@@ -961,10 +958,10 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
   LT_TRY(launch_flag_table(g, r.tmpl, r.nmesh, t->flag_tab, K0, Count{C, &S[0]}, F, s));
   if (r.mlp)  // learned flags, the geometric ones as the fallback below conf_min
     LT_TRY(launch_mlp_flag(t, r.mlp, Count{C, &S[0]}, r.uo, r.ld, r.conf_min, F, nullptr, s));
-  k_cycle_begin<<<1, 64, 0, s>>>(S, t->dctr);
-  // adapt K0 -> K[0]
+  // adapt K0 -> K[0]; its scan's clear also starts the cycle: leaves before
+  // the cycle S[1] <- S[0], the fixpoint flag cleared
   ScanState st;
-  LT_TRY(prep_scan(t, C, kTileMax, s, 1 | 4, &st));
+  LT_TRY(prep_scan(t, C, kTileMax, s, 1 | 4 | 8, &st, &S[1], &S[0]));
   st.items.p = &S[1];
   st.commit = &S[0];
   st.commit_cap = C;
@@ -989,11 +986,11 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
       k_balance_mark<2><<<mgrid, kBlock, 0, s>>>(g, K[ki], Count{C, &S[0]}, D, t->mbuf[mi], 0,
                                                  t->dctr, conv, t->elist, t->elist_cap);
     if (pass == r.passes) break;
-    LT_TRY(prep_scan(t, C, kTileMax, s, 2 | 4, &st));  // also records convergence
-    // the pass reads its input count from S[4]: the last tile commits the
-    // new count to S[0] while workgroups of the capacity-sized grid may still
-    // be taking tickets, and each must see the count the scan started from
-    k_pass_count<<<1, 64, 0, s>>>(&S[4], &S[0]);
+    // the clear also records convergence, and copies the pass's input count
+    // to S[4], where the pass reads it: the last tile commits the new count
+    // to S[0] while workgroups of the capacity-sized grid may still be taking
+    // tickets, and each must see the count the scan started from
+    LT_TRY(prep_scan(t, C, kTileMax, s, 2 | 4, &st, &S[4], &S[0]));
     st.items.p = &S[4];
     st.commit = &S[0];
     st.commit_cap = C;
@@ -1003,7 +1000,7 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
     ki = 1 - ki;
     mi = 1 - mi;
   }
-  k_check_marks<<<1, 64, 0, s>>>(t->dctr);
+  k_check_marks<<<1, 64, 0, s>>>(t->dctr, &S[3], &S[0]);
   LT_HIP(hipGetLastError());
   if (ki != 0) return fail(LT_ERR_ARG, "balance passes of a captured cycle must be even");
   // map
@@ -1037,11 +1034,9 @@ lt_status record_cycle(lt_tree_s* t, const CycleRec& r, hipStream_t s) {
   if (r.precision == 1) {
     LT_TRY(launch_split_transfer(t, Count{C, &S[0]}, r.p, r.nvar, r.uo, r.ld, r.un, r.ld, s));
   } else if (r.p < 0) {  // per-mesh degrees
-    k_groups_of<<<1, 64, 0, s>>>(&S[3], &S[0]);
     LT_TRY(launch_transfer_mixed(t, K[0], Count{C, &S[0]}, &S[3], r.nvar, r.uo, r.ld, r.un, r.ld, s));
   } else {
-    k_groups_of<<<1, 64, 0, s>>>(&S[3], &S[0]);
-    LT_TRY(launch_transfer(t, Count{C, &S[0]}, &S[3], r.p, r.ops, r.nvar, r.uo, r.ld, r.un, r.ld, s));
+    LT_TRY(launch_transfer(t, Count{C, &S[0], t->n_cur}, &S[3], r.p, r.ops, r.nvar, r.uo, r.ld, r.un, r.ld, s));
   }
   // the new keys become the next cycle's input, once connectivity is done
   LT_HIP(hipStreamWaitEvent(s, r.join, 0));

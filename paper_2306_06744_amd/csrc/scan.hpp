@@ -45,6 +45,9 @@ enum : unsigned {
 struct Count {
   int64_t n;
   const int64_t* p;
+  // captured cycles: the count expected at capture (0: none); a launch may
+  // size its grid for it and stride over the rest
+  int64_t hint = 0;
   __device__ int64_t get() const { return p ? *p : n; }
 };
 

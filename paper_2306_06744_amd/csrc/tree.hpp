@@ -137,13 +137,16 @@ namespace lt {
 // items (kTileMax or kTileMin, matching the kernel's workgroup) and the
 // counters; fills st for a scan kernel on `stream`.  flags: 1 = also clear
 // the error word, 2 = record the balance fixpoint (no marks since the last
-// clear; captured cycles), 4 = also clear the lists.
+// clear; captured cycles), 4 = also clear the lists, 8 = clear the fixpoint
+// flag (a captured cycle's start).  cnt_dst / cnt_src (captured cycles): the
+// same launch copies one device count to another word.
 lt_status prep_scan(lt_tree_s* t, int64_t n_items, int64_t tile, hipStream_t stream, int flags,
-                    ScanState* st);
+                    ScanState* st, int64_t* cnt_dst = nullptr, const int64_t* cnt_src = nullptr);
 // The same over caller-provided look-back words (status_cap of them) and
 // counters, allocating nothing (LT_ERR_ARG when the words do not suffice).
 lt_status prep_scan_fixed(uint64_t* status, int64_t status_cap, DevCtr* ctr, int64_t n_items,
-                          int64_t tile, hipStream_t stream, int flags, ScanState* st);
+                          int64_t tile, hipStream_t stream, int flags, ScanState* st,
+                          int64_t* cnt_dst = nullptr, const int64_t* cnt_src = nullptr);
 // The same on connectivity's own look-back words and counters, so that
 // lt_connect may run beside lt_map and lt_transfer on another stream.
 lt_status prep_scan_conn(lt_tree_s* t, int64_t n_items, hipStream_t stream, int flags,
