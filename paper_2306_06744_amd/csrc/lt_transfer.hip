@@ -477,8 +477,8 @@ __global__ __launch_bounds__(64 * N) void k_interp3(const double* __restrict__ o
                                                     MixedArgs mx) {
   constexpr int NN = N * N;
   constexpr int NP = NN * N;
-  __shared__ double T[N][NN][64];
-  __shared__ double M[4][NN];  // A_0, A_1, P_0, P_1
+  __shared__ double T[2][N][NN][64];  // the x/y-passed slabs of each z round
+  __shared__ double M[4][NN];         // A_0, A_1, P_0, P_1
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t n = cn.get();
   const int64_t ng = *ngroups;
@@ -498,69 +498,74 @@ __global__ __launch_bounds__(64 * N) void k_interp3(const double* __restrict__ o
     bool live = j < n;
     if constexpr (MIXED) live = live && int(mx.np_of_mesh[key_mesh(mx.g, mx.keys[j])]) == NP;
     const int kd = live ? int(kind[j]) : 0;
-    // every wave sees the same 64 elements, so the rounds agree across the block
-    const int rounds = __ballot(kd < 0) != 0 ? 2 : 1;
     const int64_t s = live ? int64_t(src[j]) : 0;
     const int c = kd > 0 ? kd - 1 : 0;
-    double acc[NN];
+    const bool copy = !MIXED && live && kd == 0;  // a copy of the group (the copy pass left the group out)
+    // x and y passes: a refined child from its parent's slab w (round 0), a
+    // fused parent from the slabs w of its four children of each z half
+    // (rounds 0 and 1), each child's rows loaded while the one before is
+    // projected
+    if (kd > 0) {
+      double in[NN], sl[NN];
 #pragma unroll
-    for (int r = 0; r < NN; ++r) acc[r] = 0.0;
-    for (int rz = 0; rz < rounds; ++rz) {
-      double sl[NN];
+      for (int r = 0; r < NN; ++r) in[r] = U[int64_t(r) * ldo + s];
+      xy_pass<N>(M[c & 1], M[(c >> 1) & 1], in, sl);
 #pragma unroll
-      for (int r = 0; r < NN; ++r) sl[r] = 0.0;
-      if (kd > 0) {
-        if (rz == 0) {
-          double in[NN];
-#pragma unroll
-          for (int r = 0; r < NN; ++r) in[r] = U[int64_t(r) * ldo + s];
-          xy_pass<N>(M[c & 1], M[(c >> 1) & 1], in, sl);
-        }
-      } else if (kd < 0) {
+      for (int r = 0; r < NN; ++r) T[0][w][r][lane] = sl[r];
+    } else if (kd < 0) {
 #pragma unroll 1
-        for (int cc = 0; cc < 4; ++cc) {
-          const int child = cc + 4 * rz;
-          double in[NN], t[NN];
+      for (int rz = 0; rz < 2; ++rz) {
+        double sl[NN], in[2][NN];
 #pragma unroll
-          for (int r = 0; r < NN; ++r) in[r] = U[int64_t(r) * ldo + s + child];
-          xy_pass<N>(M[2 + (cc & 1)], M[2 + (cc >> 1)], in, t);
+        for (int r = 0; r < NN; ++r) {
+          sl[r] = 0.0;
+          in[0][r] = U[int64_t(r) * ldo + s + 4 * rz];
+        }
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          if (cc < 3) {
+#pragma unroll
+            for (int r = 0; r < NN; ++r) in[(cc + 1) & 1][r] = U[int64_t(r) * ldo + s + 4 * rz + cc + 1];
+          }
+          double t[NN];
+          xy_pass<N>(M[2 + (cc & 1)], M[2 + (cc >> 1)], in[cc & 1], t);
 #pragma unroll
           for (int r = 0; r < NN; ++r) sl[r] += t[r];
         }
+#pragma unroll
+        for (int r = 0; r < NN; ++r) T[rz][w][r][lane] = sl[r];
       }
-#pragma unroll
-      for (int r = 0; r < NN; ++r) T[w][r][lane] = sl[r];
-      __syncthreads();
-      if (kd > 0 && rz == 0) {
-        const double* Mz = M[(c >> 2) & 1] + w * N;
-#pragma unroll
-        for (int r = 0; r < NN; ++r) {
-          double a = 0.0;
-#pragma unroll
-          for (int k = 0; k < N; ++k) a += Mz[k] * T[k][r][lane];
-          acc[r] = a;
-        }
-      } else if (kd < 0) {
-        const double* Mz = M[2 + rz] + w * N;
-#pragma unroll
-        for (int r = 0; r < NN; ++r) {
-          double a = 0.0;
-#pragma unroll
-          for (int k = 0; k < N; ++k) a += Mz[k] * T[k][r][lane];
-          acc[r] += a;
-        }
-      }
-      __syncthreads();
     }
+    __syncthreads();
+    // z pass over the slabs of the block's waves, and the stores
     double* O = un + int64_t(v) * vstride * ldn + int64_t(w) * NN * ldn + j;
-    if (kd != 0) {
+    if (kd > 0) {
+      const double* Mz = M[(c >> 2) & 1] + w * N;
 #pragma unroll
-      for (int r = 0; r < NN; ++r) __builtin_nontemporal_store(acc[r], O + int64_t(r) * ldn);
-    } else if (!MIXED && live) {  // a copy of the group (the copy pass left the group out)
+      for (int r = 0; r < NN; ++r) {
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) a += Mz[k] * T[0][k][r][lane];
+        __builtin_nontemporal_store(a, O + int64_t(r) * ldn);
+      }
+    } else if (kd < 0) {
+      const double* P0 = M[2] + w * N;
+      const double* P1 = M[3] + w * N;
+#pragma unroll
+      for (int r = 0; r < NN; ++r) {
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) a += P0[k] * T[0][k][r][lane];
+#pragma unroll
+        for (int k = 0; k < N; ++k) a += P1[k] * T[1][k][r][lane];
+        __builtin_nontemporal_store(a, O + int64_t(r) * ldn);
+      }
+    } else if (copy) {
 #pragma unroll
       for (int r = 0; r < NN; ++r)
         __builtin_nontemporal_store(__builtin_nontemporal_load(U + int64_t(r) * ldo + s), O + int64_t(r) * ldn);
     }
+    __syncthreads();
   }
 }
 
