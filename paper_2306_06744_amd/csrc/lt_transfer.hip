@@ -411,29 +411,51 @@ __global__ __launch_bounds__(64 * N) void k_interp3_ref(const double* __restrict
   const double* U = uo + int64_t(v) * vstride * ldo + int64_t(w) * NN * ldo;
   double* O0 = un + int64_t(v) * vstride * ldn + int64_t(w) * NN * ldn;
   __syncthreads();
-  for (int64_t gi = blockIdx.x; gi < ng; gi += gridDim.x) {
-    int64_t grp = groups[gi];
-    if constexpr (MIXED) {
-      if ((grp & 3) != N - 1) continue;  // another degree's entry (uniform over the block)
-      grp >>= 2;
+  // Software pipeline over the block's groups: the map and the input rows of
+  // the next group are loaded before this group's stores are issued.  Loads
+  // and stores share one counter, so a load issued after a group's stores
+  // would wait for them; loaded a group ahead, the rows are in registers by
+  // the time the stores before them matter.
+  auto next = [&](int64_t from) -> int64_t {  // the block's next entry of this degree, or ng
+    for (int64_t q = from; q < ng; q += gridDim.x) {
+      if constexpr (!MIXED) return q;
+      if ((groups[q] & 3) == N - 1) return q;
     }
-    const int64_t j = grp * 64 + lane;
-    bool live = j < n;
-    if constexpr (MIXED) live = live && int(mx.np_of_mesh[key_mesh(mx.g, mx.keys[j])]) == NP;
-    const int kd = live ? int(kind[j]) : 0;
-    // a copy loads its own source, a refined child its parent: the same rows
-    double in[NN];
-    const bool work = live && (!MIXED || kd > 0);
-    if (work) {
-      const int64_t s = int64_t(src[j]);
+    return ng;
+  };
+  struct Item {
+    int64_t j;
+    int kd;
+    bool live;
+  };
+  auto map_of = [&](int64_t q) -> Item {
+    Item it{0, 0, false};
+    if (q >= ng) return it;
+    int64_t grp = groups[q];
+    if constexpr (MIXED) grp >>= 2;
+    it.j = grp * 64 + lane;
+    it.live = it.j < n;
+    if constexpr (MIXED)
+      it.live = it.live && int(mx.np_of_mesh[key_mesh(mx.g, mx.keys[it.j])]) == NP;
+    it.kd = it.live ? int(kind[it.j]) : 0;
+    return it;
+  };
+  // a copy loads its own source, a refined child its parent: the same rows
+  auto load_rows = [&](const Item& it, double* in) {
+    if (it.live && (!MIXED || it.kd > 0)) {
+      const int64_t s = int64_t(src[it.j]);
 #pragma unroll
       for (int r = 0; r < NN; ++r) in[r] = __builtin_nontemporal_load(U + int64_t(r) * ldo + s);
     }
-    double* O = O0 + j;
-    if (!MIXED && live && kd == 0) {  // a copy of the group (the copy pass left the group out)
-#pragma unroll
-      for (int r = 0; r < NN; ++r) __builtin_nontemporal_store(in[r], O + int64_t(r) * ldn);
-    }
+  };
+  int64_t gi = next(blockIdx.x);
+  Item cur = map_of(gi);
+  double in[NN];
+  load_rows(cur, in);
+  while (gi < ng) {
+    const int64_t gn = next(gi + gridDim.x);
+    const Item nxt = map_of(gn);
+    const int kd = cur.kd;
     const int c = kd > 0 ? kd - 1 : 0;
     if (kd > 0) {
       double sl[NN];
@@ -441,7 +463,17 @@ __global__ __launch_bounds__(64 * N) void k_interp3_ref(const double* __restrict
 #pragma unroll
       for (int r = 0; r < NN; ++r) T[w][r][lane] = sl[r];
     }
+    double cp[NN];  // a copy's rows, kept while the next group's rows arrive
+    const bool copy = !MIXED && cur.live && kd == 0;
+#pragma unroll
+    for (int r = 0; r < NN; ++r) cp[r] = in[r];
+    load_rows(nxt, in);
     __syncthreads();
+    double* O = O0 + cur.j;
+    if (copy) {  // a copy of the group (the copy pass left the group out)
+#pragma unroll
+      for (int r = 0; r < NN; ++r) __builtin_nontemporal_store(cp[r], O + int64_t(r) * ldn);
+    }
     if (kd > 0) {
       const double* Mz = M[(c >> 2) & 1] + w * N;
 #pragma unroll
@@ -453,6 +485,8 @@ __global__ __launch_bounds__(64 * N) void k_interp3_ref(const double* __restrict
       }
     }
     __syncthreads();
+    gi = gn;
+    cur = nxt;
   }
 }
 
