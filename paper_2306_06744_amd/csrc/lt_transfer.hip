@@ -768,6 +768,10 @@ struct XferScratch {
   uint64_t* status;
   int64_t status_cap;
   DevCtr* ctr;
+  // a second stream for the interpolation passes, forked from and joined to
+  // the caller's (null: everything on the caller's stream)
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 lt_status copy_pass(const TransferTune& tune, const int32_t* src, const int8_t* kind, Count n,
@@ -780,31 +784,48 @@ hipError_t launch(const TransferTune& tune, const double* ops, const int32_t* sr
                   double* un, int64_t ldn, const XferScratch& X, hipStream_t s, lt_status* st_out) {
   *st_out = LT_OK;
   if constexpr (DIM == 3) {
-    const int64_t ngroups = (n.n + 63) / 64;
-    // the copies of interpolation groups are left to the interpolation passes
-    *st_out = copy_pass(tune, src, kind, n, nvar * N * N * N, uo, ldo, un, ldn, X.copy_delta, true, s);
-    if (*st_out != LT_OK) return hipSuccess;
     hipError_t e = hipSuccess;
+    const int64_t ngroups = (n.n + 63) / 64;
+    // The copy pass leaves out every group the interpolation passes write
+    // (their copies included), so the two write disjoint elements and run at
+    // once when a second stream is given: the interpolation passes, bound by
+    // their dependent loads, then overlap the copy's streaming traffic.  The
+    // copy is enqueued first, so that its start waits on no host call of
+    // the fork.
+    hipStream_t si = s;
+    if (X.side) {
+      e = hipEventRecord(X.fork, s);
+      if (e != hipSuccess) return e;
+      si = X.side;
+    }
+    *st_out = copy_pass(tune, src, kind, n, nvar * N * N * N, uo, ldo, un, ldn, X.copy_delta, true, s);
+    if (X.side) e = hipStreamWaitEvent(X.side, X.fork, 0);
     // grp_list holds the ordered list in [0, ngroups) and the list of
     // groups with a fused element in [ngroups, 2 ngroups)
     ScanState st;
-    *st_out = prep_scan_fixed(X.status, X.status_cap, X.ctr, ngroups, kTileMin, s, 0, &st);
-    if (*st_out != LT_OK) return hipSuccess;
-    st.items.p = ngroups_dev;
-    int32_t* flist = X.grp_list + ngroups;
-    k_group_list<<<grid_tiles(st), kScanSmall, 0, s>>>(kind, n, X.grp_list, st, flist,
-                                                   &X.ctr->nfgroups);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const dim3 gi{unsigned(std::max<int64_t>(1, std::min<int64_t>(ngroups, tune.interp_grid))),
-                  unsigned(nvar), 1u};
-    k_interp3_ref<N, false><<<gi, 64 * N, 0, s>>>(ops, src, kind, n, X.grp_list, st.total, uo, ldo, un,
-                                                  ldn, MixedArgs{});
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_interp3<N, false><<<gi, 64 * N, 0, s>>>(ops, src, kind, n, flist, &X.ctr->nfgroups, uo, ldo, un,
-                                              ldn, MixedArgs{});
-    return hipGetLastError();
+    if (*st_out == LT_OK && e == hipSuccess)
+      *st_out = prep_scan_fixed(X.status, X.status_cap, X.ctr, ngroups, kTileMin, si, 0, &st);
+    if (*st_out == LT_OK && e == hipSuccess) {
+      st.items.p = ngroups_dev;
+      int32_t* flist = X.grp_list + ngroups;
+      k_group_list<<<grid_tiles(st), kScanSmall, 0, si>>>(kind, n, X.grp_list, st, flist,
+                                                      &X.ctr->nfgroups);
+      const dim3 gi{unsigned(std::max<int64_t>(1, std::min<int64_t>(ngroups, tune.interp_grid))),
+                    unsigned(nvar), 1u};
+      k_interp3_ref<N, false><<<gi, 64 * N, 0, si>>>(ops, src, kind, n, X.grp_list, st.total, uo, ldo,
+                                                     un, ldn, MixedArgs{});
+      k_interp3<N, false><<<gi, 64 * N, 0, si>>>(ops, src, kind, n, flist, &X.ctr->nfgroups, uo, ldo, un,
+                                                 ldn, MixedArgs{});
+      e = hipGetLastError();
+    }
+    // the join is recorded on every path that forked, so that a capture
+    // in progress stays whole
+    if (X.side) {
+      const hipError_t ej = hipEventRecord(X.join, X.side);
+      const hipError_t ew = ej == hipSuccess ? hipStreamWaitEvent(s, X.join, 0) : ej;
+      if (e == hipSuccess) e = ew;
+    }
+    return e;
   } else {
     dim3 grid(unsigned((n.n + 255) / 256), unsigned(nvar));
     k_transfer<DIM, N><<<grid, 256, 0, s>>>(ops, src, kind, n, uo, ldo, un, ldn);
@@ -925,6 +946,29 @@ lt_status transfer_with(int dim, const TransferTune& tune, const int32_t* src, c
 }
 }  // namespace
 
+lt_status transfer_side(lt_tree_s* t, hipStream_t* side, hipEvent_t* fork, hipEvent_t* join) {
+  if (!t->xs) {
+    hipStream_t q = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&a, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      if (q) (void)hipStreamDestroy(q);
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+      return fail(LT_ERR_HIP, std::string("transfer stream: ") + hipGetErrorString(e));
+    }
+    t->xs = q;
+    t->xev[0] = a;
+    t->xev[1] = b;
+  }
+  *side = t->xs;
+  *fork = t->xev[0];
+  *join = t->xev[1];
+  return LT_OK;
+}
+
 lt_status launch_transfer_mixed(lt_tree_s* t, const uint64_t* keys, Count n, const int64_t* ngroups_dev,
                                 int nvar, const double* uo, int64_t ldo, double* un, int64_t ldn,
                                 hipStream_t s) {
@@ -945,6 +989,14 @@ lt_status launch_transfer_mixed(lt_tree_s* t, const uint64_t* keys, Count n, con
   LT_TRY_STATUS(grow(t->A, &t->copy_delta, &t->copy_delta_cap, nchunks));
   LT_TRY_STATUS(grow(t->A, &t->chunk_np, &t->chunk_np_cap, nchunks));
   LT_TRY_STATUS(grow(t->A, &t->grp_list, &t->grp_cap, 6 * ngroups));
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  LT_TRY_STATUS(transfer_side(t, &side, &fork, &join));
+  hipError_t ef = hipEventRecord(fork, s);
+  if (ef != hipSuccess) return fail(LT_ERR_HIP, std::string("transfer fork: ") + hipGetErrorString(ef));
+  // the copy pass first on the caller's stream, so that its start waits on no
+  // host call of the fork; then, as in the single-degree form, the
+  // interpolation passes (which here write no copies) on the second stream
   const dim3 grid{unsigned(nchunks), unsigned(nvar), 1u};
 #define LT_CM(E)                                                                                    \
   do {                                                                                              \
@@ -961,30 +1013,39 @@ lt_status launch_transfer_mixed(lt_tree_s* t, const uint64_t* keys, Count n, con
   else
     LT_CM(2);
 #undef LT_CM
+  ef = hipStreamWaitEvent(side, fork, 0);
   ScanState st;
-  LT_TRY_STATUS(prep_scan(t, ngroups, kTileMin, s, 0, &st));
-  st.items.p = ngroups_dev;
-  int32_t* flist = t->grp_list + 3 * ngroups;
-  k_group_list_mixed<<<grid_tiles(st), kScanSmall, 0, s>>>(t->g, keys, t->mesh_np, t->map_kind, n,
-                                                           t->grp_list, st, flist, &t->dctr->nfgroups);
-  // one launch of each interpolation kernel per degree present; the blocks of a
-  // launch skip the other degrees' entries
-  const dim3 gi{unsigned(std::max<int64_t>(1, std::min<int64_t>(3 * ngroups, t->tune.interp_grid))),
-                unsigned(nvar), 1u};
-  const MixedArgs mx{t->g, keys, t->mesh_np, npm};
-#define LT_MX(NN, OPS)                                                                                   \
-  do {                                                                                                   \
-    k_interp3_ref<NN, true><<<gi, 64 * NN, 0, s>>>(OPS, t->map_src, t->map_kind, n, t->grp_list, st.total, \
-                                                   uo, ldo, un, ldn, mx);                               \
-    k_interp3<NN, true><<<gi, 64 * NN, 0, s>>>(OPS, t->map_src, t->map_kind, n, flist,                   \
-                                               &t->dctr->nfgroups, uo, ldo, un, ldn, mx);               \
+  lt_status r = ef == hipSuccess ? prep_scan(t, ngroups, kTileMin, side, 0, &st) : LT_OK;
+  if (r == LT_OK && ef == hipSuccess) {
+    st.items.p = ngroups_dev;
+    int32_t* flist = t->grp_list + 3 * ngroups;
+    k_group_list_mixed<<<grid_tiles(st), kScanSmall, 0, side>>>(t->g, keys, t->mesh_np, t->map_kind, n,
+                                                                t->grp_list, st, flist, &t->dctr->nfgroups);
+    // one launch of each interpolation kernel per degree present; the blocks
+    // of a launch skip the other degrees' entries
+    const dim3 gi{unsigned(std::max<int64_t>(1, std::min<int64_t>(3 * ngroups, t->tune.interp_grid))),
+                  unsigned(nvar), 1u};
+    const MixedArgs mx{t->g, keys, t->mesh_np, npm};
+#define LT_MX(NN, OPS)                                                                                 \
+  do {                                                                                                 \
+    k_interp3_ref<NN, true><<<gi, 64 * NN, 0, side>>>(OPS, t->map_src, t->map_kind, n, t->grp_list,    \
+                                                      st.total, uo, ldo, un, ldn, mx);                 \
+    k_interp3<NN, true><<<gi, 64 * NN, 0, side>>>(OPS, t->map_src, t->map_kind, n, flist,              \
+                                                  &t->dctr->nfgroups, uo, ldo, un, ldn, mx);           \
   } while (0)
-  if (ops[0]) LT_MX(2, ops[0]);
-  if (ops[1]) LT_MX(3, ops[1]);
-  if (ops[2]) LT_MX(4, ops[2]);
+    if (ops[0]) LT_MX(2, ops[0]);
+    if (ops[1]) LT_MX(3, ops[1]);
+    if (ops[2]) LT_MX(4, ops[2]);
 #undef LT_MX
+  }
   const hipError_t e = hipGetLastError();
+  // the join on every path that forked, so that a capture in progress stays whole
+  const hipError_t ej = hipEventRecord(join, side);
+  const hipError_t ew = ej == hipSuccess ? hipStreamWaitEvent(s, join, 0) : ej;
+  if (r != LT_OK) return r;
+  if (ef != hipSuccess) return fail(LT_ERR_HIP, std::string("transfer fork: ") + hipGetErrorString(ef));
   if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("mixed transfer launch: ") + hipGetErrorString(e));
+  if (ew != hipSuccess) return fail(LT_ERR_HIP, std::string("transfer join: ") + hipGetErrorString(ew));
   return LT_OK;
 }
 
@@ -1001,6 +1062,7 @@ lt_status launch_transfer(lt_tree_s* t, Count n, const int64_t* ngroups_dev, int
     LT_TRY_STATUS(grow(t->A, &t->status, &t->status_cap,
                        std::max<int64_t>(1, (ngroups + kTileMin - 1) / kTileMin)));
     X = XferScratch{t->copy_delta, t->grp_list, t->status, t->status_cap, t->dctr};
+    LT_TRY_STATUS(transfer_side(t, &X.side, &X.fork, &X.join));
   }
   return transfer_with(t->g.dim, t->tune, t->map_src, t->map_kind, n, ngroups_dev, p, ops, nvar,
                        u_old, ld_old, u_new, ld_new, X, s);

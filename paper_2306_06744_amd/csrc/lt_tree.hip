@@ -239,8 +239,21 @@ __global__ __launch_bounds__(kScanBig) void k_adapt(KeyGeom g, const uint64_t* _
       const uint64_t step = uint64_t(1) << (g.dim * (g.dmax - d) + g.mb);
       const uint64_t k0 = kk - uint64_t(c) * step;
       bool all = h >= 0 && h + nc <= n;
-      for (int j = 0; all && j < nc; ++j)
-        if (in[h + j] != k0 + uint64_t(j) * step || flags[h + j] != -1) all = false;
+      if (all) {
+        // every sibling's key and flag loaded before any is compared: one
+        // round trip instead of a chain of 2^dim dependent ones
+        uint64_t sk[8];
+        int sf[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (j < nc) {
+            sk[j] = in[h + j];
+            sf[j] = flags[h + j];
+          }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (j < nc) all = all && sk[j] == k0 + uint64_t(j) * step && sf[j] == -1;
+      }
       if (all) a = c == 0 ? 2 : 3;
     }
     act[k] = a;
@@ -496,13 +509,16 @@ __global__ __launch_bounds__(kScanBig) void k_balance_refine(KeyGeom g, const ui
   const int64_t base = tile * kTileMax + int64_t(threadIdx.x) * kItems;
   const int nc = g.nchild();
   uint32_t w[kItems];
+  uint64_t key[kItems];  // read with the marks, ahead of the look-back
   int64_t local = 0;
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
     const int64_t i = base + k;
     w[k] = 0;
+    key[k] = 0;
     if (i >= n) continue;
     w[k] = mark[i] | 8u;  // bit 3: valid item
+    key[k] = in[i];
     local += (w[k] & 1u) ? nc : 1;
   }
   // leaves the next pass examines (bit 2): the children of split leaves and
@@ -519,8 +535,7 @@ __global__ __launch_bounds__(kScanBig) void k_balance_refine(KeyGeom g, const ui
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
     if (!(w[k] & 8u)) continue;
-    const int64_t i = base + k;
-    const uint64_t kk = in[i];
+    const uint64_t kk = key[k];
     const int cnt = (w[k] & 1u) ? nc : 1;
     const int nex = (w[k] & 1u) ? nc : ((w[k] & 2u) ? 1 : 0);
     if (o + cnt > cap) {
@@ -1549,6 +1564,9 @@ void lt_destroy(lt_tree t) {
   fr(t->fr_fb);
   if (t->hctr) (void)hipHostFree(t->hctr);
   if (t->hcctr) (void)hipHostFree(t->hcctr);
+  if (t->xs) (void)hipStreamDestroy(t->xs);
+  for (hipEvent_t e : t->xev)
+    if (e) (void)hipEventDestroy(e);
   delete t;
 }
 

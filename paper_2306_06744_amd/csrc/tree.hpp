@@ -181,6 +181,9 @@ lt_status launch_transfer(lt_tree_s* t, int p, const double* ops, int nvar, cons
 // a count that may live on the device; asynchronous.  keys: the new leaves'
 // keys (each element's mesh, hence its degree, comes from its key), which a
 // captured cycle holds in another buffer than the tree's current one.
+// The tree's second stream for the interpolation passes of a 3D transfer and
+// its fork/join events, made on first use (default priority, non-blocking).
+lt_status transfer_side(lt_tree_s* t, hipStream_t* side, hipEvent_t* fork, hipEvent_t* join);
 lt_status launch_transfer_mixed(lt_tree_s* t, const uint64_t* keys, Count n, const int64_t* ngroups_dev,
                                 int nvar, const double* uo, int64_t ldo, double* un, int64_t ldn,
                                 hipStream_t s);
@@ -285,4 +288,6 @@ struct lt_tree_s {
   int64_t grp_cap = 0;
   int64_t* copy_delta = nullptr;  // per copy chunk: source offset of a pure run, or a flag
   int64_t copy_delta_cap = 0;
+  hipStream_t xs = nullptr;       // transfer: second stream of the interpolation passes
+  hipEvent_t xev[2] = {};         //   its fork and join events
 };
