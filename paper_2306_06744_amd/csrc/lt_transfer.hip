@@ -844,8 +844,10 @@ lt_status copy_pass(const TransferTune& tune, const int32_t* src, const int8_t* 
   const int epl = tune.copy_epl;
   const int64_t CH = 256 * int64_t(epl);
   const int64_t nchunks = (n.n + CH - 1) / CH;
-  // a capacity-sized launch with a hint: workgroups for the hinted count and
-  // an eighth more, striding over whatever lies beyond
+  // A capacity-sized launch with a hint: workgroups for the hinted count and
+  // an eighth more, striding over whatever lies beyond.  The slack keeps
+  // striding rare: a workgroup's second chunk waits behind its first, and a
+  // grid of 15/16 of the count made the captured cycle ~12% slower.
   const int64_t nlaunch =
       n.hint > 0 ? std::max<int64_t>(1, std::min(nchunks, (n.hint + n.hint / 8 + CH - 1) / CH)) : nchunks;
   const dim3 grid{unsigned(nlaunch), unsigned(rows), 1u};
