@@ -731,6 +731,13 @@ __global__ __launch_bounds__(kScanSmall) void k_group_list_mixed(KeyGeom g, cons
     if (gidx >= ngroups) continue;
     unsigned any = 0, fus = 0;  // bit N-1 per degree
     const int64_t j0 = gidx * 64;
+    if (j0 + 64 <= n) {  // a group of copies only (nearly all): eight words, no element loop
+      const uint64_t* w8 = reinterpret_cast<const uint64_t*>(kind + j0);
+      uint64_t acc = 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc |= w8[q];
+      if (acc == 0) continue;
+    }
     for (int64_t j = j0; j < j0 + 64 && j < n; ++j) {
       const int kd = kind[j];
       if (kd == 0) continue;
