@@ -172,12 +172,14 @@ lt_status lt_flag_batch(lt_tree t, const lt_flag_params* per_mesh, int nmesh, in
 lt_status lt_set_mesh_degree(lt_tree t, const int* p, void* stream);
 
 /* FP64 solution transfer (Section 4.2) of an ensemble whose meshes have
- * their own degree (lt_set_mesh_degree), every kernel one launch for all
- * meshes and degrees.  Layout u[(v * NPM + i) * ld + e] with NPM the largest
+ * their own degree (lt_set_mesh_degree): the copy pass and the group list one
+ * launch each for all meshes, each interpolation kernel one launch per degree
+ * present.  Layout u[(v * NPM + i) * ld + e] with NPM the largest
  * (p+1)^3 over the meshes; an element of a mesh of degree p uses the rows
  * i < (p+1)^3 of each variable block, and its other rows are neither read nor
- * written.  Otherwise as lt_transfer at precision 0 (LT_ERR_STATE without
- * degrees or a prior lt_adapt).  Asynchronous unless the mapping was stale. */
+ * written.  Otherwise as lt_transfer at precision 0, its second stream
+ * included (LT_ERR_STATE without degrees or a prior lt_adapt).  Asynchronous
+ * unless the mapping was stale. */
 lt_status lt_transfer_mixed(lt_tree t, int nvar, const double* u_old, int64_t ld_old, double* u_new,
                             int64_t ld_new, void* stream);
 
@@ -257,7 +259,12 @@ lt_status lt_map(lt_tree t, void* stream);
  *                are exact.  Needs 64 points per element (dim 3 with p = 3,
  *                or dim 2 with p = 7).  Relative L2 error ~1e-7 against FP64.
  * Other values return LT_ERR_ARG, as does nvar * n_p outside [1, 65535].
- * Asynchronous (unless the mapping was stale). */
+ * Asynchronous (unless the mapping was stale).  In 3D at precision 0 the
+ * interpolation passes run on a second stream owned by the tree (made on the
+ * first such call), forked from `stream` after the copy pass is enqueued and
+ * joined back to it: later work on `stream` sees the whole transfer.  A caller
+ * that captures this call into a graph makes one such call eagerly first (or
+ * uses lt_transfer_noalloc, which stays on `stream`). */
 lt_status lt_transfer(lt_tree t, int p, int nvar, const double* u_old, int64_t ld_old,
                       double* u_new, int64_t ld_new, int precision, void* stream);
 
