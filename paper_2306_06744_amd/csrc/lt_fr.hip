@@ -553,6 +553,28 @@ __global__ __launch_bounds__(64 * (DIM == 3 ? N * N : N) / H) void k_fr_volume(
     }
     const double HxL = *row(fb, fb_index<DIM>(0, v, l, NFP, 1, 0), ldf);
     const double HxR = *row(fb, fb_index<DIM>(1, v, l, NFP, 1, 0), ldf);
+    // the y and z face values too: consumed (below) before the barrier, so
+    // that their loads overlap this variable's flux work instead of being
+    // sunk to their use after the barrier, where nothing hides them
+    double HyL[N], HyR[N], HzL[N], HzR[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      HyL[i] = *row(fb, fb_index<DIM>(2, v, i + N * z, NFP, 1, 0), ldf);
+      HyR[i] = *row(fb, fb_index<DIM>(3, v, i + N * z, NFP, 1, 0), ldf);
+      HzL[i] = HzR[i] = 0.0;
+      if constexpr (DIM == 3) {
+        HzL[i] = *row(fb, fb_index<DIM>(4, v, i + N * y, NFP, 1, 0), ldf);
+        HzR[i] = *row(fb, fb_index<DIM>(5, v, i + N * y, NFP, 1, 0), ldf);
+      }
+    }
+    // the stage's u0 term likewise (u0 is read only when c0 is nonzero): one
+    // round trip for the line instead of one per point in the store loop
+    double U0[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) U0[i] = 0.0;
+    if (c0 != 0.0)
+#pragma unroll
+      for (int i = 0; i < N; ++i) U0[i] = *row(u0, int64_t(v) * NP + l * N + i, ld);
     const bool is_e = v == NV - 1;
     double cur[N];
 #pragma unroll
@@ -592,6 +614,9 @@ __global__ __launch_bounds__(64 * (DIM == 3 ? N * N : N) / H) void k_fr_volume(
         R[i] = d + dgL[i] * jL + dgR[i] * jR;
       }
     }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      asm volatile("" ::"v"(HyL[i]), "v"(HyR[i]), "v"(HzL[i]), "v"(HzR[i]), "v"(U0[i]));
     __syncthreads();
     // y: point (i, y, z) on the line of points (i, k, z)
 #pragma unroll
@@ -604,8 +629,7 @@ __global__ __launch_bounds__(64 * (DIM == 3 ? N * N : N) / H) void k_fr_volume(
         FL += lL[k] * x;
         FR += lR[k] * x;
       }
-      R[i] += d + gLy * (*row(fb, fb_index<DIM>(2, v, i + N * z, NFP, 1, 0), ldf) - FL) +
-              gRy * (*row(fb, fb_index<DIM>(3, v, i + N * z, NFP, 1, 0), ldf) - FR);
+      R[i] += d + gLy * (HyL[i] - FL) + gRy * (HyR[i] - FR);
     }
     if constexpr (DIM == 3) {  // z: the line of points (i, y, k)
 #pragma unroll
@@ -618,8 +642,7 @@ __global__ __launch_bounds__(64 * (DIM == 3 ? N * N : N) / H) void k_fr_volume(
           FL += lL[k] * x;
           FR += lR[k] * x;
         }
-        R[i] += d + gLz * (*row(fb, fb_index<DIM>(4, v, i + N * y, NFP, 1, 0), ldf) - FL) +
-                gRz * (*row(fb, fb_index<DIM>(5, v, i + N * y, NFP, 1, 0), ldf) - FR);
+        R[i] += d + gLz * (HzL[i] - FL) + gRz * (HzR[i] - FR);
       }
     }
     if (live) {
@@ -627,7 +650,7 @@ __global__ __launch_bounds__(64 * (DIM == 3 ? N * N : N) / H) void k_fr_volume(
       for (int i = 0; i < N; ++i) {
         const int64_t o = int64_t(v) * NP + l * N + i;
         double r = c1 * cur[i] + c2 * (scale * R[i]);
-        if (c0 != 0.0) r += c0 * *row(u0, o, ld);
+        if (c0 != 0.0) r += c0 * U0[i];
         *row(out, o, ldo) = r;
       }
     }
