@@ -374,9 +374,12 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Row `row` (per lane) of a 4 x 4 register block, as a masked sum: exact for
+// finite values, and branch-free (nested selects on a per-lane index were
+// compiled to exec-masked branches).
 __device__ inline double pick4(const double* a, int row, int x) {
-  const double r0 = a[x], r1 = a[4 + x], r2 = a[8 + x], r3 = a[12 + x];
-  return row == 0 ? r0 : (row == 1 ? r1 : (row == 2 ? r2 : r3));
+  return double(row == 0) * a[x] + double(row == 1) * a[4 + x] + double(row == 2) * a[8 + x] +
+         double(row == 3) * a[12 + x];
 }
 
 __global__ __launch_bounds__(64 * kFlagWaves) void k_mlp_flag_fused(
@@ -493,7 +496,8 @@ __global__ __launch_bounds__(64 * kFlagWaves) void k_mlp_flag_fused(
         }
 #pragma unroll
         for (int mz = 0; mz < 4; ++mz) {
-          const double tz = z == 0 ? T[mz * 4] : (z == 1 ? T[mz * 4 + 1] : (z == 2 ? T[mz * 4 + 2] : T[mz * 4 + 3]));
+          const double tz = double(z == 0) * T[mz * 4] + double(z == 1) * T[mz * 4 + 1] +
+                            double(z == 2) * T[mz * 4 + 2] + double(z == 3) * T[mz * 4 + 3];
 #pragma unroll
           for (int x = 0; x < 4; ++x) c[mz * 4 + x] += tz * val[x];
         }
