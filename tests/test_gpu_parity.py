@@ -179,6 +179,35 @@ def test_connect_on_side_stream_beside_transfer(dim, dmax):
         assert_transfer(ug.cpu().numpy(), o.transfer(p, u_old), kind_o, TOL, f"cycle {c}")
 
 
+@pytest.mark.parametrize("p_refine,p_coarsen", [(0.9, 0.0), (0.0, 0.95), (0.3, 0.4)])
+def test_transfer_joins_caller_stream(p_refine, p_coarsen):
+    """The 3D transfer forks its interpolation passes onto a second stream of
+    the tree and joins it back: work enqueued after it on the caller's stream
+    (a copy of the result on a non-default stream, with only that stream
+    synchronised) sees every interpolated and projected element.  Mostly
+    refined or mostly fused mappings make the interpolation passes outlast
+    the copy pass, so a missing join would leave elements unwritten."""
+    import torch
+    say("joined stream", p_refine, p_coarsen)
+    g, o = both(3, 2, 7, depth=4)
+    adapt_both(g, o, synth.random_flags(511, o.size(), p_refine, p_coarsen))
+    g.balance()
+    o.balance()
+    assert_same_tree(g, o)
+    g.map()
+    u_old = synth.random_solution(512, 5, 64, o.old_size())
+    ud = torch.from_numpy(u_old).cuda()
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ug = g.transfer(3, ud)
+        host = ug.clone().to("cpu")
+    s.synchronize()
+    kind = o.map()[1]
+    say("refined", int((kind > 0).sum()), "fused", int((kind < 0).sum()), "of", kind.size)
+    assert_transfer(host.numpy(), o.transfer(3, u_old), kind, TOL, "joined")
+
+
 def test_transfer_with_padding_and_high_degree_2d():
     import torch
     say("padding")
