@@ -234,6 +234,31 @@ __device__ inline Runs gap_runs(uint64_t lo, uint64_t hi, int dim, int K) {
   return r;
 }
 
+// Leaves of the greedy tiling of [lo, hi), counted in closed form rather than
+// walked.  Let P be the point of [lo, hi] aligned to the largest octant size
+// 2^(dim j), j <= K.  The tiling then covers [lo, P) with P - lo's digits in
+// base 2^dim (one octant of size 2^(dim k) per unit of digit k), then
+// (hi - P) >> (dim K) octants of the full size, then the rest digit by digit
+// again.  No octant of the tiling crosses P: an aligned octant across it would
+// put a point aligned to a larger size inside [lo, hi].
+__device__ inline int64_t gap_leaves(uint64_t lo, uint64_t hi, int dim, int K) {
+  if (lo >= hi) return 0;
+  uint64_t P = lo;
+  for (int j = K; j >= 0; --j) {
+    const uint64_t b = uint64_t(1) << (dim * j);
+    const uint64_t p = (lo + b - 1) & ~(b - 1);
+    if (p <= hi) {
+      P = p;
+      break;
+    }
+  }
+  const uint64_t digit = (uint64_t(1) << dim) - 1, rest = hi - P;
+  int64_t n = int64_t(rest >> (dim * K));
+  for (int k = 0; k < K; ++k)
+    n += int64_t(((P - lo) >> (dim * k)) & digit) + int64_t((rest >> (dim * k)) & digit);
+  return n;
+}
+
 // Gap g of m distinct cells S: [S[g-1] + 1, S[g]) (from 0 for g = 0, up to
 // the domain's end for g = m).
 __device__ inline Gap gap_of(const uint64_t* __restrict__ S, int64_t m, int64_t g, uint64_t end) {
@@ -259,8 +284,7 @@ __global__ __launch_bounds__(kScanSmall) void k_gap_count(const uint64_t* __rest
     c[k] = 0;
     if (g >= n) continue;
     const Gap q = gap_of(S, m, g, end);
-    const Runs r = gap_runs(q.lo, q.hi, dim, K);
-    c[k] = r.n_up + int64_t(r.mid_n) + r.n_down + (g < m ? 1 : 0);
+    c[k] = gap_leaves(q.lo, q.hi, dim, K) + (g < m ? 1 : 0);
     local += c[k];
   }
   int64_t blk;
