@@ -194,64 +194,35 @@ __global__ __launch_bounds__(kScanSmall) void k_unique(const uint64_t* __restric
     if (first[k]) out[o++] = in[base + k];
 }
 
-// Greedy tiling of the Morton interval [x, hi) of finest cells by aligned
+// Greedy tiling of the Morton interval [lo, hi) of finest cells by aligned
 // octants of at most 2^(dim*K) cells (depth >= d_max - K): at every position
-// the largest aligned octant that fits.  The tiling has an ascending run, a
-// run of full 2^(dim*K) octants, and a descending run.
+// the largest aligned octant that fits.  Let P be the point of [lo, hi]
+// aligned to the largest octant size 2^(dim j), j <= K.  No octant of the
+// tiling crosses P (an aligned octant across it would put a point aligned to
+// a larger size inside [lo, hi]), so the tiling is an ascending run over
+// [lo, P) -- d_k octants of size 2^(dim k) for each digit d_k of P - lo in
+// base 2^dim, smallest first -- then (hi - P) >> (dim K) octants of the full
+// size, then a descending run over the rest, digit by digit from the top.
+// Counting and emitting both follow these digits instead of probing the
+// largest fitting octant at every position.
 struct Gap {
   uint64_t lo, hi;
 };
 
-__device__ inline int greedy_exp(uint64_t x, uint64_t hi, int dim, int K) {
-  int k = x == 0 ? K : min(K, int(__ffsll((unsigned long long)x) - 1) / dim);
-  while (k > 0 && x + (uint64_t(1) << (dim * k)) > hi) --k;
-  return k;
-}
-
-// The three runs of [lo, hi): ascending octants up to the first position
-// aligned to the full size, the number of full octants, the descending rest.
-struct Runs {
-  uint64_t mid_lo;    // first cell of the full-size run (after the ascending run)
-  uint64_t mid_n;     // full-size octants
-  int64_t n_up, n_down;
-};
-
-__device__ inline Runs gap_runs(uint64_t lo, uint64_t hi, int dim, int K) {
-  Runs r{};
-  const uint64_t full = uint64_t(1) << (dim * K);
-  uint64_t x = lo;
-  while (x < hi && !((x & (full - 1)) == 0 && x + full <= hi)) {
-    x += uint64_t(1) << (dim * greedy_exp(x, hi, dim, K));
-    ++r.n_up;
-  }
-  r.mid_lo = x;
-  r.mid_n = x < hi ? (hi - x) >> (dim * K) : 0;
-  x += r.mid_n << (dim * K);
-  while (x < hi) {
-    x += uint64_t(1) << (dim * greedy_exp(x, hi, dim, K));
-    ++r.n_down;
-  }
-  return r;
-}
-
-// Leaves of the greedy tiling of [lo, hi), counted in closed form rather than
-// walked.  Let P be the point of [lo, hi] aligned to the largest octant size
-// 2^(dim j), j <= K.  The tiling then covers [lo, P) with P - lo's digits in
-// base 2^dim (one octant of size 2^(dim k) per unit of digit k), then
-// (hi - P) >> (dim K) octants of the full size, then the rest digit by digit
-// again.  No octant of the tiling crosses P: an aligned octant across it would
-// put a point aligned to a larger size inside [lo, hi].
-__device__ inline int64_t gap_leaves(uint64_t lo, uint64_t hi, int dim, int K) {
-  if (lo >= hi) return 0;
-  uint64_t P = lo;
-  for (int j = K; j >= 0; --j) {
+// P for a non-empty gap.
+__device__ inline uint64_t gap_pivot(uint64_t lo, uint64_t hi, int dim, int K) {
+  for (int j = K; j > 0; --j) {
     const uint64_t b = uint64_t(1) << (dim * j);
     const uint64_t p = (lo + b - 1) & ~(b - 1);
-    if (p <= hi) {
-      P = p;
-      break;
-    }
+    if (p <= hi) return p;
   }
+  return lo;
+}
+
+// Leaves of the tiling of [lo, hi).
+__device__ inline int64_t gap_leaves(uint64_t lo, uint64_t hi, int dim, int K) {
+  if (lo >= hi) return 0;
+  const uint64_t P = gap_pivot(lo, hi, dim, K);
   const uint64_t digit = (uint64_t(1) << dim) - 1, rest = hi - P;
   int64_t n = int64_t(rest >> (dim * K));
   for (int k = 0; k < K; ++k)
@@ -298,10 +269,10 @@ __global__ __launch_bounds__(kScanSmall) void k_gap_count(const uint64_t* __rest
 }
 
 // One lane per gap writes its leaves at goff[g]: the ascending run, the
-// full-size run, the descending run and the closing point cell.  Nearly
-// every gap holds a few leaves; the long full-size runs (at most the
-// background's 2^(d d_min) octants, in the gaps far from every point) are
-// rare, and a lane walks them alone.
+// full-size run, the descending run (the digits above) and the closing point
+// cell.  Nearly every gap holds a few leaves; the long full-size runs (at
+// most the background's 2^(d d_min) octants, in the gaps far from every
+// point) are rare, and a lane walks them alone.
 __global__ __launch_bounds__(256) void k_gap_emit(const uint64_t* __restrict__ S, int64_t m,
                                                   uint64_t end, KeyGeom g, int K,
                                                   const int64_t* __restrict__ goff,
@@ -310,20 +281,25 @@ __global__ __launch_bounds__(256) void k_gap_emit(const uint64_t* __restrict__ S
   if (gi > m) return;
   const int dim = g.dim;
   const Gap q = gap_of(S, m, gi, end);
-  const Runs r = gap_runs(q.lo, q.hi, dim, K);
   int64_t o = goff[gi];
-  uint64_t x = q.lo;
-  for (int64_t i = 0; i < r.n_up; ++i) {
-    const int k = greedy_exp(x, q.hi, dim, K);
-    keys[o++] = make_key(g, x, g.dmax - k);
-    x += uint64_t(1) << (dim * k);
-  }
-  for (uint64_t i = 0; i < r.mid_n; ++i) keys[o++] = make_key(g, r.mid_lo + (i << (dim * K)), g.dmax - K);
-  x = r.mid_lo + (r.mid_n << (dim * K));
-  for (int64_t i = 0; i < r.n_down; ++i) {
-    const int k = greedy_exp(x, q.hi, dim, K);
-    keys[o++] = make_key(g, x, g.dmax - k);
-    x += uint64_t(1) << (dim * k);
+  if (q.lo < q.hi) {
+    const uint64_t P = gap_pivot(q.lo, q.hi, dim, K);
+    const uint64_t digit = (uint64_t(1) << dim) - 1, rest = q.hi - P;
+    uint64_t x = q.lo;
+    for (int k = 0; k < K; ++k)
+      for (uint64_t t = ((P - q.lo) >> (dim * k)) & digit; t > 0; --t) {
+        keys[o++] = make_key(g, x, g.dmax - k);
+        x += uint64_t(1) << (dim * k);
+      }
+    for (uint64_t t = rest >> (dim * K); t > 0; --t) {
+      keys[o++] = make_key(g, x, g.dmax - K);
+      x += uint64_t(1) << (dim * K);
+    }
+    for (int k = K - 1; k >= 0; --k)
+      for (uint64_t t = (rest >> (dim * k)) & digit; t > 0; --t) {
+        keys[o++] = make_key(g, x, g.dmax - k);
+        x += uint64_t(1) << (dim * k);
+      }
   }
   if (gi < m) keys[o] = make_key(g, S[gi], g.dmax);
 }
