@@ -1001,11 +1001,20 @@ lt_status launch_transfer_mixed(lt_tree_s* t, const uint64_t* keys, Count n, con
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
   LT_TRY_STATUS(transfer_side(t, &side, &fork, &join));
+  // The group list first, alone on the caller's stream: beside the copy pass
+  // its look-back tiles wait for wave slots behind the copy's workgroups
+  // (~0.3 ms alone, ~2 ms beside it at 10M leaves), and the interpolation
+  // passes on the second stream need it.  Then the copy pass on the caller's
+  // stream and, as in the single-degree form, the interpolation passes
+  // (which here write no copies) on the second stream.
+  ScanState st;
+  LT_TRY_STATUS(prep_scan(t, ngroups, kTileMin, s, 0, &st));
+  st.items.p = ngroups_dev;
+  int32_t* flist = t->grp_list + 3 * ngroups;
+  k_group_list_mixed<<<grid_tiles(st), kScanSmall, 0, s>>>(t->g, keys, t->mesh_np, t->map_kind, n,
+                                                           t->grp_list, st, flist, &t->dctr->nfgroups);
   hipError_t ef = hipEventRecord(fork, s);
   if (ef != hipSuccess) return fail(LT_ERR_HIP, std::string("transfer fork: ") + hipGetErrorString(ef));
-  // the copy pass first on the caller's stream, so that its start waits on no
-  // host call of the fork; then, as in the single-degree form, the
-  // interpolation passes (which here write no copies) on the second stream
   const dim3 grid{unsigned(nchunks), unsigned(nvar), 1u};
 #define LT_CM(E)                                                                                    \
   do {                                                                                              \
@@ -1023,13 +1032,7 @@ lt_status launch_transfer_mixed(lt_tree_s* t, const uint64_t* keys, Count n, con
     LT_CM(2);
 #undef LT_CM
   ef = hipStreamWaitEvent(side, fork, 0);
-  ScanState st;
-  lt_status r = ef == hipSuccess ? prep_scan(t, ngroups, kTileMin, side, 0, &st) : LT_OK;
-  if (r == LT_OK && ef == hipSuccess) {
-    st.items.p = ngroups_dev;
-    int32_t* flist = t->grp_list + 3 * ngroups;
-    k_group_list_mixed<<<grid_tiles(st), kScanSmall, 0, side>>>(t->g, keys, t->mesh_np, t->map_kind, n,
-                                                                t->grp_list, st, flist, &t->dctr->nfgroups);
+  if (ef == hipSuccess) {
     // one launch of each interpolation kernel per degree present; the blocks
     // of a launch skip the other degrees' entries
     const dim3 gi{unsigned(std::max<int64_t>(1, std::min<int64_t>(3 * ngroups, t->tune.interp_grid))),
@@ -1051,7 +1054,6 @@ lt_status launch_transfer_mixed(lt_tree_s* t, const uint64_t* keys, Count n, con
   // the join on every path that forked, so that a capture in progress stays whole
   const hipError_t ej = hipEventRecord(join, side);
   const hipError_t ew = ej == hipSuccess ? hipStreamWaitEvent(s, join, 0) : ej;
-  if (r != LT_OK) return r;
   if (ef != hipSuccess) return fail(LT_ERR_HIP, std::string("transfer fork: ") + hipGetErrorString(ef));
   if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("mixed transfer launch: ") + hipGetErrorString(e));
   if (ew != hipSuccess) return fail(LT_ERR_HIP, std::string("transfer join: ") + hipGetErrorString(ew));
