@@ -144,7 +144,7 @@ lt_status capture(lt_cycle c) {
       hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess)
     st = fail(LT_ERR_HIP, "capture side stream");
-  if (st == LT_OK && t->g.dim == 3) {  // the transfer's own second stream, made outside the capture
+  if (st == LT_OK) {  // the transfer's own second stream, made outside the capture
     hipStream_t xs;
     hipEvent_t xf, xj;
     st = transfer_side(t, &xs, &xf, &xj);

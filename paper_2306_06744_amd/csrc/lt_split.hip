@@ -397,29 +397,46 @@ lt_status launch_split_transfer(lt_tree_s* t, Count cn, int p, int nvar, const d
   if (n == 0) return LT_OK;
   LT_TRY_STATUS(grow(t->A, &t->split_R, &t->split_R_cap, n));
   LT_TRY_STATUS(grow(t->A, &t->split_F, &t->split_F_cap, n));
-  ScanState st;
-  LT_TRY_STATUS(prep_scan(t, n, kTileMin, s, 0, &st));
-  st.items.p = cn.p;
-  k_split_lists<<<grid_tiles(st), kScanSmall, 0, s>>>(t->map_kind, t->split_R, t->split_F, st);
   const bf16x8* fr = static_cast<const bf16x8*>(t->split_frags);
   const bf16x8* fI = fr;
   const bf16x8* fP = fr + size_t(nc) * 3 * kMT * kKS * 64;
-  LT_TRY_STATUS(launch_copy(t, cn, int64_t(nvar) * kNP, u_old, ld_old, u_new, ld_new, s));
-  const int64_t max_ref_tiles = (n / nc + kTC - 1) / kTC + 1;
-  const int64_t max_fuse_tiles = (n + kTC - 1) / kTC + 1;
-  const dim3 gr(unsigned(std::min<int64_t>(max_ref_tiles, 2048)), unsigned(nvar));
-  const dim3 gf(unsigned(std::min<int64_t>(max_fuse_tiles, 512)), unsigned(nvar));
-  if (nc == 8) {
-    k_split_refine<8><<<gr, 512, 0, s>>>(fI, t->split_vec, t->split_R, st.total, t->map_src, u_old,
-                                         ld_old, u_new, ld_new);
-    k_split_fuse<8><<<gf, 512, 0, s>>>(fP, t->split_vec, t->split_F, st.total, t->map_src, u_old,
-                                       ld_old, u_new, ld_new);
-  } else {
-    k_split_refine<4><<<gr, 256, 0, s>>>(fI, t->split_vec, t->split_R, st.total, t->map_src, u_old,
-                                         ld_old, u_new, ld_new);
-    k_split_fuse<4><<<gf, 256, 0, s>>>(fP, t->split_vec, t->split_F, st.total, t->map_src, u_old,
-                                       ld_old, u_new, ld_new);
+  // The copy pass writes only copies and the refinement and fusion passes
+  // only refined and fused elements: the latter run on the tree's second
+  // stream beside the copy pass, forked after it is enqueued and joined back.
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  LT_TRY_STATUS(transfer_side(t, &side, &fork, &join));
+  hipError_t ef = hipEventRecord(fork, s);
+  if (ef != hipSuccess) return fail(LT_ERR_HIP, std::string("split transfer fork: ") + hipGetErrorString(ef));
+  lt_status r = launch_copy(t, cn, int64_t(nvar) * kNP, u_old, ld_old, u_new, ld_new, s);
+  ef = hipStreamWaitEvent(side, fork, 0);
+  ScanState st;
+  if (r == LT_OK && ef == hipSuccess) r = prep_scan(t, n, kTileMin, side, 0, &st);
+  if (r == LT_OK && ef == hipSuccess) {
+    st.items.p = cn.p;
+    k_split_lists<<<grid_tiles(st), kScanSmall, 0, side>>>(t->map_kind, t->split_R, t->split_F, st);
+    const int64_t max_ref_tiles = (n / nc + kTC - 1) / kTC + 1;
+    const int64_t max_fuse_tiles = (n + kTC - 1) / kTC + 1;
+    const dim3 gr(unsigned(std::min<int64_t>(max_ref_tiles, 2048)), unsigned(nvar));
+    const dim3 gf(unsigned(std::min<int64_t>(max_fuse_tiles, 512)), unsigned(nvar));
+    if (nc == 8) {
+      k_split_refine<8><<<gr, 512, 0, side>>>(fI, t->split_vec, t->split_R, st.total, t->map_src, u_old,
+                                              ld_old, u_new, ld_new);
+      k_split_fuse<8><<<gf, 512, 0, side>>>(fP, t->split_vec, t->split_F, st.total, t->map_src, u_old,
+                                            ld_old, u_new, ld_new);
+    } else {
+      k_split_refine<4><<<gr, 256, 0, side>>>(fI, t->split_vec, t->split_R, st.total, t->map_src, u_old,
+                                              ld_old, u_new, ld_new);
+      k_split_fuse<4><<<gf, 256, 0, side>>>(fP, t->split_vec, t->split_F, st.total, t->map_src, u_old,
+                                            ld_old, u_new, ld_new);
+    }
   }
+  // the join on every path that forked, so that a capture in progress stays whole
+  const hipError_t ej = hipEventRecord(join, side);
+  const hipError_t ew = ej == hipSuccess ? hipStreamWaitEvent(s, join, 0) : ej;
+  if (r != LT_OK) return r;
+  if (ef != hipSuccess) return fail(LT_ERR_HIP, std::string("split transfer fork: ") + hipGetErrorString(ef));
+  if (ew != hipSuccess) return fail(LT_ERR_HIP, std::string("split transfer join: ") + hipGetErrorString(ew));
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(LT_ERR_HIP, std::string("split transfer launch: ") + hipGetErrorString(e));
   return LT_OK;
