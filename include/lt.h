@@ -259,12 +259,13 @@ lt_status lt_map(lt_tree t, void* stream);
  *                are exact.  Needs 64 points per element (dim 3 with p = 3,
  *                or dim 2 with p = 7).  Relative L2 error ~1e-7 against FP64.
  * Other values return LT_ERR_ARG, as does nvar * n_p outside [1, 65535].
- * Asynchronous (unless the mapping was stale).  In 3D at precision 0 the
- * interpolation passes run on a second stream owned by the tree (made on the
- * first such call), forked from `stream` after the copy pass is enqueued and
- * joined back to it: later work on `stream` sees the whole transfer.  A caller
- * that captures this call into a graph makes one such call eagerly first (or
- * uses lt_transfer_noalloc, which stays on `stream`). */
+ * Asynchronous (unless the mapping was stale).  In 3D at precision 0, and at
+ * precision 1, the interpolation passes run on a second stream owned by the
+ * tree (made on the first such call), forked from `stream` after the copy
+ * pass is enqueued and joined back to it: later work on `stream` sees the
+ * whole transfer.  A caller that captures this call into a graph makes one
+ * such call eagerly first (or uses lt_transfer_noalloc, which stays on
+ * `stream`). */
 lt_status lt_transfer(lt_tree t, int p, int nvar, const double* u_old, int64_t ld_old,
                       double* u_new, int64_t ld_new, int precision, void* stream);
 
