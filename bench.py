@@ -663,7 +663,7 @@ def main():
                          "MiB (a known-size reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the adaptation cycle on a single "
+        print("bench.py measures one GPU only: the library runs the adaptation cycle on a single "
               "MI355X and has no multi-GPU path (--gpus must be 1).", file=sys.stderr)
         sys.exit(2)
     if args.warmup < 3:
