@@ -684,6 +684,8 @@ def main():
 
     tunes = {}
     copy_runs = {}
+    cyc_ms = {}
+    class_counts = []
 
     side = torch.cuda.Stream()
 
@@ -731,14 +733,20 @@ def main():
         torch.cuda.synchronize()
         events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                   for _ in range(args.steps)]
+        # cycle boundaries on the stream (no host synchronisation added): each
+        # cycle's duration on the GPU timeline, idle gaps included
+        bounds = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         sizes = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
+            bounds[k].record(stream)
             sizes.append(step(args.warmup + k, events[k]))
+        bounds[args.steps].record(stream)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         tr_ms = [a.elapsed_time(b) for a, b in events]
+        cyc_ms[precision] = [bounds[k].elapsed_time(bounds[k + 1]) for k in range(args.steps)]
         for k, (sz, ms) in enumerate(zip(sizes, tr_ms)):
             log(f"[precision {precision}] cycle {args.warmup + k}: {sz[0]} -> {sz[1]} leaves, "
                 f"{sz[2]} hanging faces, transfer {ms:.3f} ms")
@@ -758,6 +766,21 @@ def main():
             copy_runs["GBs"] = 2 * E * n / (ev[0].elapsed_time(ev[1]) / 5 * 1e-3) / 1e9
             copy_runs["leaves"] = n
         del t
+        if precision == 0:
+            # the timed cycles' copy / refined / fused counts, from an untimed
+            # replay of the same cycles (the flags depend on the keys only, so
+            # the trees and mappings repeat exactly; no transfer needed)
+            tr = lt.Tree.uniform(w.dim, w.d_min, w.d_max)
+            for c in range(args.warmup + args.steps):
+                tr.adapt(tr.flag(w.centres_at(c), w.r_in, w.r_out, nodes, w.lo, w.length,
+                                 dist_axes=w.dist_axes, periodic_dist=w.periodic_dist))
+                tr.balance()
+                tr.map()
+                if c >= args.warmup:
+                    kind = tr.mapping()[1]
+                    class_counts.append((int((kind == 0).sum()), int((kind > 0).sum()),
+                                         int((kind < 0).sum())))
+            del tr
         return sizes, elapsed, tr_ms
 
     sizes, elapsed, tr_ms = run(0)
@@ -816,7 +839,12 @@ def main():
             "cycle_hbm_frac": cyc_bytes / elapsed / (HBM_PEAK_GBS * 1e9),
             "transfer_ms_mean": sum(tr_ms) / len(tr_ms),
             "transfer_tuning": tunes.get(0),
+            "cycle_ms_median": sorted(cyc_ms[0])[len(cyc_ms[0]) // 2],
             "cycles": [{"cycle": args.warmup + k, "n_old": a, "n_new": b, "n_hang": h,
+                        # from the replay, kept only where it reproduced the timed cycle's size
+                        "copies_refined_fused": (list(class_counts[k]) if k < len(class_counts)
+                                                 and sum(class_counts[k]) == b else None),
+                        "cycle_ms": cyc_ms[0][k],
                         "transfer_ms": ms,
                         "transfer_hbm_frac": (E * a + (E + 5) * b) / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
                        for k, ((a, b, h), ms) in enumerate(zip(sizes, tr_ms))],
