@@ -701,20 +701,20 @@ __global__ __launch_bounds__(256) void k_connect_fine(KeyGeom g, const uint64_t*
   }
 }
 
-// Old -> new mapping (Section 4.2): lower bound of each new key in the old tree.
-__device__ inline void map_one(KeyGeom g, const uint64_t* __restrict__ old_keys, int64_t n_old,
-                               const uint64_t* __restrict__ keys, int64_t j, int32_t* __restrict__ src,
-                               int8_t* __restrict__ kind, unsigned* err) {
-  const uint64_t key = keys[j];
-  const int64_t B = lower_bound(old_keys, n_old, key);
+// Old -> new mapping (Section 4.2): lower bound B of each new key in the old
+// tree, then the case it falls in.  old(i) reads old key i.
+template <class Old>
+__device__ inline void map_case(KeyGeom g, const Old& old, int64_t n_old, uint64_t key, int64_t B,
+                                int64_t j, int32_t* __restrict__ src, int8_t* __restrict__ kind,
+                                unsigned* err) {
   const int d = key_depth(g, key);
-  if (B < n_old && old_keys[B] == key) {
+  if (B < n_old && old(B) == key) {
     src[j] = int32_t(B);
     kind[j] = 0;
     return;
   }
   if (B > 0 && d > 0) {
-    const uint64_t pk = old_keys[B - 1];
+    const uint64_t pk = old(B - 1);
     const uint64_t m = key_m(g, key);
     const uint64_t pm = key_m(g, pk);
     if (key_depth(g, pk) == d - 1 && (m & ~(span(g, d - 1) - 1)) == pm) {
@@ -724,9 +724,9 @@ __device__ inline void map_one(KeyGeom g, const uint64_t* __restrict__ old_keys,
     }
   }
   const int nc = g.nchild();
-  if (B + nc <= n_old && old_keys[B] == key + 1 && d < g.dmax) {
+  if (B + nc <= n_old && old(B) == key + 1 && d < g.dmax) {
     const uint64_t last = child_key(g, key_m(g, key), d, nc - 1);
-    if (old_keys[B + nc - 1] == last) {
+    if (old(B + nc - 1) == last) {
       src[j] = int32_t(B);
       kind[j] = -1;
       return;
@@ -739,14 +739,96 @@ __device__ inline void map_one(KeyGeom g, const uint64_t* __restrict__ old_keys,
   atomicOr(err, ERR_MAP);
 }
 
+// First indices of keys[0, n) >= pa and >= pb, found by the whole wave
+// together (every lane passes the same two probes): each half of the wave
+// probes 32 evenly spaced keys of its remaining range per round and keeps the
+// one gap its probe falls in -- one memory round trip per round for both
+// searches (five at 1.6M keys) instead of one per halving.
+__device__ inline void wave_lower_bound2(const uint64_t* __restrict__ keys, int64_t n, uint64_t pa,
+                                         uint64_t pb, int64_t* ra, int64_t* rb) {
+  const int lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
+  const uint64_t probe = half ? pb : pa;
+  int64_t lo = 0, hi = n;  // this half's bound lies in [lo, hi]
+  for (;;) {
+    const bool wide = hi - lo > 32;
+    if (__ballot(wide) == 0) break;  // both halves narrow: the loop is left by the whole wave
+    const int64_t step = wide ? (hi - lo + 31) / 32 : 1;
+    const int64_t p = lo + int64_t(hl) * step;
+    // the probes below the bound are a prefix of the half's lanes (the keys ascend)
+    const uint64_t m = __ballot(p < hi && keys[p] < probe);
+    const int c = __popc(unsigned(half ? (m >> 32) : m));
+    if (wide) {
+      if (c == 0) {
+        hi = lo;
+      } else {
+        const int64_t nlo = lo + int64_t(c - 1) * step + 1;
+        hi = std::min(hi, lo + int64_t(c) * step);
+        lo = nlo;
+      }
+    }
+  }
+  const int64_t p = lo + hl;
+  const uint64_t m = __ballot(p < hi && keys[p] < probe);
+  const int64_t r = lo + __popc(unsigned(half ? (m >> 32) : m));
+  *ra = __shfl(r, 0);
+  *rb = __shfl(r, 32);
+}
+
+__device__ inline void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A wave maps 64 consecutive new keys.  Their lower bounds lie between those
+// of the wave's first and last key, found by one cooperative search; the
+// old keys around that range (the case checks read B - 1 and B + 2^d - 1) go
+// to the wave's LDS window in one coalesced load, and each lane bisects its
+// own bound there.  A range wider than the window is bisected in memory.
+constexpr int kMapWin = 640;
 __global__ __launch_bounds__(kBlock) void k_map(KeyGeom g, const uint64_t* __restrict__ old_keys,
                                                 Count cn_old, const uint64_t* __restrict__ keys,
                                                 Count cn, int32_t* __restrict__ src,
                                                 int8_t* __restrict__ kind, unsigned* err) {
+  __shared__ uint64_t win[kBlock / 64][kMapWin];
   const int64_t n_old = cn_old.get(), n = cn.get();
-  for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < n;
-       j += int64_t(gridDim.x) * blockDim.x)
-    map_one(g, old_keys, n_old, keys, j, src, kind, err);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nc = g.nchild();
+  uint64_t* W = win[wv];
+  for (int64_t wb = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63); wb < n;
+       wb += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t j = wb + lane;
+    const bool live = j < n;
+    const uint64_t key = keys[live ? j : n - 1];  // lanes past the end repeat the last key
+    int64_t bf, bl;
+    wave_lower_bound2(old_keys, n_old, __shfl(key, 0), __shfl(key, 63), &bf, &bl);
+    const int64_t w0 = bf > 0 ? bf - 1 : 0;
+    const int64_t w1 = std::min(bl + nc, n_old);
+    if (w1 - w0 <= kMapWin) {
+      for (int64_t q = w0 + lane; q < w1; q += 64) W[q - w0] = old_keys[q];
+      wave_lds_fence();
+      int64_t lo = bf, hi = bl;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (W[mid - w0] < key)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      if (live) map_case(g, [&](int64_t i) { return W[i - w0]; }, n_old, key, lo, j, src, kind, err);
+      wave_lds_fence();  // every lane done with the window before the next one overwrites it
+    } else {
+      int64_t lo = bf, hi = bl;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (old_keys[mid] < key)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      if (live) map_case(g, [&](int64_t i) { return old_keys[i]; }, n_old, key, lo, j, src, kind, err);
+    }
+  }
 }
 
 
