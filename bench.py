@@ -852,7 +852,7 @@ def main():
         "roofline": {
             "bound": "hbm",
             "kernel": "FP64 transfer (lt_transfer: k_copy_chunks + k_copy3 copy pass, k_group_list + "
-                      "k_interp3 interpolation), event-timed together",
+                      "k_refine3 + k_interp3 interpolation), event-timed together",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

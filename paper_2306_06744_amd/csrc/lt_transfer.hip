@@ -490,6 +490,120 @@ __global__ __launch_bounds__(64 * N) void k_interp3_ref(const double* __restrict
   }
 }
 
+// Buffer resource over a wave's rows: base address, no stride, no range limit
+// (every offset formed below lies inside the caller's arrays).  The fourth
+// word is the GFX9-family data format for raw dword access.
+__device__ inline __amdgpu_buffer_rsrc_t rows_rsrc(const double* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), 0, 0xFFFFFFFF, 0x00020000);
+}
+typedef unsigned int u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned int))));
+constexpr int kNonTemporal = 2;  // cache-policy bit of the buffer access: streaming
+
+// The refinement pass of k_interp3_ref (one variable and group of 64 new
+// elements per block of N waves, wave w = z-slab w, the z pass through LDS),
+// in a form without branches around memory accesses:
+//  - every lane of a listed group loads and stores each row: a refined child
+//    stores its interpolated value, a copy its source value (selected, not
+//    branched), and lanes past the end repeat the last element, so that the
+//    stores of an iteration are a fixed number;
+//  - rows are addressed through a per-wave buffer resource (row r by a scalar
+//    offset, the element by a 32-bit vector offset), which keeps no address
+//    registers per row;
+//  - a group's map (kind, source) is loaded two groups ahead and its rows one
+//    group ahead, both issued before the stores of the group in hand.
+// With a fixed store count the compiler waits only for loads issued before
+// the previous group's stores, never for the stores themselves, and the
+// kernel fits 3 waves per SIMD instead of 2.  Row offsets must fit 32 bits:
+// the launch checks N*N rows of either array against that.
+template <int N>
+__global__ __launch_bounds__(64 * N) void k_refine3(const double* __restrict__ ops,
+                                                    const int32_t* __restrict__ src,
+                                                    const int8_t* __restrict__ kind, Count cn,
+                                                    const int32_t* __restrict__ groups,
+                                                    const int64_t* __restrict__ ngroups,
+                                                    const double* __restrict__ uo, int64_t ldo,
+                                                    double* __restrict__ un, int64_t ldn) {
+  constexpr int NN = N * N;
+  constexpr int NP = NN * N;
+  __shared__ double T[N][NN][64];
+  __shared__ double M[2][NN];  // A_0, A_1
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const int64_t n = cn.get();
+  const int64_t ng = *ngroups;
+  if (int64_t(blockIdx.x) >= ng) return;
+  for (int i = threadIdx.x; i < 2 * NN; i += blockDim.x) M[i / NN][i % NN] = ops[i];
+  const int v = blockIdx.y;
+  const __amdgpu_buffer_rsrc_t RU = rows_rsrc(uo + (int64_t(v) * NP + int64_t(w) * NN) * ldo);
+  const __amdgpu_buffer_rsrc_t RO = rows_rsrc(un + (int64_t(v) * NP + int64_t(w) * NN) * ldn);
+  const uint32_t so = uint32_t(ldo * 8), sn = uint32_t(ldn * 8);
+  const int64_t G = gridDim.x;
+  struct Map {
+    uint32_t j, s;
+    int kd;
+  };
+  auto map_of = [&](int64_t q) -> Map {
+    const int64_t qc = q < ng ? q : ng - 1;
+    int64_t j = int64_t(groups[qc]) * 64 + lane;
+    j = j < n ? j : n - 1;  // past the end: the last element again (same values, same address)
+    Map m;
+    m.j = uint32_t(j);
+    m.kd = int(kind[j]);
+    m.s = uint32_t(src[j]);
+    return m;
+  };
+  // a copy loads its own source, a refined child its parent: the same rows
+  auto load_rows = [&](const Map& m, double* in) {
+    const uint32_t off = m.s * 8u;
+#pragma unroll
+    for (int r = 0; r < NN; ++r)
+      in[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(RU, off, uint32_t(r) * so,
+                                                                              kNonTemporal));
+  };
+  __syncthreads();
+  int64_t q = blockIdx.x;
+  Map m0 = map_of(q), m1 = map_of(q + G);
+  double in[NN];
+  load_rows(m0, in);
+  // Nothing may be in flight where the loop begins: the counter state at its
+  // head is then the one its own iterations leave (only stores), and the
+  // first wait inside covers loads alone.
+#pragma unroll
+  for (int r = 0; r < NN; ++r) asm volatile("" ::"v"(in[r]));
+  asm volatile("" ::"v"(m0.j), "v"(m0.kd), "v"(m1.j), "v"(m1.s), "v"(m1.kd));
+  __builtin_amdgcn_s_waitcnt(0);
+  while (q < ng) {
+    const Map m2 = map_of(q + 2 * G);
+    double nx[NN];
+    load_rows(m1, nx);
+    const int c = m0.kd > 0 ? m0.kd - 1 : 0;
+    {
+      double sl[NN];
+      xy_pass<N>(M[c & 1], M[(c >> 1) & 1], in, sl);
+#pragma unroll
+      for (int r = 0; r < NN; ++r) T[w][r][lane] = sl[r];
+    }
+    __syncthreads();
+    const double* Mz = M[(c >> 2) & 1] + w * N;
+    const bool refined = m0.kd > 0;
+    const uint32_t oj = m0.j * 8u;
+#pragma unroll
+    for (int r = 0; r < NN; ++r) {
+      double a = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) a += Mz[k] * T[k][r][lane];
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, refined ? a : in[r]), RO, oj,
+                                            uint32_t(r) * sn, kNonTemporal);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NN; ++r) in[r] = nx[r];
+    m0 = m1;
+    m1 = m2;
+    q += G;
+  }
+}
+
 // 3D, general interpolation / projection pass, for the groups that hold a
 // fused element (refined children in the same group are handled here too).
 // A block of N waves takes listed groups of 64 consecutive new elements of
@@ -819,8 +933,13 @@ hipError_t launch(const TransferTune& tune, const double* ops, const int32_t* sr
                                                       &X.ctr->nfgroups);
       const dim3 gi{unsigned(std::max<int64_t>(1, std::min<int64_t>(ngroups, tune.interp_grid))),
                     unsigned(nvar), 1u};
-      k_interp3_ref<N, false><<<gi, 64 * N, 0, si>>>(ops, src, kind, n, X.grp_list, st.total, uo, ldo,
-                                                     un, ldn, MixedArgs{});
+      // the buffer form takes N*N rows of either array by a 32-bit offset
+      constexpr int64_t kRowsMax = (int64_t(1) << 32) / (8 * N * N);
+      if (ldo < kRowsMax && ldn < kRowsMax)
+        k_refine3<N><<<gi, 64 * N, 0, si>>>(ops, src, kind, n, X.grp_list, st.total, uo, ldo, un, ldn);
+      else
+        k_interp3_ref<N, false><<<gi, 64 * N, 0, si>>>(ops, src, kind, n, X.grp_list, st.total, uo,
+                                                       ldo, un, ldn, MixedArgs{});
       k_interp3<N, false><<<gi, 64 * N, 0, si>>>(ops, src, kind, n, flist, &X.ctr->nfgroups, uo, ldo, un,
                                                  ldn, MixedArgs{});
       e = hipGetLastError();
