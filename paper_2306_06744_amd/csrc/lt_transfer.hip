@@ -971,11 +971,14 @@ lt_status copy_pass(const TransferTune& tune, const int32_t* src, const int8_t* 
   const int64_t CH = 256 * int64_t(epl);
   const int64_t nchunks = (n.n + CH - 1) / CH;
   // A capacity-sized launch with a hint: workgroups for the hinted count and
-  // an eighth more, striding over whatever lies beyond.  The slack keeps
-  // striding rare: a workgroup's second chunk waits behind its first, and a
-  // grid of 15/16 of the count made the captured cycle ~12% slower.
+  // a 32nd more, striding over whatever lies beyond.  The slack keeps
+  // striding rare (a workgroup's second chunk waits behind its first: a grid
+  // of 15/16 of the count made the captured cycle ~12% slower), and it stays
+  // small because every workgroup past the count is still dispatched, one per
+  // chunk and row, only to exit (an eighth more cost ~58 us per captured
+  // cycle at 1.66M leaves).
   const int64_t nlaunch =
-      n.hint > 0 ? std::max<int64_t>(1, std::min(nchunks, (n.hint + n.hint / 8 + CH - 1) / CH)) : nchunks;
+      n.hint > 0 ? std::max<int64_t>(1, std::min(nchunks, (n.hint + n.hint / 32 + CH - 1) / CH)) : nchunks;
   const dim3 grid{unsigned(nlaunch), unsigned(rows), 1u};
 #define LT_COPY(E)                                                                              \
   do {                                                                                          \
