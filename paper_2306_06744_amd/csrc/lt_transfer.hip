@@ -604,6 +604,138 @@ __global__ __launch_bounds__(64 * N) void k_refine3(const double* __restrict__ o
   }
 }
 
+// The refinement pass of an ensemble with a degree per mesh (MixedArgs), in
+// the form of k_refine3: the block takes the (group, degree N) entries of its
+// degree, and a lane whose element has another degree, is a copy (the copy
+// pass writes those here) or lies past the end repeats the loads and stores
+// of the entry's first refined lane of degree N -- the same values to the
+// same address -- so that every lane stores each row.  Every listed entry has
+// such a lane (k_group_list_mixed lists (group, N) only for a group with a
+// refined element of degree N and no fused one); the entries fetched ahead
+// past the end, which are never stored, fall back to the lane's own element.
+// The mesh-degree table is read from LDS, so that a group's map needs no
+// dependent load.
+constexpr int kMeshTab = 4096;  // meshes whose degrees fit the LDS table
+template <int N>
+__global__ __launch_bounds__(64 * N) void k_refine3_mixed(const double* __restrict__ ops,
+                                                          const int32_t* __restrict__ src,
+                                                          const int8_t* __restrict__ kind, Count cn,
+                                                          const int32_t* __restrict__ groups,
+                                                          const int64_t* __restrict__ ngroups,
+                                                          const double* __restrict__ uo, int64_t ldo,
+                                                          double* __restrict__ un, int64_t ldn,
+                                                          MixedArgs mx, int nmesh) {
+  constexpr int NN = N * N;
+  constexpr int NP = NN * N;
+  __shared__ double T[N][NN][64];
+  __shared__ double M[2][NN];  // A_0, A_1
+  __shared__ uint8_t npt[kMeshTab];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const int64_t n = cn.get();
+  const int64_t ng = *ngroups;
+  if (int64_t(blockIdx.x) >= ng) return;
+  for (int i = threadIdx.x; i < 2 * NN; i += blockDim.x) M[i / NN][i % NN] = ops[i];
+  for (int i = threadIdx.x; i < nmesh; i += blockDim.x) npt[i] = mx.np_of_mesh[i];
+  const int v = blockIdx.y;
+  const __amdgpu_buffer_rsrc_t RU = rows_rsrc(uo + (int64_t(v) * mx.npm + int64_t(w) * NN) * ldo);
+  const __amdgpu_buffer_rsrc_t RO = rows_rsrc(un + (int64_t(v) * mx.npm + int64_t(w) * NN) * ldn);
+  const uint32_t so = uint32_t(ldo * 8), sn = uint32_t(ldn * 8);
+  // The block's next entry of degree N, or ng.  The entry index is the same
+  // on every lane; said explicitly, and kept in 32 bits (entries < 2^31), so
+  // that the list is read by scalar loads and the index stays in scalar
+  // registers (a vector load or register here would wait for every store
+  // before it).
+  const int ngi = int(ng);
+  const int G32 = int(gridDim.x);
+  auto next = [&](int from) -> int {
+    for (int q = __builtin_amdgcn_readfirstlane(from); q < ngi; q = __builtin_amdgcn_readfirstlane(q + G32))
+      if ((__builtin_amdgcn_readfirstlane(groups[q]) & 3) == N - 1) return q;
+    return ngi;
+  };
+  struct Map {
+    uint32_t j, s;
+    int kd;
+    uint64_t key;
+  };
+  auto map_of = [&](int q) -> Map {
+    const int qc = __builtin_amdgcn_readfirstlane(q < ngi ? q : ngi - 1);
+    int64_t j = int64_t(__builtin_amdgcn_readfirstlane(groups[qc]) >> 2) * 64 + lane;
+    j = j < n ? j : n - 1;
+    Map m;
+    m.j = uint32_t(j);
+    m.kd = int(kind[j]);
+    m.s = uint32_t(src[j]);
+    m.key = mx.keys[j];
+    return m;
+  };
+  // the lane's own element if it is a refined child of degree N, else the donor's
+  auto settle = [&](Map& m) {
+    const int np = int(npt[key_mesh(mx.g, m.key)]);  // every key names a mesh: no branch
+    const bool own = (m.kd > 0) & (np == NP);
+    const uint64_t mask = __ballot(own);
+    const int d = mask ? __builtin_ffsll(static_cast<long long>(mask)) - 1 : lane;
+    const uint32_t dj = __shfl(m.j, d), ds = __shfl(m.s, d);
+    const int dk = __shfl(m.kd, d);
+    if (!own) {
+      m.j = dj;
+      m.s = ds;
+      m.kd = dk > 0 ? dk : 1;  // the donor's child (an unlisted fallback: any child, never stored)
+    }
+  };
+  auto load_rows = [&](const Map& m, double* in) {
+    const uint32_t off = m.s * 8u;
+#pragma unroll
+    for (int r = 0; r < NN; ++r)
+      in[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(RU, off, uint32_t(r) * so,
+                                                                              kNonTemporal));
+  };
+  __syncthreads();
+  int q = next(int(blockIdx.x));
+  if (q >= ngi) return;
+  int q1 = next(q + G32);
+  Map m0 = map_of(q), m1 = map_of(q1);
+  settle(m0);
+  double in[NN];
+  load_rows(m0, in);
+#pragma unroll
+  for (int r = 0; r < NN; ++r) asm volatile("" ::"v"(in[r]));
+  asm volatile("" ::"v"(m0.j), "v"(m0.kd), "v"(m1.j), "v"(m1.s), "v"(m1.kd), "v"(m1.key));
+  __builtin_amdgcn_s_waitcnt(0);
+  while (q < ngi) {
+    const int q2 = next(q1 + G32);
+    Map m2 = map_of(q2);
+    settle(m1);
+    double nx[NN];
+    load_rows(m1, nx);
+    const int c = m0.kd - 1;
+    {
+      double sl[NN];
+      xy_pass<N>(M[c & 1], M[(c >> 1) & 1], in, sl);
+#pragma unroll
+      for (int r = 0; r < NN; ++r) T[w][r][lane] = sl[r];
+    }
+    __syncthreads();
+    const double* Mz = M[(c >> 2) & 1] + w * N;
+    const uint32_t oj = m0.j * 8u;
+#pragma unroll
+    for (int r = 0; r < NN; ++r) {
+      double a = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) a += Mz[k] * T[k][r][lane];
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, a), RO, oj, uint32_t(r) * sn,
+                                            kNonTemporal);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NN; ++r) in[r] = nx[r];
+    m0 = m1;
+    m1 = m2;
+    q = q1;
+    q1 = q2;
+  }
+}
+
 // 3D, general interpolation / projection pass, for the groups that hold a
 // fused element (refined children in the same group are handled here too).
 // A block of N waves takes listed groups of 64 consecutive new elements of
@@ -1160,10 +1292,20 @@ lt_status launch_transfer_mixed(lt_tree_s* t, const uint64_t* keys, Count n, con
     const dim3 gi{unsigned(std::max<int64_t>(1, std::min<int64_t>(3 * ngroups, t->tune.interp_grid))),
                   unsigned(nvar), 1u};
     const MixedArgs mx{t->g, keys, t->mesh_np, npm};
+    // the buffer form takes N*N rows of either array by a 32-bit offset and
+    // the mesh-degree table in LDS
+    auto buffer_ok = [&](int nn) {
+      const int64_t rows_max = (int64_t(1) << 32) / (8 * nn * nn);
+      return ldo < rows_max && ldn < rows_max && t->g.nmesh <= kMeshTab;
+    };
 #define LT_MX(NN, OPS)                                                                                 \
   do {                                                                                                 \
-    k_interp3_ref<NN, true><<<gi, 64 * NN, 0, side>>>(OPS, t->map_src, t->map_kind, n, t->grp_list,    \
-                                                      st.total, uo, ldo, un, ldn, mx);                 \
+    if (buffer_ok(NN))                                                                                 \
+      k_refine3_mixed<NN><<<gi, 64 * NN, 0, side>>>(OPS, t->map_src, t->map_kind, n, t->grp_list,      \
+                                                    st.total, uo, ldo, un, ldn, mx, t->g.nmesh);       \
+    else                                                                                               \
+      k_interp3_ref<NN, true><<<gi, 64 * NN, 0, side>>>(OPS, t->map_src, t->map_kind, n, t->grp_list,  \
+                                                        st.total, uo, ldo, un, ldn, mx);               \
     k_interp3<NN, true><<<gi, 64 * NN, 0, side>>>(OPS, t->map_src, t->map_kind, n, flist,              \
                                                   &t->dctr->nfgroups, uo, ldo, un, ldn, mx);           \
   } while (0)
