@@ -208,6 +208,37 @@ def test_transfer_joins_caller_stream(p_refine, p_coarsen):
     assert_transfer(host.numpy(), o.transfer(3, u_old), kind, TOL, "joined")
 
 
+def test_refinement_fallback_for_wide_rows_matches_buffer_form():
+    """The 3D refinement pass addresses a wave's rows through a buffer
+    resource with 32-bit row offsets; leading dimensions from 2^32 / (8 N^2)
+    elements (33.5M at p = 3) take the kernel's earlier form instead.  Both
+    must write the same bits: the same mapping transferred once with a tight
+    leading dimension and once with 2^25 + 64 (two 17 GB arrays, one
+    variable)."""
+    import torch
+    say("wide rows")
+    g, o = both(3, 2, 7, depth=4)
+    n_old = g.size()
+    adapt_both(g, o, synth.random_flags(611, o.size(), 0.4, 0.3))
+    g.balance()
+    g.map()
+    n = g.size()
+    ud = torch.from_numpy(synth.random_solution(612, 1, 64, n_old)).cuda()
+    ua = g.transfer(3, ud)
+    ld = (1 << 25) + 64
+    big = torch.zeros((1, 64, ld), dtype=torch.float64, device="cuda")
+    big[:, :, :n_old] = ud
+    ub = torch.zeros((1, 64, ld), dtype=torch.float64, device="cuda")
+    g.transfer(3, big, u_new=ub)
+    torch.cuda.synchronize()
+    kind = g.mapping()[1].cpu().numpy()
+    say("refined", int((kind > 0).sum()), "fused", int((kind < 0).sum()), "of", n)
+    same = bool(torch.equal(ua, ub[:, :, :n]))
+    del big, ub
+    torch.cuda.empty_cache()
+    assert (kind > 0).any() and same
+
+
 def test_transfer_with_padding_and_high_degree_2d():
     import torch
     say("padding")
